@@ -1,0 +1,163 @@
+"""Benchmark: FP64 cell-updates per second per RK stage on one MI355X.
+
+One step = CFL time step + one TVD-RK3 step (three right-hand-side
+evaluations with halo fill, face fluxes, divergence and stage update) of the
+whole grid, inputs resident in HBM.  Default workload: 3D Taylor-Green vortex,
+64^3 cells, Re 1600, Ma 0.1, viscous (power law).  Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64 = 78.6e12     # MI355X FP64 vector FLOP/s (256 CUs x 2.4 GHz x 128 flop/clk)
+PEAK_HBM = 8.0e12       # MI355X HBM3E bytes/s
+
+# Algorithmic FP64 operations per face of the flux kernel (counted from the
+# kernel source: 10 WENO5-JS reconstructions x 69, HLLC star branch 79, 3D
+# viscous/heat flux 183) and algorithmic bytes per face (the primitive
+# values of one cell, 7 x 8 B, read once; 5 x 8 B of flux written).
+FLOPS_PER_FACE = {(1, False): 6 * 69 + 79, (1, True): 6 * 69 + 79 + 40,
+                  (2, False): 8 * 69 + 79, (2, True): 8 * 69 + 79 + 101,
+                  (3, False): 10 * 69 + 79, (3, True): 10 * 69 + 79 + 183}
+BYTES_PER_FACE = 7 * 8 + 5 * 8
+
+
+def workload(name):
+    from paper_2406_19494_amd import workloads as W
+    if name == "tgv64":
+        case, P = W.tgv(64)
+        return case, P, None, "3D Taylor-Green vortex 64^3, Re 1600, Ma 0.1, FP64, CFL 0.5"
+    if name == "channel":
+        case, P = W.channel()
+        return case, P, None, "channel 192x128x128, tanh beta 2, Ma_b 0.5, Re_b 3000, FP64"
+    if name == "porous_bl":
+        case, P, K = W.porous_bl()
+        return case, P, K, "Mach-6 porous boundary layer 1024x256, FP64"
+    if name == "sod":
+        case, P = W.sod(200)
+        return case, P, None, "Sod 200 cells, FP64"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(case, P, K, budget_s):
+    """The oracle on the host cores: RK3 steps of the same workload until the
+    time budget is spent (at least one step)."""
+    from oracle.pyoracle import Oracle
+    o = Oracle(case, K=K)
+    U = o.cons(P)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        dt = o.dt(U, case.cfl)
+        U = o.step(U, dt)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": case.ncells * 3 * steps / el, "unit": "cell-updates/s per RK stage",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{steps} CFL+RK3 steps of the same {case.n[0]}x{case.n[1]}x{case.n[2]} "
+                      f"workload ({el:.1f} s, OpenMP threads={threads})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="tgv64")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the multi-GPU block decomposition is designed, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2406_19494_amd.solver import Solver
+
+    case, P, K, desc = workload(args.workload)
+    s = Solver(case, K=K)
+    U = s.init_state(P)
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def one_step():
+        s.compute_dt(U, cfl=case.cfl, out=dt)
+        s.step(U, dt)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    assert s.flags() == 0, "non-physical state during the benchmark"
+    ms_step = ms / args.steps
+    value = case.ncells * 3 / (ms_step * 1e-3)
+
+    # per-kernel timing (HIP events on the same stream) -> dominant kernel
+    names = {0: "k_prim_halo", 1: "k_flux<x>", 2: "k_flux<y>", 3: "k_flux<z>", 4: "k_update"}
+    kt = {}
+    for w in [0] + list(range(1, case.ndim + 1)) + [4]:
+        kt[w] = s.time_kernel(U, w, reps=20)
+    dom = max(kt, key=lambda k: kt[k])
+    visc = case.visc_law != "none"
+    if 1 <= dom <= 3:
+        D = dom - 1
+        faces = 1
+        for e in range(3):
+            faces *= case.n[e] + (1 if e == D else 0)
+        flops = FLOPS_PER_FACE[(case.ndim, visc)] * faces
+        achieved = flops / (kt[dom] * 1e-3)
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                "kernel": names[dom], "avg_ms": kt[dom],
+                "algorithmic_flops_per_face": FLOPS_PER_FACE[(case.ndim, visc)],
+                "faces_per_launch": faces}
+    else:
+        roof = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": None, "traffic": None, "kernel": names[dom], "avg_ms": kt[dom]}
+
+    out = {
+        "metric": "FP64 cell-updates/s per RK stage",
+        "value": value,
+        "unit": "cell-updates/s per RK stage",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (analytic initial condition, seeded where random)",
+        "config": {"workload": desc, "cells": case.ncells, "rk_stages": 3,
+                   "step": "CFL dt + TVD-RK3 (WENO5-JS, HLLC, 4th-order viscous)"},
+        "roofline": roof,
+        "kernel_ms": {names[k]: v for k, v in kt.items()},
+        "wall_s": wall,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(case, P, K, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * dcf.h -- C ABI of the differentiable compressible-flow library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates the finite-volume right-hand side of the
+ * compressible Navier-Stokes equations for cell-averaged conserved variables
+ * (paper: Section 2.1, Eqs. (1)-(6)), fills halo cells to impose boundary
+ * conditions (Section 3.2), integrates in time with the three-stage TVD
+ * Runge-Kutta scheme (Section 2.1, text after Eq. (6)), and differentiates
+ * whole trajectories with a hand-written adjoint so that boundary-condition
+ * parameters can be optimised end to end (Section 1 and Section 3.2,
+ * "Disturbance Wall").  Every step runs in HIP kernels; the host code only
+ * validates arguments, carves the workspace and enqueues kernels.
+ *
+ * Conventions
+ *  - Every function returns a dcf_status (0 = DCF_OK, < 0 error) and never
+ *    throws or exits.  dcf_last_error() gives a thread-local message for the
+ *    last failure.
+ *  - Argument errors are detected on the host before anything is enqueued.
+ *    Non-physical states met by the kernels (rho <= 0, p <= 0, T <= 0, or a
+ *    non-finite value) set a flag that dcf_flags() reports.
+ *  - "dev" pointers are device memory owned by the caller (for example torch
+ *    tensors); they must stay valid until the work enqueued on `stream`
+ *    completes.  "host" pointers are read before the call returns.
+ *  - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL is the
+ *    null stream).  No call synchronises except dcf_flags(),
+ *    dcf_gradient() (its segment loop reads nothing back, but it returns
+ *    only after enqueueing every segment) and dcf_destroy().
+ *  - A context is one solve (grid + gas + boundaries).  A context is not
+ *    thread-safe; many contexts per process are fine.
+ *
+ * State layout: an interior-only, dense FP64 array U[nv][nz][ny][nx] with
+ * nv = ndim + 2 conserved variables (rho, rho*u[, rho*v[, rho*w]], E),
+ * x fastest (Eq. (2)).  Unused axes have n = 1.  Primitive input arrays are
+ * P[5][nz][ny][nx] = (rho, u, v, w, p), unused velocities zero.
+ */
+#ifndef DCF_H
+#define DCF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int dcf_status;
+#define DCF_OK 0
+#define DCF_EINVAL (-1)       /* invalid argument                              */
+#define DCF_ENOMEM (-2)       /* workspace too small / host allocation failed   */
+#define DCF_EDEVICE (-3)      /* HIP runtime error                              */
+#define DCF_ENONPHYS (-4)     /* non-physical state flagged by a kernel         */
+#define DCF_EBUDGET (-5)      /* request exceeds a memory budget                */
+#define DCF_EUNSUPPORTED (-6) /* valid but unsupported combination              */
+
+/* boundary kinds (Section 3.2: halo cells carry the boundary condition) */
+#define DCF_BC_PERIODIC 0
+#define DCF_BC_WALL 1      /* isothermal no-slip wall                                  */
+#define DCF_BC_POROUS 2    /* isothermal wall with a Darcy transpiration strip        */
+#define DCF_BC_ZEROGRAD 3  /* zero-gradient extrapolation                             */
+#define DCF_BC_DIRICHLET 4 /* prescribed primitive profile                            */
+
+#define DCF_VISC_NONE 0
+#define DCF_VISC_POWER 1      /* mu = mu_ref (T/T_ref)^omega                          */
+#define DCF_VISC_SUTHERLAND 2 /* mu = mu_ref (T/T_ref)^1.5 (T_ref+S)/(T+S), Sec. 3.2 */
+
+#define DCF_STRETCH_UNIFORM 0
+#define DCF_STRETCH_TANH2 1 /* x = lo + L (1 - tanh(beta (1 - 2 s))/tanh beta)/2, s = xi/n */
+#define DCF_STRETCH_TANH1 2 /* x = lo + L (1 + tanh(beta (s - 1))/tanh beta)           */
+
+#define DCF_SOURCE_NONE 0
+#define DCF_SOURCE_MASSFLUX 1 /* body force S = [0, f, 0, 0, f u], f = -<R_rhou>_V */
+
+#define DCF_FLAG_NONPHYS 1u
+
+typedef struct dcf_ctx dcf_ctx;
+
+/* Grid (Section 2.2: a single-device domain of [Nx, Ny, Nz] interior cells
+ * plus Nh = 3 halo layers per active axis; stretched Cartesian meshes,
+ * Section 2).  Cell i of an axis spans xi in [i, i+1] of the map above. */
+typedef struct {
+  int ndim;            /* 1, 2 or 3                                        */
+  int n[3];            /* interior cells per axis; 1 on unused axes        */
+  double lo[3], hi[3]; /* axis extents                                     */
+  int stretch[3];      /* DCF_STRETCH_*                                    */
+  double beta[3];      /* tanh stretching parameter                        */
+} dcf_grid;
+
+/* Ideal gas and transport (Section 2.1: Fourier heat flux, Stokes stress;
+ * Section 3.2: Sutherland law).  lambda = mu * cp / Pr, cp = gamma R/(gamma-1). */
+typedef struct {
+  double gamma, R, Pr;
+  int visc_law;      /* DCF_VISC_*                                       */
+  double mu_ref, T_ref;
+  double visc_param; /* power-law exponent, or Sutherland constant S      */
+} dcf_gas;
+
+/* One face's boundary condition.  Faces: 0..5 = x-, x+, y-, y+, z-, z+. */
+typedef struct {
+  int kind;                 /* DCF_BC_*                                          */
+  double T_wall;            /* wall temperature (WALL, POROUS)                   */
+  const double *dirichlet;  /* dev, DIRICHLET: [5][n_t2][n_t1] (rho,u,v,w,p)     */
+  int porous_begin;         /* POROUS: strip [begin, end) along the face's first  */
+  int porous_end;           /*   tangential axis, all cells along the second one  */
+  double p_inf;             /* POROUS: reference pressure of the Darcy law        */
+} dcf_bc;
+
+/* ---- context ------------------------------------------------------------ */
+/* Creates a context on the current HIP device, computes the grid metrics
+ * with a kernel (the only allocation the library makes: O(nx+ny+nz)
+ * doubles) and sets every face to DCF_BC_PERIODIC. */
+dcf_status dcf_create(const dcf_grid *grid, const dcf_gas *gas, dcf_ctx **out);
+dcf_status dcf_destroy(dcf_ctx *ctx);
+
+/* nv, interior cell count and the byte size of one state array. */
+dcf_status dcf_state_info(const dcf_ctx *ctx, int *nv, long *ncell, size_t *state_bytes);
+
+/* Workspace: caller-owned device memory (256-byte aligned) of at least the
+ * size reported for the same (mode, nsteps, seg_len).  mode 0 = forward
+ * (rhs, rk3_step, dt, diagnostics, cost); mode 1 = adds vjp_step; mode 2 =
+ * adds the trajectory gradient over exactly `nsteps` steps with checkpoints
+ * every `seg_len` steps (dcf_gradient).  nsteps/seg_len are ignored below
+ * mode 2.  The library keeps the pointer until the next call. */
+dcf_status dcf_workspace_size(const dcf_ctx *ctx, int mode, int nsteps, int seg_len,
+                              size_t *bytes);
+dcf_status dcf_set_workspace(dcf_ctx *ctx, int mode, int nsteps, int seg_len, void *dev,
+                             size_t bytes);
+
+/* Boundary condition of one face (Section 3.2).  Periodic faces must be
+ * set in pairs.  Porous: the wall-normal velocity along the inward normal
+ * is v_w = -K_i (p_w - p_inf)/p_inf, p_w the pressure of the first interior
+ * cell; ghost velocity = 2 v_w n - u_mirror, tangential no-slip, isothermal
+ * T_g = 2 T_wall - T_mirror.  At most one face may be porous. */
+dcf_status dcf_set_bc(dcf_ctx *ctx, int face, const dcf_bc *bc);
+
+/* Porous coefficients K (dev, nK doubles, indexed strip-fastest); the
+ * differentiable boundary parameters handed down by the solver. */
+dcf_status dcf_set_params(dcf_ctx *ctx, const double *K_dev, int nK);
+int dcf_num_params(const dcf_ctx *ctx);
+
+/* Source term (Eq. (1), sum_i S_i). */
+dcf_status dcf_set_source(dcf_ctx *ctx, int kind);
+
+/* Wall-pressure cost face: j(U) = sum_i (A_i/A)(p_i - p_ref)^2 over the
+ * cells next to `face` (-1 disables). */
+dcf_status dcf_set_cost(dcf_ctx *ctx, int face, double p_ref);
+
+/* ---- forward ------------------------------------------------------------ */
+/* U (dev, out) from primitives P (dev). */
+dcf_status dcf_init_state(dcf_ctx *ctx, const double *P_dev, double *U_dev, void *stream);
+
+/* R = dU/dt of Eq. (6) including the source; R has the layout of U. */
+dcf_status dcf_rhs(dcf_ctx *ctx, const double *U_dev, double *R_dev, void *stream);
+
+/* dt_dev[0] = min(dt_max, cfl / max_cells[sum_d (|u_d|+c)/dx_d
+ *             + 2 nu_eff sum_d 1/dx_d^2]), nu_eff = max(4/3, gamma/Pr) mu/rho. */
+dcf_status dcf_compute_dt(dcf_ctx *ctx, const double *U_dev, double cfl, double dt_max,
+                          double *dt_dev, void *stream);
+
+/* One TVD-RK3 step (Shu-Osher form) in place, with dt read from dt_dev[0]. */
+dcf_status dcf_rk3_step(dcf_ctx *ctx, double *U_dev, const double *dt_dev, void *stream);
+
+/* out_dev[8] = (<rho|u|^2/2>_V, <mu|omega|^2>_V, total mass, total x/y/z
+ * momentum, total energy, volume). */
+dcf_status dcf_diagnostics(dcf_ctx *ctx, const double *U_dev, double *out_dev, void *stream);
+
+/* ---- adjoint ------------------------------------------------------------ */
+/* Vector-Jacobian product of one RK3 step U^n -> U^{n+1} with dt_dev[0]
+ * held constant: lam_n = (dU^{n+1}/dU^n)^T lam_np1, and, when dJdK_dev is
+ * not NULL, dJdK_dev += (dU^{n+1}/dK)^T lam_np1.  lam_n may not alias
+ * lam_np1.  Unsupported with the mass-flux source. */
+dcf_status dcf_vjp_step(dcf_ctx *ctx, const double *Un_dev, const double *dt_dev,
+                        const double *lam_np1_dev, double *lam_n_dev, double *dJdK_dev,
+                        void *stream);
+
+/* J_dev[0] += w * j(U); when g_dev is not NULL, g_dev += w * dj/dU. */
+dcf_status dcf_cost_term(dcf_ctx *ctx, const double *U_dev, double w, double *J_dev,
+                         double *g_dev, void *stream);
+
+/* J = (1/nsteps) sum_{n=1..nsteps} j(U^n) over a fixed-dt trajectory from U0,
+ * and its gradient with respect to K and U0 by checkpointing every seg_len
+ * steps and recomputing each segment in reverse (workspace mode 2).  Any
+ * output pointer may be NULL except J_dev. */
+dcf_status dcf_gradient(dcf_ctx *ctx, const double *U0_dev, int nsteps, const double *dt_dev,
+                        int seg_len, double *J_dev, double *dJdK_dev, double *dJdU0_dev,
+                        void *stream);
+
+/* ---- measurement ---------------------------------------------------------- */
+/* Times `reps` back-to-back launches of one kernel family on `stream` with
+ * HIP events and returns the mean duration in milliseconds (synchronises).
+ * which: 0 primitive box + halos, 1/2/3 face fluxes along x/y/z, 4 the
+ * divergence + RK stage update.  The inputs it needs (primitive box, face
+ * fluxes) are computed from U once before timing. */
+dcf_status dcf_time_kernel(dcf_ctx *ctx, const double *U_dev, int which, int reps,
+                           double *avg_ms, void *stream);
+
+/* ---- status ------------------------------------------------------------- */
+/* Synchronises `stream`, returns and clears the kernel flags (DCF_FLAG_*). */
+dcf_status dcf_flags(dcf_ctx *ctx, unsigned *flags_host, void *stream);
+const char *dcf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DCF_H */

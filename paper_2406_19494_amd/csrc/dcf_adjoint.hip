@@ -1,0 +1,771 @@
+// dcf_adjoint.hip -- hand-written reverse mode (VJP) of one TVD-RK3 step of
+// the finite-volume right-hand side (Eq. (6)), through the halo-cell boundary
+// conditions including the differentiable porous wall (Section 3.2), so that
+// gradients of a cost along a trajectory reach the wall parameters (the
+// end-to-end optimisation of Section 1).
+//
+// Per stage (state V, stage output W = a Un + b (V + dt R(V))), given the
+// stage-output adjoint Wb:
+//   Rb = b dt Wb,  Fb(face) = Rb(right cell)/dx - Rb(left cell)/dx,
+//   Qb = sum over faces of (dF/dQ)^T Fb        (convective + dissipative),
+//   Qb += D_t^T Gb   (tangential derivatives were cell-centred, then
+//                     interpolated: their adjoint Gb is gathered along t),
+//   Tb += mu'(T) mub, then the halo fill is transposed axis by axis in the
+//   reverse order z, y, x (ghost adjoints fold into their sources and, for
+//   the porous wall, into dJ/dK), and Vb = b Wb + (dQ/dU)^T Qb.
+// Every scatter of the reverse pass is done as a deterministic gather: face
+// adjoints are accumulated in LDS tiles offset by offset (one writer per
+// cell per phase), and the tile only writes the cells all of whose faces it
+// computed; no atomics anywhere, so results are bitwise reproducible.
+#include "dcf_adjoint.hpp"
+#include "dcf_kernels.hpp"
+
+namespace dcf {
+
+constexpr int TF = 64;  // faces per tile line
+constexpr int TW = 4;   // lines per tile (TF * TW = 256 threads)
+
+// ---------------------------------------------------------------------------
+// Reverse of WENO5-JS: g[0..4] += d y / d (a..e) * yb.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void weno5_vjp(double a, double b, double c, double d, double e,
+                                          double yb, double *g) {
+  const double eps = 1.0e-6;
+  const double sixth = 1.0 / 6.0;
+  const double c1312 = 13.0 / 12.0;
+  double q0 = (2.0 * a - 7.0 * b + 11.0 * c) * sixth;
+  double q1 = (-b + 5.0 * c + 2.0 * d) * sixth;
+  double q2 = (2.0 * c + 5.0 * d - e) * sixth;
+  double r0 = a - 2.0 * b + c, s0 = a - 4.0 * b + 3.0 * c;
+  double r1 = b - 2.0 * c + d, s1 = b - d;
+  double r2 = c - 2.0 * d + e, s2 = 3.0 * c - 4.0 * d + e;
+  double e0 = eps + (c1312 * r0 * r0 + 0.25 * s0 * s0);
+  double e1 = eps + (c1312 * r1 * r1 + 0.25 * s1 * s1);
+  double e2 = eps + (c1312 * r2 * r2 + 0.25 * s2 * s2);
+  double t0 = e0 * e0, t1 = e1 * e1, t2 = e2 * e2;
+  double w0 = 0.1 * t1 * t2, w1 = 0.6 * t0 * t2, w2 = 0.3 * t0 * t1;
+  double W = w0 + w1 + w2;
+  double y = (w0 * q0 + w1 * q1 + w2 * q2) / W;
+  double Nb = yb / W;
+  double q0b = Nb * w0, q1b = Nb * w1, q2b = Nb * w2;
+  double w0b = Nb * (q0 - y), w1b = Nb * (q1 - y), w2b = Nb * (q2 - y);
+  double t0b = 0.6 * w1b * t2 + 0.3 * w2b * t1;
+  double t1b = 0.1 * w0b * t2 + 0.3 * w2b * t0;
+  double t2b = 0.1 * w0b * t1 + 0.6 * w1b * t0;
+  double b0b = 2.0 * e0 * t0b, b1b = 2.0 * e1 * t1b, b2b = 2.0 * e2 * t2b;
+  double r0b = 2.0 * c1312 * r0 * b0b, s0b = 0.5 * s0 * b0b;
+  double r1b = 2.0 * c1312 * r1 * b1b, s1b = 0.5 * s1 * b1b;
+  double r2b = 2.0 * c1312 * r2 * b2b, s2b = 0.5 * s2 * b2b;
+  q0b *= sixth;
+  q1b *= sixth;
+  q2b *= sixth;
+  g[0] += 2.0 * q0b + r0b + s0b;
+  g[1] += -7.0 * q0b - q1b - 2.0 * r0b - 4.0 * s0b + r1b + s1b;
+  g[2] += 11.0 * q0b + 5.0 * q1b + 2.0 * q2b + r0b + 3.0 * s0b - 2.0 * r1b + r2b + 3.0 * s2b;
+  g[3] += 2.0 * q1b + 5.0 * q2b + r1b - s1b - 2.0 * r2b - 4.0 * s2b;
+  g[4] += -q2b + r2b + s2b;
+}
+
+// Reverse of the physical flux of one state (Eq. (3), face frame).
+__device__ __forceinline__ void phys_flux_vjp(const double *q, double gm1i, const double *Fb,
+                                              double *qb) {
+  double r = q[0], u = q[1], v = q[2], w = q[3], p = q[4];
+  double k2 = u * u + v * v + w * w;
+  double E = p * gm1i + 0.5 * r * k2;
+  double Eb = Fb[4] * u;
+  qb[0] += Fb[0] * u + Fb[1] * u * u + Fb[2] * u * v + Fb[3] * u * w + Eb * 0.5 * k2;
+  qb[1] += Fb[0] * r + 2.0 * Fb[1] * r * u + Fb[2] * r * v + Fb[3] * r * w + Fb[4] * (E + p) +
+           Eb * r * u;
+  qb[2] += Fb[2] * r * u + Eb * r * v;
+  qb[3] += Fb[3] * r * u + Eb * r * w;
+  qb[4] += Fb[1] + Fb[4] * u + Eb * gm1i;
+}
+
+// Reverse of the HLLC flux (same branch choices as the forward: Davis wave
+// speeds with the left candidate kept on ties, 0 <= S selects the left side).
+__device__ void hllc_vjp(const double *qL, const double *qR, double gamma, const double *Fb,
+                         double *qLb, double *qRb) {
+  const double gm1i = 1.0 / (gamma - 1.0);
+  double rL = qL[0], uL = qL[1], vL = qL[2], wL = qL[3], pL = qL[4];
+  double rR = qR[0], uR = qR[1], vR = qR[2], wR = qR[3], pR = qR[4];
+  double EL = pL * gm1i + 0.5 * rL * (uL * uL + vL * vL + wL * wL);
+  double ER = pR * gm1i + 0.5 * rR * (uR * uR + vR * vR + wR * wR);
+  double cL = sqrt(gamma * pL / rL);
+  double cR = sqrt(gamma * pR / rR);
+  double aL = uL - cL, bL = uR - cR;
+  const bool selL = bL < aL;
+  double SL = selL ? bL : aL;
+  double aR = uL + cL, bR = uR + cR;
+  const bool selR = bR > aR;
+  double SR = selR ? bR : aR;
+  for (int m = 0; m < 5; ++m) qLb[m] = qRb[m] = 0.0;
+  if (0.0 <= SL) {
+    phys_flux_vjp(qL, gm1i, Fb, qLb);
+    return;
+  }
+  if (SR < 0.0) {
+    phys_flux_vjp(qR, gm1i, Fb, qRb);
+    return;
+  }
+  double mL = rL * (SL - uL), mR = rR * (SR - uR);
+  double Nn = pR - pL + uL * mL - uR * mR, Dd = mL - mR;
+  double Ss = Nn / Dd;
+  const bool left = (0.0 <= Ss);
+  double r = left ? rL : rR, u = left ? uL : uR, v = left ? vL : vR, w = left ? wL : wR;
+  double p = left ? pL : pR, E = left ? EL : ER, S = left ? SL : SR, m = left ? mL : mR;
+  double inv = 1.0 / (S - Ss);
+  double Us0 = m * inv;
+  double A4 = m * Ss + p;
+  double N4 = E * (S - u) + (Ss - u) * A4;
+  double Us4 = N4 * inv;
+  double fm = r * u;
+  const double F0 = Fb[0], F1 = Fb[1], F2 = Fb[2], F3 = Fb[3], F4 = Fb[4];
+  double Sb = F0 * (Us0 - r) + F1 * (Us0 * Ss - fm) + F2 * (Us0 * v - r * v) +
+              F3 * (Us0 * w - r * w) + F4 * (Us4 - E);
+  double Us0b = S * (F0 + F1 * Ss + F2 * v + F3 * w);
+  double Ssb = F1 * S * Us0;
+  double Us4b = S * F4;
+  double fmb = F0 + F1 * (u - S) + F2 * v + F3 * w;
+  double rb = -S * (F0 + F2 * v + F3 * w);
+  double ub = F1 * fm + F4 * (E + p);
+  double vb = F2 * (fm + S * Us0 - S * r);
+  double wb = F3 * (fm + S * Us0 - S * r);
+  double pb = F1 + F4 * u;
+  double Eb = F4 * (u - S);
+  double N4b = Us4b * inv, invb = Us4b * N4;
+  Eb += N4b * (S - u);
+  Sb += N4b * E;
+  ub -= N4b * (E + A4);
+  Ssb += N4b * (A4 + (Ss - u) * m);
+  double mb = N4b * (Ss - u) * Ss;
+  pb += N4b * (Ss - u);
+  mb += Us0b * inv;
+  invb += Us0b * m;
+  double db = -invb * inv * inv;
+  Sb += db;
+  Ssb -= db;
+  rb += fmb * u;
+  ub += fmb * r;
+  pb += Eb * gm1i;
+  rb += Eb * 0.5 * (u * u + v * v + w * w);
+  ub += Eb * r * u;
+  vb += Eb * r * v;
+  wb += Eb * r * w;
+  double *qKb = left ? qLb : qRb;
+  qKb[0] += rb;
+  qKb[1] += ub;
+  qKb[2] += vb;
+  qKb[3] += wb;
+  qKb[4] += pb;
+  double mLb = left ? mb : 0.0, mRb = left ? 0.0 : mb;
+  double SLb = left ? Sb : 0.0, SRb = left ? 0.0 : Sb;
+  double Nnb = Ssb / Dd, Ddb = -Ssb * Ss / Dd;
+  qRb[4] += Nnb;
+  qLb[4] -= Nnb;
+  qLb[1] += Nnb * mL;
+  mLb += Nnb * uL + Ddb;
+  qRb[1] -= Nnb * mR;
+  mRb += -Nnb * uR - Ddb;
+  qLb[0] += mLb * (SL - uL);
+  SLb += mLb * rL;
+  qLb[1] -= mLb * rL;
+  qRb[0] += mRb * (SR - uR);
+  SRb += mRb * rR;
+  qRb[1] -= mRb * rR;
+  double cLb = 0.0, cRb = 0.0;
+  if (selL) {
+    qRb[1] += SLb;
+    cRb -= SLb;
+  } else {
+    qLb[1] += SLb;
+    cLb -= SLb;
+  }
+  if (selR) {
+    qRb[1] += SRb;
+    cRb += SRb;
+  } else {
+    qLb[1] += SRb;
+    cLb += SRb;
+  }
+  // c = sqrt(gamma p / rho)
+  double xLb = cLb / (2.0 * cL), xRb = cRb / (2.0 * cR);
+  qLb[4] += xLb * gamma / rL;
+  qLb[0] -= xLb * gamma * pL / (rL * rL);
+  qRb[4] += xRb * gamma / rR;
+  qRb[0] -= xRb * gamma * pR / (rR * rR);
+}
+
+// Flux adjoint at face f of direction D from the stage-output adjoint:
+// Fb[m] = Rb_m(cell f)/dx_f - Rb_m(cell f-1)/dx_{f-1}.
+__device__ __forceinline__ void face_adjoint(const Dev &g, int D, const int *pos, int f,
+                                             const double *Rb, double *Fb) {
+  const long nc = g.ncell;
+  const int nd = g.ndim;
+  for (int m = 0; m < 5; ++m) Fb[m] = 0.0;
+  int cpos[3] = {pos[0], pos[1], pos[2]};
+  if (f < g.n[D]) {
+    cpos[D] = f;
+    long c = ((long)cpos[2] * g.n[1] + cpos[1]) * g.n[0] + cpos[0];
+    double id = g.idx[D][f];
+    for (int m = 0; m < 5; ++m) Fb[m] += Rb[m * nc + c] * id;
+  }
+  if (f >= 1) {
+    cpos[D] = f - 1;
+    long c = ((long)cpos[2] * g.n[1] + cpos[1]) * g.n[0] + cpos[0];
+    double id = g.idx[D][f - 1];
+    for (int m = 0; m < 5; ++m) Fb[m] -= Rb[m * nc + c] * id;
+  }
+  if (nd < 3) Fb[3] = 0.0;
+  if (nd < 2) Fb[2] = 0.0;
+}
+
+// Per-cell right-hand-side adjoint in the 5-component flux layout:
+// Rb[m] = b dt Wb[v(m)].
+__global__ void __launch_bounds__(256) k_rbar(Dev g, const double *Wb, const double *dtp,
+                                              double b, double *Rb) {
+  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.ncell) return;
+  const long nc = g.ncell;
+  const int nd = g.ndim;
+  double s = b * dtp[0];
+  Rb[c] = s * Wb[c];
+  Rb[nc + c] = s * Wb[nc + c];
+  Rb[2 * nc + c] = nd >= 2 ? s * Wb[2 * nc + c] : 0.0;
+  Rb[3 * nc + c] = nd >= 3 ? s * Wb[3 * nc + c] : 0.0;
+  Rb[4 * nc + c] = s * Wb[(long)(nd + 1) * nc + c];
+}
+
+// Tile geometry for direction D: tile index -> first face and line origin.
+struct Tile {
+  int f0;       // first face of the tile along D
+  int c0, c1;   // cells written by the tile along D: [c0, c1)
+  int line[3];  // tangential position of this thread's line (pos[D] unused)
+  int lane_line, lane_face;
+  long lg;      // line group of the tile
+  bool line_ok;
+};
+
+template <int OLO, int OHI>
+__device__ __forceinline__ Tile make_tile(const Dev &g, int D) {
+  constexpr int SPAN = OHI - OLO;
+  constexpr int CPT = TF - SPAN;  // cells completed per tile line
+  const int T1 = tan1(D), T2 = tan2(D);
+  const int nt1 = g.n[T1], nt2 = g.n[T2];
+  const int cmin = OLO;                         // first cell receiving contributions
+  const int ncell_line = g.n[D] + 1 + SPAN;     // cells [OLO, n + OHI]
+  const int tiles_d = (ncell_line + CPT - 1) / CPT;
+  const long lines = (long)nt1 * nt2;
+  long tile = blockIdx.x;
+  int td = (int)(tile % tiles_d);
+  long lg = tile / tiles_d;  // line group
+  Tile t;
+  const int tid = threadIdx.x;
+  if (D == 0) {
+    t.lane_face = tid % TF;
+    t.lane_line = tid / TF;
+  } else {
+    t.lane_line = tid % TW;
+    t.lane_face = tid / TW;
+  }
+  long ln = lg * TW + t.lane_line;  // line index over (t1 fastest, t2)
+  t.line_ok = ln < lines;
+  int a = t.line_ok ? (int)(ln % nt1) : 0;
+  int bq = t.line_ok ? (int)(ln / nt1) : 0;
+  t.line[D] = 0;
+  t.line[T1] = a;
+  t.line[T2] = bq;
+  t.c0 = cmin + td * CPT;
+  t.c1 = min(t.c0 + CPT, g.n[D] + OHI + 1);
+  t.f0 = t.c0 - OHI;
+  t.lg = lg;
+  return t;
+}
+
+template <int OLO, int OHI>
+__host__ inline unsigned tile_count(const Dev &g, int D) {
+  constexpr int SPAN = OHI - OLO;
+  constexpr int CPT = TF - SPAN;
+  const int ncell_line = g.n[D] + 1 + SPAN;
+  const long tiles_d = (ncell_line + CPT - 1) / CPT;
+  const long lines = (long)g.n[tan1(D)] * g.n[tan2(D)];
+  return (unsigned)(tiles_d * ((lines + TW - 1) / TW));
+}
+
+// ---------------------------------------------------------------------------
+// Convective adjoint along D: WENO5-JS + HLLC reversed per face, gathered
+// into Qb (rho, u, v, w, p) over the cells f-3 .. f+2.
+// ---------------------------------------------------------------------------
+template <int NDIM, int D>
+__global__ void __launch_bounds__(256) k_conv_vjp(Dev g, AdjBuffers A) {
+  constexpr int OLO = -3, OHI = 2, NOFF = OHI - OLO + 1, SPAN = OHI - OLO;
+  constexpr int NCW = TF + SPAN;  // window cells per line
+  constexpr int T1 = tan1(D), T2 = tan2(D);
+  constexpr int NC = 5;
+  __shared__ double acc[NC][TW][NCW];
+  Tile t = make_tile<OLO, OHI>(g, D);
+  for (int i = threadIdx.x; i < NC * TW * NCW; i += 256) (&acc[0][0][0])[i] = 0.0;
+  __syncthreads();
+
+  const int f = t.f0 + t.lane_face;
+  const bool active = t.line_ok && f >= 0 && f <= g.n[D];
+  double contrib[NOFF][NC];
+#pragma unroll
+  for (int o = 0; o < NOFF; ++o)
+#pragma unroll
+    for (int q = 0; q < NC; ++q) contrib[o][q] = 0.0;
+  if (active) {
+    int pos[3] = {t.line[0], t.line[1], t.line[2]};
+    pos[D] = f;
+    double Fb[5];
+    face_adjoint(g, D, pos, f, A.Rb, Fb);
+    const long base = (long)(pos[2] + g.h[2]) * g.sb[2] + (long)(pos[1] + g.h[1]) * g.sb[1] +
+                      (pos[0] + g.h[0]);
+    const long s = g.sb[D];
+    const int qi[5] = {QR, QU + D, QU + T1, QU + T2, QP};
+    double v[5][6];
+    double qL[5], qR[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const bool act = !((m == 2 && T1 >= NDIM) || (m == 3 && T2 >= NDIM));
+#pragma unroll
+      for (int o = 0; o < 6; ++o) v[m][o] = act ? g.Q[qi[m]][base + (o - 3) * s] : 0.0;
+      qL[m] = act ? weno5(v[m][0], v[m][1], v[m][2], v[m][3], v[m][4]) : 0.0;
+      qR[m] = act ? weno5(v[m][5], v[m][4], v[m][3], v[m][2], v[m][1]) : 0.0;
+    }
+    double Fr[5] = {Fb[0], Fb[1 + D], Fb[1 + T1], Fb[1 + T2], Fb[4]};
+    double qLb[5], qRb[5];
+    hllc_vjp(qL, qR, g.gamma, Fr, qLb, qRb);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const bool act = !((m == 2 && T1 >= NDIM) || (m == 3 && T2 >= NDIM));
+      if (!act) continue;
+      double gL[5] = {0, 0, 0, 0, 0}, gR[5] = {0, 0, 0, 0, 0};
+      weno5_vjp(v[m][0], v[m][1], v[m][2], v[m][3], v[m][4], qLb[m], gL);
+      weno5_vjp(v[m][5], v[m][4], v[m][3], v[m][2], v[m][1], qRb[m], gR);
+      // cells f-3 .. f+2 <-> offsets 0 .. 5
+      contrib[0][m] += gL[0];
+      contrib[1][m] += gL[1] + gR[4];
+      contrib[2][m] += gL[2] + gR[3];
+      contrib[3][m] += gL[3] + gR[2];
+      contrib[4][m] += gL[4] + gR[1];
+      contrib[5][m] += gR[0];
+    }
+  }
+  // offset-ordered accumulation: one writer per window cell per phase
+#pragma unroll
+  for (int o = 0; o < NOFF; ++o) {
+    if (active) {
+      const int w = t.lane_face + o;  // window cell of (f + OLO + o)
+#pragma unroll
+      for (int q = 0; q < NC; ++q) acc[q][t.lane_line][w] += contrib[o][q];
+    }
+    __syncthreads();
+  }
+  // write the completed cells: window cell w <-> cell t.f0 + OLO + w
+  for (int i = threadIdx.x; i < TW * NCW; i += 256) {
+    const int ll = i / NCW, w = i % NCW;
+    const int cell = t.f0 + OLO + w;
+    if (cell < t.c0 || cell >= t.c1) continue;
+    long ln = t.lg * TW + ll;
+    if (ln >= (long)g.n[T1] * g.n[T2]) continue;
+    int p[3];
+    p[D] = cell;
+    p[T1] = (int)(ln % g.n[T1]);
+    p[T2] = (int)(ln / g.n[T1]);
+    const long b = (long)(p[2] + g.h[2]) * g.sb[2] + (long)(p[1] + g.h[1]) * g.sb[1] +
+                   (p[0] + g.h[0]);
+    A.Qb[QR][b] += acc[0][ll][w];
+    A.Qb[QU + D][b] += acc[1][ll][w];
+    if (T1 < NDIM) A.Qb[QU + T1][b] += acc[2][ll][w];
+    if (T2 < NDIM) A.Qb[QU + T2][b] += acc[3][ll][w];
+    A.Qb[QP][b] += acc[4][ll][w];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dissipative adjoint along D: the face stress/heat flux reversed to
+// face-level adjoints, then expanded over cells f-2 .. f+1 into
+// Qb (u, v, w, T, mu) and into Gb (adjoint of the cell-centred tangential
+// velocity derivatives).
+// ---------------------------------------------------------------------------
+template <int NDIM, int D>
+__global__ void __launch_bounds__(256) k_visc_vjp(Dev g, AdjBuffers A) {
+  constexpr int OLO = -2, OHI = 1, NOFF = OHI - OLO + 1, SPAN = OHI - OLO;
+  constexpr int NCW = TF + SPAN;
+  constexpr int T1 = tan1(D), T2 = tan2(D);
+  constexpr int NC = 9;  // u, v, w, T, mu, G(t1,t1) G(t1,D) G(t2,t2) G(t2,D)
+  __shared__ double acc[NC][TW][NCW];
+  Tile t = make_tile<OLO, OHI>(g, D);
+  for (int i = threadIdx.x; i < NC * TW * NCW; i += 256) (&acc[0][0][0])[i] = 0.0;
+  __syncthreads();
+
+  const int f = t.f0 + t.lane_face;
+  const bool active = t.line_ok && f >= 0 && f <= g.n[D];
+  // face-level adjoints
+  double ufb[3] = {0, 0, 0}, dnb[3] = {0, 0, 0}, dTb = 0.0, mufb = 0.0;
+  double divtb = 0.0, dtnb[3] = {0, 0, 0};
+  double mfD = 0.0;
+  if (active) {
+    int pos[3] = {t.line[0], t.line[1], t.line[2]};
+    pos[D] = f;
+    double Fb[5];
+    face_adjoint(g, D, pos, f, A.Rb, Fb);
+    const long base = (long)(pos[2] + g.h[2]) * g.sb[2] + (long)(pos[1] + g.h[1]) * g.sb[1] +
+                      (pos[0] + g.h[0]);
+    const long s = g.sb[D];
+    double vel[3][4], Tc[4], muc[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      long cb = base + (o - 2) * s;
+      vel[0][o] = g.Q[QU][cb];
+      vel[1][o] = NDIM >= 2 ? g.Q[QV][cb] : 0.0;
+      vel[2][o] = NDIM >= 3 ? g.Q[QW][cb] : 0.0;
+      Tc[o] = g.Q[QT][cb];
+      muc[o] = g.Q[QMU][cb];
+    }
+    mfD = g.mf[D][f];
+    double muf = interp4(muc[0], muc[1], muc[2], muc[3]);
+    double uf[3], dn[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      uf[c] = interp4(vel[c][0], vel[c][1], vel[c][2], vel[c][3]);
+      dn[c] = dface4(vel[c][0], vel[c][1], vel[c][2], vel[c][3]) * mfD;
+    }
+    double dT = dface4(Tc[0], Tc[1], Tc[2], Tc[3]) * mfD;
+    double divt = 0.0, dtn[3] = {0.0, 0.0, 0.0};
+    const double *Qn = g.Q[QU + D];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int tt = r == 0 ? T1 : T2;
+      if (tt >= NDIM) continue;
+      const long st = g.sb[tt];
+      const double mct = g.mc[tt][pos[tt]];
+      const double *Qtt = g.Q[QU + tt];
+      double gtt[4], gtn[4];
+#pragma unroll
+      for (int o = 0; o < 4; ++o) {
+        long cb = base + (o - 2) * s;
+        gtt[o] = dcell4(Qtt[cb - 2 * st], Qtt[cb - st], Qtt[cb + st], Qtt[cb + 2 * st]) * mct;
+        gtn[o] = dcell4(Qn[cb - 2 * st], Qn[cb - st], Qn[cb + st], Qn[cb + 2 * st]) * mct;
+      }
+      divt += interp4(gtt[0], gtt[1], gtt[2], gtt[3]);
+      dtn[tt] = interp4(gtn[0], gtn[1], gtn[2], gtn[3]);
+    }
+    double brk[3] = {0.0, 0.0, 0.0};
+    brk[D] = (4.0 / 3.0) * dn[D] - (2.0 / 3.0) * divt;
+    if (T1 < NDIM) brk[T1] = dtn[T1] + dn[T1];
+    if (T2 < NDIM) brk[T2] = dtn[T2] + dn[T2];
+    double tau[3] = {muf * brk[0], muf * brk[1], muf * brk[2]};
+    const double cpPr = g.cp / g.Pr;
+    double lam = muf * cpPr;
+    // reverse
+    double enb = -Fb[4];
+    double taub[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      taub[c] = -Fb[1 + c] + enb * uf[c];
+      ufb[c] = enb * tau[c];
+    }
+    double lamb = enb * dT;
+    dTb = enb * lam;
+    mufb = lamb * cpPr + taub[0] * brk[0] + taub[1] * brk[1] + taub[2] * brk[2];
+    dnb[D] = taub[D] * muf * (4.0 / 3.0);
+    divtb = -taub[D] * muf * (2.0 / 3.0);
+    if (T1 < NDIM) {
+      dtnb[T1] = taub[T1] * muf;
+      dnb[T1] = taub[T1] * muf;
+    }
+    if (T2 < NDIM) {
+      dtnb[T2] = taub[T2] * muf;
+      dnb[T2] = taub[T2] * muf;
+    }
+  }
+  const double I4[4] = {-1.0 / 16.0, 9.0 / 16.0, 9.0 / 16.0, -1.0 / 16.0};
+  const double D4[4] = {1.0 / 24.0, -27.0 / 24.0, 27.0 / 24.0, -1.0 / 24.0};
+#pragma unroll
+  for (int o = 0; o < NOFF; ++o) {
+    if (active) {
+      const int w = t.lane_face + o;
+      const int ll = t.lane_line;
+      const double dm = D4[o] * mfD, im = I4[o];
+#pragma unroll
+      for (int c = 0; c < NDIM; ++c) acc[c][ll][w] += ufb[c] * im + dnb[c] * dm;
+      acc[3][ll][w] += dTb * dm;
+      acc[4][ll][w] += mufb * im;
+      if (T1 < NDIM) {
+        acc[5][ll][w] += divtb * im;
+        acc[6][ll][w] += dtnb[T1] * im;
+      }
+      if (T2 < NDIM) {
+        acc[7][ll][w] += divtb * im;
+        acc[8][ll][w] += dtnb[T2] * im;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < TW * NCW; i += 256) {
+    const int ll = i / NCW, w = i % NCW;
+    const int cell = t.f0 + OLO + w;
+    if (cell < t.c0 || cell >= t.c1) continue;
+    long ln = t.lg * TW + ll;
+    if (ln >= (long)g.n[T1] * g.n[T2]) continue;
+    int p[3];
+    p[D] = cell;
+    p[T1] = (int)(ln % g.n[T1]);
+    p[T2] = (int)(ln / g.n[T1]);
+    const long b = (long)(p[2] + g.h[2]) * g.sb[2] + (long)(p[1] + g.h[1]) * g.sb[1] +
+                   (p[0] + g.h[0]);
+    A.Qb[QU][b] += acc[0][ll][w];
+    if (NDIM >= 2) A.Qb[QV][b] += acc[1][ll][w];
+    if (NDIM >= 3) A.Qb[QW][b] += acc[2][ll][w];
+    A.Qb[QT][b] += acc[3][ll][w];
+    A.Qb[QMU][b] += acc[4][ll][w];
+    if (T1 < NDIM) {
+      A.Gb[3 * T1 + T1][b] += acc[5][ll][w];
+      A.Gb[3 * T1 + D][b] += acc[6][ll][w];
+    }
+    if (T2 < NDIM) {
+      A.Gb[3 * T2 + T2][b] += acc[7][ll][w];
+      A.Gb[3 * T2 + D][b] += acc[8][ll][w];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gather of the tangential-derivative adjoints (transpose of the
+// cell-centred 4th-order difference along t), then mu'(T) folding.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double dviscosity(const Dev &g, double T) {
+  if (g.visc == VISC_POWER) {
+    double t = T / g.T_ref;
+    return g.mu_ref * g.vparam * pow(t, g.vparam - 1.0) / g.T_ref;
+  }
+  if (g.visc == VISC_SUTHERLAND) {
+    double t = T / g.T_ref;
+    double s = g.vparam / g.T_ref;
+    double mu = g.mu_ref * t * sqrt(t) * (1.0 + s) / (t + s);
+    return mu * (1.5 / t - 1.0 / (t + s)) / g.T_ref;
+  }
+  return 0.0;
+}
+
+__global__ void __launch_bounds__(256) k_tangential_vjp(Dev g, AdjBuffers A) {
+  long b = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= g.nbox) return;
+  int p[3];
+  p[0] = (int)(b % g.N[0]) - g.h[0];
+  p[1] = (int)((b / g.N[0]) % g.N[1]) - g.h[1];
+  p[2] = (int)(b / ((long)g.N[0] * g.N[1])) - g.h[2];
+  const int nd = g.ndim;
+  if (A.Gb[0] != nullptr) {
+    for (int phi = 0; phi < nd; ++phi) {
+      double add = 0.0;
+      for (int t = 0; t < nd; ++t) {
+        const double *G = A.Gb[3 * t + phi];
+        const long st = g.sb[t];
+        // y = x + k along t contributes coef(k) * mc(y) * G(y)
+        const int ks[4] = {-1, 1, -2, 2};
+        const double cf[4] = {8.0 / 12.0, -8.0 / 12.0, -1.0 / 12.0, 1.0 / 12.0};
+        for (int r = 0; r < 4; ++r) {
+          int yt = p[t] + ks[r];
+          if (yt < 0 || yt >= g.n[t]) continue;
+          add += cf[r] * g.mc[t][yt] * G[b + ks[r] * st];
+        }
+      }
+      A.Qb[QU + phi][b] += add;
+    }
+  }
+  if (g.visc != VISC_NONE) A.Qb[QT][b] += dviscosity(g, g.Q[QT][b]) * A.Qb[QMU][b];
+}
+
+// ---------------------------------------------------------------------------
+// Transpose of the halo fill along axis d: one thread per column (both
+// sides, all three layers), folding ghost adjoints into their sources.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, double *dJdK) {
+  const int nd = g.ndim;
+  const int t1 = tan1(d), t2 = tan2(d);
+  int lo1 = 0, n1 = g.n[t1], lo2 = 0, n2 = g.n[t2];
+  if (t1 < d) { lo1 = -g.h[t1]; n1 = g.N[t1]; }
+  if (t2 < d) { lo2 = -g.h[t2]; n2 = g.N[t2]; }
+  long col = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= (long)n1 * n2) return;
+  const int a = lo1 + (int)(col % n1), bq = lo2 + (int)(col / n1);
+  auto box = [&](int s) {
+    int p[3];
+    p[d] = s;
+    p[t1] = a;
+    p[t2] = bq;
+    return (long)(p[2] + g.h[2]) * g.sb[2] + (long)(p[1] + g.h[1]) * g.sb[1] + (p[0] + g.h[0]);
+  };
+  const int n = g.n[d];
+  for (int side = 0; side < 2; ++side) {
+    const int face = 2 * d + side;
+    const int kind = g.bck[face];
+    if (kind == BC_DIRICHLET) continue;
+    for (int m = 0; m < 3; ++m) {
+      const long G = box(side == 0 ? -1 - m : n + m);
+      int src;
+      if (kind == BC_PERIODIC) src = side == 0 ? n - 1 - m : m;
+      else if (kind == BC_ZEROGRAD) src = side == 0 ? 0 : n - 1;
+      else src = side == 0 ? m : n - 1 - m;
+      const long S = box(src);
+      if (kind == BC_PERIODIC || kind == BC_ZEROGRAD) {
+        for (int q = 0; q < 6; ++q) A.Qb[q][S] += A.Qb[q][G];
+        continue;
+      }
+      // wall: rho_g = p_g/(R T_g), p_g = p_s, T_g = 2 T_w - T_s, u_g = -u_s
+      double rg = g.Q[QR][G], pg = g.Q[QP][G];
+      double rb = A.Qb[QR][G];
+      double pgb = A.Qb[QP][G] + rb * rg / pg;
+      double Tgb = A.Qb[QT][G] - rb * rg * rg * g.R / pg;
+      A.Qb[QP][S] += pgb;
+      A.Qb[QT][S] -= Tgb;
+      for (int c = 0; c < nd; ++c) A.Qb[QU + c][S] -= A.Qb[QU + c][G];
+      if (kind == BC_POROUS && face == g.pface && a >= g.pb && a < g.pe && bq >= 0 &&
+          bq < g.n[t2]) {
+        // v_g[d] = 2 sigma v_n - v_s[d], v_n = -K (p_w - p_inf)/p_inf
+        const double sigma = side == 0 ? 1.0 : -1.0;
+        const long W = box(side == 0 ? 0 : n - 1);
+        const int kk = bq * (g.pe - g.pb) + (a - g.pb);
+        double vnb = 2.0 * sigma * A.Qb[QU + d][G];
+        double pw = g.Q[QP][W];
+        A.Qb[QP][W] += -g.K[kk] / g.pinf * vnb;
+        if (dJdK) dJdK[kk] += -(pw - g.pinf) / g.pinf * vnb;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Interior: Vb = b Wb + (dQ/dU)^T Qb, with Q = (rho, u, v, w, p, T(p, rho)).
+// acc_out = acc_in + a Wb (the Un adjoint accumulator); with fold != 0 the
+// accumulator is added into Vb instead (last stage, V = Un).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_interior_vjp(Dev g, AdjBuffers A, const double *V,
+                                                      const double *Wb, double a, double b,
+                                                      double *Vb, const double *acc_in,
+                                                      double *acc_out, int fold) {
+  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.ncell) return;
+  const long nc = g.ncell;
+  const int nd = g.ndim;
+  int i = (int)(c % g.n[0]), j = (int)((c / g.n[0]) % g.n[1]),
+      k = (int)(c / ((long)g.n[0] * g.n[1]));
+  const long bx = (long)(k + g.h[2]) * g.sb[2] + (long)(j + g.h[1]) * g.sb[1] + (i + g.h[0]);
+  double rho = V[c];
+  double ir = 1.0 / rho;
+  double u[3] = {V[nc + c] * ir, nd >= 2 ? V[2 * nc + c] * ir : 0.0,
+                 nd >= 3 ? V[3 * nc + c] * ir : 0.0};
+  double E = V[(long)(nd + 1) * nc + c];
+  double k2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  double p = (g.gamma - 1.0) * (E - 0.5 * rho * k2);
+  double T = p / (rho * g.R);
+  double rb = A.Qb[QR][bx], pb = A.Qb[QP][bx], Tb = A.Qb[QT][bx];
+  double ub[3] = {A.Qb[QU][bx], nd >= 2 ? A.Qb[QV][bx] : 0.0, nd >= 3 ? A.Qb[QW][bx] : 0.0};
+  pb += Tb / (rho * g.R);
+  rb -= Tb * T * ir;
+  const double gm1 = g.gamma - 1.0;
+  double Ub[5];
+  Ub[0] = rb + gm1 * 0.5 * k2 * pb;
+  for (int d = 0; d < nd; ++d) {
+    Ub[1 + d] = ub[d] * ir - gm1 * u[d] * pb;
+    Ub[0] -= ub[d] * u[d] * ir;
+  }
+  Ub[nd + 1] = gm1 * pb;
+  for (int v = 0; v < nd + 2; ++v) {
+    const long x = (long)v * nc + c;
+    double w = Wb[x];
+    double vb = b * w + Ub[v];
+    double accv = (acc_in ? acc_in[x] : 0.0) + a * w;
+    if (fold) {
+      Vb[x] = accv + vb;
+    } else {
+      Vb[x] = vb;
+      acc_out[x] = accv;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host sequencing.
+// ---------------------------------------------------------------------------
+using AdjKernel = void (*)(Dev, AdjBuffers);
+
+static AdjKernel conv_kernel(int nd, int D) {
+  if (nd == 1) return k_conv_vjp<1, 0>;
+  if (nd == 2) return D == 0 ? k_conv_vjp<2, 0> : k_conv_vjp<2, 1>;
+  return D == 0 ? k_conv_vjp<3, 0> : (D == 1 ? k_conv_vjp<3, 1> : k_conv_vjp<3, 2>);
+}
+static AdjKernel visc_kernel(int nd, int D) {
+  if (nd == 1) return k_visc_vjp<1, 0>;
+  if (nd == 2) return D == 0 ? k_visc_vjp<2, 0> : k_visc_vjp<2, 1>;
+  return D == 0 ? k_visc_vjp<3, 0> : (D == 1 ? k_visc_vjp<3, 1> : k_visc_vjp<3, 2>);
+}
+
+static inline unsigned blocks(long n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
+
+#define DCF_TRY(x)                    \
+  do {                                \
+    hipError_t e_ = (x);              \
+    if (e_ != hipSuccess) return e_;  \
+  } while (0)
+
+// Reverse of one stage: Vb = b Wb + R'(V)^T (b dt Wb), accumulators as in
+// k_interior_vjp.  Needs g.Q to hold nothing on entry (recomputed here).
+static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A, const double *V, const double *Wb,
+                            const double *dt, double a, double b, double *Vb,
+                            const double *acc_in, double *acc_out, int fold, double *dJdK,
+                            hipStream_t st) {
+  DCF_TRY(launch_prim_halo(g, V, st));
+  for (int q = 0; q < NQ; ++q) DCF_TRY(launch_fill(A.Qb[q], 0.0, g.nbox, st));
+  const bool visc = g.visc != VISC_NONE;
+  if (visc && A.Gb[0])
+    for (int q = 0; q < 9; ++q) DCF_TRY(launch_fill(A.Gb[q], 0.0, g.nbox, st));
+  k_rbar<<<blocks(g.ncell), 256, 0, st>>>(g, Wb, dt, b, A.Rb);
+  DCF_TRY(hipGetLastError());
+  for (int D = 0; D < g.ndim; ++D) {
+    hipLaunchKernelGGL(conv_kernel(g.ndim, D), dim3(tile_count<-3, 2>(g, D)), dim3(256), 0, st, g,
+                       A);
+    DCF_TRY(hipGetLastError());
+    if (visc) {
+      hipLaunchKernelGGL(visc_kernel(g.ndim, D), dim3(tile_count<-2, 1>(g, D)), dim3(256), 0, st,
+                         g, A);
+      DCF_TRY(hipGetLastError());
+    }
+  }
+  if (visc) {
+    k_tangential_vjp<<<blocks(g.nbox), 256, 0, st>>>(g, A);
+    DCF_TRY(hipGetLastError());
+  }
+  for (int d = g.ndim - 1; d >= 0; --d) {
+    const int t1 = tan1(d), t2 = tan2(d);
+    long n1 = t1 < d ? g.N[t1] : g.n[t1];
+    long n2 = t2 < d ? g.N[t2] : g.n[t2];
+    k_halo_vjp<<<blocks(n1 * n2), 256, 0, st>>>(g, A, d, dJdK);
+    DCF_TRY(hipGetLastError());
+  }
+  k_interior_vjp<<<blocks(g.ncell), 256, 0, st>>>(g, A, V, Wb, a, b, Vb, acc_in, acc_out, fold);
+  return hipGetLastError();
+}
+
+hipError_t vjp_step(Dev g, const AdjBuffers &A, const double *Un, double *U1, double *U2,
+                    const double *dt, const double *lam1, double *lam0, double *dJdK,
+                    hipStream_t st) {
+  // recompute the stage states U1, U2 from Un
+  DCF_TRY(launch_prim_halo(g, Un, st));
+  DCF_TRY(launch_fluxes(g, st));
+  DCF_TRY(launch_update(g, Un, Un, U1, nullptr, dt, 0.0, 1.0, nullptr, st));
+  DCF_TRY(launch_prim_halo(g, U1, st));
+  DCF_TRY(launch_fluxes(g, st));
+  DCF_TRY(launch_update(g, Un, U1, U2, nullptr, dt, 0.75, 0.25, nullptr, st));
+  // stage 3: W = Un/3 + 2/3 (U2 + dt R(U2))
+  DCF_TRY(stage_vjp(g, A, U2, lam1, dt, 1.0 / 3.0, 2.0 / 3.0, A.Ub2, nullptr, A.acc, 0, dJdK, st));
+  // stage 2: W = 3/4 Un + 1/4 (U1 + dt R(U1))
+  DCF_TRY(stage_vjp(g, A, U1, A.Ub2, dt, 0.75, 0.25, A.Ub1, A.acc, A.acc, 0, dJdK, st));
+  // stage 1: W = Un + dt R(Un)
+  DCF_TRY(stage_vjp(g, A, Un, A.Ub1, dt, 0.0, 1.0, lam0, A.acc, nullptr, 1, dJdK, st));
+  return hipSuccess;
+}
+
+}  // namespace dcf

@@ -1,0 +1,33 @@
+// dcf_adjoint.hpp -- buffers and entry of the hand-written adjoint (VJP) of
+// one TVD-RK3 step.
+#pragma once
+
+#include "dcf_common.hpp"
+
+namespace dcf {
+
+struct AdjBuffers {
+  double *Qb[NQ];   // adjoint of the primitive box (rho, u, v, w, p, T, mu)
+  double *Gb[9];    // adjoint of cell-centred velocity derivatives d u_phi / d x_t (3 t + phi)
+  double *Ub1, *Ub2, *acc;  // stage adjoints and the running lambda^n accumulator
+  double *Rb;       // per-cell adjoint of the right-hand side
+};
+
+// Lays the adjoint buffers out in the workspace (or measures them).
+template <class Carver> void carve_adjoint(Carver &cv, const Dev &g, AdjBuffers &a) {
+  for (int q = 0; q < NQ; ++q) a.Qb[q] = cv.template take<double>(g.nbox);
+  const bool visc = g.visc != VISC_NONE && g.ndim >= 2;
+  for (int q = 0; q < 9; ++q) a.Gb[q] = visc ? cv.template take<double>(g.nbox) : nullptr;
+  a.Ub1 = cv.template take<double>((long)g.nv * g.ncell);
+  a.Ub2 = cv.template take<double>((long)g.nv * g.ncell);
+  a.acc = cv.template take<double>((long)g.nv * g.ncell);
+  a.Rb = cv.template take<double>((long)5 * g.ncell);
+}
+
+// lam0 = (dU^{n+1}/dU^n)^T lam1 and dJdK += (dU^{n+1}/dK)^T lam1 (if not
+// null); U1 and U2 are scratch state arrays for the recomputed stages.
+hipError_t vjp_step(Dev g, const AdjBuffers &a, const double *Un, double *U1, double *U2,
+                    const double *dt, const double *lam1, double *lam0, double *dJdK,
+                    hipStream_t st);
+
+}  // namespace dcf

@@ -1,0 +1,522 @@
+// dcf_api.hip -- host runtime behind the C ABI declared in include/dcf.h:
+// argument validation, workspace carving, and the enqueue sequences of the
+// forward step, the adjoint step and the checkpointed trajectory gradient.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dcf.h"
+#include "dcf_adjoint.hpp"
+#include "dcf_kernels.hpp"
+
+using namespace dcf;
+
+namespace {
+thread_local std::string g_last_error;
+
+dcf_status fail(dcf_status code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define DCF_HIP(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(DCF_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+  } while (0)
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Carver {
+  char *base;
+  size_t off = 0;
+  explicit Carver(void *b) : base((char *)b) {}
+  template <class T> T *take(size_t count) {
+    T *p = base ? (T *)(base + off) : nullptr;
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+}  // namespace
+
+struct dcf_ctx {
+  int device = 0;
+  dcf_grid grid;
+  dcf_gas gas;
+  Dev g;
+  double *metric_mem = nullptr;
+  int cost_face = -1;
+  double cost_pref = 0.0;
+  int nK = 0;
+  // workspace
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  int ws_mode = -1;
+  int ws_nsteps = 0, ws_seg = 0;
+  double *U1 = nullptr, *U2 = nullptr, *part = nullptr, *force = nullptr;
+  AdjBuffers adj;
+  double *ckpt = nullptr;  // gradient checkpoints
+  double *seg = nullptr;   // per-segment recomputed states
+  double *lam_a = nullptr, *lam_b = nullptr, *gbuf = nullptr, *zero_dt = nullptr;
+};
+
+extern "C" {
+
+const char *dcf_last_error(void) { return g_last_error.c_str(); }
+
+dcf_status dcf_create(const dcf_grid *grid, const dcf_gas *gas, dcf_ctx **out) {
+  if (!grid || !gas || !out) return fail(DCF_EINVAL, "dcf_create: null argument");
+  *out = nullptr;
+  if (grid->ndim < 1 || grid->ndim > 3) return fail(DCF_EINVAL, "ndim must be 1, 2 or 3");
+  for (int d = 0; d < 3; ++d) {
+    if (d < grid->ndim) {
+      if (grid->n[d] < 3) return fail(DCF_EINVAL, "axis %d needs at least 3 cells", d);
+      if (!(grid->hi[d] > grid->lo[d])) return fail(DCF_EINVAL, "axis %d: hi <= lo", d);
+      if (grid->stretch[d] < 0 || grid->stretch[d] > 2)
+        return fail(DCF_EINVAL, "axis %d: unknown stretching", d);
+      if (grid->stretch[d] != 0 && !(grid->beta[d] > 0.0))
+        return fail(DCF_EINVAL, "axis %d: stretching needs beta > 0", d);
+    } else if (grid->n[d] != 1) {
+      return fail(DCF_EINVAL, "unused axis %d must have n = 1", d);
+    }
+  }
+  if (!(gas->gamma > 1.0) || !(gas->R > 0.0))
+    return fail(DCF_EINVAL, "gas needs gamma > 1 and R > 0");
+  if (gas->visc_law < 0 || gas->visc_law > 2) return fail(DCF_EINVAL, "unknown viscosity law");
+  if (gas->visc_law != 0 && (!(gas->Pr > 0.0) || !(gas->T_ref > 0.0) || gas->mu_ref < 0.0))
+    return fail(DCF_EINVAL, "viscous gas needs Pr > 0, T_ref > 0, mu_ref >= 0");
+  long ncell = (long)grid->n[0] * grid->n[1] * grid->n[2];
+  if (ncell > (1L << 31) - 1) return fail(DCF_EINVAL, "grid too large");
+
+  dcf_ctx *c = new (std::nothrow) dcf_ctx();
+  if (!c) return fail(DCF_ENOMEM, "host allocation failed");
+  (void)hipGetDevice(&c->device);
+  c->grid = *grid;
+  c->gas = *gas;
+  Dev &g = c->g;
+  memset(&g, 0, sizeof g);
+  g.ndim = grid->ndim;
+  g.nv = grid->ndim + 2;
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = grid->n[d];
+    g.h[d] = d < grid->ndim ? NH : 0;
+    g.N[d] = g.n[d] + 2 * g.h[d];
+  }
+  g.ncell = ncell;
+  g.nbox = (long)g.N[0] * g.N[1] * g.N[2];
+  g.sb[0] = 1;
+  g.sb[1] = g.N[0];
+  g.sb[2] = (long)g.N[0] * g.N[1];
+  for (int D = 0; D < 3; ++D) {
+    for (int e = 0; e < 3; ++e) g.fn[D][e] = g.n[e] + (e == D ? 1 : 0);
+    g.fcount[D] = (long)g.fn[D][0] * g.fn[D][1] * g.fn[D][2];
+  }
+  g.gamma = gas->gamma;
+  g.R = gas->R;
+  g.Pr = gas->Pr;
+  g.cp = gas->gamma * gas->R / (gas->gamma - 1.0);
+  g.mu_ref = gas->mu_ref;
+  g.T_ref = gas->T_ref;
+  g.vparam = gas->visc_param;
+  g.visc = gas->visc_law;
+  for (int f = 0; f < 6; ++f) g.bck[f] = BC_PERIODIC;
+  g.pface = -1;
+  g.source = SRC_NONE;
+
+  size_t total = 0;
+  for (int d = 0; d < 3; ++d) total += 4 * (size_t)(g.n[d] + 1);
+  hipError_t e = hipMalloc((void **)&c->metric_mem, total * sizeof(double));
+  if (e != hipSuccess) {
+    delete c;
+    return fail(DCF_EDEVICE, "hipMalloc(metrics): %s", hipGetErrorString(e));
+  }
+  double *p = c->metric_mem;
+  for (int d = 0; d < 3; ++d) {
+    size_t m = g.n[d] + 1;
+    g.dx[d] = p;
+    g.idx[d] = p + m;
+    g.mc[d] = p + 2 * m;
+    g.mf[d] = p + 3 * m;
+    double lo = grid->lo[d], hi = grid->hi[d];
+    int kind = d < grid->ndim ? grid->stretch[d] : 0;
+    if (d >= grid->ndim) {  // unused axis: unit width
+      lo = 0.0;
+      hi = 1.0;
+    }
+    e = launch_metrics(kind, lo, hi, grid->beta[d], g.n[d], (double *)g.dx[d], (double *)g.idx[d],
+                       (double *)g.mc[d], (double *)g.mf[d], 0);
+    if (e == hipSuccess) e = hipStreamSynchronize(0);
+    if (e != hipSuccess) {
+      (void)hipFree(c->metric_mem);
+      delete c;
+      return fail(DCF_EDEVICE, "metrics kernel: %s", hipGetErrorString(e));
+    }
+    p += 4 * m;
+  }
+  *out = c;
+  return DCF_OK;
+}
+
+dcf_status dcf_destroy(dcf_ctx *c) {
+  if (!c) return DCF_OK;
+  (void)hipDeviceSynchronize();
+  if (c->metric_mem) (void)hipFree(c->metric_mem);
+  delete c;
+  return DCF_OK;
+}
+
+dcf_status dcf_state_info(const dcf_ctx *c, int *nv, long *ncell, size_t *bytes) {
+  if (!c) return fail(DCF_EINVAL, "null context");
+  if (nv) *nv = c->g.nv;
+  if (ncell) *ncell = c->g.ncell;
+  if (bytes) *bytes = sizeof(double) * (size_t)c->g.nv * c->g.ncell;
+  return DCF_OK;
+}
+
+int dcf_num_params(const dcf_ctx *c) { return c ? c->nK : 0; }
+
+}  // extern "C"
+
+// Lays the workspace out (or only measures it when base == nullptr).
+static size_t carve(dcf_ctx *c, void *base, int mode, int nsteps, int seg_len) {
+  Carver cv(base);
+  Dev &g = c->g;
+  const long nbox = g.nbox, ncell = g.ncell, nv = g.nv;
+  for (int q = 0; q < NQ; ++q) g.Q[q] = cv.take<double>(nbox);
+  for (int D = 0; D < 3; ++D) g.F[D] = D < g.ndim ? cv.take<double>(5 * g.fcount[D]) : nullptr;
+  c->U1 = cv.take<double>(nv * ncell);
+  c->U2 = cv.take<double>(nv * ncell);
+  c->part = cv.take<double>(8 * RED_BLOCKS);
+  c->force = cv.take<double>(4);
+  g.flags = cv.take<unsigned>(64);
+  if (mode >= 1) carve_adjoint(cv, g, c->adj);
+  if (mode >= 2) {
+    int nseg = (nsteps + seg_len - 1) / seg_len;
+    c->ckpt = cv.take<double>((size_t)nseg * nv * ncell);
+    c->seg = cv.take<double>((size_t)(seg_len + 1) * nv * ncell);
+    c->lam_a = cv.take<double>(nv * ncell);
+    c->lam_b = cv.take<double>(nv * ncell);
+    c->gbuf = cv.take<double>(nv * ncell);
+  }
+  return cv.off;
+}
+
+extern "C" {
+
+dcf_status dcf_workspace_size(const dcf_ctx *c, int mode, int nsteps, int seg_len,
+                              size_t *bytes) {
+  if (!c || !bytes) return fail(DCF_EINVAL, "null argument");
+  if (mode < 0 || mode > 2) return fail(DCF_EINVAL, "mode must be 0, 1 or 2");
+  if (mode == 2 && (nsteps < 1 || seg_len < 1))
+    return fail(DCF_EINVAL, "gradient workspace needs nsteps >= 1 and seg_len >= 1");
+  dcf_ctx tmp = *c;
+  *bytes = carve(&tmp, nullptr, mode, nsteps, seg_len);
+  return DCF_OK;
+}
+
+dcf_status dcf_set_workspace(dcf_ctx *c, int mode, int nsteps, int seg_len, void *dev,
+                             size_t bytes) {
+  if (!c || !dev) return fail(DCF_EINVAL, "null argument");
+  if (((uintptr_t)dev) & 255) return fail(DCF_EINVAL, "workspace must be 256-byte aligned");
+  if (mode < 0 || mode > 2) return fail(DCF_EINVAL, "mode must be 0, 1 or 2");
+  if (mode == 2 && (nsteps < 1 || seg_len < 1))
+    return fail(DCF_EINVAL, "gradient workspace needs nsteps >= 1 and seg_len >= 1");
+  dcf_ctx tmp = *c;
+  size_t need = carve(&tmp, nullptr, mode, nsteps, seg_len);
+  if (need > bytes) return fail(DCF_ENOMEM, "workspace needs %zu bytes, got %zu", need, bytes);
+  carve(c, dev, mode, nsteps, seg_len);
+  DCF_HIP(hipMemset(c->g.flags, 0, 64 * sizeof(unsigned)));
+  c->ws = dev;
+  c->ws_bytes = bytes;
+  c->ws_mode = mode;
+  c->ws_nsteps = mode == 2 ? nsteps : 0;
+  c->ws_seg = mode == 2 ? seg_len : 0;
+  return DCF_OK;
+}
+
+dcf_status dcf_set_bc(dcf_ctx *c, int face, const dcf_bc *bc) {
+  if (!c || !bc) return fail(DCF_EINVAL, "null argument");
+  if (face < 0 || face > 5) return fail(DCF_EINVAL, "face must be 0..5");
+  int d = face / 2;
+  if (d >= c->g.ndim) return fail(DCF_EINVAL, "face %d is on an unused axis", face);
+  if (bc->kind < 0 || bc->kind > 4) return fail(DCF_EINVAL, "unknown boundary kind");
+  Dev &g = c->g;
+  if (bc->kind == BC_WALL || bc->kind == BC_POROUS) {
+    if (!(bc->T_wall > 0.0)) return fail(DCF_EINVAL, "wall needs T_wall > 0");
+  }
+  if (bc->kind == BC_DIRICHLET && !bc->dirichlet)
+    return fail(DCF_EINVAL, "Dirichlet face needs a profile");
+  if (bc->kind == BC_POROUS) {
+    if (g.pface >= 0 && g.pface != face) return fail(DCF_EUNSUPPORTED, "only one porous face");
+    int t1 = tan1(d);
+    int nt1 = g.n[t1];
+    if (bc->porous_begin < 0 || bc->porous_end > nt1 || bc->porous_begin >= bc->porous_end)
+      return fail(DCF_EINVAL, "porous strip [%d,%d) outside [0,%d)", bc->porous_begin,
+                  bc->porous_end, nt1);
+    if (!(bc->p_inf > 0.0)) return fail(DCF_EINVAL, "porous wall needs p_inf > 0");
+    g.pface = face;
+    g.pb = bc->porous_begin;
+    g.pe = bc->porous_end;
+    g.pinf = bc->p_inf;
+    c->nK = (g.pe - g.pb) * g.n[tan2(d)];
+  } else if (g.pface == face) {
+    g.pface = -1;
+    c->nK = 0;
+  }
+  g.bck[face] = bc->kind;
+  g.Tw[face] = bc->T_wall;
+  g.dir[face] = bc->dirichlet;
+  return DCF_OK;
+}
+
+dcf_status dcf_set_params(dcf_ctx *c, const double *K, int nK) {
+  if (!c) return fail(DCF_EINVAL, "null context");
+  if (nK != c->nK) return fail(DCF_EINVAL, "expected %d porous coefficients, got %d", c->nK, nK);
+  if (nK > 0 && !K) return fail(DCF_EINVAL, "null K");
+  c->g.K = K;
+  return DCF_OK;
+}
+
+dcf_status dcf_set_source(dcf_ctx *c, int kind) {
+  if (!c) return fail(DCF_EINVAL, "null context");
+  if (kind != SRC_NONE && kind != SRC_MASSFLUX) return fail(DCF_EINVAL, "unknown source");
+  c->g.source = kind;
+  return DCF_OK;
+}
+
+dcf_status dcf_set_cost(dcf_ctx *c, int face, double pref) {
+  if (!c) return fail(DCF_EINVAL, "null context");
+  if (face < -1 || face > 5 || (face >= 0 && face / 2 >= c->g.ndim))
+    return fail(DCF_EINVAL, "bad cost face %d", face);
+  c->cost_face = face;
+  c->cost_pref = pref;
+  return DCF_OK;
+}
+
+}  // extern "C"
+
+// Checks that the context is complete before anything is enqueued.
+static dcf_status ready(dcf_ctx *c, int need_mode) {
+  if (!c) return fail(DCF_EINVAL, "null context");
+  if (c->ws_mode < need_mode)
+    return fail(DCF_ENOMEM, "workspace for mode %d not set (have mode %d)", need_mode, c->ws_mode);
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  if (dev != c->device) return fail(DCF_EINVAL, "context belongs to device %d, current is %d",
+                                    c->device, dev);
+  const Dev &g = c->g;
+  for (int d = 0; d < g.ndim; ++d) {
+    bool p0 = g.bck[2 * d] == BC_PERIODIC, p1 = g.bck[2 * d + 1] == BC_PERIODIC;
+    if (p0 != p1) return fail(DCF_EINVAL, "axis %d: periodic faces must come in pairs", d);
+  }
+  if (g.pface >= 0 && c->nK > 0 && !g.K)
+    return fail(DCF_EINVAL, "porous face set but no coefficients (dcf_set_params)");
+  return DCF_OK;
+}
+
+// One right-hand-side evaluation into the face-flux buffers (and the force).
+static dcf_status eval_fluxes(dcf_ctx *c, const double *U, hipStream_t st) {
+  Dev &g = c->g;
+  DCF_HIP(launch_prim_halo(g, U, st));
+  DCF_HIP(launch_fluxes(g, st));
+  if (g.source == SRC_MASSFLUX) DCF_HIP(launch_force(g, c->part, c->force, st));
+  return DCF_OK;
+}
+
+static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_t st) {
+  Dev &g = c->g;
+  dcf_status s;
+  if ((s = eval_fluxes(c, U, st))) return s;
+  DCF_HIP(launch_update(g, U, U, c->U1, nullptr, dt, 0.0, 1.0, c->force, st));
+  if ((s = eval_fluxes(c, c->U1, st))) return s;
+  DCF_HIP(launch_update(g, U, c->U1, c->U2, nullptr, dt, 0.75, 0.25, c->force, st));
+  if ((s = eval_fluxes(c, c->U2, st))) return s;
+  DCF_HIP(launch_update(g, U, c->U2, U, nullptr, dt, 1.0 / 3.0, 2.0 / 3.0, c->force, st));
+  return DCF_OK;
+}
+
+extern "C" {
+
+dcf_status dcf_init_state(dcf_ctx *c, const double *P, double *U, void *stream) {
+  dcf_status s = ready(c, 0);
+  if (s) return s;
+  if (!P || !U) return fail(DCF_EINVAL, "null array");
+  DCF_HIP(launch_init_state(c->g, P, U, (hipStream_t)stream));
+  return DCF_OK;
+}
+
+dcf_status dcf_rhs(dcf_ctx *c, const double *U, double *R, void *stream) {
+  dcf_status s = ready(c, 0);
+  if (s) return s;
+  if (!U || !R) return fail(DCF_EINVAL, "null array");
+  hipStream_t st = (hipStream_t)stream;
+  if ((s = eval_fluxes(c, U, st))) return s;
+  DCF_HIP(launch_update(c->g, U, U, nullptr, R, nullptr, 0.0, 0.0, c->force, st));
+  return DCF_OK;
+}
+
+dcf_status dcf_compute_dt(dcf_ctx *c, const double *U, double cfl, double dt_max, double *dt,
+                          void *stream) {
+  dcf_status s = ready(c, 0);
+  if (s) return s;
+  if (!U || !dt) return fail(DCF_EINVAL, "null array");
+  if (!(cfl > 0.0)) return fail(DCF_EINVAL, "cfl must be > 0");
+  if (!(dt_max > 0.0)) dt_max = 1.0e300;
+  DCF_HIP(launch_dt(c->g, U, cfl, dt_max, c->part, dt, (hipStream_t)stream));
+  return DCF_OK;
+}
+
+dcf_status dcf_rk3_step(dcf_ctx *c, double *U, const double *dt, void *stream) {
+  dcf_status s = ready(c, 0);
+  if (s) return s;
+  if (!U || !dt) return fail(DCF_EINVAL, "null array");
+  return rk3_stages(c, U, dt, (hipStream_t)stream);
+}
+
+dcf_status dcf_diagnostics(dcf_ctx *c, const double *U, double *out, void *stream) {
+  dcf_status s = ready(c, 0);
+  if (s) return s;
+  if (!U || !out) return fail(DCF_EINVAL, "null array");
+  hipStream_t st = (hipStream_t)stream;
+  DCF_HIP(launch_prim_halo(c->g, U, st));
+  DCF_HIP(launch_diag(c->g, U, c->part, out, st));
+  return DCF_OK;
+}
+
+dcf_status dcf_cost_term(dcf_ctx *c, const double *U, double w, double *J, double *grad,
+                         void *stream) {
+  dcf_status s = ready(c, 0);
+  if (s) return s;
+  if (!U || !J) return fail(DCF_EINVAL, "null array");
+  if (c->cost_face < 0) return fail(DCF_EINVAL, "no cost face set (dcf_set_cost)");
+  DCF_HIP(launch_cost(c->g, c->cost_face, c->cost_pref, U, w, J, grad, (hipStream_t)stream));
+  return DCF_OK;
+}
+
+dcf_status dcf_flags(dcf_ctx *c, unsigned *flags_host, void *stream) {
+  if (!c || !flags_host) return fail(DCF_EINVAL, "null argument");
+  if (c->ws_mode < 0) return fail(DCF_ENOMEM, "workspace not set");
+  hipStream_t st = (hipStream_t)stream;
+  unsigned f = 0;
+  DCF_HIP(hipMemcpyAsync(&f, c->g.flags, sizeof f, hipMemcpyDeviceToHost, st));
+  DCF_HIP(hipStreamSynchronize(st));
+  *flags_host = f;
+  if (f) {
+    unsigned z = 0;
+    DCF_HIP(hipMemcpyAsync(c->g.flags, &z, sizeof z, hipMemcpyHostToDevice, st));
+    DCF_HIP(hipStreamSynchronize(st));
+  }
+  return DCF_OK;
+}
+
+dcf_status dcf_vjp_step(dcf_ctx *c, const double *Un, const double *dt, const double *lam1,
+                        double *lam0, double *dJdK, void *stream) {
+  dcf_status s = ready(c, 1);
+  if (s) return s;
+  if (!Un || !dt || !lam1 || !lam0) return fail(DCF_EINVAL, "null array");
+  if (lam0 == lam1) return fail(DCF_EINVAL, "lam_n may not alias lam_np1");
+  if (c->g.source != SRC_NONE)
+    return fail(DCF_EUNSUPPORTED, "adjoint of the mass-flux source is not implemented");
+  return vjp_step(c->g, c->adj, Un, c->U1, c->U2, dt, lam1, lam0, dJdK, (hipStream_t)stream)
+             ? fail(DCF_EDEVICE, "vjp launch failed")
+             : DCF_OK;
+}
+
+dcf_status dcf_gradient(dcf_ctx *c, const double *U0, int nsteps, const double *dt, int seg_len,
+                        double *J, double *dJdK, double *dJdU0, void *stream) {
+  dcf_status s = ready(c, 2);
+  if (s) return s;
+  if (c->ws_nsteps != nsteps || c->ws_seg != seg_len)
+    return fail(DCF_EINVAL, "workspace was sized for nsteps=%d seg_len=%d, not %d/%d",
+                c->ws_nsteps, c->ws_seg, nsteps, seg_len);
+  if (!U0 || !dt || !J) return fail(DCF_EINVAL, "null array");
+  if (c->cost_face < 0) return fail(DCF_EINVAL, "no cost face set (dcf_set_cost)");
+  if (c->g.source != SRC_NONE)
+    return fail(DCF_EUNSUPPORTED, "adjoint of the mass-flux source is not implemented");
+  hipStream_t st = (hipStream_t)stream;
+  Dev &g = c->g;
+  const long M = (long)g.nv * g.ncell;
+  const int nseg = (nsteps + seg_len - 1) / seg_len;
+  const double w = 1.0 / nsteps;
+  // forward sweep: checkpoints at segment starts, cost accumulation
+  DCF_HIP(launch_fill(J, 0.0, 1, st));
+  double *U = c->seg;  // running state
+  DCF_HIP(launch_copy(U, U0, M, st));
+  for (int n = 0; n < nsteps; ++n) {
+    if (n % seg_len == 0) DCF_HIP(launch_copy(c->ckpt + (long)(n / seg_len) * M, U, M, st));
+    if ((s = rk3_stages(c, U, dt, st))) return s;
+    DCF_HIP(launch_cost(g, c->cost_face, c->cost_pref, U, w, J, nullptr, st));
+  }
+  // reverse sweep
+  double *lam = c->lam_a, *lam_prev = c->lam_b;
+  DCF_HIP(launch_fill(lam, 0.0, M, st));
+  if (dJdK && c->nK > 0) DCF_HIP(launch_fill(dJdK, 0.0, c->nK, st));
+  for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+    int n0 = sgi * seg_len;
+    int n1 = n0 + seg_len < nsteps ? n0 + seg_len : nsteps;
+    // recompute states U^{n0} .. U^{n1} of this segment
+    DCF_HIP(launch_copy(c->seg, c->ckpt + (long)sgi * M, M, st));
+    for (int n = n0; n < n1; ++n) {
+      double *Ua = c->seg + (long)(n - n0) * M, *Ub = Ua + M;
+      DCF_HIP(launch_copy(Ub, Ua, M, st));
+      if ((s = rk3_stages(c, Ub, dt, st))) return s;
+    }
+    for (int n = n1; n > n0; --n) {
+      // lam holds dJ/dU^n from later steps; add the cost term of U^n
+      const double *Ucur = c->seg + (long)(n - n0) * M;
+      DCF_HIP(launch_cost(g, c->cost_face, c->cost_pref, Ucur, w, c->force + 2,
+                          lam, st));
+      const double *Uprev = c->seg + (long)(n - 1 - n0) * M;
+      if (vjp_step(g, c->adj, Uprev, c->U1, c->U2, dt, lam, lam_prev, dJdK, st))
+        return fail(DCF_EDEVICE, "vjp launch failed");
+      double *t = lam;
+      lam = lam_prev;
+      lam_prev = t;
+    }
+  }
+  if (dJdU0) DCF_HIP(launch_copy(dJdU0, lam, M, st));
+  return DCF_OK;
+}
+
+dcf_status dcf_time_kernel(dcf_ctx *c, const double *U, int which, int reps, double *avg_ms,
+                           void *stream) {
+  dcf_status s = ready(c, 0);
+  if (s) return s;
+  if (!U || !avg_ms || reps < 1) return fail(DCF_EINVAL, "bad argument");
+  if (which < 0 || which > 4 || (which >= 1 && which <= 3 && which > c->g.ndim))
+    return fail(DCF_EINVAL, "unknown kernel %d", which);
+  hipStream_t st = (hipStream_t)stream;
+  Dev &g = c->g;
+  if ((s = eval_fluxes(c, U, st))) return s;
+  DCF_HIP(launch_fill(c->U2, 1.0e-3, 1, st));  // a tiny dt for the update kernel
+  hipEvent_t e0, e1;
+  DCF_HIP(hipEventCreate(&e0));
+  DCF_HIP(hipEventCreate(&e1));
+  DCF_HIP(hipEventRecord(e0, st));
+  for (int r = 0; r < reps; ++r) {
+    hipError_t e = hipSuccess;
+    if (which == 0) e = launch_prim_halo(g, U, st);
+    else if (which <= 3) e = launch_flux_dir(g, which - 1, st);
+    else e = launch_update(g, U, U, c->U1, nullptr, c->U2, 0.0, 1.0, c->force, st);
+    if (e != hipSuccess) return fail(DCF_EDEVICE, "launch: %s", hipGetErrorString(e));
+  }
+  DCF_HIP(hipEventRecord(e1, st));
+  DCF_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  DCF_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = ms / reps;
+  return DCF_OK;
+}
+
+}  // extern "C"

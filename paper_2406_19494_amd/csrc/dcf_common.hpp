@@ -1,0 +1,158 @@
+// dcf_common.hpp -- device-side data structures and the per-face numerics of
+// the finite-volume compressible Navier-Stokes right-hand side (gfx950, FP64).
+//
+// Paper correspondence:
+//   conserved vector and total energy ............ Section 2.1, Eq. (2)
+//   convective fluxes F^c, G^c, H^c ................ Eq. (3)
+//   dissipative fluxes (stress, heat flux) ......... Eqs. (4)-(5), Fourier law
+//   semi-discrete update with cell widths .......... Eq. (6)
+//   WENO-type reconstruction + HLLC Riemann solver . Section 2.1 / Section 3.1
+//   halo-cell boundary conditions .................. Section 3.2
+// Schemes named but not written out in the paper use their published
+// definitions: WENO5-JS (Jiang & Shu 1996, eps = 1e-6, power 2), HLLC
+// (Toro, Spruce & Speares 1994) with Davis wave speeds, 4th-order central
+// differences for the dissipative fluxes, and three-stage TVD Runge-Kutta
+// (Shu & Osher 1988).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dcf {
+
+constexpr int NH = 3;  // halo layers per active axis (Section 2.2)
+
+enum : int { BC_PERIODIC = 0, BC_WALL = 1, BC_POROUS = 2, BC_ZEROGRAD = 3, BC_DIRICHLET = 4 };
+enum : int { VISC_NONE = 0, VISC_POWER = 1, VISC_SUTHERLAND = 2 };
+enum : int { SRC_NONE = 0, SRC_MASSFLUX = 1 };
+enum : int { QR = 0, QU = 1, QV = 2, QW = 3, QP = 4, QT = 5, QMU = 6, NQ = 7 };
+
+// Everything a kernel needs about one solve, passed by value.
+struct Dev {
+  int ndim, nv;
+  int n[3], h[3], N[3];  // interior cells, halo layers, box cells per axis
+  long ncell, nbox;
+  long sb[3];            // box strides per axis
+  // grid metrics per axis (device arrays): widths, 1/width, dxi/dx at
+  // centres (n) and at faces (n+1)
+  const double *dx[3], *idx[3], *mc[3], *mf[3];
+  // gas
+  double gamma, R, Pr, cp, mu_ref, T_ref, vparam;
+  int visc;
+  // boundaries
+  int bck[6];
+  double Tw[6];
+  const double *dir[6];
+  int pface, pb, pe;
+  double pinf;
+  const double *K;
+  int source;
+  // workspace
+  double *Q[NQ];         // primitive box arrays
+  double *F[3];          // face fluxes per direction, 5 components each
+  long fcount[3];        // faces per direction (component stride of F)
+  int fn[3][3];          // face-array extents per direction
+  unsigned *flags;
+};
+
+__device__ __forceinline__ bool finite_pos(double x) { return x > 0.0 && x < 1.0e300; }
+
+// Dynamic viscosity: power law, or Sutherland's law (Section 3.2).
+__device__ __forceinline__ double viscosity(const Dev &g, double T) {
+  if (g.visc == VISC_POWER) return g.mu_ref * pow(T / g.T_ref, g.vparam);
+  if (g.visc == VISC_SUTHERLAND) {
+    double t = T / g.T_ref;
+    double s = g.vparam / g.T_ref;
+    return g.mu_ref * t * sqrt(t) * (1.0 + s) / (t + s);
+  }
+  return 0.0;
+}
+
+// WENO5-JS value at the right face of cell c from (a, b, c, d, e).  The
+// nonlinear weights alpha_k = d_k / (eps + beta_k)^2 are normalised after
+// multiplying through by the product of the three denominators, which needs
+// one division instead of four.
+__device__ __forceinline__ double weno5(double a, double b, double c, double d, double e) {
+  const double eps = 1.0e-6;
+  const double sixth = 1.0 / 6.0;
+  const double c1312 = 13.0 / 12.0;
+  double q0 = (2.0 * a - 7.0 * b + 11.0 * c) * sixth;
+  double q1 = (-b + 5.0 * c + 2.0 * d) * sixth;
+  double q2 = (2.0 * c + 5.0 * d - e) * sixth;
+  double r0 = a - 2.0 * b + c, s0 = a - 4.0 * b + 3.0 * c;
+  double r1 = b - 2.0 * c + d, s1 = b - d;
+  double r2 = c - 2.0 * d + e, s2 = 3.0 * c - 4.0 * d + e;
+  double t0 = eps + (c1312 * r0 * r0 + 0.25 * s0 * s0);
+  double t1 = eps + (c1312 * r1 * r1 + 0.25 * s1 * s1);
+  double t2 = eps + (c1312 * r2 * r2 + 0.25 * s2 * s2);
+  t0 *= t0;
+  t1 *= t1;
+  t2 *= t2;
+  double w0 = 0.1 * t1 * t2, w1 = 0.6 * t0 * t2, w2 = 0.3 * t0 * t1;
+  return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+}
+
+// HLLC flux in the face frame.  q = (rho, u_n, u_t1, u_t2, p) on each side;
+// F = (mass, normal momentum, t1 momentum, t2 momentum, energy).  Ties at
+// 0 <= S select the left-side state.  Star state written with one
+// reciprocal r = 1/(S_K - S*):
+//   U*_K = r [rho (S-u), rho (S-u) S*, rho (S-u) v, rho (S-u) w,
+//             E (S-u) + (S*-u)(rho (S-u) S* + p)].
+__device__ __forceinline__ void hllc(const double *qL, const double *qR, double gamma,
+                                     double *F) {
+  const double gm1i = 1.0 / (gamma - 1.0);
+  double rL = qL[0], uL = qL[1], vL = qL[2], wL = qL[3], pL = qL[4];
+  double rR = qR[0], uR = qR[1], vR = qR[2], wR = qR[3], pR = qR[4];
+  double EL = pL * gm1i + 0.5 * rL * (uL * uL + vL * vL + wL * wL);
+  double ER = pR * gm1i + 0.5 * rR * (uR * uR + vR * vR + wR * wR);
+  double cL = sqrt(gamma * pL / rL);
+  double cR = sqrt(gamma * pR / rR);
+  double SL = fmin(uL - cL, uR - cR);
+  double SR = fmax(uL + cL, uR + cR);
+  double mL = rL * (SL - uL), mR = rR * (SR - uR);
+  double Ss = (pR - pL + uL * mL - uR * mR) / (mL - mR);
+  if (0.0 <= SL) {
+    F[0] = rL * uL;
+    F[1] = rL * uL * uL + pL;
+    F[2] = rL * uL * vL;
+    F[3] = rL * uL * wL;
+    F[4] = uL * (EL + pL);
+    return;
+  }
+  if (SR < 0.0) {
+    F[0] = rR * uR;
+    F[1] = rR * uR * uR + pR;
+    F[2] = rR * uR * vR;
+    F[3] = rR * uR * wR;
+    F[4] = uR * (ER + pR);
+    return;
+  }
+  const bool left = (0.0 <= Ss);
+  double r = left ? rL : rR, u = left ? uL : uR, v = left ? vL : vR, w = left ? wL : wR;
+  double p = left ? pL : pR, E = left ? EL : ER, S = left ? SL : SR, m = left ? mL : mR;
+  double inv = 1.0 / (S - Ss);
+  double Us0 = m * inv;
+  double Us4 = (E * (S - u) + (Ss - u) * (m * Ss + p)) * inv;
+  double fm = r * u;
+  F[0] = fm + S * (Us0 - r);
+  F[1] = fm * u + p + S * (Us0 * Ss - fm);
+  F[2] = fm * v + S * (Us0 * v - r * v);
+  F[3] = fm * w + S * (Us0 * w - r * w);
+  F[4] = u * (E + p) + S * (Us4 - E);
+}
+
+// 4th-order central interpolation and derivatives in index space.
+__device__ __forceinline__ double interp4(double a, double b, double c, double d) {
+  return (9.0 * (b + c) - (a + d)) * (1.0 / 16.0);
+}
+__device__ __forceinline__ double dface4(double a, double b, double c, double d) {
+  return (27.0 * (c - b) - (d - a)) * (1.0 / 24.0);
+}
+__device__ __forceinline__ double dcell4(double m2, double m1, double p1, double p2) {
+  return (8.0 * (p1 - m1) - (p2 - m2)) * (1.0 / 12.0);
+}
+
+__host__ __device__ __forceinline__ constexpr int tan1(int d) { return d == 0 ? 1 : 0; }
+__host__ __device__ __forceinline__ constexpr int tan2(int d) { return d == 2 ? 1 : 2; }
+
+}  // namespace dcf

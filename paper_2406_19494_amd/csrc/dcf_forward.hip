@@ -1,0 +1,735 @@
+// dcf_forward.hip -- forward kernels: grid metrics, conversion to
+// primitives fused with the halo fill, per-direction face fluxes, the fused
+// divergence + source + TVD-RK3 stage update, and deterministic reductions
+// (CFL time step, body force, diagnostics, wall-pressure cost).
+#include "dcf_kernels.hpp"
+
+namespace dcf {
+
+// ---------------------------------------------------------------------------
+// Grid metrics of one axis (stretched Cartesian meshes, Section 2; the tanh
+// law of Section 3.2).  Face i at xi = i, centre at xi = i + 1/2.
+// ---------------------------------------------------------------------------
+__device__ void axis_map(int kind, double lo, double hi, double beta, int n, double s, double *x,
+                         double *dxdxi) {
+  double L = hi - lo;
+  if (kind == 1) {  // symmetric clustering toward both ends
+    double a = beta * (1.0 - 2.0 * s);
+    double th = tanh(beta);
+    *x = lo + L * 0.5 * (1.0 - tanh(a) / th);
+    double ch = cosh(a);
+    *dxdxi = L * beta / (n * th * ch * ch);
+  } else if (kind == 2) {  // clustering toward lo
+    double a = beta * (s - 1.0);
+    double th = tanh(beta);
+    *x = lo + L * (1.0 + tanh(a) / th);
+    double ch = cosh(a);
+    *dxdxi = L * beta / (n * th * ch * ch);
+  } else {
+    *x = lo + L * s;
+    *dxdxi = L / n;
+  }
+}
+
+__global__ void k_metrics(int kind, double lo, double hi, double beta, int n, double *dx,
+                          double *idx, double *mc, double *mf) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  double x0, g0;
+  axis_map(kind, lo, hi, beta, n, (double)i / n, &x0, &g0);
+  mf[i] = 1.0 / g0;
+  if (i < n) {
+    double x1, g1, xc, gc;
+    axis_map(kind, lo, hi, beta, n, (double)(i + 1) / n, &x1, &g1);
+    axis_map(kind, lo, hi, beta, n, (i + 0.5) / n, &xc, &gc);
+    dx[i] = x1 - x0;
+    idx[i] = 1.0 / (x1 - x0);
+    mc[i] = 1.0 / gc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Primitives from conserved variables (Eq. (2), ideal gas).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void cons_to_prim(const Dev &g, const double *U, long c, double *q) {
+  const int nd = g.ndim;
+  const long nc = g.ncell;
+  double rho = U[c];
+  double ir = 1.0 / rho;
+  double u = U[nc + c] * ir;
+  double v = nd >= 2 ? U[2 * nc + c] * ir : 0.0;
+  double w = nd >= 3 ? U[3 * nc + c] * ir : 0.0;
+  double E = U[(long)(nd + 1) * nc + c];
+  double p = (g.gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v + w * w));
+  q[QR] = rho;
+  q[QU] = u;
+  q[QV] = v;
+  q[QW] = w;
+  q[QP] = p;
+  q[QT] = p / (rho * g.R);
+}
+
+__global__ void k_init_state(Dev g, const double *P, double *U) {
+  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.ncell) return;
+  const long nc = g.ncell;
+  const int nd = g.ndim;
+  double rho = P[c], u = P[nc + c], v = P[2 * nc + c], w = P[3 * nc + c], p = P[4 * nc + c];
+  U[c] = rho;
+  U[nc + c] = rho * u;
+  if (nd >= 2) U[2 * nc + c] = rho * v;
+  if (nd >= 3) U[3 * nc + c] = rho * w;
+  U[(long)(nd + 1) * nc + c] = p / (g.gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w);
+}
+
+// ---------------------------------------------------------------------------
+// Primitive box with halos.  One thread per box cell.  The halo fill of the
+// paper (values assigned to halo cells) is applied axis by axis, x then y
+// then z, each over the full extent of the axes filled before; a thread
+// resolves that chain for its own cell: it follows the source cells back to
+// the interior (or to a Dirichlet profile) and applies the per-axis ghost
+// transforms in x, y, z order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int ghost_source(int kind, int side, int m, int n) {
+  if (kind == BC_PERIODIC) return side == 0 ? n - 1 - m : m;
+  if (kind == BC_ZEROGRAD) return side == 0 ? 0 : n - 1;
+  return side == 0 ? m : n - 1 - m;  // walls mirror
+}
+
+__global__ void k_prim_halo(Dev g, const double *U) {
+  long b = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= g.nbox) return;
+  const int nd = g.ndim;
+  int p[3];
+  p[0] = (int)(b % g.N[0]) - g.h[0];
+  p[1] = (int)((b / g.N[0]) % g.N[1]) - g.h[1];
+  p[2] = (int)(b / ((long)g.N[0] * g.N[1])) - g.h[2];
+  int s[3] = {p[0], p[1], p[2]};
+  int side[3] = {0, 0, 0};
+  bool gh[3] = {false, false, false};
+  int top = -1;
+  for (int d = 0; d < nd; ++d) {
+    if (p[d] < 0 || p[d] >= g.n[d]) {
+      gh[d] = true;
+      side[d] = p[d] < 0 ? 0 : 1;
+      int m = side[d] == 0 ? -1 - p[d] : p[d] - g.n[d];
+      int kind = g.bck[2 * d + side[d]];
+      if (kind == BC_DIRICHLET)
+        top = d;
+      else
+        s[d] = ghost_source(kind, side[d], m, g.n[d]);
+    }
+  }
+  double q[6];
+  int start = 0;
+  if (top >= 0) {
+    const int d = top;
+    const int t1 = tan1(d), t2 = tan2(d);
+    int a = t1 < nd ? (t1 < d ? p[t1] : s[t1]) : 0;
+    int bb = t2 < nd ? (t2 < d ? p[t2] : s[t2]) : 0;
+    a = min(max(a, 0), g.n[t1] - 1);
+    bb = min(max(bb, 0), g.n[t2] - 1);
+    const long nt = (long)g.n[t1] * g.n[t2];
+    const long o = (long)bb * g.n[t1] + a;
+    const double *P = g.dir[2 * d + side[d]];
+    q[QR] = P[o];
+    q[QU] = P[nt + o];
+    q[QV] = P[2 * nt + o];
+    q[QW] = P[3 * nt + o];
+    q[QP] = P[4 * nt + o];
+    q[QT] = q[QP] / (q[QR] * g.R);
+    start = top + 1;
+  } else {
+    long c = ((long)s[2] * g.n[1] + s[1]) * g.n[0] + s[0];
+    cons_to_prim(g, U, c, q);
+    if (!(gh[0] || gh[1] || gh[2])) {
+      if (!(finite_pos(q[QR]) && finite_pos(q[QP]))) atomicOr(g.flags, 1u);
+    }
+  }
+  for (int d = start; d < nd; ++d) {
+    if (!gh[d]) continue;
+    const int face = 2 * d + side[d];
+    const int kind = g.bck[face];
+    if (kind != BC_WALL && kind != BC_POROUS) continue;  // copies keep the value
+    double src_n = q[QU + d];
+    q[QU] = -q[QU];
+    q[QV] = -q[QV];
+    q[QW] = -q[QW];
+    if (kind == BC_POROUS && face == g.pface) {
+      const int t1 = tan1(d), t2 = tan2(d);
+      int a = t1 < nd ? (t1 < d ? p[t1] : s[t1]) : 0;
+      int bb = t2 < nd ? (t2 < d ? p[t2] : s[t2]) : 0;
+      if (a >= g.pb && a < g.pe && bb >= 0 && bb < g.n[t2]) {
+        // Darcy transpiration through the porous strip: inward-normal
+        // velocity -K (p_w - p_inf)/p_inf, p_w of the first interior cell.
+        int w[3];
+        w[d] = side[d] == 0 ? 0 : g.n[d] - 1;
+        w[t1] = a;
+        w[t2] = bb;
+        long cw = ((long)w[2] * g.n[1] + w[1]) * g.n[0] + w[0];
+        double qw[6];
+        cons_to_prim(g, U, cw, qw);
+        int kk = bb * (g.pe - g.pb) + (a - g.pb);
+        double vn = -g.K[kk] * (qw[QP] - g.pinf) / g.pinf;
+        double sigma = side[d] == 0 ? 1.0 : -1.0;
+        q[QU + d] = 2.0 * sigma * vn - src_n;
+      }
+    }
+    double Tg = 2.0 * g.Tw[face] - q[QT];
+    if (!(Tg > 0.0)) atomicOr(g.flags, 1u);
+    q[QT] = Tg;
+    q[QR] = q[QP] / (g.R * Tg);
+  }
+  g.Q[QR][b] = q[QR];
+  g.Q[QU][b] = q[QU];
+  if (nd >= 2) g.Q[QV][b] = q[QV];
+  if (nd >= 3) g.Q[QW][b] = q[QW];
+  g.Q[QP][b] = q[QP];
+  if (g.visc != VISC_NONE) {
+    g.Q[QT][b] = q[QT];
+    g.Q[QMU][b] = viscosity(g, q[QT]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Face fluxes of direction D: F = F^c - F^d at every face of the interior
+// cells (Eq. (6)).  One thread per face; face f along D lies between cells
+// f-1 and f.  Stored in the global 5-component layout (mass, x/y/z momentum,
+// energy).
+// ---------------------------------------------------------------------------
+template <int NDIM, int D, bool VISC>
+__global__ void __launch_bounds__(256) k_flux(Dev g) {
+  constexpr int T1 = tan1(D), T2 = tan2(D);
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.fcount[D]) return;
+  int pos[3];
+  pos[0] = (int)(t % g.fn[D][0]);
+  pos[1] = (int)((t / g.fn[D][0]) % g.fn[D][1]);
+  pos[2] = (int)(t / ((long)g.fn[D][0] * g.fn[D][1]));
+  // box index of the cell right of the face
+  const long base = (long)(pos[2] + g.h[2]) * g.sb[2] + (long)(pos[1] + g.h[1]) * g.sb[1] +
+                    (pos[0] + g.h[0]);
+  const long s = g.sb[D];
+  const int f = pos[D];
+
+  const double *Qr = g.Q[QR], *Qp = g.Q[QP];
+  const double *Qn = g.Q[QU + D];
+  double qL[5], qR[5];
+  {
+    double v[6];
+#pragma unroll
+    for (int o = 0; o < 6; ++o) v[o] = Qr[base + (o - 3) * s];
+    qL[0] = weno5(v[0], v[1], v[2], v[3], v[4]);
+    qR[0] = weno5(v[5], v[4], v[3], v[2], v[1]);
+#pragma unroll
+    for (int o = 0; o < 6; ++o) v[o] = Qn[base + (o - 3) * s];
+    qL[1] = weno5(v[0], v[1], v[2], v[3], v[4]);
+    qR[1] = weno5(v[5], v[4], v[3], v[2], v[1]);
+    if (T1 < NDIM) {
+      const double *Qt = g.Q[QU + T1];
+#pragma unroll
+      for (int o = 0; o < 6; ++o) v[o] = Qt[base + (o - 3) * s];
+      qL[2] = weno5(v[0], v[1], v[2], v[3], v[4]);
+      qR[2] = weno5(v[5], v[4], v[3], v[2], v[1]);
+    } else {
+      qL[2] = qR[2] = 0.0;
+    }
+    if (T2 < NDIM) {
+      const double *Qt = g.Q[QU + T2];
+#pragma unroll
+      for (int o = 0; o < 6; ++o) v[o] = Qt[base + (o - 3) * s];
+      qL[3] = weno5(v[0], v[1], v[2], v[3], v[4]);
+      qR[3] = weno5(v[5], v[4], v[3], v[2], v[1]);
+    } else {
+      qL[3] = qR[3] = 0.0;
+    }
+#pragma unroll
+    for (int o = 0; o < 6; ++o) v[o] = Qp[base + (o - 3) * s];
+    qL[4] = weno5(v[0], v[1], v[2], v[3], v[4]);
+    qR[4] = weno5(v[5], v[4], v[3], v[2], v[1]);
+  }
+  double Fc[5];
+  hllc(qL, qR, g.gamma, Fc);
+  double G[5];
+  G[0] = Fc[0];
+  G[1 + D] = Fc[1];
+  G[1 + T1] = Fc[2];
+  G[1 + T2] = Fc[3];
+  G[4] = Fc[4];
+
+  if (VISC) {
+    // Dissipative flux (Eqs. (4)-(5), Fourier's law) from 4th-order central
+    // interpolation / differences over the cells f-2 .. f+1.
+    double vel[3][4], Tc[4], muc[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      long cb = base + (o - 2) * s;
+      vel[0][o] = g.Q[QU][cb];
+      vel[1][o] = NDIM >= 2 ? g.Q[QV][cb] : 0.0;
+      vel[2][o] = NDIM >= 3 ? g.Q[QW][cb] : 0.0;
+      Tc[o] = g.Q[QT][cb];
+      muc[o] = g.Q[QMU][cb];
+    }
+    const double mfD = g.mf[D][f];
+    double muf = interp4(muc[0], muc[1], muc[2], muc[3]);
+    double uf[3], dn[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      uf[c] = interp4(vel[c][0], vel[c][1], vel[c][2], vel[c][3]);
+      dn[c] = dface4(vel[c][0], vel[c][1], vel[c][2], vel[c][3]) * mfD;
+    }
+    double dT = dface4(Tc[0], Tc[1], Tc[2], Tc[3]) * mfD;
+    double divt = 0.0, dtn[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int tt = r == 0 ? T1 : T2;
+      if (tt >= NDIM) continue;
+      const long st = g.sb[tt];
+      const double mct = g.mc[tt][pos[tt]];
+      const double *Qtt = g.Q[QU + tt];
+      double gtt[4], gtn[4];
+#pragma unroll
+      for (int o = 0; o < 4; ++o) {
+        long cb = base + (o - 2) * s;
+        gtt[o] = dcell4(Qtt[cb - 2 * st], Qtt[cb - st], Qtt[cb + st], Qtt[cb + 2 * st]) * mct;
+        gtn[o] = dcell4(Qn[cb - 2 * st], Qn[cb - st], Qn[cb + st], Qn[cb + 2 * st]) * mct;
+      }
+      divt += interp4(gtt[0], gtt[1], gtt[2], gtt[3]);
+      dtn[tt] = interp4(gtn[0], gtn[1], gtn[2], gtn[3]);
+    }
+    double tau[3] = {0.0, 0.0, 0.0};
+    tau[D] = muf * ((4.0 / 3.0) * dn[D] - (2.0 / 3.0) * divt);
+    if (T1 < NDIM) tau[T1] = muf * (dtn[T1] + dn[T1]);
+    if (T2 < NDIM) tau[T2] = muf * (dtn[T2] + dn[T2]);
+    double lam = muf * g.cp / g.Pr;
+    double en = uf[0] * tau[0] + uf[1] * tau[1] + uf[2] * tau[2] + lam * dT;
+    G[1] -= tau[0];
+    G[2] -= tau[1];
+    G[3] -= tau[2];
+    G[4] -= en;
+  }
+  double *F = g.F[D];
+  const long fc = g.fcount[D];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) F[m * fc + t] = G[m];
+}
+
+// Index of the face left of cell (i, j, k) in direction D's face array.
+__device__ __forceinline__ long face_index(const Dev &g, int D, int i, int j, int k) {
+  return ((long)k * g.fn[D][1] + j) * g.fn[D][0] + i;
+}
+
+// x-momentum right-hand side without source at cell c, for the body force.
+__device__ __forceinline__ double rhs_xmom(const Dev &g, int i, int j, int k) {
+  double r = 0.0;
+  for (int D = 0; D < g.ndim; ++D) {
+    long fl = face_index(g, D, i, j, k);
+    long fr = fl + (D == 0 ? 1 : (D == 1 ? g.fn[1][0] : (long)g.fn[2][0] * g.fn[2][1]));
+    int pos = D == 0 ? i : (D == 1 ? j : k);
+    const double *F = g.F[D] + 1 * g.fcount[D];
+    r -= (F[fr] - F[fl]) * g.idx[D][pos];
+  }
+  return r;
+}
+
+__device__ __forceinline__ double cell_volume(const Dev &g, int i, int j, int k) {
+  double V = g.dx[0][i];
+  if (g.ndim >= 2) V *= g.dx[1][j];
+  if (g.ndim >= 3) V *= g.dx[2][k];
+  return V;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic block reductions (fixed tree for a fixed launch shape).
+// ---------------------------------------------------------------------------
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *sh /*[NV*256]*/) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) sh[q * 256 + t] = v[q];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) sh[q * 256 + t] += sh[q * 256 + t + w];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = sh[q * 256];
+}
+
+__device__ __forceinline__ double block_max(double v, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] = fmax(sh[t], sh[t + w]);
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// Body force, pass 1: per-block partial sums of V*R_rhou and V.
+__global__ void __launch_bounds__(256) k_force_partial(Dev g, double *part) {
+  __shared__ double sh[2 * 256];
+  double v[2] = {0.0, 0.0};
+  for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < g.ncell;
+       c += (long)gridDim.x * blockDim.x) {
+    int i = (int)(c % g.n[0]), j = (int)((c / g.n[0]) % g.n[1]),
+        k = (int)(c / ((long)g.n[0] * g.n[1]));
+    double V = cell_volume(g, i, j, k);
+    v[0] += V * rhs_xmom(g, i, j, k);
+    v[1] += V;
+  }
+  block_sum<2>(v, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = v[0];
+    part[2 * blockIdx.x + 1] = v[1];
+  }
+}
+
+// Body force, pass 2: f = -sum(V R_rhou)/sum(V).
+__global__ void __launch_bounds__(256) k_force_final(const double *part, int nparts, double *f) {
+  __shared__ double sh[2 * 256];
+  double v[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nparts; b += 256) {
+    v[0] += part[2 * b];
+    v[1] += part[2 * b + 1];
+  }
+  block_sum<2>(v, sh);
+  if (threadIdx.x == 0) f[0] = -v[0] / v[1];
+}
+
+// ---------------------------------------------------------------------------
+// Divergence of the face fluxes (Eq. (6)) plus the source, fused with the
+// TVD-RK3 stage: Uout = a*Un + b*(Uin + dt*R).  With Rout != nullptr the
+// kernel writes R instead (rhs evaluation).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_update(Dev g, const double *Un, const double *Uin,
+                                                double *Uout, double *Rout, const double *dtp,
+                                                double a, double bcoef, const double *force) {
+  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.ncell) return;
+  int i = (int)(c % g.n[0]), j = (int)((c / g.n[0]) % g.n[1]),
+      k = (int)(c / ((long)g.n[0] * g.n[1]));
+  const int nd = g.ndim;
+  double R[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int D = 0; D < nd; ++D) {
+    long fl = face_index(g, D, i, j, k);
+    long fr = fl + (D == 0 ? 1 : (D == 1 ? g.fn[1][0] : (long)g.fn[2][0] * g.fn[2][1]));
+    int pos = D == 0 ? i : (D == 1 ? j : k);
+    double id = g.idx[D][pos];
+    const double *F = g.F[D];
+    const long fc = g.fcount[D];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) R[m] -= (F[m * fc + fr] - F[m * fc + fl]) * id;
+  }
+  if (g.source == SRC_MASSFLUX) {
+    double f = force[0];
+    long b = (long)(k + g.h[2]) * g.sb[2] + (long)(j + g.h[1]) * g.sb[1] + (i + g.h[0]);
+    R[1] += f;
+    R[4] += f * g.Q[QU][b];
+  }
+  const long nc = g.ncell;
+  // conserved component v <- flux entry m
+  double Rv[5];
+  Rv[0] = R[0];
+  Rv[1] = R[1];
+  if (nd >= 2) Rv[2] = R[2];
+  if (nd >= 3) Rv[3] = R[3];
+  Rv[nd + 1] = R[4];
+  if (Rout) {
+    for (int v = 0; v < nd + 2; ++v) Rout[v * nc + c] = Rv[v];
+    return;
+  }
+  const double dt = dtp[0];
+  for (int v = 0; v < nd + 2; ++v) {
+    double un = Un[v * nc + c];
+    double ui = Uin[v * nc + c];
+    Uout[v * nc + c] = a * un + bcoef * (ui + dt * Rv[v]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CFL time step: dt = min(dt_max, cfl / max_cells sigma).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_dt_partial(Dev g, const double *U, double *part) {
+  __shared__ double sh[256];
+  double smax = 0.0;
+  for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < g.ncell;
+       c += (long)gridDim.x * blockDim.x) {
+    int pos[3] = {(int)(c % g.n[0]), (int)((c / g.n[0]) % g.n[1]),
+                  (int)(c / ((long)g.n[0] * g.n[1]))};
+    double q[6];
+    cons_to_prim(g, U, c, q);
+    double cs = sqrt(g.gamma * q[QP] / q[QR]);
+    double conv = 0.0, inv2 = 0.0;
+    for (int d = 0; d < g.ndim; ++d) {
+      double id = g.idx[d][pos[d]];
+      conv += (fabs(q[QU + d]) + cs) * id;
+      inv2 += id * id;
+    }
+    double sig = conv;
+    if (g.visc != VISC_NONE) {
+      double mu = viscosity(g, q[QT]);
+      double nu = fmax(4.0 / 3.0, g.gamma / g.Pr) * mu / q[QR];
+      sig += 2.0 * nu * inv2;
+    }
+    if (!(sig < 1.0e300)) sig = 1.0e300;  // non-finite: flagged elsewhere
+    smax = fmax(smax, sig);
+  }
+  smax = block_max(smax, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = smax;
+}
+
+__global__ void __launch_bounds__(256) k_dt_final(const double *part, int nparts, double cfl,
+                                                  double dt_max, double *dt) {
+  __shared__ double sh[256];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += 256) m = fmax(m, part[b]);
+  m = block_max(m, sh);
+  if (threadIdx.x == 0) dt[0] = fmin(dt_max, cfl / m);
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics: volume means of kinetic energy and mu |omega|^2, and the
+// conserved totals.  Needs the primitive box (vorticity from 4th-order
+// cell-centred differences).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_diag_partial(Dev g, const double *U, double *part) {
+  __shared__ double sh[8 * 256];
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const long nc = g.ncell;
+  for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < nc;
+       c += (long)gridDim.x * blockDim.x) {
+    int i = (int)(c % g.n[0]), j = (int)((c / g.n[0]) % g.n[1]),
+        k = (int)(c / ((long)g.n[0] * g.n[1]));
+    double V = cell_volume(g, i, j, k);
+    long b = (long)(k + g.h[2]) * g.sb[2] + (long)(j + g.h[1]) * g.sb[1] + (i + g.h[0]);
+    double rho = g.Q[QR][b], u = g.Q[QU][b];
+    double vv = g.ndim >= 2 ? g.Q[QV][b] : 0.0, w = g.ndim >= 3 ? g.Q[QW][b] : 0.0;
+    v[0] += V * 0.5 * rho * (u * u + vv * vv + w * w);
+    if (g.ndim == 3) {
+      int pos[3] = {i, j, k};
+      auto D = [&](int q, int t) {
+        const double *A = g.Q[q];
+        long st = g.sb[t];
+        return dcell4(A[b - 2 * st], A[b - st], A[b + st], A[b + 2 * st]) * g.mc[t][pos[t]];
+      };
+      double wx = D(QW, 1) - D(QV, 2);
+      double wy = D(QU, 2) - D(QW, 0);
+      double wz = D(QV, 0) - D(QU, 1);
+      double mu = g.visc != VISC_NONE ? g.Q[QMU][b] : 0.0;
+      v[1] += V * mu * (wx * wx + wy * wy + wz * wz);
+    }
+    v[2] += V * U[c];
+    v[3] += V * U[nc + c];
+    if (g.ndim >= 2) v[4] += V * U[2 * nc + c];
+    if (g.ndim >= 3) v[5] += V * U[3 * nc + c];
+    v[6] += V * U[(long)(g.ndim + 1) * nc + c];
+    v[7] += V;
+  }
+  block_sum<8>(v, sh);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 8; ++q) part[8 * blockIdx.x + q] = v[q];
+}
+
+__global__ void __launch_bounds__(256) k_diag_final(const double *part, int nparts, double *out) {
+  __shared__ double sh[8 * 256];
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nparts; b += 256)
+    for (int q = 0; q < 8; ++q) v[q] += part[8 * b + q];
+  block_sum<8>(v, sh);
+  if (threadIdx.x == 0) {
+    out[0] = v[0] / v[7];
+    out[1] = v[1] / v[7];
+    for (int q = 2; q < 8; ++q) out[q] = v[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wall-pressure cost term j(U) = sum_i (A_i/A)(p_i - p_ref)^2 over the cells
+// next to the cost face, accumulated as J += w j; optional gradient
+// g += w dj/dU.  One block; the face has O(n^2) cells.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_cost(Dev g, int face, double pref, const double *U,
+                                              double w, double *J, double *grad) {
+  __shared__ double sh[2 * 256];
+  const int d = face / 2, side = face % 2;
+  const int t1 = tan1(d), t2 = tan2(d);
+  const int na = g.n[t1], nb = g.n[t2];
+  const long nface = (long)na * nb;
+  const int nd = g.ndim;
+  const long nc = g.ncell;
+  // total area (fixed order), then the weighted sum
+  double v[2] = {0.0, 0.0};
+  for (long x = threadIdx.x; x < nface; x += 256) {
+    int a = (int)(x % na), bb = (int)(x / na);
+    double A = 1.0;
+    if (t1 < nd) A *= g.dx[t1][a];
+    if (t2 < nd) A *= g.dx[t2][bb];
+    int p[3];
+    p[d] = side == 0 ? 0 : g.n[d] - 1;
+    p[t1] = a;
+    p[t2] = bb;
+    long c = ((long)p[2] * g.n[1] + p[1]) * g.n[0] + p[0];
+    double q[6];
+    cons_to_prim(g, U, c, q);
+    double dp = q[QP] - pref;
+    v[0] += A * dp * dp;
+    v[1] += A;
+  }
+  block_sum<2>(v, sh);
+  const double area = v[1];
+  if (threadIdx.x == 0) J[0] += w * (v[0] / area);
+  if (!grad) return;
+  for (long x = threadIdx.x; x < nface; x += 256) {
+    int a = (int)(x % na), bb = (int)(x / na);
+    double A = 1.0;
+    if (t1 < nd) A *= g.dx[t1][a];
+    if (t2 < nd) A *= g.dx[t2][bb];
+    int p[3];
+    p[d] = side == 0 ? 0 : g.n[d] - 1;
+    p[t1] = a;
+    p[t2] = bb;
+    long c = ((long)p[2] * g.n[1] + p[1]) * g.n[0] + p[0];
+    double q[6];
+    cons_to_prim(g, U, c, q);
+    double s = w * (A / area) * 2.0 * (q[QP] - pref) * (g.gamma - 1.0);
+    // p = (gamma-1)(E - |m|^2/(2 rho)): dp/drho = (gamma-1)|u|^2/2,
+    // dp/dm_i = -(gamma-1) u_i, dp/dE = gamma-1
+    double ke = 0.5 * (q[QU] * q[QU] + q[QV] * q[QV] + q[QW] * q[QW]);
+    grad[c] += s * ke;
+    grad[nc + c] -= s * q[QU];
+    if (nd >= 2) grad[2 * nc + c] -= s * q[QV];
+    if (nd >= 3) grad[3 * nc + c] -= s * q[QW];
+    grad[(long)(nd + 1) * nc + c] += s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Template instantiation table for the flux kernels.
+// ---------------------------------------------------------------------------
+using FluxKernel = void (*)(Dev);
+
+FluxKernel flux_kernel(int ndim, int D, bool visc) {
+#define DCF_FK(N, DD)                                               \
+  if (ndim == N && D == DD) return visc ? (FluxKernel)k_flux<N, DD, true> \
+                                         : (FluxKernel)k_flux<N, DD, false>;
+  DCF_FK(1, 0)
+  DCF_FK(2, 0)
+  DCF_FK(2, 1)
+  DCF_FK(3, 0)
+  DCF_FK(3, 1)
+  DCF_FK(3, 2)
+#undef DCF_FK
+  return nullptr;
+}
+
+}  // namespace dcf
+
+// ---------------------------------------------------------------------------
+// Small elementwise helpers (fills and copies as kernels, so that a captured
+// graph holds no memset or memcpy nodes).
+// ---------------------------------------------------------------------------
+namespace dcf {
+
+__global__ void k_fill(double *p, double v, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_copy(double *dst, const double *src, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+__global__ void k_axpy(double *y, double a, const double *x, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+
+static inline unsigned grid_for(long n, int bs = 256) {
+  long b = (n + bs - 1) / bs;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+static inline unsigned grid_capped(long n, int cap) {
+  long b = (n + 255) / 256;
+  if (b > cap) b = cap;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_fill(double *p, double v, long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_fill<<<grid_capped(n, 4096), 256, 0, st>>>(p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_copy(double *dst, const double *src, long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_copy<<<grid_capped(n, 4096), 256, 0, st>>>(dst, src, n);
+  return hipGetLastError();
+}
+hipError_t launch_axpy(double *y, double a, const double *x, long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_axpy<<<grid_capped(n, 4096), 256, 0, st>>>(y, a, x, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_metrics(int kind, double lo, double hi, double beta, int n, double *dx,
+                          double *idx, double *mc, double *mf, hipStream_t st) {
+  k_metrics<<<grid_for(n + 1), 256, 0, st>>>(kind, lo, hi, beta, n, dx, idx, mc, mf);
+  return hipGetLastError();
+}
+hipError_t launch_init_state(const Dev &g, const double *P, double *U, hipStream_t st) {
+  k_init_state<<<grid_for(g.ncell), 256, 0, st>>>(g, P, U);
+  return hipGetLastError();
+}
+hipError_t launch_prim_halo(const Dev &g, const double *U, hipStream_t st) {
+  k_prim_halo<<<grid_for(g.nbox), 256, 0, st>>>(g, U);
+  return hipGetLastError();
+}
+hipError_t launch_flux_dir(const Dev &g, int D, hipStream_t st) {
+  FluxKernel k = flux_kernel(g.ndim, D, g.visc != VISC_NONE);
+  if (!k) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k, dim3(grid_for(g.fcount[D])), dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+hipError_t launch_fluxes(const Dev &g, hipStream_t st) {
+  for (int D = 0; D < g.ndim; ++D) {
+    hipError_t e = launch_flux_dir(g, D, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+hipError_t launch_force(const Dev &g, double *part, double *force, hipStream_t st) {
+  unsigned nb = grid_capped(g.ncell, RED_BLOCKS);
+  k_force_partial<<<nb, 256, 0, st>>>(g, part);
+  k_force_final<<<1, 256, 0, st>>>(part, (int)nb, force);
+  return hipGetLastError();
+}
+hipError_t launch_update(const Dev &g, const double *Un, const double *Uin, double *Uout,
+                         double *Rout, const double *dt, double a, double b,
+                         const double *force, hipStream_t st) {
+  k_update<<<grid_for(g.ncell), 256, 0, st>>>(g, Un, Uin, Uout, Rout, dt, a, b, force);
+  return hipGetLastError();
+}
+hipError_t launch_dt(const Dev &g, const double *U, double cfl, double dt_max, double *part,
+                     double *dt, hipStream_t st) {
+  unsigned nb = grid_capped(g.ncell, RED_BLOCKS);
+  k_dt_partial<<<nb, 256, 0, st>>>(g, U, part);
+  k_dt_final<<<1, 256, 0, st>>>(part, (int)nb, cfl, dt_max, dt);
+  return hipGetLastError();
+}
+hipError_t launch_diag(const Dev &g, const double *U, double *part, double *out,
+                       hipStream_t st) {
+  unsigned nb = grid_capped(g.ncell, RED_BLOCKS);
+  k_diag_partial<<<nb, 256, 0, st>>>(g, U, part);
+  k_diag_final<<<1, 256, 0, st>>>(part, (int)nb, out);
+  return hipGetLastError();
+}
+hipError_t launch_cost(const Dev &g, int face, double pref, const double *U, double w,
+                       double *J, double *grad, hipStream_t st) {
+  k_cost<<<1, 256, 0, st>>>(g, face, pref, U, w, J, grad);
+  return hipGetLastError();
+}
+
+}  // namespace dcf

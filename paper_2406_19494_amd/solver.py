@@ -1,0 +1,194 @@
+"""Python front end of the HIP library: one ``Solver`` per case.
+
+PyTorch provides device memory and the stream; every computation runs in the
+library's HIP kernels behind the C ABI (include/dcf.h).  The methods here
+only marshal arguments.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import binding as B
+from .workloads import Case
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class Solver:
+    """A solve on the GPU.
+
+    mode: 0 forward, 1 forward + single-step VJP, 2 trajectory gradient with
+    ``nsteps`` steps and checkpoints every ``seg_len`` steps.
+    """
+
+    def __init__(self, case: Case, K=None, mode: int = 0, nsteps: int = 0, seg_len: int = 0,
+                 device: str = "cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the dcf library needs a GPU (no CPU fallback)")
+        self.case = case
+        self.device = torch.device(device)
+        L = B.lib()
+        g = B.dcf_grid()
+        g.ndim = case.ndim
+        for d in range(3):
+            g.n[d] = case.n[d]
+            g.lo[d] = case.lo[d]
+            g.hi[d] = case.hi[d]
+            g.stretch[d] = B.STRETCH[case.stretch[d]]
+            g.beta[d] = case.beta[d]
+        gas = B.dcf_gas(case.gamma, case.R, case.Pr, B.VISC[case.visc_law], case.mu_ref,
+                        case.T_ref, case.visc_param)
+        ctx = C.c_void_p()
+        B.call("dcf_create", C.byref(g), C.byref(gas), C.byref(ctx))
+        self.ctx = ctx
+        self._keep = []
+        for f in range(2 * case.ndim):
+            bc = B.dcf_bc()
+            bc.kind = B.BC[case.bc[f]]
+            bc.T_wall = case.T_wall[f]
+            if f in case.dirichlet:
+                prof = torch.as_tensor(np.ascontiguousarray(case.dirichlet[f]), dtype=torch.float64,
+                                       device=self.device)
+                self._keep.append(prof)
+                bc.dirichlet = prof.data_ptr()
+            if case.bc[f] == "porous":
+                bc.porous_begin, bc.porous_end, bc.p_inf = (case.porous_begin, case.porous_end,
+                                                            case.p_inf)
+            B.call("dcf_set_bc", ctx, f, C.byref(bc))
+        B.call("dcf_set_source", ctx, B.SOURCE[case.source])
+        if case.cost_face >= 0:
+            B.call("dcf_set_cost", ctx, case.cost_face, case.p_inf)
+        self.nk = L.dcf_num_params(ctx)
+        self.K = None
+        if self.nk:
+            Kt = torch.zeros(self.nk, dtype=torch.float64, device=self.device) if K is None else \
+                torch.as_tensor(np.asarray(K), dtype=torch.float64, device=self.device).contiguous()
+            self.set_params(Kt)
+        self.mode, self.nsteps, self.seg_len = mode, nsteps, seg_len
+        size = C.c_size_t()
+        B.call("dcf_workspace_size", ctx, mode, nsteps, seg_len, C.byref(size))
+        self.workspace = torch.empty(size.value, dtype=torch.uint8, device=self.device)
+        B.call("dcf_set_workspace", ctx, mode, nsteps, seg_len, _ptr(self.workspace), size.value)
+        nv, ncell, nbytes = C.c_int(), C.c_long(), C.c_size_t()
+        B.call("dcf_state_info", ctx, C.byref(nv), C.byref(ncell), C.byref(nbytes))
+        self.nv, self.ncell = nv.value, ncell.value
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            try:
+                B.lib().dcf_destroy(ctx)
+            except Exception:
+                pass
+            self.ctx = None
+
+    # ---------------------------------------------------------------- state
+    @property
+    def shape(self):
+        c = self.case
+        return (c.nv, c.n[2], c.n[1], c.n[0])
+
+    def empty_state(self):
+        return torch.empty(self.shape, dtype=torch.float64, device=self.device)
+
+    def set_params(self, K: torch.Tensor):
+        K = K.to(device=self.device, dtype=torch.float64).contiguous()
+        self.K = K
+        B.call("dcf_set_params", self.ctx, _ptr(K), int(K.numel()))
+
+    def init_state(self, P, stream=None) -> torch.Tensor:
+        Pt = torch.as_tensor(np.ascontiguousarray(P), dtype=torch.float64, device=self.device)
+        U = self.empty_state()
+        B.call("dcf_init_state", self.ctx, _ptr(Pt), _ptr(U), _stream(stream))
+        return U
+
+    # -------------------------------------------------------------- forward
+    def rhs(self, U: torch.Tensor, stream=None) -> torch.Tensor:
+        R = torch.empty_like(U)
+        B.call("dcf_rhs", self.ctx, _ptr(U), _ptr(R), _stream(stream))
+        return R
+
+    def compute_dt(self, U, cfl=None, dt_max=0.0, out=None, stream=None) -> torch.Tensor:
+        dt = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        B.call("dcf_compute_dt", self.ctx, _ptr(U), float(self.case.cfl if cfl is None else cfl),
+               float(dt_max), _ptr(dt), _stream(stream))
+        return dt
+
+    def step(self, U: torch.Tensor, dt: torch.Tensor, stream=None):
+        B.call("dcf_rk3_step", self.ctx, _ptr(U), _ptr(dt), _stream(stream))
+
+    def run(self, U: torch.Tensor, nsteps: int, dt_fixed: float = 0.0, t_end: float = 0.0,
+            cfl=None):
+        """Advance U in place.  With dt_fixed > 0 the step is fixed; otherwise
+        the CFL step is computed on the device each step (t_end > 0 clips the
+        last step, which reads the step size back to the host)."""
+        dt = torch.empty(1, dtype=torch.float64, device=self.device)
+        t = 0.0
+        steps = 0
+        if dt_fixed > 0.0:
+            dt.fill_(dt_fixed)
+            for _ in range(nsteps):
+                self.step(U, dt)
+            return nsteps, dt_fixed * nsteps
+        while steps < nsteps:
+            if t_end > 0.0 and t >= t_end:
+                break
+            self.compute_dt(U, cfl=cfl, dt_max=(t_end - t) if t_end > 0.0 else 0.0, out=dt)
+            if t_end > 0.0:
+                t += float(dt.item())
+            self.step(U, dt)
+            steps += 1
+        return steps, t
+
+    def diagnostics(self, U: torch.Tensor, stream=None) -> dict:
+        out = torch.empty(8, dtype=torch.float64, device=self.device)
+        B.call("dcf_diagnostics", self.ctx, _ptr(U), _ptr(out), _stream(stream))
+        o = out.cpu().numpy()
+        return dict(ek=o[0], eps=o[1], mass=o[2], mom=o[3:6].copy(), energy=o[6], vol=o[7])
+
+    def time_kernel(self, U, which: int, reps: int = 20, stream=None) -> float:
+        """Mean duration (ms) of one kernel family, timed with HIP events."""
+        ms = C.c_double()
+        B.call("dcf_time_kernel", self.ctx, _ptr(U), int(which), int(reps), C.byref(ms),
+               _stream(stream))
+        return ms.value
+
+    def flags(self, stream=None) -> int:
+        f = C.c_uint()
+        B.call("dcf_flags", self.ctx, C.byref(f), _stream(stream))
+        return f.value
+
+    # -------------------------------------------------------------- adjoint
+    def cost_term(self, U, w=1.0, J=None, grad=None, stream=None):
+        J = torch.zeros(1, dtype=torch.float64, device=self.device) if J is None else J
+        B.call("dcf_cost_term", self.ctx, _ptr(U), float(w), _ptr(J), _ptr(grad), _stream(stream))
+        return J
+
+    def vjp_step(self, Un, dt, lam, dJdK=None, stream=None) -> torch.Tensor:
+        out = torch.empty_like(lam)
+        B.call("dcf_vjp_step", self.ctx, _ptr(Un), _ptr(dt), _ptr(lam), _ptr(out), _ptr(dJdK),
+               _stream(stream))
+        return out
+
+    def gradient(self, U0, dt, stream=None):
+        """J, dJ/dK, dJ/dU0 over the trajectory sized at construction."""
+        J = torch.zeros(1, dtype=torch.float64, device=self.device)
+        gK = torch.zeros(max(self.nk, 1), dtype=torch.float64, device=self.device)
+        gU = torch.empty_like(U0)
+        B.call("dcf_gradient", self.ctx, _ptr(U0), int(self.nsteps), _ptr(dt), int(self.seg_len),
+               _ptr(J), _ptr(gK) if self.nk else None, _ptr(gU), _stream(stream))
+        return J, gK[: self.nk], gU

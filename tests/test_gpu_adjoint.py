@@ -1,0 +1,144 @@
+"""GPU adjoint parity: the hand-written VJP of one RK3 step and the
+checkpointed trajectory gradient against the oracle's dense-Jacobian adjoint,
+its forward-mode JVP (dot-product test) and finite differences."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.pyoracle import Oracle
+from paper_2406_19494_amd import workloads as W
+from paper_2406_19494_amd.solver import Solver
+from tests.test_oracle_pins import _tiny_porous
+
+pytestmark = pytest.mark.gpu
+
+VJP_TOL = 1e-10
+
+
+def adjoint_cases():
+    out = []
+    c, P = W.sod(24)
+    out.append(("sod1d", c, P, None, 2e-3))
+    c = W.Case(name="p1d", ndim=1, n=(16, 1, 1), lo=(0, 0, 0), hi=(2, 1, 1), gamma=1.4, R=1.3,
+               Pr=0.7, visc_law="power", mu_ref=0.01, T_ref=1.0, visc_param=0.7,
+               bc=("periodic",) * 6)
+    out.append(("periodic1d_visc", c, W.random_smooth(c, seed=3, amp=0.2), None, 1e-3))
+    c = W.Case(name="w2d", ndim=2, n=(10, 9, 1), lo=(0, -1, 0), hi=(1.5, 1, 1),
+               stretch=("uniform", "tanh2", "uniform"), beta=(0, 1.8, 0), gamma=1.4, R=1.0,
+               Pr=0.72, visc_law="sutherland", mu_ref=0.02, T_ref=1.0, visc_param=0.4,
+               bc=("periodic", "periodic", "wall", "wall", "periodic", "periodic"),
+               T_wall=(0, 0, 1.2, 0.9, 0, 0))
+    out.append(("wall2d_visc", c, W.random_smooth(c, seed=4, amp=0.2), None, 5e-4))
+    case, P, K = _tiny_porous()
+    out.append(("porous_bl2d", case, P, K, 1e-3))
+    c, P = W.tgv(6)
+    out.append(("tgv3d", c, P, None, 1e-2))
+    c = W.Case(name="mix3d", ndim=3, n=(7, 6, 5), lo=(0, 0, 0), hi=(1, 1, 1),
+               stretch=("tanh1", "uniform", "uniform"), beta=(1.5, 0, 0), gamma=1.4, R=1.0,
+               Pr=0.7, visc_law="power", mu_ref=0.005, T_ref=1.0, visc_param=0.7,
+               bc=("zerograd", "zerograd", "wall", "wall", "periodic", "periodic"),
+               T_wall=(0, 0, 1.0, 1.0, 0, 0))
+    out.append(("mixed3d_visc", c, W.random_smooth(c, seed=9, amp=0.2), None, 1e-3))
+    return out
+
+
+CASES = adjoint_cases()
+
+
+@pytest.mark.parametrize("name,case,P,K,dt", CASES, ids=[c[0] for c in CASES])
+def test_vjp_step_matches_dense_oracle_adjoint(name, case, P, K, dt):
+    print(f"[vjp parity] {name} n={case.n}", flush=True)
+    o = Oracle(case, K=K)
+    s = Solver(case, K=K, mode=1)
+    U = o.cons(P)
+    rng = np.random.default_rng(11)
+    lam = rng.normal(size=U.shape)
+    lu_or, lk_or = o.vjp_step(U, lam, dt)
+    Ug = torch.as_tensor(U, device="cuda")
+    dtg = torch.full((1,), dt, dtype=torch.float64, device="cuda")
+    gK = torch.zeros(max(s.nk, 1), dtype=torch.float64, device="cuda")
+    lu = s.vjp_step(Ug, dtg, torch.as_tensor(lam, device="cuda"),
+                    dJdK=gK if s.nk else None).cpu().numpy()
+    scale = np.abs(lu_or).max(axis=(1, 2, 3))
+    err = np.abs(lu - lu_or).max(axis=(1, 2, 3)) / scale
+    assert np.all(err <= VJP_TOL), (name, err)
+    if s.nk:
+        gk = gK.cpu().numpy()[: s.nk]
+        assert np.abs(gk - lk_or).max() <= VJP_TOL * np.abs(lk_or).max(), (gk, lk_or)
+
+
+@pytest.mark.parametrize("name,case,P,K,dt", CASES[3:4], ids=[CASES[3][0]])
+def test_dot_product_gpu_vjp_vs_oracle_jvp(name, case, P, K, dt):
+    o = Oracle(case, K=K)
+    s = Solver(case, K=K, mode=1)
+    U = o.cons(P)
+    rng = np.random.default_rng(12)
+    v = rng.normal(size=U.shape) * np.abs(U).max(axis=(1, 2, 3), keepdims=True)
+    vk = rng.normal(size=o.nk)
+    lam = rng.normal(size=U.shape)
+    _, jv = o.jvp_step(U, v, dt, vk)
+    gK = torch.zeros(s.nk, dtype=torch.float64, device="cuda")
+    lu = s.vjp_step(torch.as_tensor(U, device="cuda"),
+                    torch.full((1,), dt, dtype=torch.float64, device="cuda"),
+                    torch.as_tensor(lam, device="cuda"), dJdK=gK).cpu().numpy()
+    lhs = np.sum(lam * jv)
+    rhs = np.sum(lu * v) + np.sum(gK.cpu().numpy() * vk)
+    assert abs(lhs - rhs) <= 1e-10 * max(abs(lhs), np.sum(np.abs(lam * jv))), (lhs, rhs)
+
+
+def test_trajectory_gradient_matches_oracle():
+    case, P, K = _tiny_porous()
+    o = Oracle(case, K=K)
+    U0 = o.cons(P)
+    dt, nsteps = 1e-3, 5
+    J_or, gk_or, gu_or = o.gradient(U0, nsteps, dt)
+    for seg in (2, 5):
+        s = Solver(case, K=K, mode=2, nsteps=nsteps, seg_len=seg)
+        J, gk, gu = s.gradient(torch.as_tensor(U0, device="cuda"),
+                               torch.full((1,), dt, dtype=torch.float64, device="cuda"))
+        assert abs(J.item() - J_or) <= 1e-12 * abs(J_or)
+        gk = gk.cpu().numpy()
+        assert np.abs(gk - gk_or).max() <= VJP_TOL * np.abs(gk_or).max(), (seg, gk, gk_or)
+        gu = gu.cpu().numpy()
+        err = np.abs(gu - gu_or).max(axis=(1, 2, 3)) / np.abs(gu_or).max(axis=(1, 2, 3))
+        assert np.all(err <= VJP_TOL), (seg, err)
+
+
+def test_gradient_matches_gpu_finite_differences_full_bl():
+    """Mach-6 porous boundary layer at full size (1024 x 256), 2000-step
+    checkpointed trajectory; dJ/dK_i against central differences of the GPU
+    forward on 8 seeded K_i."""
+    case, P, K = W.porous_bl()
+    s0 = Solver(case, K=K)
+    U0 = s0.init_state(P)
+    dt = 0.5 * s0.compute_dt(U0, cfl=1.0).item()
+    nsteps, seg = 2000, 45
+    dtg = torch.full((1,), dt, dtype=torch.float64, device="cuda")
+    s = Solver(case, K=K, mode=2, nsteps=nsteps, seg_len=seg)
+    J, gk, _ = s.gradient(U0, dtg)
+    gk = gk.cpu().numpy()
+    print(f"[bl gradient] J={J.item():.6e} |g|max={np.abs(gk).max():.3e} dt={dt:.3e}", flush=True)
+
+    def J_of(Kp):
+        sf = Solver(case, K=Kp, mode=0)
+        U = U0.clone()
+        Jt = torch.zeros(1, dtype=torch.float64, device="cuda")
+        for _ in range(nsteps):
+            sf.step(U, dtg)
+            sf.cost_term(U, w=1.0 / nsteps, J=Jt)
+        return Jt.item()
+
+    assert abs(J_of(K) - J.item()) <= 1e-13 * abs(J.item())
+    # J ~ 1e-14 is a sum of (p - p_inf)^2 with p - p_inf ~ 1e-5 p_inf, so J
+    # carries ~1e-11 relative round-off; the step h = 0.02 keeps the
+    # finite-difference round-off near 1e-7 of the derivative, and J is close
+    # to quadratic in K (central differences are exact for quadratics).
+    rng = np.random.default_rng(5)
+    idx = rng.choice(case.nk, size=8, replace=False)
+    for i in idx:
+        h = 0.02
+        e = np.zeros_like(K)
+        e[i] = h
+        fd = (J_of(K + e) - J_of(K - e)) / (2 * h)
+        print(f"[bl fd] i={i} fd={fd:.10e} adj={gk[i]:.10e}", flush=True)
+        assert abs(fd - gk[i]) <= 1e-6 * np.abs(gk).max(), (i, fd, gk[i])
