@@ -67,6 +67,39 @@ def cpu_baseline(case, P, K, budget_s):
                       f"workload ({el:.1f} s, OpenMP threads={threads})"}
 
 
+def adjoint_ratio(steps=20):
+    """Adjoint/forward cost on the Mach-6 porous boundary layer (1024 x 256):
+    per step, t(vjp_step incl. stage recompute) / t(rk3_step), HIP events."""
+    import torch
+    from paper_2406_19494_amd import workloads as W
+    from paper_2406_19494_amd.solver import Solver
+    case, P, K = W.porous_bl()
+    s = Solver(case, K=K, mode=1)
+    U = s.init_state(P)
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    s.compute_dt(U, cfl=0.5, out=dt)
+    lam = torch.ones_like(U)
+    gK = torch.zeros(s.nk, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        s.step(U, dt)
+        s.vjp_step(U, dt, lam, dJdK=gK)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for _ in range(steps):
+        s.step(U, dt)
+    ev[1].record(stream)
+    for _ in range(steps):
+        s.vjp_step(U, dt, lam, dJdK=gK)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    f = ev[0].elapsed_time(ev[1]) / steps
+    a = ev[1].elapsed_time(ev[2]) / steps
+    return {"workload": "Mach-6 porous boundary layer 1024x256", "forward_ms_per_step": f,
+            "vjp_ms_per_step": a, "adjoint_forward_ratio": a / f}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,7 +108,20 @@ def main():
     ap.add_argument("--workload", default="tgv64")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 512 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = 512 * 1024 * 1024 // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
               "(the multi-GPU block decomposition is designed, not built)", file=sys.stderr)
@@ -113,9 +159,13 @@ def main():
     value = case.ncells * 3 / (ms_step * 1e-3)
 
     # per-kernel timing (HIP events on the same stream) -> dominant kernel
-    names = {0: "k_prim_halo", 1: "k_flux<x>", 2: "k_flux<y>", 3: "k_flux<z>", 4: "k_update"}
+    names = {0: "k_prim_halo", 1: "k_flux_x", 2: "k_flux_yz<y>", 3: "k_flux_yz<z>", 4: "k_update",
+             5: "k_grad"}
     kt = {}
-    for w in [0] + list(range(1, case.ndim + 1)) + [4]:
+    kinds = [0] + list(range(1, case.ndim + 1)) + [4]
+    if case.visc_law != "none" and case.ndim >= 2:
+        kinds.append(5)
+    for w in kinds:
         kt[w] = s.time_kernel(U, w, reps=20)
     dom = max(kt, key=lambda k: kt[k])
     visc = case.visc_law != "none"
@@ -154,6 +204,8 @@ def main():
         "kernel_ms": {names[k]: v for k, v in kt.items()},
         "wall_s": wall,
     }
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_ratio()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, P, K, args.cpu_budget)
     print(json.dumps(out), flush=True)

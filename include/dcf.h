@@ -193,6 +193,20 @@ dcf_status dcf_gradient(dcf_ctx *ctx, const double *U0_dev, int nsteps, const do
 dcf_status dcf_time_kernel(dcf_ctx *ctx, const double *U_dev, int which, int reps,
                            double *avg_ms, void *stream);
 
+/* Incremental form of dcf_gradient, for schedulers that interleave many
+ * solves: begin validates and records the request (same arguments as
+ * dcf_gradient, J and dJdK zeroed on `stream`); advance enqueues at most
+ * max_units units of work -- a forward step with its checkpoint and cost
+ * term, a recomputed step of the current segment, or one reverse step -- and
+ * sets *done once the reverse sweep has reached U0; finish copies dJ/dU0
+ * (nullable).  Between calls nothing is read back; the host keeps only the
+ * position in the trajectory. */
+dcf_status dcf_gradient_begin(dcf_ctx *ctx, const double *U0_dev, int nsteps,
+                              const double *dt_dev, int seg_len, double *J_dev, double *dJdK_dev,
+                              void *stream);
+dcf_status dcf_gradient_advance(dcf_ctx *ctx, int max_units, int *done, void *stream);
+dcf_status dcf_gradient_finish(dcf_ctx *ctx, double *dJdU0_dev, void *stream);
+
 /* ---- status ------------------------------------------------------------- */
 /* Synchronises `stream`, returns and clears the kernel flags (DCF_FLAG_*). */
 dcf_status dcf_flags(dcf_ctx *ctx, unsigned *flags_host, void *stream);

@@ -62,6 +62,9 @@ _SIGS = {
     "dcf_vjp_step": [_vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "dcf_cost_term": [_vp, _vp, C.c_double, _vp, _vp, _vp],
     "dcf_gradient": [_vp, _vp, C.c_int, _vp, C.c_int, _vp, _vp, _vp, _vp],
+    "dcf_gradient_begin": [_vp, _vp, C.c_int, _vp, C.c_int, _vp, _vp, _vp],
+    "dcf_gradient_advance": [_vp, C.c_int, C.POINTER(C.c_int), _vp],
+    "dcf_gradient_finish": [_vp, _vp, _vp],
     "dcf_flags": [_vp, C.POINTER(C.c_uint), _vp],
     "dcf_time_kernel": [_vp, _vp, C.c_int, C.c_int, C.POINTER(C.c_double), _vp],
 }

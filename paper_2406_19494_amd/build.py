@@ -21,6 +21,9 @@ ARCH = "gfx950"
 FLAGS = [
     "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # contract a*b+c only within one source expression, so that kernels that
+    # share the per-face code round identically
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     "-I", os.path.join(ROOT, "include"),
 ]

@@ -67,6 +67,17 @@ struct dcf_ctx {
   double *ckpt = nullptr;  // gradient checkpoints
   double *seg = nullptr;   // per-segment recomputed states
   double *lam_a = nullptr, *lam_b = nullptr, *gbuf = nullptr, *zero_dt = nullptr;
+  // incremental gradient state (dcf_gradient_begin / advance / finish)
+  struct {
+    bool active = false;
+    int phase = 0;   // 0 forward sweep, 1 segment recompute, 2 reverse steps, 3 done
+    int n = 0;       // forward: steps taken; recompute: step within segment; reverse: step index
+    int sgi = 0;     // current segment (reverse)
+    int nsteps = 0, seg_len = 0;
+    const double *dt = nullptr;
+    double *J = nullptr, *dJdK = nullptr;
+    double *lam = nullptr, *lam_prev = nullptr;
+  } gr;
 };
 
 extern "C" {
@@ -193,6 +204,9 @@ static size_t carve(dcf_ctx *c, void *base, int mode, int nsteps, int seg_len) {
   const long nbox = g.nbox, ncell = g.ncell, nv = g.nv;
   for (int q = 0; q < NQ; ++q) g.Q[q] = cv.take<double>(nbox);
   for (int D = 0; D < 3; ++D) g.F[D] = D < g.ndim ? cv.take<double>(5 * g.fcount[D]) : nullptr;
+  const bool need_g = g.visc != VISC_NONE && g.ndim >= 2;
+  for (int q = 0; q < 9; ++q)
+    g.G[q] = (need_g && q / 3 < g.ndim && q % 3 < g.ndim) ? cv.take<double>(nbox) : nullptr;
   c->U1 = cv.take<double>(nv * ncell);
   c->U2 = cv.take<double>(nv * ncell);
   c->part = cv.take<double>(8 * RED_BLOCKS);
@@ -431,8 +445,8 @@ dcf_status dcf_vjp_step(dcf_ctx *c, const double *Un, const double *dt, const do
              : DCF_OK;
 }
 
-dcf_status dcf_gradient(dcf_ctx *c, const double *U0, int nsteps, const double *dt, int seg_len,
-                        double *J, double *dJdK, double *dJdU0, void *stream) {
+dcf_status dcf_gradient_begin(dcf_ctx *c, const double *U0, int nsteps, const double *dt,
+                              int seg_len, double *J, double *dJdK, void *stream) {
   dcf_status s = ready(c, 2);
   if (s) return s;
   if (c->ws_nsteps != nsteps || c->ws_seg != seg_len)
@@ -443,48 +457,111 @@ dcf_status dcf_gradient(dcf_ctx *c, const double *U0, int nsteps, const double *
   if (c->g.source != SRC_NONE)
     return fail(DCF_EUNSUPPORTED, "adjoint of the mass-flux source is not implemented");
   hipStream_t st = (hipStream_t)stream;
+  const long M = (long)c->g.nv * c->g.ncell;
+  auto &gr = c->gr;
+  gr = {};
+  gr.active = true;
+  gr.nsteps = nsteps;
+  gr.seg_len = seg_len;
+  gr.dt = dt;
+  gr.J = J;
+  gr.dJdK = c->nK > 0 ? dJdK : nullptr;
+  gr.lam = c->lam_a;
+  gr.lam_prev = c->lam_b;
+  DCF_HIP(launch_fill(J, 0.0, 1, st));
+  if (gr.dJdK) DCF_HIP(launch_fill(gr.dJdK, 0.0, c->nK, st));
+  DCF_HIP(launch_copy(c->seg, U0, M, st));  // running state of the forward sweep
+  return DCF_OK;
+}
+
+// One unit of gradient work: a forward step (with checkpoint and cost), a
+// recomputed step of the current segment, or a reverse step.
+static dcf_status gradient_unit(dcf_ctx *c, hipStream_t st) {
+  auto &gr = c->gr;
   Dev &g = c->g;
   const long M = (long)g.nv * g.ncell;
-  const int nseg = (nsteps + seg_len - 1) / seg_len;
-  const double w = 1.0 / nsteps;
-  // forward sweep: checkpoints at segment starts, cost accumulation
-  DCF_HIP(launch_fill(J, 0.0, 1, st));
-  double *U = c->seg;  // running state
-  DCF_HIP(launch_copy(U, U0, M, st));
-  for (int n = 0; n < nsteps; ++n) {
-    if (n % seg_len == 0) DCF_HIP(launch_copy(c->ckpt + (long)(n / seg_len) * M, U, M, st));
-    if ((s = rk3_stages(c, U, dt, st))) return s;
-    DCF_HIP(launch_cost(g, c->cost_face, c->cost_pref, U, w, J, nullptr, st));
-  }
-  // reverse sweep
-  double *lam = c->lam_a, *lam_prev = c->lam_b;
-  DCF_HIP(launch_fill(lam, 0.0, M, st));
-  if (dJdK && c->nK > 0) DCF_HIP(launch_fill(dJdK, 0.0, c->nK, st));
-  for (int sgi = nseg - 1; sgi >= 0; --sgi) {
-    int n0 = sgi * seg_len;
-    int n1 = n0 + seg_len < nsteps ? n0 + seg_len : nsteps;
-    // recompute states U^{n0} .. U^{n1} of this segment
-    DCF_HIP(launch_copy(c->seg, c->ckpt + (long)sgi * M, M, st));
-    for (int n = n0; n < n1; ++n) {
-      double *Ua = c->seg + (long)(n - n0) * M, *Ub = Ua + M;
-      DCF_HIP(launch_copy(Ub, Ua, M, st));
-      if ((s = rk3_stages(c, Ub, dt, st))) return s;
+  const double w = 1.0 / gr.nsteps;
+  const int nseg = (gr.nsteps + gr.seg_len - 1) / gr.seg_len;
+  dcf_status s;
+  if (gr.phase == 0) {  // forward sweep
+    if (gr.n % gr.seg_len == 0)
+      DCF_HIP(launch_copy(c->ckpt + (long)(gr.n / gr.seg_len) * M, c->seg, M, st));
+    if ((s = rk3_stages(c, c->seg, gr.dt, st))) return s;
+    DCF_HIP(launch_cost(g, c->cost_face, c->cost_pref, c->seg, w, gr.J, nullptr, st));
+    if (++gr.n == gr.nsteps) {
+      gr.phase = 1;
+      gr.sgi = nseg - 1;
+      gr.n = 0;
+      DCF_HIP(launch_fill(gr.lam, 0.0, M, st));
+      DCF_HIP(launch_copy(c->seg, c->ckpt + (long)gr.sgi * M, M, st));
     }
-    for (int n = n1; n > n0; --n) {
-      // lam holds dJ/dU^n from later steps; add the cost term of U^n
-      const double *Ucur = c->seg + (long)(n - n0) * M;
-      DCF_HIP(launch_cost(g, c->cost_face, c->cost_pref, Ucur, w, c->force + 2,
-                          lam, st));
-      const double *Uprev = c->seg + (long)(n - 1 - n0) * M;
-      if (vjp_step(g, c->adj, Uprev, c->U1, c->U2, dt, lam, lam_prev, dJdK, st))
-        return fail(DCF_EDEVICE, "vjp launch failed");
-      double *t = lam;
-      lam = lam_prev;
-      lam_prev = t;
-    }
+    return DCF_OK;
   }
-  if (dJdU0) DCF_HIP(launch_copy(dJdU0, lam, M, st));
+  const int n0 = gr.sgi * gr.seg_len;
+  const int n1 = n0 + gr.seg_len < gr.nsteps ? n0 + gr.seg_len : gr.nsteps;
+  if (gr.phase == 1) {  // recompute U^{n0+1} .. U^{n1} of the segment
+    double *Ua = c->seg + (long)gr.n * M, *Ub = Ua + M;
+    DCF_HIP(launch_copy(Ub, Ua, M, st));
+    if ((s = rk3_stages(c, Ub, gr.dt, st))) return s;
+    if (++gr.n == n1 - n0) {
+      gr.phase = 2;
+      gr.n = n1;
+    }
+    return DCF_OK;
+  }
+  if (gr.phase == 2) {  // reverse step n -> n-1
+    const int n = gr.n;
+    const double *Ucur = c->seg + (long)(n - n0) * M;
+    DCF_HIP(launch_cost(g, c->cost_face, c->cost_pref, Ucur, w, c->force + 2, gr.lam, st));
+    const double *Uprev = c->seg + (long)(n - 1 - n0) * M;
+    if (vjp_step(g, c->adj, Uprev, c->U1, c->U2, gr.dt, gr.lam, gr.lam_prev, gr.dJdK, st))
+      return fail(DCF_EDEVICE, "vjp launch failed");
+    double *t = gr.lam;
+    gr.lam = gr.lam_prev;
+    gr.lam_prev = t;
+    gr.n = n - 1;
+    if (gr.n == n0) {
+      if (gr.sgi == 0) {
+        gr.phase = 3;
+      } else {
+        gr.sgi -= 1;
+        gr.phase = 1;
+        gr.n = 0;
+        DCF_HIP(launch_copy(c->seg, c->ckpt + (long)gr.sgi * M, M, st));
+      }
+    }
+    return DCF_OK;
+  }
   return DCF_OK;
+}
+
+dcf_status dcf_gradient_advance(dcf_ctx *c, int max_units, int *done, void *stream) {
+  if (!c || !done) return fail(DCF_EINVAL, "null argument");
+  if (!c->gr.active) return fail(DCF_EINVAL, "no gradient in progress (dcf_gradient_begin)");
+  hipStream_t st = (hipStream_t)stream;
+  dcf_status s;
+  for (int u = 0; u < max_units && c->gr.phase != 3; ++u)
+    if ((s = gradient_unit(c, st))) return s;
+  *done = c->gr.phase == 3 ? 1 : 0;
+  return DCF_OK;
+}
+
+dcf_status dcf_gradient_finish(dcf_ctx *c, double *dJdU0, void *stream) {
+  if (!c) return fail(DCF_EINVAL, "null context");
+  if (!c->gr.active || c->gr.phase != 3) return fail(DCF_EINVAL, "gradient not complete");
+  if (dJdU0)
+    DCF_HIP(launch_copy(dJdU0, c->gr.lam, (long)c->g.nv * c->g.ncell, (hipStream_t)stream));
+  c->gr.active = false;
+  return DCF_OK;
+}
+
+dcf_status dcf_gradient(dcf_ctx *c, const double *U0, int nsteps, const double *dt, int seg_len,
+                        double *J, double *dJdK, double *dJdU0, void *stream) {
+  dcf_status s = dcf_gradient_begin(c, U0, nsteps, dt, seg_len, J, dJdK, stream);
+  if (s) return s;
+  int done = 0;
+  if ((s = dcf_gradient_advance(c, 1 << 30, &done, stream))) return s;
+  return dcf_gradient_finish(c, dJdU0, stream);
 }
 
 dcf_status dcf_time_kernel(dcf_ctx *c, const double *U, int which, int reps, double *avg_ms,
@@ -492,7 +569,7 @@ dcf_status dcf_time_kernel(dcf_ctx *c, const double *U, int which, int reps, dou
   dcf_status s = ready(c, 0);
   if (s) return s;
   if (!U || !avg_ms || reps < 1) return fail(DCF_EINVAL, "bad argument");
-  if (which < 0 || which > 4 || (which >= 1 && which <= 3 && which > c->g.ndim))
+  if (which < 0 || which > 5 || (which >= 1 && which <= 3 && which > c->g.ndim))
     return fail(DCF_EINVAL, "unknown kernel %d", which);
   hipStream_t st = (hipStream_t)stream;
   Dev &g = c->g;
@@ -506,6 +583,7 @@ dcf_status dcf_time_kernel(dcf_ctx *c, const double *U, int which, int reps, dou
     hipError_t e = hipSuccess;
     if (which == 0) e = launch_prim_halo(g, U, st);
     else if (which <= 3) e = launch_flux_dir(g, which - 1, st);
+    else if (which == 5) e = launch_grad(g, st);
     else e = launch_update(g, U, U, c->U1, nullptr, c->U2, 0.0, 1.0, c->force, st);
     if (e != hipSuccess) return fail(DCF_EDEVICE, "launch: %s", hipGetErrorString(e));
   }

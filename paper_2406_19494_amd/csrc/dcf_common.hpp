@@ -49,6 +49,7 @@ struct Dev {
   int source;
   // workspace
   double *Q[NQ];         // primitive box arrays
+  double *G[9];          // cell-centred velocity derivatives d u_phi/d x_t, index 3 t + phi
   double *F[3];          // face fluxes per direction, 5 components each
   long fcount[3];        // faces per direction (component stride of F)
   int fn[3][3];          // face-array extents per direction
@@ -150,6 +151,14 @@ __device__ __forceinline__ double dface4(double a, double b, double c, double d)
 }
 __device__ __forceinline__ double dcell4(double m2, double m1, double p1, double p2) {
   return (8.0 * (p1 - m1) - (p2 - m2)) * (1.0 / 12.0);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  This bijection of [0, nb) gives XCD x a contiguous range of logical
+// tile indices, so neighbouring tiles that share halo cells meet in one L2.
+__device__ __forceinline__ unsigned xcd_remap(unsigned L, unsigned nb) {
+  const unsigned x = L % 8u, i = L / 8u, per = nb / 8u, rem = nb % 8u;
+  return x < rem ? x * (per + 1u) + i : rem * (per + 1u) + (x - rem) * per + i;
 }
 
 __host__ __device__ __forceinline__ constexpr int tan1(int d) { return d == 0 ? 1 : 0; }

@@ -96,14 +96,33 @@ __device__ __forceinline__ int ghost_source(int kind, int side, int m, int n) {
   return side == 0 ? m : n - 1 - m;  // walls mirror
 }
 
-__global__ void k_prim_halo(Dev g, const double *U) {
-  long b = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= g.nbox) return;
+__global__ void __launch_bounds__(256) k_prim_halo(Dev g, const double *U) {
+  const unsigned b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= (unsigned)g.nbox) return;
   const int nd = g.ndim;
+  const unsigned N0 = g.N[0], N01 = (unsigned)g.N[0] * g.N[1];
   int p[3];
-  p[0] = (int)(b % g.N[0]) - g.h[0];
-  p[1] = (int)((b / g.N[0]) % g.N[1]) - g.h[1];
-  p[2] = (int)(b / ((long)g.N[0] * g.N[1])) - g.h[2];
+  p[2] = (int)(b / N01) - g.h[2];
+  const unsigned rr = b % N01;
+  p[1] = (int)(rr / N0) - g.h[1];
+  p[0] = (int)(rr % N0) - g.h[0];
+  if (p[0] >= 0 && p[0] < g.n[0] && p[1] >= 0 && p[1] < g.n[1] && p[2] >= 0 && p[2] < g.n[2]) {
+    // interior cell: primitives of its own conserved state
+    double q[6];
+    const long c = ((long)p[2] * g.n[1] + p[1]) * g.n[0] + p[0];
+    cons_to_prim(g, U, c, q);
+    if (!(finite_pos(q[QR]) && finite_pos(q[QP]))) atomicOr(g.flags, 1u);
+    g.Q[QR][b] = q[QR];
+    g.Q[QU][b] = q[QU];
+    if (nd >= 2) g.Q[QV][b] = q[QV];
+    if (nd >= 3) g.Q[QW][b] = q[QW];
+    g.Q[QP][b] = q[QP];
+    if (g.visc != VISC_NONE) {
+      g.Q[QT][b] = q[QT];
+      g.Q[QMU][b] = viscosity(g, q[QT]);
+    }
+    return;
+  }
   int s[3] = {p[0], p[1], p[2]};
   int side[3] = {0, 0, 0};
   bool gh[3] = {false, false, false};
@@ -142,9 +161,6 @@ __global__ void k_prim_halo(Dev g, const double *U) {
   } else {
     long c = ((long)s[2] * g.n[1] + s[1]) * g.n[0] + s[0];
     cons_to_prim(g, U, c, q);
-    if (!(gh[0] || gh[1] || gh[2])) {
-      if (!(finite_pos(q[QR]) && finite_pos(q[QP]))) atomicOr(g.flags, 1u);
-    }
   }
   for (int d = start; d < nd; ++d) {
     if (!gh[d]) continue;
@@ -192,83 +208,82 @@ __global__ void k_prim_halo(Dev g, const double *U) {
 }
 
 // ---------------------------------------------------------------------------
-// Face fluxes of direction D: F = F^c - F^d at every face of the interior
-// cells (Eq. (6)).  One thread per face; face f along D lies between cells
-// f-1 and f.  Stored in the global 5-component layout (mass, x/y/z momentum,
-// energy).
+// Cell-centred velocity derivatives d u_phi / d x_t (4th order, index space
+// times the analytic metric) on every cell that a face flux reads them from:
+// position along t interior, the other active positions within two layers.
+// G[3 t + phi] are box arrays.
 // ---------------------------------------------------------------------------
-template <int NDIM, int D, bool VISC>
-__global__ void __launch_bounds__(256) k_flux(Dev g) {
-  constexpr int T1 = tan1(D), T2 = tan2(D);
-  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.fcount[D]) return;
-  int pos[3];
-  pos[0] = (int)(t % g.fn[D][0]);
-  pos[1] = (int)((t / g.fn[D][0]) % g.fn[D][1]);
-  pos[2] = (int)(t / ((long)g.fn[D][0] * g.fn[D][1]));
-  // box index of the cell right of the face
-  const long base = (long)(pos[2] + g.h[2]) * g.sb[2] + (long)(pos[1] + g.h[1]) * g.sb[1] +
-                    (pos[0] + g.h[0]);
-  const long s = g.sb[D];
-  const int f = pos[D];
+__global__ void __launch_bounds__(256) k_grad(Dev g) {
+  const unsigned b = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (b >= (unsigned)g.nbox) return;
+  const unsigned N0 = g.N[0], N01 = (unsigned)g.N[0] * g.N[1];
+  int p[3];
+  p[2] = (int)(b / N01) - g.h[2];
+  const unsigned r = b % N01;
+  p[1] = (int)(r / N0) - g.h[1];
+  p[0] = (int)(r % N0) - g.h[0];
+  const int nd = g.ndim;
+  bool near[3];
+  for (int e = 0; e < 3; ++e) near[e] = e >= nd || (p[e] >= -2 && p[e] < g.n[e] + 2);
+  for (int t = 0; t < nd; ++t) {
+    if (p[t] < 0 || p[t] >= g.n[t]) continue;
+    bool ok = true;
+    for (int e = 0; e < nd; ++e)
+      if (e != t && !near[e]) ok = false;
+    if (!ok) continue;
+    const long st = g.sb[t];
+    const double mct = g.mc[t][p[t]];
+    for (int phi = 0; phi < nd; ++phi) {
+      const double *A = g.Q[QU + phi];
+      g.G[3 * t + phi][b] = dcell4(A[b - 2 * st], A[b - st], A[b + st], A[b + 2 * st]) * mct;
+    }
+  }
+}
 
-  const double *Qr = g.Q[QR], *Qp = g.Q[QP];
-  const double *Qn = g.Q[QU + D];
+// ---------------------------------------------------------------------------
+// Total flux F = F^c - F^d at one face of direction D (Eq. (6)), in the
+// global 5-component layout (mass, x/y/z momentum, energy).  The stencil is
+// read through accessors: P(q, o) is primitive q of the cell at offset o from
+// the face (o = -3 .. 2; the face lies between offsets -1 and 0), Gv(k, o) is
+// the k-th tangential velocity derivative of that cell (o = -2 .. 1; k = 2 r
+// + 0: d u_t / d t, k = 2 r + 1: d u_D / d t, r over the active tangential
+// axes).
+// ---------------------------------------------------------------------------
+template <int NDIM, int D, bool VISC, class PA, class GA>
+__device__ __forceinline__ void face_flux(const Dev &g, const PA &P, const GA &Gv, int f,
+                                          double *G) {
+  constexpr int T1 = tan1(D), T2 = tan2(D);
+  constexpr int qi[5] = {QR, QU + D, QU + T1, QU + T2, QP};
   double qL[5], qR[5];
-  {
-    double v[6];
 #pragma unroll
-    for (int o = 0; o < 6; ++o) v[o] = Qr[base + (o - 3) * s];
-    qL[0] = weno5(v[0], v[1], v[2], v[3], v[4]);
-    qR[0] = weno5(v[5], v[4], v[3], v[2], v[1]);
-#pragma unroll
-    for (int o = 0; o < 6; ++o) v[o] = Qn[base + (o - 3) * s];
-    qL[1] = weno5(v[0], v[1], v[2], v[3], v[4]);
-    qR[1] = weno5(v[5], v[4], v[3], v[2], v[1]);
-    if (T1 < NDIM) {
-      const double *Qt = g.Q[QU + T1];
-#pragma unroll
-      for (int o = 0; o < 6; ++o) v[o] = Qt[base + (o - 3) * s];
-      qL[2] = weno5(v[0], v[1], v[2], v[3], v[4]);
-      qR[2] = weno5(v[5], v[4], v[3], v[2], v[1]);
-    } else {
-      qL[2] = qR[2] = 0.0;
+  for (int m = 0; m < 5; ++m) {
+    if ((m == 2 && T1 >= NDIM) || (m == 3 && T2 >= NDIM)) {
+      qL[m] = qR[m] = 0.0;
+      continue;
     }
-    if (T2 < NDIM) {
-      const double *Qt = g.Q[QU + T2];
-#pragma unroll
-      for (int o = 0; o < 6; ++o) v[o] = Qt[base + (o - 3) * s];
-      qL[3] = weno5(v[0], v[1], v[2], v[3], v[4]);
-      qR[3] = weno5(v[5], v[4], v[3], v[2], v[1]);
-    } else {
-      qL[3] = qR[3] = 0.0;
-    }
-#pragma unroll
-    for (int o = 0; o < 6; ++o) v[o] = Qp[base + (o - 3) * s];
-    qL[4] = weno5(v[0], v[1], v[2], v[3], v[4]);
-    qR[4] = weno5(v[5], v[4], v[3], v[2], v[1]);
+    double v0 = P(qi[m], -3), v1 = P(qi[m], -2), v2 = P(qi[m], -1);
+    double v3 = P(qi[m], 0), v4 = P(qi[m], 1), v5 = P(qi[m], 2);
+    qL[m] = weno5(v0, v1, v2, v3, v4);
+    qR[m] = weno5(v5, v4, v3, v2, v1);
   }
   double Fc[5];
   hllc(qL, qR, g.gamma, Fc);
-  double G[5];
   G[0] = Fc[0];
   G[1 + D] = Fc[1];
   G[1 + T1] = Fc[2];
   G[1 + T2] = Fc[3];
   G[4] = Fc[4];
-
   if (VISC) {
     // Dissipative flux (Eqs. (4)-(5), Fourier's law) from 4th-order central
-    // interpolation / differences over the cells f-2 .. f+1.
+    // interpolation / differences over the cells at offsets -2 .. 1.
     double vel[3][4], Tc[4], muc[4];
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
-      long cb = base + (o - 2) * s;
-      vel[0][o] = g.Q[QU][cb];
-      vel[1][o] = NDIM >= 2 ? g.Q[QV][cb] : 0.0;
-      vel[2][o] = NDIM >= 3 ? g.Q[QW][cb] : 0.0;
-      Tc[o] = g.Q[QT][cb];
-      muc[o] = g.Q[QMU][cb];
+      vel[0][o] = P(QU, o - 2);
+      vel[1][o] = NDIM >= 2 ? P(QV, o - 2) : 0.0;
+      vel[2][o] = NDIM >= 3 ? P(QW, o - 2) : 0.0;
+      Tc[o] = P(QT, o - 2);
+      muc[o] = P(QMU, o - 2);
     }
     const double mfD = g.mf[D][f];
     double muf = interp4(muc[0], muc[1], muc[2], muc[3]);
@@ -284,18 +299,8 @@ __global__ void __launch_bounds__(256) k_flux(Dev g) {
     for (int r = 0; r < 2; ++r) {
       const int tt = r == 0 ? T1 : T2;
       if (tt >= NDIM) continue;
-      const long st = g.sb[tt];
-      const double mct = g.mc[tt][pos[tt]];
-      const double *Qtt = g.Q[QU + tt];
-      double gtt[4], gtn[4];
-#pragma unroll
-      for (int o = 0; o < 4; ++o) {
-        long cb = base + (o - 2) * s;
-        gtt[o] = dcell4(Qtt[cb - 2 * st], Qtt[cb - st], Qtt[cb + st], Qtt[cb + 2 * st]) * mct;
-        gtn[o] = dcell4(Qn[cb - 2 * st], Qn[cb - st], Qn[cb + st], Qn[cb + 2 * st]) * mct;
-      }
-      divt += interp4(gtt[0], gtt[1], gtt[2], gtt[3]);
-      dtn[tt] = interp4(gtn[0], gtn[1], gtn[2], gtn[3]);
+      divt += interp4(Gv(2 * r, -2), Gv(2 * r, -1), Gv(2 * r, 0), Gv(2 * r, 1));
+      dtn[tt] = interp4(Gv(2 * r + 1, -2), Gv(2 * r + 1, -1), Gv(2 * r + 1, 0), Gv(2 * r + 1, 1));
     }
     double tau[3] = {0.0, 0.0, 0.0};
     tau[D] = muf * ((4.0 / 3.0) * dn[D] - (2.0 / 3.0) * divt);
@@ -308,6 +313,133 @@ __global__ void __launch_bounds__(256) k_flux(Dev g) {
     G[3] -= tau[2];
     G[4] -= en;
   }
+}
+
+// LDS slots: primitives rho,u,v,w,p,T,mu then the tangential derivatives.
+template <int NDIM, bool VISC> struct Slots {
+  static constexpr int NP = VISC ? 7 : 5;
+  static constexpr int NG = VISC ? 2 * (NDIM - 1) : 0;
+  static constexpr int NC = NP + NG;
+};
+
+// Box array (and G index) behind LDS slot `sl` of direction D.
+template <int NDIM, int D, bool VISC>
+__device__ __forceinline__ const double *slot_array(const Dev &g, int sl) {
+  constexpr int T1 = tan1(D), T2 = tan2(D);
+  if (sl < 5) return g.Q[sl];
+  if (VISC) {
+    if (sl == 5) return g.Q[QT];
+    if (sl == 6) return g.Q[QMU];
+    const int k = sl - 7, r = k / 2;
+    const int t = r == 0 ? T1 : T2;
+    return g.G[3 * t + ((k & 1) ? D : t)];
+  }
+  return nullptr;
+}
+
+__device__ __forceinline__ int slot_of(int q) { return q; }  // QR..QMU map 1:1
+
+// ---------------------------------------------------------------------------
+// x faces: the face index space ((k ny + j) (nx+1) + f) is cut into chunks of
+// 256 consecutive faces; a chunk's stencil cells (each row segment widened by
+// 3 + 2 cells) are staged in LDS once, then every thread computes one face
+// from LDS.  Coalesced loads, one global read per staged value.
+// ---------------------------------------------------------------------------
+template <int NDIM, bool VISC>
+__global__ void __launch_bounds__(256) k_flux_x(Dev g, int nwmax) {
+  extern __shared__ double lds[];
+  using S = Slots<NDIM, VISC>;
+  const int nf = g.n[0] + 1;
+  const unsigned total = (unsigned)g.fcount[0];
+  const unsigned t0 = blockIdx.x * 256u;
+  const unsigned tl = min(t0 + 255u, total - 1u);
+  const unsigned r0 = t0 / nf, f0 = t0 % nf;
+  const unsigned rl = tl / nf;
+  const int first_len = (nf - (int)f0) + 5;
+  const int nw = (int)(tl - t0 + 1) + 5 * (int)(rl - r0 + 1);
+  const unsigned ny = g.n[1];
+  for (int w = threadIdx.x; w < nw; w += 256) {
+    int seg, xc;
+    if (w < first_len) {
+      seg = 0;
+      xc = (int)f0 - 3 + w;
+    } else {
+      const int q = w - first_len;
+      seg = 1 + q / (nf + 5);
+      xc = -3 + q % (nf + 5);
+    }
+    const unsigned r = r0 + seg;
+    const int j = (int)(r % ny), k = (int)(r / ny);
+    const long bx = (long)(k + g.h[2]) * g.sb[2] + (long)(j + g.h[1]) * g.sb[1] + (xc + g.h[0]);
+#pragma unroll
+    for (int sl = 0; sl < S::NC; ++sl) {
+      if ((sl == QV && NDIM < 2) || (sl == QW && NDIM < 3)) continue;
+      lds[sl * nwmax + w] = slot_array<NDIM, 0, VISC>(g, sl)[bx];
+    }
+  }
+  __syncthreads();
+  const unsigned t = t0 + threadIdx.x;
+  if (t > tl) return;
+  const unsigned r = t / nf;
+  const int f = (int)(t % nf);
+  const int w0 = (int)(t - t0) + 5 * (int)(r - r0) + 3;  // window index of offset 0
+  auto P = [&](int q, int o) { return lds[slot_of(q) * nwmax + w0 + o]; };
+  auto Gv = [&](int kk, int o) { return lds[(S::NP + kk) * nwmax + w0 + o]; };
+  double G[5];
+  face_flux<NDIM, 0, VISC>(g, P, Gv, f, G);
+  if (!(fabs(G[0]) + fabs(G[4]) < 1.0e300)) atomicOr(g.flags, 1u);  // non-finite flux
+  double *F = g.F[0];
+  const long fc = g.fcount[0];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) F[m * fc + t] = G[m];
+}
+
+// ---------------------------------------------------------------------------
+// y / z faces: 16 (x) x 16 (faces along D) tiles; the tile's 21 cells along D
+// by 16 along x are staged in LDS per primitive / derivative.
+// ---------------------------------------------------------------------------
+template <int NDIM, int D, bool VISC>
+__global__ void __launch_bounds__(256) k_flux_yz(Dev g) {
+  using S = Slots<NDIM, VISC>;
+  constexpr int TX = 16, TD = 16, TR = TD + 5;
+  __shared__ double lds[S::NC][TR][TX];
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  // tiles along D are consecutive in the remapped order (they share 5 rows)
+  const unsigned nbx = gridDim.x, nby = gridDim.y;
+  const unsigned lin = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
+  const unsigned lg = xcd_remap(lin, nbx * nby * gridDim.z);
+  const unsigned by = lg % nby, rest = lg / nby;
+  const int i0 = (int)(rest % nbx) * TX, f0 = (int)by * TD, oc = (int)(rest / nbx);
+  const int nD = g.n[D];
+  // oc is the remaining axis' index: z for D = 1, y for D = 2
+  for (int idx = threadIdx.x; idx < TR * TX; idx += 256) {
+    const int a = idx / TX, x = idx % TX;
+    const int i = i0 + x, s = f0 - 3 + a;
+    if (i >= g.n[0] || s > nD + 2) continue;
+    int p[3];
+    p[0] = i;
+    p[D] = s;
+    p[3 - D] = oc;  // D = 1 -> axis 2, D = 2 -> axis 1
+    const long bx = (long)(p[2] + g.h[2]) * g.sb[2] + (long)(p[1] + g.h[1]) * g.sb[1] + (p[0] + g.h[0]);
+#pragma unroll
+    for (int sl = 0; sl < S::NC; ++sl) {
+      if ((sl == QV && NDIM < 2) || (sl == QW && NDIM < 3)) continue;
+      lds[sl][a][x] = slot_array<NDIM, D, VISC>(g, sl)[bx];
+    }
+  }
+  __syncthreads();
+  const int i = i0 + tx, f = f0 + ty;
+  if (i >= g.n[0] || f > nD) return;
+  auto P = [&](int q, int o) { return lds[slot_of(q)][ty + 3 + o][tx]; };
+  auto Gv = [&](int kk, int o) { return lds[S::NP + kk][ty + 3 + o][tx]; };
+  double G[5];
+  face_flux<NDIM, D, VISC>(g, P, Gv, f, G);
+  if (!(fabs(G[0]) + fabs(G[4]) < 1.0e300)) atomicOr(g.flags, 1u);  // non-finite flux
+  int p[3];
+  p[0] = i;
+  p[D] = f;
+  p[3 - D] = oc;
+  const long t = ((long)p[2] * g.fn[D][1] + p[1]) * g.fn[D][0] + p[0];
   double *F = g.F[D];
   const long fc = g.fcount[D];
 #pragma unroll
@@ -608,25 +740,6 @@ __global__ void __launch_bounds__(256) k_cost(Dev g, int face, double pref, cons
   }
 }
 
-// ---------------------------------------------------------------------------
-// Template instantiation table for the flux kernels.
-// ---------------------------------------------------------------------------
-using FluxKernel = void (*)(Dev);
-
-FluxKernel flux_kernel(int ndim, int D, bool visc) {
-#define DCF_FK(N, DD)                                               \
-  if (ndim == N && D == DD) return visc ? (FluxKernel)k_flux<N, DD, true> \
-                                         : (FluxKernel)k_flux<N, DD, false>;
-  DCF_FK(1, 0)
-  DCF_FK(2, 0)
-  DCF_FK(2, 1)
-  DCF_FK(3, 0)
-  DCF_FK(3, 1)
-  DCF_FK(3, 2)
-#undef DCF_FK
-  return nullptr;
-}
-
 }  // namespace dcf
 
 // ---------------------------------------------------------------------------
@@ -687,15 +800,49 @@ hipError_t launch_prim_halo(const Dev &g, const double *U, hipStream_t st) {
   k_prim_halo<<<grid_for(g.nbox), 256, 0, st>>>(g, U);
   return hipGetLastError();
 }
-hipError_t launch_flux_dir(const Dev &g, int D, hipStream_t st) {
-  FluxKernel k = flux_kernel(g.ndim, D, g.visc != VISC_NONE);
-  if (!k) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k, dim3(grid_for(g.fcount[D])), dim3(256), 0, st, g);
+static int x_window(const Dev &g) {
+  const int nf = g.n[0] + 1;
+  return 256 + 5 * ((255 + nf - 1) / nf + 1);
+}
+
+template <int NDIM, bool VISC>
+static hipError_t launch_x(const Dev &g, hipStream_t st) {
+  const int nw = x_window(g);
+  const size_t shm = sizeof(double) * Slots<NDIM, VISC>::NC * nw;
+  k_flux_x<NDIM, VISC><<<grid_for(g.fcount[0]), 256, shm, st>>>(g, nw);
   return hipGetLastError();
 }
+
+template <int NDIM, int D, bool VISC>
+static hipError_t launch_yz(const Dev &g, hipStream_t st) {
+  dim3 grid((g.n[0] + 15) / 16, (g.n[D] + 1 + 15) / 16, D == 1 ? g.n[2] : g.n[1]);
+  k_flux_yz<NDIM, D, VISC><<<grid, 256, 0, st>>>(g);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad(const Dev &g, hipStream_t st) {
+  if (g.visc == VISC_NONE || g.ndim < 2) return hipSuccess;
+  k_grad<<<grid_for(g.nbox), 256, 0, st>>>(g);
+  return hipGetLastError();
+}
+
+hipError_t launch_flux_dir(const Dev &g, int D, hipStream_t st) {
+  const bool v = g.visc != VISC_NONE;
+  switch (g.ndim * 10 + D) {
+    case 10: return v ? launch_x<1, true>(g, st) : launch_x<1, false>(g, st);
+    case 20: return v ? launch_x<2, true>(g, st) : launch_x<2, false>(g, st);
+    case 21: return v ? launch_yz<2, 1, true>(g, st) : launch_yz<2, 1, false>(g, st);
+    case 30: return v ? launch_x<3, true>(g, st) : launch_x<3, false>(g, st);
+    case 31: return v ? launch_yz<3, 1, true>(g, st) : launch_yz<3, 1, false>(g, st);
+    case 32: return v ? launch_yz<3, 2, true>(g, st) : launch_yz<3, 2, false>(g, st);
+  }
+  return hipErrorInvalidValue;
+}
 hipError_t launch_fluxes(const Dev &g, hipStream_t st) {
+  hipError_t e = launch_grad(g, st);
+  if (e != hipSuccess) return e;
   for (int D = 0; D < g.ndim; ++D) {
-    hipError_t e = launch_flux_dir(g, D, st);
+    e = launch_flux_dir(g, D, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -14,6 +14,7 @@ hipError_t launch_init_state(const Dev &g, const double *P, double *U, hipStream
 hipError_t launch_prim_halo(const Dev &g, const double *U, hipStream_t st);
 hipError_t launch_fluxes(const Dev &g, hipStream_t st);
 hipError_t launch_flux_dir(const Dev &g, int D, hipStream_t st);
+hipError_t launch_grad(const Dev &g, hipStream_t st);
 hipError_t launch_force(const Dev &g, double *part, double *force, hipStream_t st);
 hipError_t launch_update(const Dev &g, const double *Un, const double *Uin, double *Uout,
                          double *Rout, const double *dt, double a, double b,

@@ -184,6 +184,21 @@ class Solver:
                _stream(stream))
         return out
 
+    def workspace_bytes(self) -> int:
+        return int(self.workspace.numel())
+
+    def gradient_begin(self, U0, dt, J, gK, stream=None):
+        B.call("dcf_gradient_begin", self.ctx, _ptr(U0), int(self.nsteps), _ptr(dt),
+               int(self.seg_len), _ptr(J), _ptr(gK) if self.nk else None, _stream(stream))
+
+    def gradient_advance(self, max_units: int, stream=None) -> bool:
+        done = C.c_int()
+        B.call("dcf_gradient_advance", self.ctx, int(max_units), C.byref(done), _stream(stream))
+        return bool(done.value)
+
+    def gradient_finish(self, gU=None, stream=None):
+        B.call("dcf_gradient_finish", self.ctx, _ptr(gU), _stream(stream))
+
     def gradient(self, U0, dt, stream=None):
         """J, dJ/dK, dJ/dU0 over the trajectory sized at construction."""
         J = torch.zeros(1, dtype=torch.float64, device=self.device)

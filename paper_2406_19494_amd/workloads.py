@@ -278,7 +278,8 @@ def porous_bl(nx: int = 1024, ny: int = 256, Ma: float = 6.0, T_inf_K: float = 6
               Tw_K: float = 300.0, Re_unit: float = 1.0e4, Pr: float = 0.72,
               x0: float = 1.0, x1: float = 1.5, H: float = 0.4, beta: float = 2.2,
               strip: Optional[Tuple[int, int]] = None, k_max: float = 0.5,
-              seed: int = 1994, nsteps: int = 2000, dt_fixed: float = 0.0
+              seed: int = 1994, nsteps: int = 2000, dt_fixed: float = 0.0,
+              pulse: float = 0.02, pulse_radius: float = 0.02
               ) -> Tuple[Case, np.ndarray, np.ndarray]:
     """Free stream rho = u = T = 1; p_inf = 1/(gamma Ma^2), R = p_inf; mu_inf =
     1/Re_unit (lengths in mm, Re_unit = 1e7/m * 1 mm).  Isothermal wall at
@@ -323,10 +324,12 @@ def porous_bl(nx: int = 1024, ny: int = 256, Ma: float = 6.0, T_inf_K: float = 6
     rhov = -np.cumsum(drhou * dy[:, None], axis=0)
     rho = 1.0 / T
     P = _prim(nx, ny, 1)
-    P[0, 0] = rho
+    xm = 0.5 * (x0 + x1)
+    pw = p_inf * (1.0 + pulse * np.exp(-((x[0] - xm) ** 2 + y[0] ** 2) / pulse_radius ** 2))
+    P[0, 0] = rho * pw / p_inf
     P[1, 0] = u
     P[2, 0] = rhov / rho
-    P[4, 0] = p_inf
+    P[4, 0] = pw
     # Dirichlet inflow profile at x- : [5][n_t2 = 1][n_t1 = ny]
     uin, Tin = profile(np.full(ny, x0 - 0.5 * (x1 - x0) / nx), yy)
     D = np.zeros((5, 1, ny))

@@ -60,6 +60,9 @@ def small_cases():
     c = W.Case(name="mix3d", ndim=3, n=(13, 9, 7), lo=(0, 0, 0), hi=(1, 1, 1),
                stretch=("tanh1", "uniform", "uniform"), beta=(1.5, 0, 0), gamma=1.4, R=1.0,
                visc_law="none", bc=("zerograd", "zerograd", "wall", "wall", "periodic", "periodic"),
-               T_wall=(0, 0, 2.0, 2.0, 0, 0))  # T in [1/3, 3]: mirror 2 T_w - T stays > 0
-    cases.append(("mixed3d_rough", c, W.random_rough(c, seed=9), None))
+               T_wall=(0, 0, 1.0, 1.0, 0, 0))
+    # cell-wise random data with T in [0.67, 1.5]: the mirror 2 T_w - T stays
+    # positive and the reconstructed states stay physical
+    cases.append(("mixed3d_rough", c, W.random_rough(c, seed=9, rho=(0.8, 1.2), vel=(-0.3, 0.3),
+                                                     p=(0.8, 1.2)), None))
     return cases
