@@ -67,6 +67,57 @@ def cpu_baseline(case, P, K, budget_s):
                       f"workload ({el:.1f} s, OpenMP threads={threads})"}
 
 
+def source_digest():
+    """sha256 of the forward kernel sources (counters are tied to them)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("dcf_forward.hip", "dcf_common.hpp"):
+        with open(os.path.join(ROOT, "paper_2406_19494_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by the
+    factors a plain 512 MiB copy gives), or None when no summary exists or
+    the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals, kern = {}, {}
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) >= 2 and parts[0] in ("source_sha", "copy_factor_fetch",
+                                                  "copy_factor_write"):
+                vals[parts[0]] = parts[1]
+            elif len(parts) == 4 and parts[0] == "kernel":
+                kern[parts[1]] = (float(parts[2]), float(parts[3]))
+    if vals.get("source_sha") != source_digest() or kernel not in kern:
+        return None
+    fk, wk = kern[kernel]
+    return 1024.0 * (fk * float(vals["copy_factor_fetch"]) + wk * float(vals["copy_factor_write"]))
+
+
+def serving_bench(M=32, rate=20.0, seed=2024):
+    """Continuous batching vs sequential solves on a seeded trace of forward
+    and gradient requests (Sod 200-4096 cells, TGV 32^3/48^3/64^3, porous BL
+    256x64/512x128), 50-400 steps each, Poisson arrivals at `rate`/s."""
+    from paper_2406_19494_amd import serving as S
+    trace = S.draw_trace(M, rate, seed, steps=(50, 400), tgv=(32, 48, 64), bl=(1, 2))
+    res, t_b, sch = S.serve(trace, budget_bytes=200e9, max_slots=16)
+    sb = S.summarize(res, t_b)
+    res_s, t_s, _ = S.serve_sequential(trace)
+    ss = S.summarize(res_s, t_s)
+    work = sum(3.0 * S.cells_of(r) * r.nsteps for r in trace)
+    return {"trace": f"{M} requests, Poisson {rate}/s (seed {seed}), steps 50-400, "
+                     "sod 200-4096 / tgv 32-64^3 / porous BL 256x64-512x128, 50% gradients",
+            "offered_cell_updates": work,
+            "batched": sb, "sequential": ss, "peak_active": sch.peak_active,
+            "throughput_ratio": sb["cell_updates_per_s"] / ss["cell_updates_per_s"]}
+
+
 def adjoint_ratio(steps=20):
     """Adjoint/forward cost on the Mach-6 porous boundary layer (1024 x 256):
     per step, t(vjp_step incl. stage recompute) / t(rk3_step), HIP events."""
@@ -109,6 +160,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 512 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -177,13 +229,15 @@ def main():
         flops = FLOPS_PER_FACE[(case.ndim, visc)] * faces
         achieved = flops / (kt[dom] * 1e-3)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
+                "traffic": measured_traffic(names[dom], args.workload),
                 "kernel": names[dom], "avg_ms": kt[dom],
                 "algorithmic_flops_per_face": FLOPS_PER_FACE[(case.ndim, visc)],
                 "faces_per_launch": faces}
     else:
         roof = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "frac": None, "traffic": None, "kernel": names[dom], "avg_ms": kt[dom]}
+                "frac": None, "traffic": measured_traffic(names[dom], args.workload),
+                "kernel": names[dom], "avg_ms": kt[dom]}
 
     out = {
         "metric": "FP64 cell-updates/s per RK stage",
@@ -202,10 +256,13 @@ def main():
                    "step": "CFL dt + TVD-RK3 (WENO5-JS, HLLC, 4th-order viscous)"},
         "roofline": roof,
         "kernel_ms": {names[k]: v for k, v in kt.items()},
+        "source_sha": source_digest(),
         "wall_s": wall,
     }
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio()
+    if not args.no_serving:
+        out["serving"] = serving_bench()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, P, K, args.cpu_budget)
     print(json.dumps(out), flush=True)

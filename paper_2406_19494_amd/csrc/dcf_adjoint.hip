@@ -302,62 +302,71 @@ __global__ void __launch_bounds__(256) k_conv_vjp(Dev g, AdjBuffers A) {
   constexpr int T1 = tan1(D), T2 = tan2(D);
   constexpr int NC = 5;
   __shared__ double acc[NC][TW][NCW];
+  __shared__ double buf[NOFF][TW][TF];  // one component's contributions per face
   Tile t = make_tile<OLO, OHI>(g, D);
   for (int i = threadIdx.x; i < NC * TW * NCW; i += 256) (&acc[0][0][0])[i] = 0.0;
-  __syncthreads();
 
   const int f = t.f0 + t.lane_face;
   const bool active = t.line_ok && f >= 0 && f <= g.n[D];
-  double contrib[NOFF][NC];
-#pragma unroll
-  for (int o = 0; o < NOFF; ++o)
-#pragma unroll
-    for (int q = 0; q < NC; ++q) contrib[o][q] = 0.0;
+  const int qi[5] = {QR, QU + D, QU + T1, QU + T2, QP};
+  double qLb[5] = {0, 0, 0, 0, 0}, qRb[5] = {0, 0, 0, 0, 0};
+  long base = 0, s = g.sb[D];
   if (active) {
     int pos[3] = {t.line[0], t.line[1], t.line[2]};
     pos[D] = f;
     double Fb[5];
     face_adjoint(g, D, pos, f, A.Rb, Fb);
-    const long base = (long)(pos[2] + g.h[2]) * g.sb[2] + (long)(pos[1] + g.h[1]) * g.sb[1] +
-                      (pos[0] + g.h[0]);
-    const long s = g.sb[D];
-    const int qi[5] = {QR, QU + D, QU + T1, QU + T2, QP};
-    double v[5][6];
+    base = bidx(g, pos[0], pos[1], pos[2]);
     double qL[5], qR[5];
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
       const bool act = !((m == 2 && T1 >= NDIM) || (m == 3 && T2 >= NDIM));
-#pragma unroll
-      for (int o = 0; o < 6; ++o) v[m][o] = act ? g.Q[qi[m]][base + (o - 3) * s] : 0.0;
-      qL[m] = act ? weno5(v[m][0], v[m][1], v[m][2], v[m][3], v[m][4]) : 0.0;
-      qR[m] = act ? weno5(v[m][5], v[m][4], v[m][3], v[m][2], v[m][1]) : 0.0;
+      if (!act) {
+        qL[m] = qR[m] = 0.0;
+        continue;
+      }
+      const double *Qm = g.Q[qi[m]];
+      double v0 = Qm[base - 3 * s], v1 = Qm[base - 2 * s], v2 = Qm[base - s];
+      double v3 = Qm[base], v4 = Qm[base + s], v5 = Qm[base + 2 * s];
+      qL[m] = weno5(v0, v1, v2, v3, v4);
+      qR[m] = weno5(v5, v4, v3, v2, v1);
     }
     double Fr[5] = {Fb[0], Fb[1 + D], Fb[1 + T1], Fb[1 + T2], Fb[4]};
-    double qLb[5], qRb[5];
     hllc_vjp(qL, qR, g.gamma, Fr, qLb, qRb);
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      const bool act = !((m == 2 && T1 >= NDIM) || (m == 3 && T2 >= NDIM));
-      if (!act) continue;
-      double gL[5] = {0, 0, 0, 0, 0}, gR[5] = {0, 0, 0, 0, 0};
-      weno5_vjp(v[m][0], v[m][1], v[m][2], v[m][3], v[m][4], qLb[m], gL);
-      weno5_vjp(v[m][5], v[m][4], v[m][3], v[m][2], v[m][1], qRb[m], gR);
-      // cells f-3 .. f+2 <-> offsets 0 .. 5
-      contrib[0][m] += gL[0];
-      contrib[1][m] += gL[1] + gR[4];
-      contrib[2][m] += gL[2] + gR[3];
-      contrib[3][m] += gL[3] + gR[2];
-      contrib[4][m] += gL[4] + gR[1];
-      contrib[5][m] += gR[0];
-    }
   }
-  // offset-ordered accumulation: one writer per window cell per phase
-#pragma unroll
-  for (int o = 0; o < NOFF; ++o) {
+  // per component: reverse the two reconstructions, stage the contributions
+  // to cells f-3 .. f+2 in LDS, then gather them per window cell in a fixed
+  // order of faces (deterministic, no atomics)
+  for (int m = 0; m < 5; ++m) {
+    const bool act = !((m == 2 && T1 >= NDIM) || (m == 3 && T2 >= NDIM));
+    if (!act) continue;  // uniform across the block
+    double c[NOFF] = {0, 0, 0, 0, 0, 0};
     if (active) {
-      const int w = t.lane_face + o;  // window cell of (f + OLO + o)
+      const double *Qm = g.Q[qi[m]];
+      double v0 = Qm[base - 3 * s], v1 = Qm[base - 2 * s], v2 = Qm[base - s];
+      double v3 = Qm[base], v4 = Qm[base + s], v5 = Qm[base + 2 * s];
+      double gL[5] = {0, 0, 0, 0, 0}, gR[5] = {0, 0, 0, 0, 0};
+      weno5_vjp(v0, v1, v2, v3, v4, qLb[m], gL);
+      weno5_vjp(v5, v4, v3, v2, v1, qRb[m], gR);
+      c[0] = gL[0];
+      c[1] = gL[1] + gR[4];
+      c[2] = gL[2] + gR[3];
+      c[3] = gL[3] + gR[2];
+      c[4] = gL[4] + gR[1];
+      c[5] = gR[0];
+    }
 #pragma unroll
-      for (int q = 0; q < NC; ++q) acc[q][t.lane_line][w] += contrib[o][q];
+    for (int o = 0; o < NOFF; ++o) buf[o][t.lane_line][t.lane_face] = c[o];
+    __syncthreads();
+    for (int i = threadIdx.x; i < TW * NCW; i += 256) {
+      const int ll = i / NCW, w = i % NCW;
+      double sum = 0.0;
+#pragma unroll
+      for (int o = 0; o < NOFF; ++o) {
+        const int fl = w - o;  // face (lane) whose offset o lands on window cell w
+        if (fl >= 0 && fl < TF) sum += buf[o][ll][fl];
+      }
+      acc[m][ll][w] += sum;
     }
     __syncthreads();
   }
@@ -372,8 +381,7 @@ __global__ void __launch_bounds__(256) k_conv_vjp(Dev g, AdjBuffers A) {
     p[D] = cell;
     p[T1] = (int)(ln % g.n[T1]);
     p[T2] = (int)(ln / g.n[T1]);
-    const long b = (long)(p[2] + g.h[2]) * g.sb[2] + (long)(p[1] + g.h[1]) * g.sb[1] +
-                   (p[0] + g.h[0]);
+    const long b = bidx(g, p[0], p[1], p[2]);
     A.Qb[QR][b] += acc[0][ll][w];
     A.Qb[QU + D][b] += acc[1][ll][w];
     if (T1 < NDIM) A.Qb[QU + T1][b] += acc[2][ll][w];
@@ -410,8 +418,7 @@ __global__ void __launch_bounds__(256) k_visc_vjp(Dev g, AdjBuffers A) {
     pos[D] = f;
     double Fb[5];
     face_adjoint(g, D, pos, f, A.Rb, Fb);
-    const long base = (long)(pos[2] + g.h[2]) * g.sb[2] + (long)(pos[1] + g.h[1]) * g.sb[1] +
-                      (pos[0] + g.h[0]);
+    const long base = bidx(g, pos[0], pos[1], pos[2]);
     const long s = g.sb[D];
     double vel[3][4], Tc[4], muc[4];
 #pragma unroll
@@ -513,8 +520,7 @@ __global__ void __launch_bounds__(256) k_visc_vjp(Dev g, AdjBuffers A) {
     p[D] = cell;
     p[T1] = (int)(ln % g.n[T1]);
     p[T2] = (int)(ln / g.n[T1]);
-    const long b = (long)(p[2] + g.h[2]) * g.sb[2] + (long)(p[1] + g.h[1]) * g.sb[1] +
-                   (p[0] + g.h[0]);
+    const long b = bidx(g, p[0], p[1], p[2]);
     A.Qb[QU][b] += acc[0][ll][w];
     if (NDIM >= 2) A.Qb[QV][b] += acc[1][ll][w];
     if (NDIM >= 3) A.Qb[QW][b] += acc[2][ll][w];
@@ -550,12 +556,13 @@ __device__ __forceinline__ double dviscosity(const Dev &g, double T) {
 }
 
 __global__ void __launch_bounds__(256) k_tangential_vjp(Dev g, AdjBuffers A) {
-  long b = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= g.nbox) return;
+  const long bl = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (bl >= g.nbox) return;
   int p[3];
-  p[0] = (int)(b % g.N[0]) - g.h[0];
-  p[1] = (int)((b / g.N[0]) % g.N[1]) - g.h[1];
-  p[2] = (int)(b / ((long)g.N[0] * g.N[1])) - g.h[2];
+  p[0] = (int)(bl % g.N[0]) - g.h[0];
+  p[1] = (int)((bl / g.N[0]) % g.N[1]) - g.h[1];
+  p[2] = (int)(bl / ((long)g.N[0] * g.N[1])) - g.h[2];
+  const long b = bidx(g, p[0], p[1], p[2]);
   const int nd = g.ndim;
   if (A.Gb[0] != nullptr) {
     for (int phi = 0; phi < nd; ++phi) {
@@ -596,7 +603,7 @@ __global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, do
     p[d] = s;
     p[t1] = a;
     p[t2] = bq;
-    return (long)(p[2] + g.h[2]) * g.sb[2] + (long)(p[1] + g.h[1]) * g.sb[1] + (p[0] + g.h[0]);
+    return bidx(g, p[0], p[1], p[2]);
   };
   const int n = g.n[d];
   for (int side = 0; side < 2; ++side) {
@@ -652,7 +659,7 @@ __global__ void __launch_bounds__(256) k_interior_vjp(Dev g, AdjBuffers A, const
   const int nd = g.ndim;
   int i = (int)(c % g.n[0]), j = (int)((c / g.n[0]) % g.n[1]),
       k = (int)(c / ((long)g.n[0] * g.n[1]));
-  const long bx = (long)(k + g.h[2]) * g.sb[2] + (long)(j + g.h[1]) * g.sb[1] + (i + g.h[0]);
+  const long bx = bidx(g, i, j, k);
   double rho = V[c];
   double ir = 1.0 / rho;
   double u[3] = {V[nc + c] * ir, nd >= 2 ? V[2 * nc + c] * ir : 0.0,
@@ -718,10 +725,8 @@ static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A, const double *V, 
                             const double *acc_in, double *acc_out, int fold, double *dJdK,
                             hipStream_t st) {
   DCF_TRY(launch_prim_halo(g, V, st));
-  for (int q = 0; q < NQ; ++q) DCF_TRY(launch_fill(A.Qb[q], 0.0, g.nbox, st));
+  DCF_TRY(launch_fill(A.zero_begin, 0.0, A.zero_count, st));
   const bool visc = g.visc != VISC_NONE;
-  if (visc && A.Gb[0])
-    for (int q = 0; q < 9; ++q) DCF_TRY(launch_fill(A.Gb[q], 0.0, g.nbox, st));
   k_rbar<<<blocks(g.ncell), 256, 0, st>>>(g, Wb, dt, b, A.Rb);
   DCF_TRY(hipGetLastError());
   for (int D = 0; D < g.ndim; ++D) {
@@ -751,14 +756,15 @@ static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A, const double *V, 
 
 hipError_t vjp_step(Dev g, const AdjBuffers &A, const double *Un, double *U1, double *U2,
                     const double *dt, const double *lam1, double *lam0, double *dJdK,
-                    hipStream_t st) {
-  // recompute the stage states U1, U2 from Un
-  DCF_TRY(launch_prim_halo(g, Un, st));
-  DCF_TRY(launch_fluxes(g, st));
-  DCF_TRY(launch_update(g, Un, Un, U1, nullptr, dt, 0.0, 1.0, nullptr, st));
-  DCF_TRY(launch_prim_halo(g, U1, st));
-  DCF_TRY(launch_fluxes(g, st));
-  DCF_TRY(launch_update(g, Un, U1, U2, nullptr, dt, 0.75, 0.25, nullptr, st));
+                    hipStream_t st, bool recompute) {
+  if (recompute) {  // the stage states U1, U2 of Un
+    DCF_TRY(launch_prim_halo(g, Un, st));
+    DCF_TRY(launch_fluxes(g, st));
+    DCF_TRY(launch_update(g, Un, Un, U1, nullptr, dt, 0.0, 1.0, nullptr, st));
+    DCF_TRY(launch_prim_halo(g, U1, st));
+    DCF_TRY(launch_fluxes(g, st));
+    DCF_TRY(launch_update(g, Un, U1, U2, nullptr, dt, 0.75, 0.25, nullptr, st));
+  }
   // stage 3: W = Un/3 + 2/3 (U2 + dt R(U2))
   DCF_TRY(stage_vjp(g, A, U2, lam1, dt, 1.0 / 3.0, 2.0 / 3.0, A.Ub2, nullptr, A.acc, 0, dJdK, st));
   // stage 2: W = 3/4 Un + 1/4 (U1 + dt R(U1))

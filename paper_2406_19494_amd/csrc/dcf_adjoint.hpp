@@ -11,13 +11,20 @@ struct AdjBuffers {
   double *Gb[9];    // adjoint of cell-centred velocity derivatives d u_phi / d x_t (3 t + phi)
   double *Ub1, *Ub2, *acc;  // stage adjoints and the running lambda^n accumulator
   double *Rb;       // per-cell adjoint of the right-hand side
+  double *zero_begin;  // Qb and Gb are carved back to back: one fill clears both
+  long zero_count;
 };
 
 // Lays the adjoint buffers out in the workspace (or measures them).
 template <class Carver> void carve_adjoint(Carver &cv, const Dev &g, AdjBuffers &a) {
-  for (int q = 0; q < NQ; ++q) a.Qb[q] = cv.template take<double>(g.nbox);
+  const size_t off0 = cv.off;
+  for (int q = 0; q < NQ; ++q) a.Qb[q] = cv.template take<double>(g.nboxp);
   const bool visc = g.visc != VISC_NONE && g.ndim >= 2;
-  for (int q = 0; q < 9; ++q) a.Gb[q] = visc ? cv.template take<double>(g.nbox) : nullptr;
+  for (int q = 0; q < 9; ++q)
+    a.Gb[q] = (visc && q / 3 < g.ndim && q % 3 < g.ndim) ? cv.template take<double>(g.nboxp)
+                                                           : nullptr;
+  a.zero_begin = a.Qb[0];
+  a.zero_count = (long)((cv.off - off0) / sizeof(double));
   a.Ub1 = cv.template take<double>((long)g.nv * g.ncell);
   a.Ub2 = cv.template take<double>((long)g.nv * g.ncell);
   a.acc = cv.template take<double>((long)g.nv * g.ncell);
@@ -25,9 +32,10 @@ template <class Carver> void carve_adjoint(Carver &cv, const Dev &g, AdjBuffers 
 }
 
 // lam0 = (dU^{n+1}/dU^n)^T lam1 and dJdK += (dU^{n+1}/dK)^T lam1 (if not
-// null); U1 and U2 are scratch state arrays for the recomputed stages.
+// null).  With recompute, U1 and U2 are scratch arrays that receive the
+// stage states; without, they must already hold the stage states of Un.
 hipError_t vjp_step(Dev g, const AdjBuffers &a, const double *Un, double *U1, double *U2,
                     const double *dt, const double *lam1, double *lam0, double *dJdK,
-                    hipStream_t st);
+                    hipStream_t st, bool recompute = true);
 
 }  // namespace dcf

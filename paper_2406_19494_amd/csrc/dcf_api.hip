@@ -66,6 +66,7 @@ struct dcf_ctx {
   AdjBuffers adj;
   double *ckpt = nullptr;  // gradient checkpoints
   double *seg = nullptr;   // per-segment recomputed states
+  double *sst = nullptr;   // per-segment stage states U1, U2 of every step
   double *lam_a = nullptr, *lam_b = nullptr, *gbuf = nullptr, *zero_dt = nullptr;
   // incremental gradient state (dcf_gradient_begin / advance / finish)
   struct {
@@ -124,9 +125,14 @@ dcf_status dcf_create(const dcf_grid *grid, const dcf_gas *gas, dcf_ctx **out) {
   }
   g.ncell = ncell;
   g.nbox = (long)g.N[0] * g.N[1] * g.N[2];
+  g.ho[0] = 16;
+  g.ho[1] = g.h[1];
+  g.ho[2] = g.h[2];
+  const long pitch = ((long)g.ho[0] + g.n[0] + g.h[0] + 15) / 16 * 16;
   g.sb[0] = 1;
-  g.sb[1] = g.N[0];
-  g.sb[2] = (long)g.N[0] * g.N[1];
+  g.sb[1] = pitch;
+  g.sb[2] = pitch * g.N[1];
+  g.nboxp = pitch * g.N[1] * g.N[2];
   for (int D = 0; D < 3; ++D) {
     for (int e = 0; e < 3; ++e) g.fn[D][e] = g.n[e] + (e == D ? 1 : 0);
     g.fcount[D] = (long)g.fn[D][0] * g.fn[D][1] * g.fn[D][2];
@@ -201,7 +207,7 @@ int dcf_num_params(const dcf_ctx *c) { return c ? c->nK : 0; }
 static size_t carve(dcf_ctx *c, void *base, int mode, int nsteps, int seg_len) {
   Carver cv(base);
   Dev &g = c->g;
-  const long nbox = g.nbox, ncell = g.ncell, nv = g.nv;
+  const long nbox = g.nboxp, ncell = g.ncell, nv = g.nv;
   for (int q = 0; q < NQ; ++q) g.Q[q] = cv.take<double>(nbox);
   for (int D = 0; D < 3; ++D) g.F[D] = D < g.ndim ? cv.take<double>(5 * g.fcount[D]) : nullptr;
   const bool need_g = g.visc != VISC_NONE && g.ndim >= 2;
@@ -217,6 +223,7 @@ static size_t carve(dcf_ctx *c, void *base, int mode, int nsteps, int seg_len) {
     int nseg = (nsteps + seg_len - 1) / seg_len;
     c->ckpt = cv.take<double>((size_t)nseg * nv * ncell);
     c->seg = cv.take<double>((size_t)(seg_len + 1) * nv * ncell);
+    c->sst = cv.take<double>((size_t)2 * seg_len * nv * ncell);
     c->lam_a = cv.take<double>(nv * ncell);
     c->lam_b = cv.take<double>(nv * ncell);
     c->gbuf = cv.take<double>(nv * ncell);
@@ -346,15 +353,19 @@ static dcf_status eval_fluxes(dcf_ctx *c, const double *U, hipStream_t st) {
   return DCF_OK;
 }
 
-static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_t st) {
+// One RK3 step in place; the stage states go to U1, U2 (default: scratch).
+static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_t st,
+                             double *U1 = nullptr, double *U2 = nullptr) {
   Dev &g = c->g;
+  if (!U1) U1 = c->U1;
+  if (!U2) U2 = c->U2;
   dcf_status s;
   if ((s = eval_fluxes(c, U, st))) return s;
-  DCF_HIP(launch_update(g, U, U, c->U1, nullptr, dt, 0.0, 1.0, c->force, st));
-  if ((s = eval_fluxes(c, c->U1, st))) return s;
-  DCF_HIP(launch_update(g, U, c->U1, c->U2, nullptr, dt, 0.75, 0.25, c->force, st));
-  if ((s = eval_fluxes(c, c->U2, st))) return s;
-  DCF_HIP(launch_update(g, U, c->U2, U, nullptr, dt, 1.0 / 3.0, 2.0 / 3.0, c->force, st));
+  DCF_HIP(launch_update(g, U, U, U1, nullptr, dt, 0.0, 1.0, c->force, st));
+  if ((s = eval_fluxes(c, U1, st))) return s;
+  DCF_HIP(launch_update(g, U, U1, U2, nullptr, dt, 0.75, 0.25, c->force, st));
+  if ((s = eval_fluxes(c, U2, st))) return s;
+  DCF_HIP(launch_update(g, U, U2, U, nullptr, dt, 1.0 / 3.0, 2.0 / 3.0, c->force, st));
   return DCF_OK;
 }
 
@@ -499,10 +510,11 @@ static dcf_status gradient_unit(dcf_ctx *c, hipStream_t st) {
   }
   const int n0 = gr.sgi * gr.seg_len;
   const int n1 = n0 + gr.seg_len < gr.nsteps ? n0 + gr.seg_len : gr.nsteps;
-  if (gr.phase == 1) {  // recompute U^{n0+1} .. U^{n1} of the segment
+  if (gr.phase == 1) {  // recompute U^{n0+1} .. U^{n1} of the segment, keeping stage states
     double *Ua = c->seg + (long)gr.n * M, *Ub = Ua + M;
     DCF_HIP(launch_copy(Ub, Ua, M, st));
-    if ((s = rk3_stages(c, Ub, gr.dt, st))) return s;
+    double *S1 = c->sst + (long)(2 * gr.n) * M, *S2 = S1 + M;
+    if ((s = rk3_stages(c, Ub, gr.dt, st, S1, S2))) return s;
     if (++gr.n == n1 - n0) {
       gr.phase = 2;
       gr.n = n1;
@@ -514,7 +526,8 @@ static dcf_status gradient_unit(dcf_ctx *c, hipStream_t st) {
     const double *Ucur = c->seg + (long)(n - n0) * M;
     DCF_HIP(launch_cost(g, c->cost_face, c->cost_pref, Ucur, w, c->force + 2, gr.lam, st));
     const double *Uprev = c->seg + (long)(n - 1 - n0) * M;
-    if (vjp_step(g, c->adj, Uprev, c->U1, c->U2, gr.dt, gr.lam, gr.lam_prev, gr.dJdK, st))
+    double *S1 = c->sst + (long)(2 * (n - 1 - n0)) * M, *S2 = S1 + M;
+    if (vjp_step(g, c->adj, Uprev, S1, S2, gr.dt, gr.lam, gr.lam_prev, gr.dJdK, st, false))
       return fail(DCF_EDEVICE, "vjp launch failed");
     double *t = gr.lam;
     gr.lam = gr.lam_prev;

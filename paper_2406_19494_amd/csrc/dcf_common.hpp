@@ -31,7 +31,9 @@ enum : int { QR = 0, QU = 1, QV = 2, QW = 3, QP = 4, QT = 5, QMU = 6, NQ = 7 };
 struct Dev {
   int ndim, nv;
   int n[3], h[3], N[3];  // interior cells, halo layers, box cells per axis
-  long ncell, nbox;
+  int ho[3];             // array index of interior cell 0 along each axis
+  long ncell, nbox;      // interior cells; box cells (N0 N1 N2)
+  long nboxp;            // elements of one box array (rows padded to 16 doubles)
   long sb[3];            // box strides per axis
   // grid metrics per axis (device arrays): widths, 1/width, dxi/dx at
   // centres (n) and at faces (n+1)
@@ -57,6 +59,13 @@ struct Dev {
 };
 
 __device__ __forceinline__ bool finite_pos(double x) { return x > 0.0 && x < 1.0e300; }
+
+// Box arrays: interior cell 0 of each row sits on a 128-byte boundary (x
+// offset 16 doubles, row pitch a multiple of 16), so tiles of 16 cells along
+// x load whole cache lines.
+__host__ __device__ __forceinline__ long bidx(const Dev &g, int i, int j, int k) {
+  return (long)(k + g.ho[2]) * g.sb[2] + (long)(j + g.ho[1]) * g.sb[1] + (i + g.ho[0]);
+}
 
 // Dynamic viscosity: power law, or Sutherland's law (Section 3.2).
 __device__ __forceinline__ double viscosity(const Dev &g, double T) {

@@ -97,15 +97,16 @@ __device__ __forceinline__ int ghost_source(int kind, int side, int m, int n) {
 }
 
 __global__ void __launch_bounds__(256) k_prim_halo(Dev g, const double *U) {
-  const unsigned b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= (unsigned)g.nbox) return;
+  const unsigned bl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (bl >= (unsigned)g.nbox) return;
   const int nd = g.ndim;
   const unsigned N0 = g.N[0], N01 = (unsigned)g.N[0] * g.N[1];
   int p[3];
-  p[2] = (int)(b / N01) - g.h[2];
-  const unsigned rr = b % N01;
+  p[2] = (int)(bl / N01) - g.h[2];
+  const unsigned rr = bl % N01;
   p[1] = (int)(rr / N0) - g.h[1];
   p[0] = (int)(rr % N0) - g.h[0];
+  const long b = bidx(g, p[0], p[1], p[2]);
   if (p[0] >= 0 && p[0] < g.n[0] && p[1] >= 0 && p[1] < g.n[1] && p[2] >= 0 && p[2] < g.n[2]) {
     // interior cell: primitives of its own conserved state
     double q[6];
@@ -214,14 +215,15 @@ __global__ void __launch_bounds__(256) k_prim_halo(Dev g, const double *U) {
 // G[3 t + phi] are box arrays.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_grad(Dev g) {
-  const unsigned b = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (b >= (unsigned)g.nbox) return;
+  const unsigned bl = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (bl >= (unsigned)g.nbox) return;
   const unsigned N0 = g.N[0], N01 = (unsigned)g.N[0] * g.N[1];
   int p[3];
-  p[2] = (int)(b / N01) - g.h[2];
-  const unsigned r = b % N01;
+  p[2] = (int)(bl / N01) - g.h[2];
+  const unsigned r = bl % N01;
   p[1] = (int)(r / N0) - g.h[1];
   p[0] = (int)(r % N0) - g.h[0];
+  const long b = bidx(g, p[0], p[1], p[2]);
   const int nd = g.ndim;
   bool near[3];
   for (int e = 0; e < 3; ++e) near[e] = e >= nd || (p[e] >= -2 && p[e] < g.n[e] + 2);
@@ -370,7 +372,7 @@ __global__ void __launch_bounds__(256) k_flux_x(Dev g, int nwmax) {
     }
     const unsigned r = r0 + seg;
     const int j = (int)(r % ny), k = (int)(r / ny);
-    const long bx = (long)(k + g.h[2]) * g.sb[2] + (long)(j + g.h[1]) * g.sb[1] + (xc + g.h[0]);
+    const long bx = bidx(g, xc, j, k);
 #pragma unroll
     for (int sl = 0; sl < S::NC; ++sl) {
       if ((sl == QV && NDIM < 2) || (sl == QW && NDIM < 3)) continue;
@@ -420,7 +422,7 @@ __global__ void __launch_bounds__(256) k_flux_yz(Dev g) {
     p[0] = i;
     p[D] = s;
     p[3 - D] = oc;  // D = 1 -> axis 2, D = 2 -> axis 1
-    const long bx = (long)(p[2] + g.h[2]) * g.sb[2] + (long)(p[1] + g.h[1]) * g.sb[1] + (p[0] + g.h[0]);
+    const long bx = bidx(g, p[0], p[1], p[2]);
 #pragma unroll
     for (int sl = 0; sl < S::NC; ++sl) {
       if ((sl == QV && NDIM < 2) || (sl == QW && NDIM < 3)) continue;
@@ -449,19 +451,6 @@ __global__ void __launch_bounds__(256) k_flux_yz(Dev g) {
 // Index of the face left of cell (i, j, k) in direction D's face array.
 __device__ __forceinline__ long face_index(const Dev &g, int D, int i, int j, int k) {
   return ((long)k * g.fn[D][1] + j) * g.fn[D][0] + i;
-}
-
-// x-momentum right-hand side without source at cell c, for the body force.
-__device__ __forceinline__ double rhs_xmom(const Dev &g, int i, int j, int k) {
-  double r = 0.0;
-  for (int D = 0; D < g.ndim; ++D) {
-    long fl = face_index(g, D, i, j, k);
-    long fr = fl + (D == 0 ? 1 : (D == 1 ? g.fn[1][0] : (long)g.fn[2][0] * g.fn[2][1]));
-    int pos = D == 0 ? i : (D == 1 ? j : k);
-    const double *F = g.F[D] + 1 * g.fcount[D];
-    r -= (F[fr] - F[fl]) * g.idx[D][pos];
-  }
-  return r;
 }
 
 __device__ __forceinline__ double cell_volume(const Dev &g, int i, int j, int k) {
@@ -502,17 +491,46 @@ __device__ __forceinline__ double block_max(double v, double *sh) {
   return sh[0];
 }
 
-// Body force, pass 1: per-block partial sums of V*R_rhou and V.
+// Body force, pass 1.  The volume-weighted sum of the unforced x-momentum
+// right-hand side, sum_c V_c R_c = -sum_D sum_c A_D (F_D(c+1/2) - F_D(c-1/2))
+// with A_D = V_c / dx_D constant along a grid line, telescopes along every
+// line to its two boundary faces: -sum_lines A_D (F_D(n) - F_D(0)).  (On a
+// periodic axis both boundary faces see the same stencil values, so their
+// fluxes are equal and cancel.)  Per-block partial sums of that boundary
+// term and of the volume, over one thread per boundary line.
 __global__ void __launch_bounds__(256) k_force_partial(Dev g, double *part) {
   __shared__ double sh[2 * 256];
   double v[2] = {0.0, 0.0};
-  for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < g.ncell;
-       c += (long)gridDim.x * blockDim.x) {
-    int i = (int)(c % g.n[0]), j = (int)((c / g.n[0]) % g.n[1]),
-        k = (int)(c / ((long)g.n[0] * g.n[1]));
-    double V = cell_volume(g, i, j, k);
-    v[0] += V * rhs_xmom(g, i, j, k);
-    v[1] += V;
+  const int nd = g.ndim;
+  long nl[3] = {0, 0, 0}, tot = 0;
+  for (int D = 0; D < nd; ++D) {
+    nl[D] = (long)g.n[tan1(D)] * g.n[tan2(D)];
+    tot += nl[D];
+  }
+  for (long x = (long)blockIdx.x * blockDim.x + threadIdx.x; x < tot;
+       x += (long)gridDim.x * blockDim.x) {
+    int D = 0;
+    long l = x;
+    while (l >= nl[D]) l -= nl[D++];
+    const int T1 = tan1(D), T2 = tan2(D);
+    const int a = (int)(l % g.n[T1]), b = (int)(l / g.n[T1]);
+    double A = 1.0;
+    if (T1 < nd) A *= g.dx[T1][a];
+    if (T2 < nd) A *= g.dx[T2][b];
+    int p[3];
+    p[T1] = a;
+    p[T2] = b;
+    p[D] = 0;
+    const long f0 = ((long)p[2] * g.fn[D][1] + p[1]) * g.fn[D][0] + p[0];
+    p[D] = g.n[D];
+    const long f1 = ((long)p[2] * g.fn[D][1] + p[1]) * g.fn[D][0] + p[0];
+    const double *F = g.F[D] + 1 * g.fcount[D];
+    v[0] -= A * (F[f1] - F[f0]);
+    if (D == 0) {  // volume: sum over x-lines of A_x * line length
+      double Lx = 0.0;
+      for (int i = 0; i < g.n[0]; ++i) Lx += g.dx[0][i];
+      v[1] += A * Lx;
+    }
   }
   block_sum<2>(v, sh);
   if (threadIdx.x == 0) {
@@ -559,7 +577,7 @@ __global__ void __launch_bounds__(256) k_update(Dev g, const double *Un, const d
   }
   if (g.source == SRC_MASSFLUX) {
     double f = force[0];
-    long b = (long)(k + g.h[2]) * g.sb[2] + (long)(j + g.h[1]) * g.sb[1] + (i + g.h[0]);
+    long b = bidx(g, i, j, k);
     R[1] += f;
     R[4] += f * g.Q[QU][b];
   }
@@ -638,7 +656,7 @@ __global__ void __launch_bounds__(256) k_diag_partial(Dev g, const double *U, do
     int i = (int)(c % g.n[0]), j = (int)((c / g.n[0]) % g.n[1]),
         k = (int)(c / ((long)g.n[0] * g.n[1]));
     double V = cell_volume(g, i, j, k);
-    long b = (long)(k + g.h[2]) * g.sb[2] + (long)(j + g.h[1]) * g.sb[1] + (i + g.h[0]);
+    long b = bidx(g, i, j, k);
     double rho = g.Q[QR][b], u = g.Q[QU][b];
     double vv = g.ndim >= 2 ? g.Q[QV][b] : 0.0, w = g.ndim >= 3 ? g.Q[QW][b] : 0.0;
     v[0] += V * 0.5 * rho * (u * u + vv * vv + w * w);
@@ -848,7 +866,9 @@ hipError_t launch_fluxes(const Dev &g, hipStream_t st) {
   return hipSuccess;
 }
 hipError_t launch_force(const Dev &g, double *part, double *force, hipStream_t st) {
-  unsigned nb = grid_capped(g.ncell, RED_BLOCKS);
+  long lines = 0;
+  for (int D = 0; D < g.ndim; ++D) lines += (long)g.n[tan1(D)] * g.n[tan2(D)];
+  unsigned nb = grid_capped(lines, RED_BLOCKS);
   k_force_partial<<<nb, 256, 0, st>>>(g, part);
   k_force_final<<<1, 256, 0, st>>>(part, (int)nb, force);
   return hipGetLastError();

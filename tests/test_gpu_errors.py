@@ -1,0 +1,92 @@
+"""Error paths of the C ABI on a device context: every argument error is a
+status (never a crash), reported before anything is enqueued."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2406_19494_amd import binding as B
+from paper_2406_19494_amd import workloads as W
+from paper_2406_19494_amd.solver import Solver
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(case):
+    g = B.dcf_grid()
+    g.ndim = case.ndim
+    for d in range(3):
+        g.n[d], g.lo[d], g.hi[d] = case.n[d], case.lo[d], case.hi[d]
+        g.stretch[d], g.beta[d] = B.STRETCH[case.stretch[d]], case.beta[d]
+    gas = B.dcf_gas(case.gamma, case.R, case.Pr, B.VISC[case.visc_law], case.mu_ref, case.T_ref,
+                    case.visc_param)
+    ctx = C.c_void_p()
+    B.call("dcf_create", C.byref(g), C.byref(gas), C.byref(ctx))
+    return ctx
+
+
+def test_workspace_too_small_and_unset():
+    case, P = W.tgv(8)
+    L = B.lib()
+    ctx = _ctx(case)
+    U = torch.zeros((5, 8, 8, 8), dtype=torch.float64, device="cuda")
+    R = torch.empty_like(U)
+    # no workspace yet
+    assert L.dcf_rhs(ctx, C.c_void_p(U.data_ptr()), C.c_void_p(R.data_ptr()), None) == -2
+    size = C.c_size_t()
+    B.call("dcf_workspace_size", ctx, 0, 0, 0, C.byref(size))
+    ws = torch.empty(size.value, dtype=torch.uint8, device="cuda")
+    assert L.dcf_set_workspace(ctx, 0, 0, 0, C.c_void_p(ws.data_ptr()), size.value - 1) == -2
+    # misaligned
+    assert L.dcf_set_workspace(ctx, 0, 0, 0, C.c_void_p(ws.data_ptr() + 8), size.value) == -1
+    B.call("dcf_set_workspace", ctx, 0, 0, 0, C.c_void_p(ws.data_ptr()), size.value)
+    # mode-0 workspace cannot run the adjoint
+    lam = torch.zeros_like(U)
+    dt = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+    rc = L.dcf_vjp_step(ctx, C.c_void_p(U.data_ptr()), C.c_void_p(dt.data_ptr()),
+                        C.c_void_p(lam.data_ptr()), C.c_void_p(R.data_ptr()), None, None)
+    assert rc == -2
+    L.dcf_destroy(ctx)
+
+
+def test_unpaired_periodic_face_rejected():
+    case, P = W.channel(nx=8, ny=8, nz=8)
+    case = W.Case(**{**case.__dict__, "bc": ("periodic", "zerograd", "wall", "wall",
+                                             "periodic", "periodic")})
+    with pytest.raises(B.DcfError) as ei:
+        s = Solver(case)
+        s.rhs(s.init_state(P))
+    assert ei.value.code == -1 and "pairs" in str(ei.value)
+
+
+def test_adjoint_of_body_force_unsupported():
+    case, P = W.channel(nx=8, ny=8, nz=8)
+    s = Solver(case, mode=1)
+    U = s.init_state(P)
+    dt = torch.full((1,), 1e-4, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.DcfError) as ei:
+        s.vjp_step(U, dt, torch.zeros_like(U))
+    assert ei.value.code == -6
+
+
+def test_bad_porous_strip_and_params():
+    case, P, K = W.porous_bl(nx=32, ny=16, strip=(8, 24), nsteps=1)
+    bad = W.Case(**{**case.__dict__, "porous_end": 40})
+    with pytest.raises(B.DcfError) as ei:
+        Solver(bad, K=K)
+    assert ei.value.code == -1
+    s = Solver(case, K=K)
+    with pytest.raises(B.DcfError):
+        s.set_params(torch.zeros(case.nk + 1, dtype=torch.float64, device="cuda"))
+
+
+def test_gradient_sized_for_other_trajectory_rejected():
+    case, P, K = W.porous_bl(nx=32, ny=16, strip=(8, 24), nsteps=1)
+    s = Solver(case, K=K, mode=2, nsteps=4, seg_len=2)
+    U = s.init_state(P)
+    dt = torch.full((1,), 1e-6, dtype=torch.float64, device="cuda")
+    s.nsteps = 5  # not what the workspace was sized for
+    with pytest.raises(B.DcfError) as ei:
+        s.gradient(U, dt)
+    assert ei.value.code == -1
