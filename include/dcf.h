@@ -54,10 +54,11 @@ typedef int dcf_status;
 
 /* boundary kinds (Section 3.2: halo cells carry the boundary condition) */
 #define DCF_BC_PERIODIC 0
-#define DCF_BC_WALL 1      /* isothermal no-slip wall                                  */
-#define DCF_BC_POROUS 2    /* isothermal wall with a Darcy transpiration strip        */
+#define DCF_BC_WALL 1      /* no-slip wall, isothermal or adiabatic                    */
+#define DCF_BC_POROUS 2    /* wall with a Darcy transpiration strip                   */
 #define DCF_BC_ZEROGRAD 3  /* zero-gradient extrapolation                             */
 #define DCF_BC_DIRICHLET 4 /* prescribed primitive profile                            */
+#define DCF_BC_DISTURB 5   /* wall with normal velocity A sin(2 pi kappa x), Eq. (8)   */
 
 #define DCF_VISC_NONE 0
 #define DCF_VISC_POWER 1      /* mu = mu_ref (T/T_ref)^omega                          */
@@ -97,11 +98,13 @@ typedef struct {
 /* One face's boundary condition.  Faces: 0..5 = x-, x+, y-, y+, z-, z+. */
 typedef struct {
   int kind;                 /* DCF_BC_*                                          */
-  double T_wall;            /* wall temperature (WALL, POROUS)                   */
+  double T_wall;            /* wall kinds: temperature > 0, or 0 for adiabatic   */
   const double *dirichlet;  /* dev, DIRICHLET: [5][n_t2][n_t1] (rho,u,v,w,p)     */
   int porous_begin;         /* POROUS: strip [begin, end) along the face's first  */
   int porous_end;           /*   tangential axis, all cells along the second one  */
   double p_inf;             /* POROUS: reference pressure of the Darcy law        */
+  double dist_amp;          /* DISTURB: amplitude A                               */
+  double dist_kappa;        /* DISTURB: wavenumber kappa                          */
 } dcf_bc;
 
 /* ---- context ------------------------------------------------------------ */
@@ -126,10 +129,17 @@ dcf_status dcf_set_workspace(dcf_ctx *ctx, int mode, int nsteps, int seg_len, vo
                              size_t bytes);
 
 /* Boundary condition of one face (Section 3.2).  Periodic faces must be
- * set in pairs.  Porous: the wall-normal velocity along the inward normal
- * is v_w = -K_i (p_w - p_inf)/p_inf, p_w the pressure of the first interior
- * cell; ghost velocity = 2 v_w n - u_mirror, tangential no-slip, isothermal
- * T_g = 2 T_wall - T_mirror.  At most one face may be porous. */
+ * set in pairs.  Walls mirror the velocity (u_g = -u_mirror, no slip) and
+ * the pressure; isothermal walls (T_wall > 0) set T_g = 2 T_wall - T_mirror
+ * and rho_g = p_g/(R T_g), adiabatic walls (T_wall = 0) mirror T and rho.
+ * Porous: the wall-normal velocity along the inward normal is
+ * v_w = -K_i (p_w - p_inf)/p_inf, p_w the pressure of the first interior
+ * cell, and the ghost normal velocity is 2 v_w - u_mirror.  Disturbance
+ * wall (Section 3.2, Eq. (8)): v_w = A sin(2 pi kappa x_c), x_c the centre
+ * of the wall face along the face's first tangential axis (x for y walls,
+ * y for x walls).  At most one face may be porous.  Returns DCF_EINVAL for
+ * an unknown kind, a negative or non-finite T_wall, or a porous strip
+ * outside the face. */
 dcf_status dcf_set_bc(dcf_ctx *ctx, int face, const dcf_bc *bc);
 
 /* Porous coefficients K (dev, nK doubles, indexed strip-fastest); the

@@ -328,9 +328,11 @@ template <class T> struct Solver {
               Q[3][G] = P[3 * nt + o];
               Q[4][G] = P[4 * nt + o];
               Q[5][G] = Q[4][G] / (Q[0][G] * c.R);
-            } else { /* isothermal no-slip wall, optionally porous */
+            } else { /* no-slip wall: isothermal or adiabatic, optionally porous
+                        or with a prescribed normal velocity */
               long S = at(d, side == 0 ? m : n[d] - 1 - m, a, b);
               T vel[3] = {-1.0 * Q[1][S], -1.0 * Q[2][S], -1.0 * Q[3][S]};
+              double sigma = side == 0 ? 1.0 : -1.0;
               if (kind == ORC_POROUS && face == c.porous_face && a >= c.porous_begin &&
                   a < c.porous_end && b >= 0 && b < n[t2(d)]) {
                 /* Darcy transpiration: wall-normal velocity along the inward
@@ -339,17 +341,29 @@ template <class T> struct Solver {
                 long W = at(d, side == 0 ? 0 : n[d] - 1, a, b);
                 int kk = b * (c.porous_end - c.porous_begin) + (a - c.porous_begin);
                 T vn = -1.0 * K[kk] * (Q[4][W] - c.p_inf) / c.p_inf;
-                double sigma = side == 0 ? 1.0 : -1.0;
+                vel[d] = 2.0 * sigma * vn - Q[1 + d][S];
+              }
+              if (kind == ORC_DISTURB && a >= 0 && a < n[t1(d)]) {
+                /* Disturbance wall: v_n = A sin(2 pi kappa x) at the centre
+                 * of the wall face along the first tangential axis. */
+                const Axis &ta = ax[t1(d)];
+                double xc = 0.5 * (ta.xf[a] + ta.xf[a + 1]);
+                double vn = c.dist_amp[face] * std::sin(2.0 * M_PI * c.dist_kappa[face] * xc);
                 vel[d] = 2.0 * sigma * vn - Q[1 + d][S];
               }
               T p = Q[4][S];
-              T Tg = 2.0 * c.T_wall[face] - Q[5][S];
-              Q[0][G] = p / (c.R * Tg);
+              if (c.T_wall[face] > 0.0) { /* isothermal */
+                T Tg = 2.0 * c.T_wall[face] - Q[5][S];
+                Q[0][G] = p / (c.R * Tg);
+                Q[5][G] = Tg;
+              } else { /* adiabatic: temperature and density mirror */
+                Q[0][G] = Q[0][S];
+                Q[5][G] = Q[5][S];
+              }
               Q[1][G] = vel[0];
               Q[2][G] = vel[1];
               Q[3][G] = vel[2];
               Q[4][G] = p;
-              Q[5][G] = Tg;
             }
           }
       }

@@ -32,7 +32,9 @@ enum {
   ORC_WALL = 1,      /* isothermal no-slip wall                            */
   ORC_POROUS = 2,    /* isothermal wall with Darcy transpiration strip     */
   ORC_ZEROGRAD = 3,  /* zero-gradient extrapolation                         */
-  ORC_DIRICHLET = 4  /* prescribed primitive profile                        */
+  ORC_DIRICHLET = 4, /* prescribed primitive profile                        */
+  ORC_DISTURB = 5    /* no-slip wall with prescribed normal velocity
+                        A sin(2 pi kappa x_t) (Section 3.2, Eq. (8))        */
 };
 
 enum { ORC_VISC_NONE = 0, ORC_VISC_POWER = 1, ORC_VISC_SUTHERLAND = 2 };
@@ -50,7 +52,8 @@ typedef struct {
   double mu_ref, T_ref;  /* viscosity at the reference temperature          */
   double visc_param;     /* power-law exponent, or Sutherland constant       */
   int bc[6];             /* faces x-, x+, y-, y+, z-, z+                    */
-  double T_wall[6];      /* wall temperature per face (walls only)           */
+  double T_wall[6];      /* wall temperature per face; 0 = adiabatic wall     */
+  double dist_amp[6], dist_kappa[6]; /* disturbance wall amplitude, wavenumber */
   const double *dirichlet[6]; /* [5][n_t2][n_t1] per Dirichlet face          */
   int porous_face;       /* face carrying the porous strip, -1 for none      */
   int porous_begin, porous_end; /* strip range along the first tangential axis */

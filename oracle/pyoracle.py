@@ -12,7 +12,7 @@ import numpy as np
 
 from . import build as _build
 
-_BC = {"periodic": 0, "wall": 1, "porous": 2, "zerograd": 3, "dirichlet": 4}
+_BC = {"periodic": 0, "wall": 1, "porous": 2, "zerograd": 3, "dirichlet": 4, "disturb": 5}
 _VISC = {"none": 0, "power": 1, "sutherland": 2}
 _STRETCH = {"uniform": 0, "tanh2": 1, "tanh1": 2}
 _SRC = {"none": 0, "massflux": 1}
@@ -27,6 +27,7 @@ class OrcCase(C.Structure):
         ("gamma", C.c_double), ("R", C.c_double), ("Pr", C.c_double),
         ("visc_law", C.c_int), ("mu_ref", C.c_double), ("T_ref", C.c_double),
         ("visc_param", C.c_double), ("bc", C.c_int * 6), ("T_wall", C.c_double * 6),
+        ("dist_amp", C.c_double * 6), ("dist_kappa", C.c_double * 6),
         ("dirichlet", _dp * 6), ("porous_face", C.c_int), ("porous_begin", C.c_int),
         ("porous_end", C.c_int), ("p_inf", C.c_double), ("source", C.c_int),
         ("cost_face", C.c_int),
@@ -100,6 +101,8 @@ class Oracle:
         for f in range(6):
             s.bc[f] = _BC[case.bc[f]]
             s.T_wall[f] = case.T_wall[f]
+            s.dist_amp[f] = case.dist_amp[f]
+            s.dist_kappa[f] = case.dist_kappa[f]
             if f in case.dirichlet:
                 arr = np.ascontiguousarray(case.dirichlet[f], dtype=np.float64)
                 self._keep.append(arr)

@@ -15,7 +15,7 @@ DCF_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONPHYS", -5: "EBUDGET",
           -6: "EUNSUPPORTED"}
 
-BC = {"periodic": 0, "wall": 1, "porous": 2, "zerograd": 3, "dirichlet": 4}
+BC = {"periodic": 0, "wall": 1, "porous": 2, "zerograd": 3, "dirichlet": 4, "disturb": 5}
 VISC = {"none": 0, "power": 1, "sutherland": 2}
 STRETCH = {"uniform": 0, "tanh2": 1, "tanh1": 2}
 SOURCE = {"none": 0, "massflux": 1}
@@ -40,7 +40,8 @@ class dcf_gas(C.Structure):
 
 class dcf_bc(C.Structure):
     _fields_ = [("kind", C.c_int), ("T_wall", C.c_double), ("dirichlet", C.c_void_p),
-                ("porous_begin", C.c_int), ("porous_end", C.c_int), ("p_inf", C.c_double)]
+                ("porous_begin", C.c_int), ("porous_end", C.c_int), ("p_inf", C.c_double),
+                ("dist_amp", C.c_double), ("dist_kappa", C.c_double)]
 
 
 _vp = C.c_void_p

@@ -621,13 +621,22 @@ __global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, do
         for (int q = 0; q < 6; ++q) A.Qb[q][S] += A.Qb[q][G];
         continue;
       }
-      // wall: rho_g = p_g/(R T_g), p_g = p_s, T_g = 2 T_w - T_s, u_g = -u_s
-      double rg = g.Q[QR][G], pg = g.Q[QP][G];
-      double rb = A.Qb[QR][G];
-      double pgb = A.Qb[QP][G] + rb * rg / pg;
-      double Tgb = A.Qb[QT][G] - rb * rg * rg * g.R / pg;
-      A.Qb[QP][S] += pgb;
-      A.Qb[QT][S] -= Tgb;
+      // walls: p_g = p_s, u_g = -u_s (plus a prescribed normal part that
+      // depends on the state only through the porous p_w below);
+      // isothermal: rho_g = p_g/(R T_g), T_g = 2 T_w - T_s; adiabatic:
+      // rho_g = rho_s, T_g = T_s
+      if (g.Tw[face] > 0.0) {
+        double rg = g.Q[QR][G], pg = g.Q[QP][G];
+        double rb = A.Qb[QR][G];
+        double pgb = A.Qb[QP][G] + rb * rg / pg;
+        double Tgb = A.Qb[QT][G] - rb * rg * rg * g.R / pg;
+        A.Qb[QP][S] += pgb;
+        A.Qb[QT][S] -= Tgb;
+      } else {
+        A.Qb[QR][S] += A.Qb[QR][G];
+        A.Qb[QP][S] += A.Qb[QP][G];
+        A.Qb[QT][S] += A.Qb[QT][G];
+      }
       for (int c = 0; c < nd; ++c) A.Qb[QU + c][S] -= A.Qb[QU + c][G];
       if (kind == BC_POROUS && face == g.pface && a >= g.pb && a < g.pe && bq >= 0 &&
           bq < g.n[t2]) {

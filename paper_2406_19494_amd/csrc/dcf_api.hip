@@ -150,7 +150,7 @@ dcf_status dcf_create(const dcf_grid *grid, const dcf_gas *gas, dcf_ctx **out) {
   g.source = SRC_NONE;
 
   size_t total = 0;
-  for (int d = 0; d < 3; ++d) total += 4 * (size_t)(g.n[d] + 1);
+  for (int d = 0; d < 3; ++d) total += 5 * (size_t)(g.n[d] + 1);
   hipError_t e = hipMalloc((void **)&c->metric_mem, total * sizeof(double));
   if (e != hipSuccess) {
     delete c;
@@ -163,6 +163,7 @@ dcf_status dcf_create(const dcf_grid *grid, const dcf_gas *gas, dcf_ctx **out) {
     g.idx[d] = p + m;
     g.mc[d] = p + 2 * m;
     g.mf[d] = p + 3 * m;
+    g.xm[d] = p + 4 * m;
     double lo = grid->lo[d], hi = grid->hi[d];
     int kind = d < grid->ndim ? grid->stretch[d] : 0;
     if (d >= grid->ndim) {  // unused axis: unit width
@@ -170,14 +171,14 @@ dcf_status dcf_create(const dcf_grid *grid, const dcf_gas *gas, dcf_ctx **out) {
       hi = 1.0;
     }
     e = launch_metrics(kind, lo, hi, grid->beta[d], g.n[d], (double *)g.dx[d], (double *)g.idx[d],
-                       (double *)g.mc[d], (double *)g.mf[d], 0);
+                       (double *)g.mc[d], (double *)g.mf[d], (double *)g.xm[d], 0);
     if (e == hipSuccess) e = hipStreamSynchronize(0);
     if (e != hipSuccess) {
       (void)hipFree(c->metric_mem);
       delete c;
       return fail(DCF_EDEVICE, "metrics kernel: %s", hipGetErrorString(e));
     }
-    p += 4 * m;
+    p += 5 * m;
   }
   *out = c;
   return DCF_OK;
@@ -269,11 +270,14 @@ dcf_status dcf_set_bc(dcf_ctx *c, int face, const dcf_bc *bc) {
   if (face < 0 || face > 5) return fail(DCF_EINVAL, "face must be 0..5");
   int d = face / 2;
   if (d >= c->g.ndim) return fail(DCF_EINVAL, "face %d is on an unused axis", face);
-  if (bc->kind < 0 || bc->kind > 4) return fail(DCF_EINVAL, "unknown boundary kind");
+  if (bc->kind < 0 || bc->kind > 5) return fail(DCF_EINVAL, "unknown boundary kind");
   Dev &g = c->g;
-  if (bc->kind == BC_WALL || bc->kind == BC_POROUS) {
-    if (!(bc->T_wall > 0.0)) return fail(DCF_EINVAL, "wall needs T_wall > 0");
+  if (is_wall(bc->kind)) {
+    if (!(bc->T_wall >= 0.0) || bc->T_wall > 1e300)
+      return fail(DCF_EINVAL, "wall needs T_wall > 0 (isothermal) or 0 (adiabatic)");
   }
+  if (bc->kind == BC_DISTURB && !(fabs(bc->dist_amp) < 1e300 && fabs(bc->dist_kappa) < 1e300))
+    return fail(DCF_EINVAL, "disturbance amplitude and wavenumber must be finite");
   if (bc->kind == BC_DIRICHLET && !bc->dirichlet)
     return fail(DCF_EINVAL, "Dirichlet face needs a profile");
   if (bc->kind == BC_POROUS) {
@@ -294,7 +298,9 @@ dcf_status dcf_set_bc(dcf_ctx *c, int face, const dcf_bc *bc) {
     c->nK = 0;
   }
   g.bck[face] = bc->kind;
-  g.Tw[face] = bc->T_wall;
+  g.Tw[face] = is_wall(bc->kind) ? bc->T_wall : 0.0;
+  g.damp[face] = bc->kind == BC_DISTURB ? bc->dist_amp : 0.0;
+  g.dkap[face] = bc->kind == BC_DISTURB ? bc->dist_kappa : 0.0;
   g.dir[face] = bc->dirichlet;
   return DCF_OK;
 }

@@ -22,7 +22,12 @@ namespace dcf {
 
 constexpr int NH = 3;  // halo layers per active axis (Section 2.2)
 
-enum : int { BC_PERIODIC = 0, BC_WALL = 1, BC_POROUS = 2, BC_ZEROGRAD = 3, BC_DIRICHLET = 4 };
+enum : int {
+  BC_PERIODIC = 0, BC_WALL = 1, BC_POROUS = 2, BC_ZEROGRAD = 3, BC_DIRICHLET = 4, BC_DISTURB = 5
+};
+__host__ __device__ __forceinline__ bool is_wall(int k) {
+  return k == BC_WALL || k == BC_POROUS || k == BC_DISTURB;
+}
 enum : int { VISC_NONE = 0, VISC_POWER = 1, VISC_SUTHERLAND = 2 };
 enum : int { SRC_NONE = 0, SRC_MASSFLUX = 1 };
 enum : int { QR = 0, QU = 1, QV = 2, QW = 3, QP = 4, QT = 5, QMU = 6, NQ = 7 };
@@ -38,12 +43,14 @@ struct Dev {
   // grid metrics per axis (device arrays): widths, 1/width, dxi/dx at
   // centres (n) and at faces (n+1)
   const double *dx[3], *idx[3], *mc[3], *mf[3];
+  const double *xm[3];   // cell-centre coordinates (midpoint of the two faces)
   // gas
   double gamma, R, Pr, cp, mu_ref, T_ref, vparam;
   int visc;
   // boundaries
   int bck[6];
-  double Tw[6];
+  double Tw[6];          // wall temperature; 0 = adiabatic wall
+  double damp[6], dkap[6];  // disturbance wall: v_n = damp sin(2 pi dkap x_t1)
   const double *dir[6];
   int pface, pb, pe;
   double pinf;

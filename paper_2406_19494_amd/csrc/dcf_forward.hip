@@ -32,7 +32,7 @@ __device__ void axis_map(int kind, double lo, double hi, double beta, int n, dou
 }
 
 __global__ void k_metrics(int kind, double lo, double hi, double beta, int n, double *dx,
-                          double *idx, double *mc, double *mf) {
+                          double *idx, double *mc, double *mf, double *xm) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i > n) return;
   double x0, g0;
@@ -44,6 +44,7 @@ __global__ void k_metrics(int kind, double lo, double hi, double beta, int n, do
     axis_map(kind, lo, hi, beta, n, (i + 0.5) / n, &xc, &gc);
     dx[i] = x1 - x0;
     idx[i] = 1.0 / (x1 - x0);
+    xm[i] = 0.5 * (x0 + x1);
     mc[i] = 1.0 / gc;
   }
 }
@@ -167,15 +168,16 @@ __global__ void __launch_bounds__(256) k_prim_halo(Dev g, const double *U) {
     if (!gh[d]) continue;
     const int face = 2 * d + side[d];
     const int kind = g.bck[face];
-    if (kind != BC_WALL && kind != BC_POROUS) continue;  // copies keep the value
+    if (!is_wall(kind)) continue;  // copies keep the value
     double src_n = q[QU + d];
     q[QU] = -q[QU];
     q[QV] = -q[QV];
     q[QW] = -q[QW];
+    const int t1 = tan1(d), t2 = tan2(d);
+    const int a = t1 < nd ? (t1 < d ? p[t1] : s[t1]) : 0;
+    const int bb = t2 < nd ? (t2 < d ? p[t2] : s[t2]) : 0;
+    const double sigma = side[d] == 0 ? 1.0 : -1.0;
     if (kind == BC_POROUS && face == g.pface) {
-      const int t1 = tan1(d), t2 = tan2(d);
-      int a = t1 < nd ? (t1 < d ? p[t1] : s[t1]) : 0;
-      int bb = t2 < nd ? (t2 < d ? p[t2] : s[t2]) : 0;
       if (a >= g.pb && a < g.pe && bb >= 0 && bb < g.n[t2]) {
         // Darcy transpiration through the porous strip: inward-normal
         // velocity -K (p_w - p_inf)/p_inf, p_w of the first interior cell.
@@ -188,14 +190,20 @@ __global__ void __launch_bounds__(256) k_prim_halo(Dev g, const double *U) {
         cons_to_prim(g, U, cw, qw);
         int kk = bb * (g.pe - g.pb) + (a - g.pb);
         double vn = -g.K[kk] * (qw[QP] - g.pinf) / g.pinf;
-        double sigma = side[d] == 0 ? 1.0 : -1.0;
         q[QU + d] = 2.0 * sigma * vn - src_n;
       }
+    } else if (kind == BC_DISTURB && a >= 0 && a < g.n[t1]) {
+      // Disturbance wall (Section 3.2, Eq. (8)): prescribed inward-normal
+      // velocity A sin(2 pi kappa x) at the wall-face centre.
+      double vn = g.damp[face] * sin(2.0 * M_PI * g.dkap[face] * g.xm[t1][a]);
+      q[QU + d] = 2.0 * sigma * vn - src_n;
     }
-    double Tg = 2.0 * g.Tw[face] - q[QT];
-    if (!(Tg > 0.0)) atomicOr(g.flags, 1u);
-    q[QT] = Tg;
-    q[QR] = q[QP] / (g.R * Tg);
+    if (g.Tw[face] > 0.0) {  // isothermal; adiabatic keeps rho and T
+      double Tg = 2.0 * g.Tw[face] - q[QT];
+      if (!(Tg > 0.0)) atomicOr(g.flags, 1u);
+      q[QT] = Tg;
+      q[QR] = q[QP] / (g.R * Tg);
+    }
   }
   g.Q[QR][b] = q[QR];
   g.Q[QU][b] = q[QU];
@@ -806,8 +814,8 @@ hipError_t launch_axpy(double *y, double a, const double *x, long n, hipStream_t
 }
 
 hipError_t launch_metrics(int kind, double lo, double hi, double beta, int n, double *dx,
-                          double *idx, double *mc, double *mf, hipStream_t st) {
-  k_metrics<<<grid_for(n + 1), 256, 0, st>>>(kind, lo, hi, beta, n, dx, idx, mc, mf);
+                          double *idx, double *mc, double *mf, double *xm, hipStream_t st) {
+  k_metrics<<<grid_for(n + 1), 256, 0, st>>>(kind, lo, hi, beta, n, dx, idx, mc, mf, xm);
   return hipGetLastError();
 }
 hipError_t launch_init_state(const Dev &g, const double *P, double *U, hipStream_t st) {

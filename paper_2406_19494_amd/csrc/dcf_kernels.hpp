@@ -9,7 +9,7 @@ namespace dcf {
 constexpr int RED_BLOCKS = 1024;  // partial-sum slots of the two-pass reductions
 
 hipError_t launch_metrics(int kind, double lo, double hi, double beta, int n, double *dx,
-                          double *idx, double *mc, double *mf, hipStream_t st);
+                          double *idx, double *mc, double *mf, double *xm, hipStream_t st);
 hipError_t launch_init_state(const Dev &g, const double *P, double *U, hipStream_t st);
 hipError_t launch_prim_halo(const Dev &g, const double *U, hipStream_t st);
 hipError_t launch_fluxes(const Dev &g, hipStream_t st);

@@ -60,6 +60,7 @@ class Solver:
             bc = B.dcf_bc()
             bc.kind = B.BC[case.bc[f]]
             bc.T_wall = case.T_wall[f]
+            bc.dist_amp, bc.dist_kappa = case.dist_amp[f], case.dist_kappa[f]
             if f in case.dirichlet:
                 prof = torch.as_tensor(np.ascontiguousarray(case.dirichlet[f]), dtype=torch.float64,
                                        device=self.device)

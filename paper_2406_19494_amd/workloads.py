@@ -33,7 +33,7 @@ from typing import Dict, Optional, Sequence, Tuple
 
 import numpy as np
 
-BC_KINDS = ("periodic", "wall", "porous", "zerograd", "dirichlet")
+BC_KINDS = ("periodic", "wall", "porous", "zerograd", "dirichlet", "disturb")
 VISC_LAWS = ("none", "power", "sutherland")
 STRETCH = ("uniform", "tanh2", "tanh1")
 SOURCES = ("none", "massflux")
@@ -58,7 +58,9 @@ class Case:
     T_ref: float = 1.0
     visc_param: float = 0.0
     bc: Tuple[str, ...] = ("periodic",) * 6
-    T_wall: Tuple[float, ...] = (0.0,) * 6
+    T_wall: Tuple[float, ...] = (0.0,) * 6        # 0 on a wall face: adiabatic
+    dist_amp: Tuple[float, ...] = (0.0,) * 6      # disturbance wall amplitude
+    dist_kappa: Tuple[float, ...] = (0.0,) * 6    # disturbance wall wavenumber
     dirichlet: Dict[int, np.ndarray] = dataclasses.field(default_factory=dict)
     porous_face: int = -1
     porous_begin: int = 0
@@ -244,7 +246,8 @@ def similarity_profile(Ma: float, Pr: float, gamma: float, Tw_ratio: float, S_ra
         (C/Pr g')' + f g' + (gamma - 1) Ma^2 C f''^2 = 0,
 
     with C = rho mu / (rho_e mu_e) = mu(T)/mu_e / g, g = T/T_e,
-    f(0) = f'(0) = 0, g(0) = Tw_ratio, f'(inf) = 1, g(inf) = 1.
+    f(0) = f'(0) = 0, g(0) = Tw_ratio (g'(0) = 0 when Tw_ratio is None: an
+    adiabatic wall), f'(inf) = 1, g(inf) = 1.
     Returns (eta, f, f', g)."""
     from scipy.integrate import solve_bvp
 
@@ -260,18 +263,70 @@ def similarity_profile(Ma: float, Pr: float, gamma: float, Tw_ratio: float, S_ra
         return np.vstack([fp, fpp, -f * fpp, gp, -f * gp - (gamma - 1.0) * Ma * Ma * C * fpp * fpp])
 
     def bc(Ya, Yb):
-        return np.array([Ya[0], Ya[1], Ya[3] - Tw_ratio, Yb[1] - 1.0, Yb[3] - 1.0])
+        wall_T = Ya[4] if Tw_ratio is None else Ya[3] - Tw_ratio
+        return np.array([Ya[0], Ya[1], wall_T, Yb[1] - 1.0, Yb[3] - 1.0])
 
     eta = np.linspace(0.0, eta_max, npts)
     fp0 = np.tanh(eta)
+    if Tw_ratio is None:  # adiabatic: recovery temperature (factor Pr^(1/2)) as first guess
+        g0 = 1.0 + 0.5 * (gamma - 1.0) * Ma * Ma * math.sqrt(Pr)
+        gguess = 1.0 + (g0 - 1.0) * (1 - fp0 ** 2)
+    else:
+        gguess = 1.0 + (Tw_ratio - 1.0) * (1 - fp0)
     Y0 = np.vstack([eta - np.tanh(eta) + np.tanh(eta) * 0.0, fp0, 0.5 * (1 - fp0 ** 2),
-                    1.0 + (Tw_ratio - 1.0) * (1 - fp0), np.zeros_like(eta)])
+                    gguess, np.zeros_like(eta)])
     Y0[0] = np.cumsum(np.r_[0.0, 0.5 * (fp0[1:] + fp0[:-1]) * np.diff(eta)])
     sol = solve_bvp(rhs, bc, eta, Y0, tol=1e-9, max_nodes=200000)
     if not sol.success:
         raise RuntimeError("similarity solution did not converge: " + sol.message)
     Y = sol.sol(eta)
     return eta, Y[0], Y[1], Y[3]
+
+
+def _similarity_fields(case: Case, Ma: float, Pr: float, Tw_ratio: Optional[float],
+                       S_ratio: float, Re_unit: float, p_e: float) -> np.ndarray:
+    """Primitive field of the similarity boundary layer at every cell of a 2D
+    case (free stream rho = u = T = 1, pressure p_e), with the wall-normal
+    velocity from continuity, and the matching Dirichlet inflow profile on
+    face x- (stored into case.dirichlet)."""
+    nx, ny = case.n[0], case.n[1]
+    x0, x1 = case.lo[0], case.hi[0]
+    x, y, _ = _mesh(case)
+    eta, f, fp, g = similarity_profile(Ma, Pr, case.gamma, Tw_ratio, S_ratio)
+    # y(eta) at station x: y = sqrt(2 mu_e x / (rho_e u_e)) * int_0^eta g d eta
+    Y_eta = np.concatenate([[0.0], np.cumsum(0.5 * (g[1:] + g[:-1]) * np.diff(eta))])
+
+    def profile(xs, ys):
+        scale = np.sqrt(2.0 * (1.0 / Re_unit) * xs)
+        yt = ys / scale
+        u = np.interp(yt, Y_eta, fp, right=1.0)
+        T = np.interp(yt, Y_eta, g, right=1.0)
+        return u, T
+
+    u, T = profile(x[0], y[0])
+    # wall-normal velocity from continuity: rho v = -int_0^y d(rho u)/dx dy
+    hx = 1e-4
+    up, Tp = profile(x[0] + hx, y[0])
+    um, Tm = profile(x[0] - hx, y[0])
+    drhou = (up / Tp - um / Tm) / (2 * hx)
+    yy = y[0][:, 0]
+    dy = np.diff(np.concatenate([[0.0], yy]))
+    rhov = -np.cumsum(drhou * dy[:, None], axis=0)
+    rho = 1.0 / T
+    P = _prim(nx, ny, 1)
+    P[0, 0] = rho
+    P[1, 0] = u
+    P[2, 0] = rhov / rho
+    P[4, 0] = p_e
+    # Dirichlet inflow profile at x- : [5][n_t2 = 1][n_t1 = ny]
+    uin, Tin = profile(np.full(ny, x0 - 0.5 * (x1 - x0) / nx), yy)
+    D = np.zeros((5, 1, ny))
+    D[0, 0] = 1.0 / Tin
+    D[1, 0] = uin
+    D[2, 0] = P[2, 0, :, 0]
+    D[4, 0] = p_e
+    case.dirichlet = {0: D}
+    return P
 
 
 def porous_bl(nx: int = 1024, ny: int = 256, Ma: float = 6.0, T_inf_K: float = 65.0,
@@ -301,45 +356,41 @@ def porous_bl(nx: int = 1024, ny: int = 256, Ma: float = 6.0, T_inf_K: float = 6
                 bc=("dirichlet", "zerograd", "porous", "zerograd", "periodic", "periodic"),
                 T_wall=(0.0, 0.0, Tw, 0.0, 0.0, 0.0), porous_face=2, porous_begin=strip[0],
                 porous_end=strip[1], p_inf=p_inf, cost_face=2, nsteps=nsteps, dt_fixed=dt_fixed)
+    P = _similarity_fields(case, Ma, Pr, Tw, S_ratio, Re_unit, p_inf)
     x, y, _ = _mesh(case)
-    eta, f, fp, g = similarity_profile(Ma, Pr, gamma, Tw, S_ratio)
-    # y(eta) at station x: y = sqrt(2 mu_e x / (rho_e u_e)) * int_0^eta g d eta
-    Y_eta = np.concatenate([[0.0], np.cumsum(0.5 * (g[1:] + g[:-1]) * np.diff(eta))])
-
-    def profile(xs, ys):
-        scale = np.sqrt(2.0 * (1.0 / Re_unit) * xs)
-        yt = ys / scale
-        u = np.interp(yt, Y_eta, fp, right=1.0)
-        T = np.interp(yt, Y_eta, g, right=1.0)
-        return u, T
-
-    u, T = profile(x[0], y[0])
-    # wall-normal velocity from continuity: rho v = -int_0^y d(rho u)/dx dy
-    hx = 1e-4
-    up, Tp = profile(x[0] + hx, y[0])
-    um, Tm = profile(x[0] - hx, y[0])
-    drhou = (up / Tp - um / Tm) / (2 * hx)
-    yy = y[0][:, 0]
-    dy = np.diff(np.concatenate([[0.0], yy]))
-    rhov = -np.cumsum(drhou * dy[:, None], axis=0)
-    rho = 1.0 / T
-    P = _prim(nx, ny, 1)
     xm = 0.5 * (x0 + x1)
     pw = p_inf * (1.0 + pulse * np.exp(-((x[0] - xm) ** 2 + y[0] ** 2) / pulse_radius ** 2))
-    P[0, 0] = rho * pw / p_inf
-    P[1, 0] = u
-    P[2, 0] = rhov / rho
+    P[0, 0] *= pw / p_inf
     P[4, 0] = pw
-    # Dirichlet inflow profile at x- : [5][n_t2 = 1][n_t1 = ny]
-    uin, Tin = profile(np.full(ny, x0 - 0.5 * (x1 - x0) / nx), yy)
-    D = np.zeros((5, 1, ny))
-    D[0, 0] = 1.0 / Tin
-    D[1, 0] = uin
-    D[2, 0] = P[2, 0, :, 0]
-    D[4, 0] = p_inf
-    case.dirichlet = {0: D}
     K = k_max * uniform01(seed, case.nk, 7)
     return case, P, K
+
+
+def laminar_bl(nx: int = 300, ny: int = 200, Ma: float = 2.25, T_e_K: float = 169.44,
+               Re_unit: float = 1.0e4, Pr: float = 0.72, x0: float = 1.0, x1: float = 1.5,
+               H: float = 0.4, beta: float = 2.2, amp: float = 0.0, kappa: float = 10.0,
+               nsteps: int = 20000) -> Tuple[Case, np.ndarray]:
+    """Mach-2.25 laminar boundary layer over an adiabatic no-slip wall
+    (Section 3.2): (x, y) in [1, 1.5] x [0, 0.4], uniform in x, tanh
+    clustering toward the wall in y (beta = 2.2), similarity inflow at x-,
+    zero-gradient at x+ and y+, unit Reynolds number 1e4, Sutherland
+    viscosity, Pr = 0.72.  With amp != 0 the wall is the disturbance wall of
+    Eq. (8), v = amp sin(2 pi kappa x).  Free stream rho = u = T = 1, p_e =
+    1/(gamma Ma^2) = R.  T_e_K only sets the Sutherland constant ratio
+    S/T_e (S = 110.4 K).  The initial field is the similarity solution
+    everywhere.  Returns (case, P)."""
+    gamma = 1.4
+    p_e = 1.0 / (gamma * Ma * Ma)
+    S_ratio = 110.4 / T_e_K
+    case = Case(name="laminar_bl", ndim=2, n=(nx, ny, 1), lo=(x0, 0.0, 0.0), hi=(x1, H, 1.0),
+                stretch=("uniform", "tanh1", "uniform"), beta=(0.0, beta, 0.0), gamma=gamma,
+                R=p_e, Pr=Pr, visc_law="sutherland", mu_ref=1.0 / Re_unit, T_ref=1.0,
+                visc_param=S_ratio,
+                bc=("dirichlet", "zerograd", "disturb", "zerograd", "periodic", "periodic"),
+                T_wall=(0.0,) * 6, dist_amp=(0.0, 0.0, amp, 0.0, 0.0, 0.0),
+                dist_kappa=(0.0, 0.0, kappa, 0.0, 0.0, 0.0), p_inf=p_e, nsteps=nsteps)
+    P = _similarity_fields(case, Ma, Pr, None, S_ratio, Re_unit, p_e)
+    return case, P
 
 
 # --------------------------------------------------------------------------

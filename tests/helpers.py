@@ -50,6 +50,17 @@ def small_cases():
     # 2D porous boundary layer (Dirichlet in, zero-gradient out/top, porous wall)
     c, P, K = W.porous_bl(nx=40, ny=24, strip=(10, 30), nsteps=1)
     cases.append(("porous_bl2d", c, P, K + 0.05))
+    # 2D Mach-2.25 laminar boundary layer: adiabatic disturbance wall
+    # (v = A sin(2 pi kappa x)), Dirichlet similarity inflow, zero-gradient
+    c, P = W.laminar_bl(nx=36, ny=20, amp=0.01, kappa=10.0)
+    cases.append(("disturb_bl2d", c, P, None))
+    # 2D box closed by adiabatic walls, stretched both ways, rough data
+    c = W.Case(name="adi2d", ndim=2, n=(17, 21, 1), lo=(0, 0, 0), hi=(1, 1.3, 1),
+               stretch=("tanh2", "tanh1", "uniform"), beta=(1.2, 1.6, 0), gamma=1.4, R=1.0,
+               Pr=0.72, visc_law="power", mu_ref=0.01, T_ref=1.0, visc_param=0.76,
+               bc=("wall",) * 4 + ("periodic",) * 2, T_wall=(0.0,) * 6)
+    cases.append(("adiabatic2d_rough", c, W.random_rough(c, seed=13, rho=(0.8, 1.2),
+                                                         vel=(-0.3, 0.3), p=(0.8, 1.2)), None))
     # 3D TGV 16^3 viscous
     c, P = W.tgv(16)
     cases.append(("tgv3d", c, P, None))

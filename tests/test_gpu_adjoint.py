@@ -39,6 +39,8 @@ def adjoint_cases():
                bc=("zerograd", "zerograd", "wall", "wall", "periodic", "periodic"),
                T_wall=(0, 0, 1.0, 1.0, 0, 0))
     out.append(("mixed3d_visc", c, W.random_smooth(c, seed=9, amp=0.2), None, 1e-3))
+    c, P = W.laminar_bl(nx=12, ny=8, amp=0.01, kappa=10.0)
+    out.append(("disturb_bl2d", c, P, None, 2e-4))
     return out
 
 

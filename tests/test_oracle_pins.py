@@ -680,3 +680,79 @@ def test_trajectory_gradient_matches_finite_differences():
         e[i] = h
         fd = (J_of(K + e) - J_of(K - e)) / (2 * h)
         assert abs(fd - gk[i]) < 1e-6 * max(abs(gk).max(), 1e-30), (i, fd, gk[i])
+
+
+# --------------------------------------------------------------------------
+# Adiabatic and disturbance walls (Section 3.2, Eq. (8)).
+# --------------------------------------------------------------------------
+def _closed_box(Tw, kind="wall", amp=(0.0,) * 6, kappa=(0.0,) * 6):
+    case = _uniform_case(2, 12, stretch=True)
+    return W.Case(**{**case.__dict__, "bc": (kind,) * 4 + ("periodic",) * 2,
+                     "T_wall": (Tw,) * 6, "dist_amp": amp, "dist_kappa": kappa})
+
+
+def test_adiabatic_walls_conserve_mass_and_energy():
+    # Adiabatic no-slip walls mirror T and rho: the wall face carries no
+    # mass (u_n = 0 by symmetry), no viscous work (the face velocity
+    # interpolated from mirrored cells is exactly zero) and no heat (the
+    # normal temperature derivative of mirrored cells is exactly zero), so a
+    # closed box conserves mass and total energy for any interior state.  An
+    # isothermal wall at another temperature does not conserve energy.
+    case = _closed_box(0.0)
+    o = Oracle(case)
+    P = W.random_smooth(case, seed=21, amp=0.2)
+    U = o.cons(P)
+    R = o.rhs(U)
+    dx, dy = o.grid(0)[1], o.grid(1)[1]
+    V = dy[:, None] * dx[None, :]
+    for v in (0, 3):
+        tot = np.sum(V * R[v, 0])
+        scale = np.sum(V * np.abs(R[v, 0]))
+        assert abs(tot) < 1e-13 * scale, (v, tot, scale)
+    oi = Oracle(_closed_box(2.0))
+    Ri = oi.rhs(U)
+    assert abs(np.sum(V * Ri[3, 0])) > 1e-3 * np.sum(V * np.abs(Ri[3, 0]))
+
+
+def test_disturbance_wall_without_amplitude_is_a_no_slip_wall():
+    # With A = 0 the disturbance wall is exactly the no-slip wall (bitwise),
+    # isothermal and adiabatic alike.
+    for Tw in (0.0, 1.3):
+        P = W.random_smooth(_closed_box(Tw), seed=22, amp=0.2)
+        a = Oracle(_closed_box(Tw, "wall"))
+        b = Oracle(_closed_box(Tw, "disturb", kappa=(3.0,) * 6))
+        U = a.cons(P)
+        assert np.array_equal(a.rhs(U), b.rhs(U))
+
+
+@pytest.mark.parametrize("face", [2, 3])
+def test_disturbance_wall_blows_and_sucks_with_the_prescribed_profile(face):
+    # Gas at rest: the only flux through a wall column is the wall-normal
+    # mass flux, so the column's total mass rate (the y-fluxes telescope and
+    # the x-fluxes of a fluid at rest cancel) is the wall-face mass flux
+    # rho v_n(x_c) = rho A sin(2 pi kappa x_c) along the inward normal, to
+    # O(v/c) of the wall Riemann problem.  Checked on the lower and the
+    # upper wall (opposite inward normals) with a phase that a wrong face
+    # coordinate or a wrong sign would break.
+    nx, ny = 24, 10
+    A, kap = 1e-3, 0.75
+    amp = [0.0] * 6
+    kk = [0.0] * 6
+    amp[face], kk[face] = A, kap
+    bc = ["periodic", "periodic", "wall", "wall", "periodic", "periodic"]
+    bc[face] = "disturb"
+    case = W.Case(name="dw", ndim=2, n=(nx, ny, 1), lo=(0.0, 0.0, 0.0), hi=(2.0, 0.5, 1.0),
+                  stretch=("uniform", "tanh2", "uniform"), beta=(0, 1.5, 0), gamma=1.4, R=1.0,
+                  Pr=0.72, visc_law="power", mu_ref=0.01, T_ref=1.0, visc_param=0.7,
+                  bc=tuple(bc), T_wall=(0.0,) * 6, dist_amp=tuple(amp), dist_kappa=tuple(kk))
+    o = Oracle(case)
+    P = np.zeros((5, 1, ny, nx))
+    P[0], P[4] = 1.2, 1.0
+    R = o.rhs(o.cons(P))
+    xf, dx, _, _ = o.grid(0)
+    dy = o.grid(1)[1]
+    xc = 0.5 * (xf[:-1] + xf[1:])
+    col = np.sum(R[0, 0] * dy[:, None], axis=0)
+    expect = 1.2 * A * np.sin(2 * np.pi * kap * xc)
+    # relative deviation of the wall Riemann problem's mass flux ~ A/c = 8.5e-4
+    assert np.abs(col - expect).max() < 2e-3 * A, (col, expect)
