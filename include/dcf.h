@@ -103,8 +103,6 @@ typedef struct {
   int porous_begin;         /* POROUS: strip [begin, end) along the face's first  */
   int porous_end;           /*   tangential axis, all cells along the second one  */
   double p_inf;             /* POROUS: reference pressure of the Darcy law        */
-  double dist_amp;          /* DISTURB: amplitude A                               */
-  double dist_kappa;        /* DISTURB: wavenumber kappa                          */
 } dcf_bc;
 
 /* ---- context ------------------------------------------------------------ */
@@ -137,13 +135,18 @@ dcf_status dcf_set_workspace(dcf_ctx *ctx, int mode, int nsteps, int seg_len, vo
  * cell, and the ghost normal velocity is 2 v_w - u_mirror.  Disturbance
  * wall (Section 3.2, Eq. (8)): v_w = A sin(2 pi kappa x_c), x_c the centre
  * of the wall face along the face's first tangential axis (x for y walls,
- * y for x walls).  At most one face may be porous.  Returns DCF_EINVAL for
- * an unknown kind, a negative or non-finite T_wall, or a porous strip
- * outside the face. */
+ * y for x walls); A and kappa are boundary parameters (dcf_set_params), so
+ * that gradients reach them.  At most one face may be porous.  Returns
+ * DCF_EINVAL for an unknown kind, a negative or non-finite T_wall, or a
+ * porous strip outside the face.  A call that changes the number of
+ * boundary parameters clears them: set them again before stepping. */
 dcf_status dcf_set_bc(dcf_ctx *ctx, int face, const dcf_bc *bc);
 
-/* Porous coefficients K (dev, nK doubles, indexed strip-fastest); the
- * differentiable boundary parameters handed down by the solver. */
+/* Boundary parameters theta (dev, nK doubles): the porous coefficients K_i
+ * (strip index fastest), then (A, kappa) of every disturbance face in face
+ * order.  These are the differentiable inputs of dcf_vjp_step and
+ * dcf_gradient (dJ/dtheta has the same layout).  The library reads them
+ * from the caller's memory at every launch. */
 dcf_status dcf_set_params(dcf_ctx *ctx, const double *K_dev, int nK);
 int dcf_num_params(const dcf_ctx *ctx);
 

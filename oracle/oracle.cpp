@@ -74,7 +74,9 @@ inline Dual sqrt(Dual a) {
 inline Dual pow(Dual a, double e) {
   return Dual(std::pow(a.v, e), e * std::pow(a.v, e - 1.0) * a.d);
 }
+inline Dual sin(Dual a) { return Dual(std::sin(a.v), std::cos(a.v) * a.d); }
 inline double sqrt(double a) { return std::sqrt(a); }
+inline double sin(double a) { return std::sin(a); }
 inline double pow(double a, double e) { return std::pow(a, e); }
 inline double val(double x) { return x; }
 inline double val(const Dual &x) { return x.v; }
@@ -212,6 +214,22 @@ template <class T> inline T dcell4(T m2, T m1, T p1, T p2) {
 /* ------------------------------------------------------------------------ */
 /* The solver on one case, templated on the scalar (double or Dual).         */
 /* ------------------------------------------------------------------------ */
+/* Position in the boundary-parameter vector K of the first parameter of
+ * face `face` if it is a disturbance wall: the porous coefficients come
+ * first, then (A, kappa) of each disturbance face in face order.  With
+ * face = 2 ndim it is the length of K. */
+static int disturb_offset(const orc_case *c, int face) {
+  int o = 0;
+  if (c->porous_face >= 0) {
+    int d = c->porous_face / 2;
+    int t2 = d == 2 ? 1 : 2;
+    o = (c->porous_end - c->porous_begin) * c->n[t2];
+  }
+  for (int f = 0; f < face && f < 6; ++f)
+    if (c->bc[f] == ORC_DISTURB) o += 2;
+  return o;
+}
+
 template <class T> struct Solver {
   const orc_case &c;
   int nd, nv;
@@ -345,10 +363,12 @@ template <class T> struct Solver {
               }
               if (kind == ORC_DISTURB && a >= 0 && a < n[t1(d)]) {
                 /* Disturbance wall: v_n = A sin(2 pi kappa x) at the centre
-                 * of the wall face along the first tangential axis. */
+                 * of the wall face along the first tangential axis; A and
+                 * kappa are boundary parameters. */
                 const Axis &ta = ax[t1(d)];
                 double xc = 0.5 * (ta.xf[a] + ta.xf[a + 1]);
-                double vn = c.dist_amp[face] * std::sin(2.0 * M_PI * c.dist_kappa[face] * xc);
+                int o = disturb_offset(&c, face);
+                T vn = K[o] * sin(2.0 * M_PI * xc * K[o + 1]);
                 vel[d] = 2.0 * sigma * vn - Q[1 + d][S];
               }
               T p = Q[4][S];
@@ -562,12 +582,7 @@ template <class T> void copy_in(const double *src, T *dst, long n) {
 /* ======================================================================== */
 extern "C" {
 
-int orc_nk(const orc_case *c) {
-  if (c->porous_face < 0) return 0;
-  int d = c->porous_face / 2;
-  int t2 = d == 2 ? 1 : 2;
-  return (c->porous_end - c->porous_begin) * c->n[t2];
-}
+int orc_nk(const orc_case *c) { return disturb_offset(c, 2 * c->ndim); }
 
 long orc_ncells(const orc_case *c) { return (long)c->n[0] * c->n[1] * c->n[2]; }
 

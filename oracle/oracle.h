@@ -16,7 +16,10 @@
  *                         (rho, rho*u[, rho*v[, rho*w]], E)
  *   primitive input P     [5][nz][ny][nx]   (rho, u, v, w, p); unused
  *                         velocity components must be zero
- *   porous coefficients K [nK], nK = (porous_end - porous_begin) * n_t2
+ *   boundary parameters K [nK]: the porous coefficients, (porous_end -
+ *                         porous_begin) * n_t2 of them, strip index fastest,
+ *                         then (A, kappa) of every disturbance-wall face in
+ *                         face order
  *   halo'd box            [nz + 2hz][ny + 2hy][nx + 2hx], h = 3 on active
  *                         axes and 0 on inactive ones
  */
@@ -34,7 +37,8 @@ enum {
   ORC_ZEROGRAD = 3,  /* zero-gradient extrapolation                         */
   ORC_DIRICHLET = 4, /* prescribed primitive profile                        */
   ORC_DISTURB = 5    /* no-slip wall with prescribed normal velocity
-                        A sin(2 pi kappa x_t) (Section 3.2, Eq. (8))        */
+                        A sin(2 pi kappa x_t) (Section 3.2, Eq. (8)); A and
+                        kappa are boundary parameters (entries of K)         */
 };
 
 enum { ORC_VISC_NONE = 0, ORC_VISC_POWER = 1, ORC_VISC_SUTHERLAND = 2 };
@@ -53,7 +57,6 @@ typedef struct {
   double visc_param;     /* power-law exponent, or Sutherland constant       */
   int bc[6];             /* faces x-, x+, y-, y+, z-, z+                    */
   double T_wall[6];      /* wall temperature per face; 0 = adiabatic wall     */
-  double dist_amp[6], dist_kappa[6]; /* disturbance wall amplitude, wavenumber */
   const double *dirichlet[6]; /* [5][n_t2][n_t1] per Dirichlet face          */
   int porous_face;       /* face carrying the porous strip, -1 for none      */
   int porous_begin, porous_end; /* strip range along the first tangential axis */

@@ -27,7 +27,6 @@ class OrcCase(C.Structure):
         ("gamma", C.c_double), ("R", C.c_double), ("Pr", C.c_double),
         ("visc_law", C.c_int), ("mu_ref", C.c_double), ("T_ref", C.c_double),
         ("visc_param", C.c_double), ("bc", C.c_int * 6), ("T_wall", C.c_double * 6),
-        ("dist_amp", C.c_double * 6), ("dist_kappa", C.c_double * 6),
         ("dirichlet", _dp * 6), ("porous_face", C.c_int), ("porous_begin", C.c_int),
         ("porous_end", C.c_int), ("p_inf", C.c_double), ("source", C.c_int),
         ("cost_face", C.c_int),
@@ -101,8 +100,6 @@ class Oracle:
         for f in range(6):
             s.bc[f] = _BC[case.bc[f]]
             s.T_wall[f] = case.T_wall[f]
-            s.dist_amp[f] = case.dist_amp[f]
-            s.dist_kappa[f] = case.dist_kappa[f]
             if f in case.dirichlet:
                 arr = np.ascontiguousarray(case.dirichlet[f], dtype=np.float64)
                 self._keep.append(arr)
@@ -114,7 +111,11 @@ class Oracle:
         self.s = s
         self.L = lib()
         self.nk = self.L.orc_nk(C.byref(s))
-        self.K = np.zeros(max(self.nk, 1)) if K is None else np.ascontiguousarray(K, dtype=np.float64)
+        assert self.nk == case.nk
+        # boundary parameters: porous coefficients, then (A, kappa) per
+        # disturbance face (taken from the case when only K is given)
+        th = case.theta(K)
+        self.K = np.ascontiguousarray(th if th.size else np.zeros(1), dtype=np.float64)
 
     # ---- helpers -------------------------------------------------------
     @property

@@ -65,9 +65,11 @@ class TrajectoryCost(torch.autograd.Function):
 
 def optimize_porous(solver: Solver, U0: torch.Tensor, dt: torch.Tensor, K0, iters: int = 10,
                     lr: float = 0.05, k_max: float = 1.0, betas=(0.9, 0.999)):
-    """Projected Adam on the porous coefficients K to reduce the wall-pressure
-    cost J (the end-to-end optimisation the gradient is for).  Returns the
-    history of (J, K)."""
+    """Projected Adam on the boundary parameters (porous coefficients K_i,
+    then any disturbance-wall (A, kappa)) to reduce the wall-pressure cost J
+    (the end-to-end optimisation the gradient is for).  The porous
+    coefficients are kept in [0, k_max].  Returns the history of (J, theta)."""
+    n_por = solver.case.n_porous
     K = torch.as_tensor(K0, dtype=torch.float64, device=U0.device).clone()
     m = torch.zeros_like(K)
     v = torch.zeros_like(K)
@@ -82,5 +84,6 @@ def optimize_porous(solver: Solver, U0: torch.Tensor, dt: torch.Tensor, K0, iter
         v = betas[1] * v + (1 - betas[1]) * g * g
         mh = m / (1 - betas[0] ** it)
         vh = v / (1 - betas[1] ** it)
-        K = (K - lr * mh / (vh.sqrt() + 1e-30)).clamp_(0.0, k_max)
+        K = K - lr * mh / (vh.sqrt() + 1e-30)
+        K[:n_por].clamp_(0.0, k_max)
     return hist

@@ -40,8 +40,7 @@ class dcf_gas(C.Structure):
 
 class dcf_bc(C.Structure):
     _fields_ = [("kind", C.c_int), ("T_wall", C.c_double), ("dirichlet", C.c_void_p),
-                ("porous_begin", C.c_int), ("porous_end", C.c_int), ("p_inf", C.c_double),
-                ("dist_amp", C.c_double), ("dist_kappa", C.c_double)]
+                ("porous_begin", C.c_int), ("porous_end", C.c_int), ("p_inf", C.c_double)]
 
 
 _vp = C.c_void_p

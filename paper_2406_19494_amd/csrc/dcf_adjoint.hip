@@ -610,6 +610,7 @@ __global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, do
     const int face = 2 * d + side;
     const int kind = g.bck[face];
     if (kind == BC_DIRICHLET) continue;
+    double vsum = 0.0;  // sum over the column's ghosts of the normal-velocity adjoint
     for (int m = 0; m < 3; ++m) {
       const long G = box(side == 0 ? -1 - m : n + m);
       int src;
@@ -649,7 +650,48 @@ __global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, do
         A.Qb[QP][W] += -g.K[kk] / g.pinf * vnb;
         if (dJdK) dJdK[kk] += -(pw - g.pinf) / g.pinf * vnb;
       }
+      vsum += A.Qb[QU + d][G];
     }
+    if (kind == BC_DISTURB && dJdK) {
+      // v_g[d] = 2 sigma A sin(phi) - v_s[d], phi = 2 pi kappa x: per-column
+      // partials of dJ/dA and dJ/dkappa, summed over columns by k_disturb_sum
+      double dA = 0.0, dk = 0.0;
+      if (a >= 0 && a < g.n[t1]) {
+        const double *th = g.K + g.doff[face];
+        const double x = g.xm[t1][a];
+        const double ph = 2.0 * M_PI * x * th[1];
+        const double w = 2.0 * (side == 0 ? 1.0 : -1.0) * vsum;
+        dA = w * sin(ph);
+        dk = w * th[0] * cos(ph) * 2.0 * M_PI * x;
+      }
+      A.dpart[(2 * side) * A.dcols + col] = dA;
+      A.dpart[(2 * side + 1) * A.dcols + col] = dk;
+    }
+  }
+}
+
+// dJ/d(A, kappa) += column sums of k_halo_vjp's partials for one disturbance
+// face (one block, fixed summation order: deterministic).
+__global__ void __launch_bounds__(256) k_disturb_sum(const double *part, long cols, double *out) {
+  __shared__ double sh[2][256];
+  double v[2] = {0.0, 0.0};
+  for (long i = threadIdx.x; i < cols; i += 256) {
+    v[0] += part[i];
+    v[1] += part[cols + i];
+  }
+  sh[0][threadIdx.x] = v[0];
+  sh[1][threadIdx.x] = v[1];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] += sh[0][0];
+    out[1] += sh[1][0];
   }
 }
 
@@ -758,6 +800,13 @@ static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A, const double *V, 
     long n2 = t2 < d ? g.N[t2] : g.n[t2];
     k_halo_vjp<<<blocks(n1 * n2), 256, 0, st>>>(g, A, d, dJdK);
     DCF_TRY(hipGetLastError());
+    for (int side = 0; side < 2 && dJdK; ++side) {
+      const int face = 2 * d + side;
+      if (g.bck[face] != BC_DISTURB) continue;
+      k_disturb_sum<<<1, 256, 0, st>>>(A.dpart + 2 * side * A.dcols, n1 * n2,
+                                       dJdK + g.doff[face]);
+      DCF_TRY(hipGetLastError());
+    }
   }
   k_interior_vjp<<<blocks(g.ncell), 256, 0, st>>>(g, A, V, Wb, a, b, Vb, acc_in, acc_out, fold);
   return hipGetLastError();

@@ -11,6 +11,8 @@ struct AdjBuffers {
   double *Gb[9];    // adjoint of cell-centred velocity derivatives d u_phi / d x_t (3 t + phi)
   double *Ub1, *Ub2, *acc;  // stage adjoints and the running lambda^n accumulator
   double *Rb;       // per-cell adjoint of the right-hand side
+  double *dpart;    // per-column partial sums of dJ/d(A, kappa), 4 per wall column
+  long dcols;       // columns per disturbance-face partial array
   double *zero_begin;  // Qb and Gb are carved back to back: one fill clears both
   long zero_count;
 };
@@ -29,6 +31,14 @@ template <class Carver> void carve_adjoint(Carver &cv, const Dev &g, AdjBuffers 
   a.Ub2 = cv.template take<double>((long)g.nv * g.ncell);
   a.acc = cv.template take<double>((long)g.nv * g.ncell);
   a.Rb = cv.template take<double>((long)5 * g.ncell);
+  long cols = 1;
+  for (int d = 0; d < g.ndim; ++d) {
+    const int t1 = tan1(d), t2 = tan2(d);
+    long n1 = t1 < d ? g.N[t1] : g.n[t1], n2 = t2 < d ? g.N[t2] : g.n[t2];
+    cols = n1 * n2 > cols ? n1 * n2 : cols;
+  }
+  a.dcols = cols;
+  a.dpart = cv.template take<double>(4 * cols);
 }
 
 // lam0 = (dU^{n+1}/dU^n)^T lam1 and dJdK += (dU^{n+1}/dK)^T lam1 (if not

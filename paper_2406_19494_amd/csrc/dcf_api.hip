@@ -145,7 +145,10 @@ dcf_status dcf_create(const dcf_grid *grid, const dcf_gas *gas, dcf_ctx **out) {
   g.T_ref = gas->T_ref;
   g.vparam = gas->visc_param;
   g.visc = gas->visc_law;
-  for (int f = 0; f < 6; ++f) g.bck[f] = BC_PERIODIC;
+  for (int f = 0; f < 6; ++f) {
+    g.bck[f] = BC_PERIODIC;
+    g.doff[f] = -1;
+  }
   g.pface = -1;
   g.source = SRC_NONE;
 
@@ -276,8 +279,7 @@ dcf_status dcf_set_bc(dcf_ctx *c, int face, const dcf_bc *bc) {
     if (!(bc->T_wall >= 0.0) || bc->T_wall > 1e300)
       return fail(DCF_EINVAL, "wall needs T_wall > 0 (isothermal) or 0 (adiabatic)");
   }
-  if (bc->kind == BC_DISTURB && !(fabs(bc->dist_amp) < 1e300 && fabs(bc->dist_kappa) < 1e300))
-    return fail(DCF_EINVAL, "disturbance amplitude and wavenumber must be finite");
+
   if (bc->kind == BC_DIRICHLET && !bc->dirichlet)
     return fail(DCF_EINVAL, "Dirichlet face needs a profile");
   if (bc->kind == BC_POROUS) {
@@ -292,16 +294,24 @@ dcf_status dcf_set_bc(dcf_ctx *c, int face, const dcf_bc *bc) {
     g.pb = bc->porous_begin;
     g.pe = bc->porous_end;
     g.pinf = bc->p_inf;
-    c->nK = (g.pe - g.pb) * g.n[tan2(d)];
   } else if (g.pface == face) {
     g.pface = -1;
-    c->nK = 0;
   }
   g.bck[face] = bc->kind;
   g.Tw[face] = is_wall(bc->kind) ? bc->T_wall : 0.0;
-  g.damp[face] = bc->kind == BC_DISTURB ? bc->dist_amp : 0.0;
-  g.dkap[face] = bc->kind == BC_DISTURB ? bc->dist_kappa : 0.0;
   g.dir[face] = bc->dirichlet;
+  // boundary-parameter layout: porous K_i first, then (A, kappa) of each
+  // disturbance face in face order
+  int nk = g.pface >= 0 ? (g.pe - g.pb) * g.n[tan2(g.pface / 2)] : 0;
+  for (int f = 0; f < 6; ++f) {
+    g.doff[f] = -1;
+    if (f / 2 < g.ndim && g.bck[f] == BC_DISTURB) {
+      g.doff[f] = nk;
+      nk += 2;
+    }
+  }
+  if (nk != c->nK) g.K = nullptr;  // layout changed: parameters must be set again
+  c->nK = nk;
   return DCF_OK;
 }
 
@@ -345,8 +355,8 @@ static dcf_status ready(dcf_ctx *c, int need_mode) {
     bool p0 = g.bck[2 * d] == BC_PERIODIC, p1 = g.bck[2 * d + 1] == BC_PERIODIC;
     if (p0 != p1) return fail(DCF_EINVAL, "axis %d: periodic faces must come in pairs", d);
   }
-  if (g.pface >= 0 && c->nK > 0 && !g.K)
-    return fail(DCF_EINVAL, "porous face set but no coefficients (dcf_set_params)");
+  if (c->nK > 0 && !g.K)
+    return fail(DCF_EINVAL, "boundary parameters not set (dcf_set_params)");
   return DCF_OK;
 }
 

@@ -50,11 +50,11 @@ struct Dev {
   // boundaries
   int bck[6];
   double Tw[6];          // wall temperature; 0 = adiabatic wall
-  double damp[6], dkap[6];  // disturbance wall: v_n = damp sin(2 pi dkap x_t1)
+  int doff[6];           // disturbance wall: offset of (A, kappa) in K, else -1
   const double *dir[6];
   int pface, pb, pe;
   double pinf;
-  const double *K;
+  const double *K;       // boundary parameters: porous K_i, then (A, kappa) per disturbance face
   int source;
   // workspace
   double *Q[NQ];         // primitive box arrays

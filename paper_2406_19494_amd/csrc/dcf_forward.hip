@@ -194,8 +194,10 @@ __global__ void __launch_bounds__(256) k_prim_halo(Dev g, const double *U) {
       }
     } else if (kind == BC_DISTURB && a >= 0 && a < g.n[t1]) {
       // Disturbance wall (Section 3.2, Eq. (8)): prescribed inward-normal
-      // velocity A sin(2 pi kappa x) at the wall-face centre.
-      double vn = g.damp[face] * sin(2.0 * M_PI * g.dkap[face] * g.xm[t1][a]);
+      // velocity A sin(2 pi kappa x) at the wall-face centre, (A, kappa)
+      // taken from the boundary parameters.
+      const double *th = g.K + g.doff[face];
+      double vn = th[0] * sin(2.0 * M_PI * g.xm[t1][a] * th[1]);
       q[QU + d] = 2.0 * sigma * vn - src_n;
     }
     if (g.Tw[face] > 0.0) {  // isothermal; adiabatic keeps rho and T

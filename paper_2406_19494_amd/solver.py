@@ -60,7 +60,6 @@ class Solver:
             bc = B.dcf_bc()
             bc.kind = B.BC[case.bc[f]]
             bc.T_wall = case.T_wall[f]
-            bc.dist_amp, bc.dist_kappa = case.dist_amp[f], case.dist_kappa[f]
             if f in case.dirichlet:
                 prof = torch.as_tensor(np.ascontiguousarray(case.dirichlet[f]), dtype=torch.float64,
                                        device=self.device)
@@ -75,10 +74,15 @@ class Solver:
             B.call("dcf_set_cost", ctx, case.cost_face, case.p_inf)
         self.nk = L.dcf_num_params(ctx)
         self.K = None
+        if self.nk != case.nk:
+            raise ValueError(f"library reports {self.nk} boundary parameters, the case "
+                             f"{case.nk}")
         if self.nk:
-            Kt = torch.zeros(self.nk, dtype=torch.float64, device=self.device) if K is None else \
-                torch.as_tensor(np.asarray(K), dtype=torch.float64, device=self.device).contiguous()
-            self.set_params(Kt)
+            # porous coefficients (or the full parameter vector), with the
+            # case's disturbance amplitudes and wavenumbers appended
+            th = K if torch.is_tensor(K) and K.numel() == self.nk else case.theta(
+                None if K is None else (K.cpu().numpy() if torch.is_tensor(K) else K))
+            self.set_params(torch.as_tensor(th, dtype=torch.float64, device=self.device))
         self.mode, self.nsteps, self.seg_len = mode, nsteps, seg_len
         size = C.c_size_t()
         B.call("dcf_workspace_size", ctx, mode, nsteps, seg_len, C.byref(size))

@@ -83,12 +83,36 @@ class Case:
         return self.ndim + 2
 
     @property
-    def nk(self) -> int:
+    def n_porous(self) -> int:
+        """Porous coefficients K_i (strip index fastest)."""
         if self.porous_face < 0:
             return 0
         d = self.porous_face // 2
         t2 = 1 if d == 2 else 2
         return (self.porous_end - self.porous_begin) * self.n[t2]
+
+    @property
+    def disturb_faces(self) -> Tuple[int, ...]:
+        return tuple(f for f in range(2 * self.ndim) if self.bc[f] == "disturb")
+
+    @property
+    def nk(self) -> int:
+        """Length of the boundary-parameter vector theta: the porous
+        coefficients, then (A, kappa) of each disturbance face in face order."""
+        return self.n_porous + 2 * len(self.disturb_faces)
+
+    def theta(self, K=None) -> np.ndarray:
+        """The boundary-parameter vector.  K may be the full vector (length
+        nk), the porous coefficients alone (the disturbance amplitudes and
+        wavenumbers are then this case's), or None (porous coefficients 0)."""
+        if K is not None and np.size(K) == self.nk and self.nk:
+            return np.asarray(K, dtype=np.float64).reshape(-1).copy()
+        Kp = np.zeros(self.n_porous) if K is None else np.asarray(K, dtype=np.float64).reshape(-1)
+        if Kp.size != self.n_porous:
+            raise ValueError(f"expected {self.n_porous} porous coefficients or {self.nk} "
+                             f"boundary parameters, got {Kp.size}")
+        extra = [v for f in self.disturb_faces for v in (self.dist_amp[f], self.dist_kappa[f])]
+        return np.concatenate([Kp, np.asarray(extra, dtype=np.float64)])
 
 
 # --------------------------------------------------------------------------
@@ -362,7 +386,7 @@ def porous_bl(nx: int = 1024, ny: int = 256, Ma: float = 6.0, T_inf_K: float = 6
     pw = p_inf * (1.0 + pulse * np.exp(-((x[0] - xm) ** 2 + y[0] ** 2) / pulse_radius ** 2))
     P[0, 0] *= pw / p_inf
     P[4, 0] = pw
-    K = k_max * uniform01(seed, case.nk, 7)
+    K = k_max * uniform01(seed, case.n_porous, 7)
     return case, P, K
 
 

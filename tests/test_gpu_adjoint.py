@@ -8,7 +8,7 @@ import torch
 from oracle.pyoracle import Oracle
 from paper_2406_19494_amd import workloads as W
 from paper_2406_19494_amd.solver import Solver
-from tests.test_oracle_pins import _tiny_porous
+from tests.test_oracle_pins import _tiny_disturb, _tiny_porous
 
 pytestmark = pytest.mark.gpu
 
@@ -88,11 +88,13 @@ def test_dot_product_gpu_vjp_vs_oracle_jvp(name, case, P, K, dt):
     assert abs(lhs - rhs) <= 1e-10 * max(abs(lhs), np.sum(np.abs(lam * jv))), (lhs, rhs)
 
 
-def test_trajectory_gradient_matches_oracle():
-    case, P, K = _tiny_porous()
+@pytest.mark.parametrize("which", ["porous", "disturb"])
+def test_trajectory_gradient_matches_oracle(which):
+    case, P, K = _tiny_porous() if which == "porous" else _tiny_disturb()
+    print(f"[trajectory gradient] {which}", flush=True)
     o = Oracle(case, K=K)
     U0 = o.cons(P)
-    dt, nsteps = 1e-3, 5
+    dt, nsteps = (1e-3, 5) if which == "porous" else (2e-4, 5)
     J_or, gk_or, gu_or = o.gradient(U0, nsteps, dt)
     for seg in (2, 5):
         s = Solver(case, K=K, mode=2, nsteps=nsteps, seg_len=seg)

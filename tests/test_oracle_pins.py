@@ -620,6 +620,18 @@ def _tiny_porous():
     return case, P, K + 0.1
 
 
+def _tiny_disturb():
+    """12 x 8 Mach-2.25 boundary layer over an adiabatic disturbance wall
+    (A = 0.01, kappa = 10) with the wall-pressure cost on that wall and a
+    seeded 10 % pressure disturbance.  Returns (case, P, theta)."""
+    case, P = W.laminar_bl(nx=12, ny=8, amp=0.01, kappa=10.0)
+    case.cost_face = 2
+    x, y, _ = W._mesh(case)
+    P = P.copy()
+    P[4] = P[4] * (1.0 + 0.1 * np.sin(2 * np.pi * (x - 1.0) / 0.5) * np.cos(3.0 * y))
+    return case, P, case.theta()
+
+
 def test_jvp_matches_finite_differences():
     case, P, K = _tiny_porous()
     o = Oracle(case, K=K)
@@ -680,6 +692,38 @@ def test_trajectory_gradient_matches_finite_differences():
         e[i] = h
         fd = (J_of(K + e) - J_of(K - e)) / (2 * h)
         assert abs(fd - gk[i]) < 1e-6 * max(abs(gk).max(), 1e-30), (i, fd, gk[i])
+
+
+def test_disturbance_parameter_gradient_matches_finite_differences():
+    # dJ/dA and dJ/dkappa of the disturbance wall (the differentiable
+    # boundary parameters of Eq. (8)) against central differences.
+    case, P, th = _tiny_disturb()
+    assert case.nk == 2 and th[0] == 0.01 and th[1] == 10.0
+    o = Oracle(case, K=th)
+    U0 = o.cons(P)
+    dt, nsteps = 2e-4, 3
+    J, g, _ = o.gradient(U0, nsteps, dt)
+
+    def J_of(t):
+        ok = Oracle(case, K=t)
+        U = U0.copy()
+        acc = 0.0
+        for _ in range(nsteps):
+            U = ok.step(U, dt)
+            acc += ok.cost_term(U) / nsteps
+        return acc
+
+    assert abs(J - J_of(th)) < 1e-15 * max(1.0, abs(J))
+    assert g[0] != 0.0 and g[1] != 0.0
+    # J is strongly nonlinear in (A, kappa) (sin(2 pi kappa x) with kappa x
+    # ~ 15), so the differences are taken with the fourth-order stencil,
+    # whose truncation sits below 1e-6 at these steps while the round-off
+    # of J (~1e-19) stays below it too.
+    for i, h in ((0, 3e-5), (1, 1e-4)):
+        e = np.zeros_like(th)
+        e[i] = h
+        fd = (8.0 * (J_of(th + e) - J_of(th - e)) - (J_of(th + 2 * e) - J_of(th - 2 * e))) / (12 * h)
+        assert abs(fd - g[i]) < 1e-6 * abs(g[i]), (i, fd, g[i])
 
 
 # --------------------------------------------------------------------------
