@@ -541,15 +541,13 @@ __global__ void __launch_bounds__(256) k_visc_vjp(Dev g, AdjBuffers A) {
 // Gather of the tangential-derivative adjoints (transpose of the
 // cell-centred 4th-order difference along t), then mu'(T) folding.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double dviscosity(const Dev &g, double T) {
-  if (g.visc == VISC_POWER) {
-    double t = T / g.T_ref;
-    return g.mu_ref * g.vparam * pow(t, g.vparam - 1.0) / g.T_ref;
-  }
+// d mu / dT from T and mu(T): omega mu / T (power law), mu (1.5/t - 1/(t+s))
+// / T_ref with t = T/T_ref, s = S/T_ref (Sutherland).
+__device__ __forceinline__ double dviscosity(const Dev &g, double T, double mu) {
+  if (g.visc == VISC_POWER) return g.vparam * mu / T;
   if (g.visc == VISC_SUTHERLAND) {
     double t = T / g.T_ref;
     double s = g.vparam / g.T_ref;
-    double mu = g.mu_ref * t * sqrt(t) * (1.0 + s) / (t + s);
     return mu * (1.5 / t - 1.0 / (t + s)) / g.T_ref;
   }
   return 0.0;
@@ -582,7 +580,7 @@ __global__ void __launch_bounds__(256) k_tangential_vjp(Dev g, AdjBuffers A) {
       A.Qb[QU + phi][b] += add;
     }
   }
-  if (g.visc != VISC_NONE) A.Qb[QT][b] += dviscosity(g, g.Q[QT][b]) * A.Qb[QMU][b];
+  if (g.visc != VISC_NONE) A.Qb[QT][b] += dviscosity(g, g.Q[QT][b], g.Q[QMU][b]) * A.Qb[QMU][b];
 }
 
 // ---------------------------------------------------------------------------

@@ -74,9 +74,50 @@ __host__ __device__ __forceinline__ long bidx(const Dev &g, int i, int j, int k)
   return (long)(k + g.ho[2]) * g.sb[2] + (long)(j + g.ho[1]) * g.sb[1] + (i + g.ho[0]);
 }
 
+// Box position of ghost cell number gi (ghost cells enumerated z-plane by
+// z-plane: whole halo planes, then per interior plane its halo rows and the
+// 2 h0 x-halo cells of each interior row).
+__host__ __device__ __forceinline__ void ghost_position(const Dev &g, unsigned gi, int p[3]) {
+  const unsigned N0 = g.N[0], h0 = g.h[0], h1 = g.h[1], h2 = g.h[2];
+  const unsigned n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+  const unsigned plane = N0 * (unsigned)g.N[1];
+  const unsigned lowz = h2 * plane, inner = plane - n0 * n1;
+  unsigned x, y, z;
+  if (gi < lowz || gi >= lowz + n2 * inner) {  // a whole halo plane
+    const unsigned r0 = gi < lowz ? gi : gi - n2 * inner;
+    z = r0 / plane;
+    if (gi >= lowz) z += n2;
+    const unsigned r = r0 % plane;
+    y = r / N0;
+    x = r % N0;
+  } else {
+    const unsigned r0 = gi - lowz;
+    z = h2 + r0 / inner;
+    unsigned r = r0 % inner;
+    const unsigned lowy = h1 * N0, mid = 2u * h0;
+    if (r < lowy) {
+      y = r / N0;
+      x = r % N0;
+    } else if (r < lowy + n1 * mid) {
+      r -= lowy;
+      y = h1 + r / mid;
+      const unsigned m = r % mid;
+      x = m < h0 ? m : n0 + m;
+    } else {
+      r -= lowy + n1 * mid;
+      y = h1 + n1 + r / N0;
+      x = r % N0;
+    }
+  }
+  p[0] = (int)x - g.h[0];
+  p[1] = (int)y - g.h[1];
+  p[2] = (int)z - g.h[2];
+}
+
 // Dynamic viscosity: power law, or Sutherland's law (Section 3.2).
 __device__ __forceinline__ double viscosity(const Dev &g, double T) {
-  if (g.visc == VISC_POWER) return g.mu_ref * pow(T / g.T_ref, g.vparam);
+  // (T/T_ref)^omega as exp(omega log(T/T_ref)): a few ulp, half the cost of pow
+  if (g.visc == VISC_POWER) return g.mu_ref * exp(g.vparam * log(T / g.T_ref));
   if (g.visc == VISC_SUTHERLAND) {
     double t = T / g.T_ref;
     double s = g.vparam / g.T_ref;

@@ -97,22 +97,22 @@ __device__ __forceinline__ int ghost_source(int kind, int side, int m, int n) {
   return side == 0 ? m : n - 1 - m;  // walls mirror
 }
 
+// Threads [0, ncell) convert interior cells (x-fastest, coalesced, one
+// branch for the whole wave); threads [ncell, nbox) fill the ghost cells.
 __global__ void __launch_bounds__(256) k_prim_halo(Dev g, const double *U) {
-  const unsigned bl = blockIdx.x * blockDim.x + threadIdx.x;
-  if (bl >= (unsigned)g.nbox) return;
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (unsigned)g.nbox) return;
   const int nd = g.ndim;
-  const unsigned N0 = g.N[0], N01 = (unsigned)g.N[0] * g.N[1];
   int p[3];
-  p[2] = (int)(bl / N01) - g.h[2];
-  const unsigned rr = bl % N01;
-  p[1] = (int)(rr / N0) - g.h[1];
-  p[0] = (int)(rr % N0) - g.h[0];
-  const long b = bidx(g, p[0], p[1], p[2]);
-  if (p[0] >= 0 && p[0] < g.n[0] && p[1] >= 0 && p[1] < g.n[1] && p[2] >= 0 && p[2] < g.n[2]) {
-    // interior cell: primitives of its own conserved state
+  if (t < (unsigned)g.ncell) {
+    const unsigned n0 = g.n[0], n01 = n0 * (unsigned)g.n[1];
+    p[2] = (int)(t / n01);
+    const unsigned rr = t % n01;
+    p[1] = (int)(rr / n0);
+    p[0] = (int)(rr % n0);
+    const long b = bidx(g, p[0], p[1], p[2]);
     double q[6];
-    const long c = ((long)p[2] * g.n[1] + p[1]) * g.n[0] + p[0];
-    cons_to_prim(g, U, c, q);
+    cons_to_prim(g, U, (long)t, q);
     if (!(finite_pos(q[QR]) && finite_pos(q[QP]))) atomicOr(g.flags, 1u);
     g.Q[QR][b] = q[QR];
     g.Q[QU][b] = q[QU];
@@ -125,6 +125,8 @@ __global__ void __launch_bounds__(256) k_prim_halo(Dev g, const double *U) {
     }
     return;
   }
+  ghost_position(g, t - (unsigned)g.ncell, p);
+  const long b = bidx(g, p[0], p[1], p[2]);
   int s[3] = {p[0], p[1], p[2]};
   int side[3] = {0, 0, 0};
   bool gh[3] = {false, false, false};
