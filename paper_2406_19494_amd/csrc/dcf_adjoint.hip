@@ -6,7 +6,8 @@
 //
 // Per stage (state V, stage output W = a Un + b (V + dt R(V))), given the
 // stage-output adjoint Wb:
-//   Rb = b dt Wb,  Fb(face) = Rb(right cell)/dx - Rb(left cell)/dx,
+//   Rb = b dt Wb,  Fb(face) = Rb(right cell)/dx - Rb(left cell)/dx (formed
+//                  per face from Wb inside the flux adjoint kernels),
 //   Qb = sum over faces of (dF/dQ)^T Fb        (convective + dissipative),
 //   Qb += D_t^T Gb   (tangential derivatives were cell-centred, then
 //                     interpolated: their adjoint Gb is gathered along t),
@@ -44,9 +45,9 @@ __device__ __forceinline__ void weno5_vjp(double a, double b, double c, double d
   double e2 = eps + (c1312 * r2 * r2 + 0.25 * s2 * s2);
   double t0 = e0 * e0, t1 = e1 * e1, t2 = e2 * e2;
   double w0 = 0.1 * t1 * t2, w1 = 0.6 * t0 * t2, w2 = 0.3 * t0 * t1;
-  double W = w0 + w1 + w2;
-  double y = (w0 * q0 + w1 * q1 + w2 * q2) / W;
-  double Nb = yb / W;
+  double iW = 1.0 / (w0 + w1 + w2);
+  double y = (w0 * q0 + w1 * q1 + w2 * q2) * iW;
+  double Nb = yb * iW;
   double q0b = Nb * w0, q1b = Nb * w1, q2b = Nb * w2;
   double w0b = Nb * (q0 - y), w1b = Nb * (q1 - y), w2b = Nb * (q2 - y);
   double t0b = 0.6 * w1b * t2 + 0.3 * w2b * t1;
@@ -195,44 +196,31 @@ __device__ void hllc_vjp(const double *qL, const double *qR, double gamma, const
   qRb[0] -= xRb * gamma * pR / (rR * rR);
 }
 
-// Flux adjoint at face f of direction D from the stage-output adjoint:
+// Flux adjoint at face f of direction D from the stage-output adjoint Wb:
+// with Rb = b dt Wb (the right-hand-side adjoint, 5-component flux layout),
 // Fb[m] = Rb_m(cell f)/dx_f - Rb_m(cell f-1)/dx_{f-1}.
-__device__ __forceinline__ void face_adjoint(const Dev &g, int D, const int *pos, int f,
-                                             const double *Rb, double *Fb) {
+__device__ __forceinline__ void face_adjoint(const Dev &g, const AdjBuffers &A, int D,
+                                             const int *pos, int f, double *Fb) {
   const long nc = g.ncell;
   const int nd = g.ndim;
+  const double s = A.bcoef * A.dtp[0];
+  const long vo[5] = {0, nc, 2 * nc, 3 * nc, (long)(nd + 1) * nc};
   for (int m = 0; m < 5; ++m) Fb[m] = 0.0;
   int cpos[3] = {pos[0], pos[1], pos[2]};
   if (f < g.n[D]) {
     cpos[D] = f;
     long c = ((long)cpos[2] * g.n[1] + cpos[1]) * g.n[0] + cpos[0];
     double id = g.idx[D][f];
-    for (int m = 0; m < 5; ++m) Fb[m] += Rb[m * nc + c] * id;
+    for (int m = 0; m < 5; ++m)
+      if (m < 2 || m == 4 || m <= nd) Fb[m] += (s * A.Wb[vo[m] + c]) * id;
   }
   if (f >= 1) {
     cpos[D] = f - 1;
     long c = ((long)cpos[2] * g.n[1] + cpos[1]) * g.n[0] + cpos[0];
     double id = g.idx[D][f - 1];
-    for (int m = 0; m < 5; ++m) Fb[m] -= Rb[m * nc + c] * id;
+    for (int m = 0; m < 5; ++m)
+      if (m < 2 || m == 4 || m <= nd) Fb[m] -= (s * A.Wb[vo[m] + c]) * id;
   }
-  if (nd < 3) Fb[3] = 0.0;
-  if (nd < 2) Fb[2] = 0.0;
-}
-
-// Per-cell right-hand-side adjoint in the 5-component flux layout:
-// Rb[m] = b dt Wb[v(m)].
-__global__ void __launch_bounds__(256) k_rbar(Dev g, const double *Wb, const double *dtp,
-                                              double b, double *Rb) {
-  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.ncell) return;
-  const long nc = g.ncell;
-  const int nd = g.ndim;
-  double s = b * dtp[0];
-  Rb[c] = s * Wb[c];
-  Rb[nc + c] = s * Wb[nc + c];
-  Rb[2 * nc + c] = nd >= 2 ? s * Wb[2 * nc + c] : 0.0;
-  Rb[3 * nc + c] = nd >= 3 ? s * Wb[3 * nc + c] : 0.0;
-  Rb[4 * nc + c] = s * Wb[(long)(nd + 1) * nc + c];
 }
 
 // Tile geometry for direction D: tile index -> first face and line origin.
@@ -315,7 +303,7 @@ __global__ void __launch_bounds__(256) k_conv_vjp(Dev g, AdjBuffers A) {
     int pos[3] = {t.line[0], t.line[1], t.line[2]};
     pos[D] = f;
     double Fb[5];
-    face_adjoint(g, D, pos, f, A.Rb, Fb);
+    face_adjoint(g, A, D, pos, f, Fb);
     base = bidx(g, pos[0], pos[1], pos[2]);
     double qL[5], qR[5];
 #pragma unroll
@@ -346,8 +334,9 @@ __global__ void __launch_bounds__(256) k_conv_vjp(Dev g, AdjBuffers A) {
       double v0 = Qm[base - 3 * s], v1 = Qm[base - 2 * s], v2 = Qm[base - s];
       double v3 = Qm[base], v4 = Qm[base + s], v5 = Qm[base + 2 * s];
       double gL[5] = {0, 0, 0, 0, 0}, gR[5] = {0, 0, 0, 0, 0};
-      weno5_vjp(v0, v1, v2, v3, v4, qLb[m], gL);
-      weno5_vjp(v5, v4, v3, v2, v1, qRb[m], gR);
+      // an upwind (supersonic) face leaves one side without adjoint
+      if (qLb[m] != 0.0) weno5_vjp(v0, v1, v2, v3, v4, qLb[m], gL);
+      if (qRb[m] != 0.0) weno5_vjp(v5, v4, v3, v2, v1, qRb[m], gR);
       c[0] = gL[0];
       c[1] = gL[1] + gR[4];
       c[2] = gL[2] + gR[3];
@@ -417,7 +406,7 @@ __global__ void __launch_bounds__(256) k_visc_vjp(Dev g, AdjBuffers A) {
     int pos[3] = {t.line[0], t.line[1], t.line[2]};
     pos[D] = f;
     double Fb[5];
-    face_adjoint(g, D, pos, f, A.Rb, Fb);
+    face_adjoint(g, A, D, pos, f, Fb);
     const long base = bidx(g, pos[0], pos[1], pos[2]);
     const long s = g.sb[D];
     double vel[3][4], Tc[4], muc[4];
@@ -440,20 +429,18 @@ __global__ void __launch_bounds__(256) k_visc_vjp(Dev g, AdjBuffers A) {
     }
     double dT = dface4(Tc[0], Tc[1], Tc[2], Tc[3]) * mfD;
     double divt = 0.0, dtn[3] = {0.0, 0.0, 0.0};
-    const double *Qn = g.Q[QU + D];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       const int tt = r == 0 ? T1 : T2;
       if (tt >= NDIM) continue;
-      const long st = g.sb[tt];
-      const double mct = g.mc[tt][pos[tt]];
-      const double *Qtt = g.Q[QU + tt];
+      // cell-centred tangential derivatives of the recomputed stage (k_grad)
+      const double *Gtt = g.G[3 * tt + tt], *Gtn = g.G[3 * tt + D];
       double gtt[4], gtn[4];
 #pragma unroll
       for (int o = 0; o < 4; ++o) {
         long cb = base + (o - 2) * s;
-        gtt[o] = dcell4(Qtt[cb - 2 * st], Qtt[cb - st], Qtt[cb + st], Qtt[cb + 2 * st]) * mct;
-        gtn[o] = dcell4(Qn[cb - 2 * st], Qn[cb - st], Qn[cb + st], Qn[cb + 2 * st]) * mct;
+        gtt[o] = Gtt[cb];
+        gtn[o] = Gtn[cb];
       }
       divt += interp4(gtt[0], gtt[1], gtt[2], gtt[3]);
       dtn[tt] = interp4(gtn[0], gtn[1], gtn[2], gtn[3]);
@@ -554,12 +541,13 @@ __device__ __forceinline__ double dviscosity(const Dev &g, double T, double mu) 
 }
 
 __global__ void __launch_bounds__(256) k_tangential_vjp(Dev g, AdjBuffers A) {
-  const long bl = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (bl >= g.nbox) return;
+  const unsigned bl = blockIdx.x * blockDim.x + threadIdx.x;  // nbox < 2^32
+  if (bl >= (unsigned)g.nbox) return;
+  const unsigned N0 = g.N[0], N01 = N0 * (unsigned)g.N[1];
   int p[3];
-  p[0] = (int)(bl % g.N[0]) - g.h[0];
-  p[1] = (int)((bl / g.N[0]) % g.N[1]) - g.h[1];
-  p[2] = (int)(bl / ((long)g.N[0] * g.N[1])) - g.h[2];
+  p[0] = (int)(bl % N0) - g.h[0];
+  p[1] = (int)((bl % N01) / N0) - g.h[1];
+  p[2] = (int)(bl / N01) - g.h[2];
   const long b = bidx(g, p[0], p[1], p[2]);
   const int nd = g.ndim;
   if (A.Gb[0] != nullptr) {
@@ -587,8 +575,9 @@ __global__ void __launch_bounds__(256) k_tangential_vjp(Dev g, AdjBuffers A) {
 // Transpose of the halo fill along axis d: one thread per column (both
 // sides, all three layers), folding ghost adjoints into their sources.
 // ---------------------------------------------------------------------------
+template <int NDIM>
 __global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, double *dJdK) {
-  const int nd = g.ndim;
+  constexpr int nd = NDIM;
   const int t1 = tan1(d), t2 = tan2(d);
   int lo1 = 0, n1 = g.n[t1], lo2 = 0, n2 = g.n[t2];
   if (t1 < d) { lo1 = -g.h[t1]; n1 = g.N[t1]; }
@@ -603,52 +592,96 @@ __global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, do
     p[t2] = bq;
     return bidx(g, p[0], p[1], p[2]);
   };
+  // adjoint components carried through the halo fill: rho, active
+  // velocities, p, T (mu-bar was folded into T-bar before)
+  constexpr int nq = NDIM + 3;
+  constexpr int qs[6] = {QR, QU, NDIM >= 2 ? QV : QP, NDIM == 3 ? QW : (NDIM == 2 ? QP : QT),
+                         NDIM == 3 ? QP : QT, QT};
   const int n = g.n[d];
   for (int side = 0; side < 2; ++side) {
     const int face = 2 * d + side;
     const int kind = g.bck[face];
     if (kind == BC_DIRICHLET) continue;
-    double vsum = 0.0;  // sum over the column's ghosts of the normal-velocity adjoint
+    const double sigma = side == 0 ? 1.0 : -1.0;
+    long G[3], S[3];
     for (int m = 0; m < 3; ++m) {
-      const long G = box(side == 0 ? -1 - m : n + m);
+      G[m] = box(side == 0 ? -1 - m : n + m);
       int src;
       if (kind == BC_PERIODIC) src = side == 0 ? n - 1 - m : m;
       else if (kind == BC_ZEROGRAD) src = side == 0 ? 0 : n - 1;
       else src = side == 0 ? m : n - 1 - m;
-      const long S = box(src);
-      if (kind == BC_PERIODIC || kind == BC_ZEROGRAD) {
-        for (int q = 0; q < 6; ++q) A.Qb[q][S] += A.Qb[q][G];
-        continue;
-      }
-      // walls: p_g = p_s, u_g = -u_s (plus a prescribed normal part that
-      // depends on the state only through the porous p_w below);
-      // isothermal: rho_g = p_g/(R T_g), T_g = 2 T_w - T_s; adiabatic:
-      // rho_g = rho_s, T_g = T_s
+      S[m] = box(src);
+    }
+    // all ghost adjoints of the column first (independent loads) ...
+    double gb[3][6];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int i = 0; i < nq; ++i) gb[m][i] = A.Qb[qs[i]][G[m]];
+    // ... mapped to contributions to their sources: copies pass through;
+    // walls: p_g = p_s, u_g = -u_s (plus a prescribed normal part that
+    // depends on the state only through the porous p_w below); isothermal:
+    // rho_g = p_g/(R T_g), T_g = 2 T_w - T_s; adiabatic: rho_g = rho_s,
+    // T_g = T_s
+    constexpr int iP = nq - 2, iT = nq - 1;
+    double cs[3][6];
+    double vsum = 0.0;  // sum over the column's ghosts of the normal-velocity adjoint
+    double gn[3];       // the normal-velocity adjoint of each ghost layer
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      gn[m] = gb[m][1];
+#pragma unroll
+      for (int c = 1; c < nd; ++c)
+        if (c == d) gn[m] = gb[m][1 + c];
+#pragma unroll
+      for (int i = 0; i < nq; ++i) cs[m][i] = gb[m][i];
+      if (!is_wall(kind)) continue;
+#pragma unroll
+      for (int c = 0; c < nd; ++c) cs[m][1 + c] = -gb[m][1 + c];
       if (g.Tw[face] > 0.0) {
-        double rg = g.Q[QR][G], pg = g.Q[QP][G];
-        double rb = A.Qb[QR][G];
-        double pgb = A.Qb[QP][G] + rb * rg / pg;
-        double Tgb = A.Qb[QT][G] - rb * rg * rg * g.R / pg;
-        A.Qb[QP][S] += pgb;
-        A.Qb[QT][S] -= Tgb;
-      } else {
-        A.Qb[QR][S] += A.Qb[QR][G];
-        A.Qb[QP][S] += A.Qb[QP][G];
-        A.Qb[QT][S] += A.Qb[QT][G];
+        const double rg = g.Q[QR][G[m]], pg = g.Q[QP][G[m]];
+        const double rb = gb[m][0];
+        cs[m][0] = 0.0;
+        cs[m][iP] = gb[m][iP] + rb * rg / pg;
+        cs[m][iT] = -(gb[m][iT] - rb * rg * rg * g.R / pg);
       }
-      for (int c = 0; c < nd; ++c) A.Qb[QU + c][S] -= A.Qb[QU + c][G];
-      if (kind == BC_POROUS && face == g.pface && a >= g.pb && a < g.pe && bq >= 0 &&
-          bq < g.n[t2]) {
-        // v_g[d] = 2 sigma v_n - v_s[d], v_n = -K (p_w - p_inf)/p_inf
-        const double sigma = side == 0 ? 1.0 : -1.0;
-        const long W = box(side == 0 ? 0 : n - 1);
-        const int kk = bq * (g.pe - g.pb) + (a - g.pb);
-        double vnb = 2.0 * sigma * A.Qb[QU + d][G];
-        double pw = g.Q[QP][W];
-        A.Qb[QP][W] += -g.K[kk] / g.pinf * vnb;
-        if (dJdK) dJdK[kk] += -(pw - g.pinf) / g.pinf * vnb;
+      vsum += gn[m];
+    }
+    if (kind == BC_POROUS && face == g.pface && a >= g.pb && a < g.pe && bq >= 0 &&
+        bq < g.n[t2]) {
+      // v_g[d] = 2 sigma v_n - v_s[d], v_n = -K (p_w - p_inf)/p_inf; the
+      // wall cell W is the source of ghost layer 0
+      const int kk = bq * (g.pe - g.pb) + (a - g.pb);
+      const double pw = g.Q[QP][S[0]];
+      double kb = 0.0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const double vnb = 2.0 * sigma * gn[m];
+        cs[0][iP] += -g.K[kk] / g.pinf * vnb;
+        kb += -(pw - g.pinf) / g.pinf * vnb;
       }
-      vsum += A.Qb[QU + d][G];
+      if (dJdK) dJdK[kk] += kb;
+    }
+    // fold into the sources (read all, then write all: distinct sources;
+    // one merged update when every layer copies the same cell)
+    if (kind == BC_ZEROGRAD) {
+#pragma unroll
+      for (int i = 0; i < nq; ++i) A.Qb[qs[i]][S[0]] += (cs[0][i] + cs[1][i]) + cs[2][i];
+    } else if (n >= 3) {
+      double sv[3][6];
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int i = 0; i < nq; ++i) sv[m][i] = A.Qb[qs[i]][S[m]];
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int i = 0; i < nq; ++i) A.Qb[qs[i]][S[m]] = sv[m][i] + cs[m][i];
+    } else {
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int i = 0; i < nq; ++i) A.Qb[qs[i]][S[m]] += cs[m][i];
     }
     if (kind == BC_DISTURB && dJdK) {
       // v_g[d] = 2 sigma A sin(phi) - v_s[d], phi = 2 pi kappa x: per-column
@@ -658,7 +691,7 @@ __global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, do
         const double *th = g.K + g.doff[face];
         const double x = g.xm[t1][a];
         const double ph = 2.0 * M_PI * x * th[1];
-        const double w = 2.0 * (side == 0 ? 1.0 : -1.0) * vsum;
+        const double w = 2.0 * sigma * vsum;
         dA = w * sin(ph);
         dk = w * th[0] * cos(ph) * 2.0 * M_PI * x;
       }
@@ -702,12 +735,13 @@ __global__ void __launch_bounds__(256) k_interior_vjp(Dev g, AdjBuffers A, const
                                                       const double *Wb, double a, double b,
                                                       double *Vb, const double *acc_in,
                                                       double *acc_out, int fold) {
-  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.ncell) return;
+  const unsigned cu = blockIdx.x * blockDim.x + threadIdx.x;  // ncell < 2^31
+  if (cu >= (unsigned)g.ncell) return;
+  const long c = cu;
   const long nc = g.ncell;
   const int nd = g.ndim;
-  int i = (int)(c % g.n[0]), j = (int)((c / g.n[0]) % g.n[1]),
-      k = (int)(c / ((long)g.n[0] * g.n[1]));
+  const unsigned n0 = g.n[0], n01 = n0 * (unsigned)g.n[1];
+  const int k = (int)(cu / n01), j = (int)((cu % n01) / n0), i = (int)(cu % n0);
   const long bx = bidx(g, i, j, k);
   double rho = V[c];
   double ir = 1.0 / rho;
@@ -769,15 +803,18 @@ static inline unsigned blocks(long n) { return (unsigned)((n + 255) / 256 > 0 ? 
 
 // Reverse of one stage: Vb = b Wb + R'(V)^T (b dt Wb), accumulators as in
 // k_interior_vjp.  Needs g.Q to hold nothing on entry (recomputed here).
-static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A, const double *V, const double *Wb,
+static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A0, const double *V, const double *Wb,
                             const double *dt, double a, double b, double *Vb,
                             const double *acc_in, double *acc_out, int fold, double *dJdK,
                             hipStream_t st) {
-  DCF_TRY(launch_prim_halo(g, V, st));
-  DCF_TRY(launch_fill(A.zero_begin, 0.0, A.zero_count, st));
   const bool visc = g.visc != VISC_NONE;
-  k_rbar<<<blocks(g.ncell), 256, 0, st>>>(g, Wb, dt, b, A.Rb);
-  DCF_TRY(hipGetLastError());
+  AdjBuffers A = A0;
+  A.Wb = Wb;
+  A.dtp = dt;
+  A.bcoef = b;
+  DCF_TRY(launch_prim_halo(g, V, st));
+  if (visc && g.ndim >= 2) DCF_TRY(launch_grad(g, st));
+  DCF_TRY(launch_fill(A.zero_begin, 0.0, A.zero_count, st));
   for (int D = 0; D < g.ndim; ++D) {
     hipLaunchKernelGGL(conv_kernel(g.ndim, D), dim3(tile_count<-3, 2>(g, D)), dim3(256), 0, st, g,
                        A);
@@ -796,7 +833,8 @@ static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A, const double *V, 
     const int t1 = tan1(d), t2 = tan2(d);
     long n1 = t1 < d ? g.N[t1] : g.n[t1];
     long n2 = t2 < d ? g.N[t2] : g.n[t2];
-    k_halo_vjp<<<blocks(n1 * n2), 256, 0, st>>>(g, A, d, dJdK);
+    auto hk = g.ndim == 1 ? k_halo_vjp<1> : (g.ndim == 2 ? k_halo_vjp<2> : k_halo_vjp<3>);
+    hk<<<blocks(n1 * n2), 256, 0, st>>>(g, A, d, dJdK);
     DCF_TRY(hipGetLastError());
     for (int side = 0; side < 2 && dJdK; ++side) {
       const int face = 2 * d + side;

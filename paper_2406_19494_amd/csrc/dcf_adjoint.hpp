@@ -10,7 +10,9 @@ struct AdjBuffers {
   double *Qb[NQ];   // adjoint of the primitive box (rho, u, v, w, p, T, mu)
   double *Gb[9];    // adjoint of cell-centred velocity derivatives d u_phi / d x_t (3 t + phi)
   double *Ub1, *Ub2, *acc;  // stage adjoints and the running lambda^n accumulator
-  double *Rb;       // per-cell adjoint of the right-hand side
+  const double *Wb;  // stage-output adjoint of the stage being reversed
+  const double *dtp; // step size (device)
+  double bcoef;      // weight b of the stage's V + dt R(V) term
   double *dpart;    // per-column partial sums of dJ/d(A, kappa), 4 per wall column
   long dcols;       // columns per disturbance-face partial array
   double *zero_begin;  // Qb and Gb are carved back to back: one fill clears both
@@ -30,7 +32,6 @@ template <class Carver> void carve_adjoint(Carver &cv, const Dev &g, AdjBuffers 
   a.Ub1 = cv.template take<double>((long)g.nv * g.ncell);
   a.Ub2 = cv.template take<double>((long)g.nv * g.ncell);
   a.acc = cv.template take<double>((long)g.nv * g.ncell);
-  a.Rb = cv.template take<double>((long)5 * g.ncell);
   long cols = 1;
   for (int d = 0; d < g.ndim; ++d) {
     const int t1 = tan1(d), t2 = tan2(d);

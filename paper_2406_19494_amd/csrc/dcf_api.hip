@@ -107,7 +107,11 @@ dcf_status dcf_create(const dcf_grid *grid, const dcf_gas *gas, dcf_ctx **out) {
   if (gas->visc_law != 0 && (!(gas->Pr > 0.0) || !(gas->T_ref > 0.0) || gas->mu_ref < 0.0))
     return fail(DCF_EINVAL, "viscous gas needs Pr > 0, T_ref > 0, mu_ref >= 0");
   long ncell = (long)grid->n[0] * grid->n[1] * grid->n[2];
-  if (ncell > (1L << 31) - 1) return fail(DCF_EINVAL, "grid too large");
+  long nboxc = 1;
+  for (int d = 0; d < 3; ++d) nboxc *= grid->n[d] + (d < grid->ndim ? 2 * NH : 0);
+  // kernels index cells with 32-bit thread indices
+  if (ncell > (1L << 31) - 1 || nboxc > (1L << 32) - 1)
+    return fail(DCF_EINVAL, "grid too large");
 
   dcf_ctx *c = new (std::nothrow) dcf_ctx();
   if (!c) return fail(DCF_ENOMEM, "host allocation failed");

@@ -571,10 +571,11 @@ __global__ void __launch_bounds__(256) k_force_final(const double *part, int npa
 __global__ void __launch_bounds__(256) k_update(Dev g, const double *Un, const double *Uin,
                                                 double *Uout, double *Rout, const double *dtp,
                                                 double a, double bcoef, const double *force) {
-  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.ncell) return;
-  int i = (int)(c % g.n[0]), j = (int)((c / g.n[0]) % g.n[1]),
-      k = (int)(c / ((long)g.n[0] * g.n[1]));
+  const unsigned cu = blockIdx.x * blockDim.x + threadIdx.x;  // ncell < 2^31
+  if (cu >= (unsigned)g.ncell) return;
+  const long c = cu;
+  const unsigned n0 = g.n[0], n01 = n0 * (unsigned)g.n[1];
+  const int k = (int)(cu / n01), j = (int)((cu % n01) / n0), i = (int)(cu % n0);
   const int nd = g.ndim;
   double R[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int D = 0; D < nd; ++D) {
