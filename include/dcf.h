@@ -172,6 +172,25 @@ dcf_status dcf_compute_dt(dcf_ctx *ctx, const double *U_dev, double cfl, double 
 /* One TVD-RK3 step (Shu-Osher form) in place, with dt read from dt_dev[0]. */
 dcf_status dcf_rk3_step(dcf_ctx *ctx, double *U_dev, const double *dt_dev, void *stream);
 
+/* ---- batched stepping (the serving loop's step launches) ---------------- */
+/* Bytes of the device table dcf_batch_rk3_step needs for n solves. */
+dcf_status dcf_batch_table_bytes(int n, size_t *bytes);
+
+/* One TVD-RK3 step of each of n independent solves with one launch per
+ * kernel and stage for the whole batch (the same kernels as dcf_rk3_step;
+ * workgroup (x, y) works on tile x of solve y, so solves of different grid
+ * sizes share a launch).  ctxs[i] (distinct contexts, workspaces set),
+ * U[i] (dev, advanced in place), dt[i] (dev, one double each).  With
+ * cfl > 0 each solve's CFL step is computed first into dt[i] (as
+ * dcf_compute_dt), otherwise dt[i] is read.  table: caller-owned device
+ * memory of dcf_batch_table_bytes(n) bytes, 16-byte aligned, rewritten by
+ * this call (an asynchronous host-to-device copy on `stream`; not for graph
+ * capture).  Results are bitwise those of n calls of dcf_rk3_step.  The
+ * solves must share ndim and the viscous flag (else DCF_EUNSUPPORTED) and
+ * carry no source term (DCF_EUNSUPPORTED). */
+dcf_status dcf_batch_rk3_step(dcf_ctx *const *ctxs, double *const *U, double *const *dt, int n,
+                              double cfl, void *table, size_t table_bytes, void *stream);
+
 /* out_dev[8] = (<rho|u|^2/2>_V, <mu|omega|^2>_V, total mass, total x/y/z
  * momentum, total energy, volume). */
 dcf_status dcf_diagnostics(dcf_ctx *ctx, const double *U_dev, double *out_dev, void *stream);

@@ -67,6 +67,9 @@ _SIGS = {
     "dcf_gradient_finish": [_vp, _vp, _vp],
     "dcf_flags": [_vp, C.POINTER(C.c_uint), _vp],
     "dcf_time_kernel": [_vp, _vp, C.c_int, C.c_int, C.POINTER(C.c_double), _vp],
+    "dcf_batch_table_bytes": [C.c_int, C.POINTER(C.c_size_t)],
+    "dcf_batch_rk3_step": [C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.c_int, C.c_double,
+                           _vp, C.c_size_t, _vp],
 }
 
 _lib = None

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libdcf.so")
-SOURCES = ["dcf_api.hip", "dcf_forward.hip", "dcf_adjoint.hip", "dcf_batch.hip"]
+SOURCES = ["dcf_api.hip", "dcf_forward.hip", "dcf_adjoint.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -361,7 +361,9 @@ __global__ void __launch_bounds__(256) k_conv_vjp(Dev g, AdjBuffers A) {
   }
   // write the completed cells: window cell w <-> cell t.f0 + OLO + w
   for (int i = threadIdx.x; i < TW * NCW; i += 256) {
-    const int ll = i / NCW, w = i % NCW;
+    // x-lines: consecutive threads take consecutive cells of a line;
+    // otherwise consecutive lines (x-neighbours) of one cell position
+    const int ll = D == 0 ? i / NCW : i % TW, w = D == 0 ? i % NCW : i / TW;
     const int cell = t.f0 + OLO + w;
     if (cell < t.c0 || cell >= t.c1) continue;
     long ln = t.lg * TW + ll;
@@ -498,7 +500,9 @@ __global__ void __launch_bounds__(256) k_visc_vjp(Dev g, AdjBuffers A) {
     __syncthreads();
   }
   for (int i = threadIdx.x; i < TW * NCW; i += 256) {
-    const int ll = i / NCW, w = i % NCW;
+    // x-lines: consecutive threads take consecutive cells of a line;
+    // otherwise consecutive lines (x-neighbours) of one cell position
+    const int ll = D == 0 ? i / NCW : i % TW, w = D == 0 ? i % NCW : i / TW;
     const int cell = t.f0 + OLO + w;
     if (cell < t.c0 || cell >= t.c1) continue;
     long ln = t.lg * TW + ll;

@@ -427,6 +427,49 @@ dcf_status dcf_rk3_step(dcf_ctx *c, double *U, const double *dt, void *stream) {
   return rk3_stages(c, U, dt, (hipStream_t)stream);
 }
 
+dcf_status dcf_batch_table_bytes(int n, size_t *bytes) {
+  if (n < 1 || !bytes) return fail(DCF_EINVAL, "need n >= 1 and a result pointer");
+  *bytes = (size_t)n * sizeof(BatchEntry);
+  return DCF_OK;
+}
+
+dcf_status dcf_batch_rk3_step(dcf_ctx *const *ctxs, double *const *U, double *const *dt, int n,
+                              double cfl, void *table, size_t table_bytes, void *stream) {
+  if (n < 1 || !ctxs || !U || !dt || !table) return fail(DCF_EINVAL, "null argument or n < 1");
+  if (table_bytes < (size_t)n * sizeof(BatchEntry))
+    return fail(DCF_EINVAL, "table needs %zu bytes, got %zu", (size_t)n * sizeof(BatchEntry),
+                table_bytes);
+  if (((uintptr_t)table) & 15) return fail(DCF_EINVAL, "table must be 16-byte aligned");
+  static thread_local std::vector<BatchEntry> h;
+  h.resize(n);
+  for (int i = 0; i < n; ++i) {
+    dcf_ctx *c = ctxs[i];
+    dcf_status s = ready(c, 0);
+    if (s) return s;
+    if (!U[i] || !dt[i]) return fail(DCF_EINVAL, "null state or step of solve %d", i);
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == c) return fail(DCF_EINVAL, "context of solve %d repeats solve %d", i, j);
+    const Dev &g = c->g;
+    if (g.ndim != ctxs[0]->g.ndim || (g.visc != VISC_NONE) != (ctxs[0]->g.visc != VISC_NONE))
+      return fail(DCF_EUNSUPPORTED, "solve %d: a batch needs one dimension and viscous flag", i);
+    if (g.source != SRC_NONE)
+      return fail(DCF_EUNSUPPORTED, "solve %d: source terms are not batched", i);
+    BatchEntry &e = h[i];
+    e.g = g;
+    e.U = U[i];
+    e.U1 = c->U1;
+    e.U2 = c->U2;
+    e.dt = dt[i];
+    e.part = c->part;
+    batch_entry_sizes(e);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  DCF_HIP(hipMemcpyAsync(table, h.data(), (size_t)n * sizeof(BatchEntry), hipMemcpyHostToDevice,
+                         st));
+  DCF_HIP(launch_batch_step((const BatchEntry *)table, h.data(), n, cfl, st));
+  return DCF_OK;
+}
+
 dcf_status dcf_diagnostics(dcf_ctx *c, const double *U, double *out, void *stream) {
   dcf_status s = ready(c, 0);
   if (s) return s;

@@ -2,6 +2,8 @@
 // primitives fused with the halo fill, per-direction face fluxes, the fused
 // divergence + source + TVD-RK3 stage update, and deterministic reductions
 // (CFL time step, body force, diagnostics, wall-pressure cost).
+#include <algorithm>
+
 #include "dcf_kernels.hpp"
 
 namespace dcf {
@@ -84,11 +86,11 @@ __global__ void k_init_state(Dev g, const double *P, double *U) {
 }
 
 // ---------------------------------------------------------------------------
-// Primitive box with halos.  One thread per box cell.  The halo fill of the
-// paper (values assigned to halo cells) is applied axis by axis, x then y
-// then z, each over the full extent of the axes filled before; a thread
-// resolves that chain for its own cell: it follows the source cells back to
-// the interior (or to a Dirichlet profile) and applies the per-axis ghost
+// Primitive box with halos.  The halo fill of the paper (values assigned to
+// halo cells, Section 3.2) is applied axis by axis, x then y then z, each
+// over the full extent of the axes filled before; a ghost thread resolves
+// that chain for its own cell: it follows the source cells back to the
+// interior (or to a Dirichlet profile) and applies the per-axis ghost
 // transforms in x, y, z order.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int ghost_source(int kind, int side, int m, int n) {
@@ -97,10 +99,11 @@ __device__ __forceinline__ int ghost_source(int kind, int side, int m, int n) {
   return side == 0 ? m : n - 1 - m;  // walls mirror
 }
 
-// Threads [0, ncell) convert interior cells (x-fastest, coalesced, one
-// branch for the whole wave); threads [ncell, nbox) fill the ghost cells.
-__global__ void __launch_bounds__(256) k_prim_halo(Dev g, const double *U) {
-  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+// Single-launch form (used when ghost cells are a small share of the box):
+// threads [0, ncell) convert interior cells (x-fastest, coalesced, one
+// branch for the whole wave); threads [ncell, nbox) fill the ghost cells,
+// converting their source cell's state themselves.
+__device__ __forceinline__ void prim_halo_body(const Dev &g, const double *U, unsigned t) {
   if (t >= (unsigned)g.nbox) return;
   const int nd = g.ndim;
   int p[3];
@@ -220,38 +223,205 @@ __global__ void __launch_bounds__(256) k_prim_halo(Dev g, const double *U) {
   }
 }
 
+__global__ void __launch_bounds__(256) k_prim_halo(Dev g, const double *U) {
+  prim_halo_body(g, U, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Interior cells: primitives of their own conserved state (x-fastest,
+// coalesced).
+__device__ __forceinline__ void prim_interior_body(const Dev &g, const double *U, unsigned t) {
+  if (t >= (unsigned)g.ncell) return;
+  const int nd = g.ndim;
+  const unsigned n0 = g.n[0], n01 = n0 * (unsigned)g.n[1];
+  const int k = (int)(t / n01), j = (int)((t % n01) / n0), i = (int)(t % n0);
+  const long b = bidx(g, i, j, k);
+  double q[6];
+  cons_to_prim(g, U, (long)t, q);
+  if (!(finite_pos(q[QR]) && finite_pos(q[QP]))) atomicOr(g.flags, 1u);
+  g.Q[QR][b] = q[QR];
+  g.Q[QU][b] = q[QU];
+  if (nd >= 2) g.Q[QV][b] = q[QV];
+  if (nd >= 3) g.Q[QW][b] = q[QW];
+  g.Q[QP][b] = q[QP];
+  if (g.visc != VISC_NONE) {
+    g.Q[QT][b] = q[QT];
+    g.Q[QMU][b] = viscosity(g, q[QT]);
+  }
+}
+
+// Ghost cell number t (after k_prim_interior): follow the chain of sources
+// back to an interior cell (or a Dirichlet profile), copy its primitives from
+// the box and apply the per-axis ghost transforms in x, y, z order; mu is
+// recomputed only where a transform changed T.
+__device__ __forceinline__ void prim_ghost_body(const Dev &g, unsigned t) {
+  if (t >= (unsigned)(g.nbox - g.ncell)) return;
+  const int nd = g.ndim;
+  int p[3];
+  ghost_position(g, t, p);
+  const long b = bidx(g, p[0], p[1], p[2]);
+  int s[3] = {p[0], p[1], p[2]};
+  int side[3] = {0, 0, 0};
+  bool gh[3] = {false, false, false};
+  int top = -1;
+  for (int d = 0; d < nd; ++d) {
+    if (p[d] < 0 || p[d] >= g.n[d]) {
+      gh[d] = true;
+      side[d] = p[d] < 0 ? 0 : 1;
+      int m = side[d] == 0 ? -1 - p[d] : p[d] - g.n[d];
+      int kind = g.bck[2 * d + side[d]];
+      if (kind == BC_DIRICHLET)
+        top = d;
+      else
+        s[d] = ghost_source(kind, side[d], m, g.n[d]);
+    }
+  }
+  double q[6];
+  double mu = -1.0;  // mu of the source while no transform changed T
+  int start = 0;
+  if (top >= 0) {
+    const int d = top;
+    const int t1 = tan1(d), t2 = tan2(d);
+    int a = t1 < nd ? (t1 < d ? p[t1] : s[t1]) : 0;
+    int bb = t2 < nd ? (t2 < d ? p[t2] : s[t2]) : 0;
+    a = min(max(a, 0), g.n[t1] - 1);
+    bb = min(max(bb, 0), g.n[t2] - 1);
+    const long nt = (long)g.n[t1] * g.n[t2];
+    const long o = (long)bb * g.n[t1] + a;
+    const double *P = g.dir[2 * d + side[d]];
+    q[QR] = P[o];
+    q[QU] = P[nt + o];
+    q[QV] = P[2 * nt + o];
+    q[QW] = P[3 * nt + o];
+    q[QP] = P[4 * nt + o];
+    q[QT] = q[QP] / (q[QR] * g.R);
+    mu = -1.0;  // recomputed below
+    start = top + 1;
+  } else {
+    // the source is an interior cell, converted by k_prim_interior
+    const long sb = bidx(g, s[0], s[1], s[2]);
+    q[QR] = g.Q[QR][sb];
+    q[QU] = g.Q[QU][sb];
+    q[QV] = nd >= 2 ? g.Q[QV][sb] : 0.0;
+    q[QW] = nd >= 3 ? g.Q[QW][sb] : 0.0;
+    q[QP] = g.Q[QP][sb];
+    if (g.visc != VISC_NONE) {
+      q[QT] = g.Q[QT][sb];
+      mu = g.Q[QMU][sb];
+    } else {
+      q[QT] = q[QP] / (q[QR] * g.R);
+    }
+  }
+  for (int d = start; d < nd; ++d) {
+    if (!gh[d]) continue;
+    const int face = 2 * d + side[d];
+    const int kind = g.bck[face];
+    if (!is_wall(kind)) continue;  // copies keep the value
+    double src_n = q[QU + d];
+    q[QU] = -q[QU];
+    q[QV] = -q[QV];
+    q[QW] = -q[QW];
+    const int t1 = tan1(d), t2 = tan2(d);
+    const int a = t1 < nd ? (t1 < d ? p[t1] : s[t1]) : 0;
+    const int bb = t2 < nd ? (t2 < d ? p[t2] : s[t2]) : 0;
+    const double sigma = side[d] == 0 ? 1.0 : -1.0;
+    if (kind == BC_POROUS && face == g.pface) {
+      if (a >= g.pb && a < g.pe && bb >= 0 && bb < g.n[t2]) {
+        // Darcy transpiration through the porous strip: inward-normal
+        // velocity -K (p_w - p_inf)/p_inf, p_w of the first interior cell.
+        int w[3];
+        w[d] = side[d] == 0 ? 0 : g.n[d] - 1;
+        w[t1] = a;
+        w[t2] = bb;
+        const double pw = g.Q[QP][bidx(g, w[0], w[1], w[2])];
+        int kk = bb * (g.pe - g.pb) + (a - g.pb);
+        double vn = -g.K[kk] * (pw - g.pinf) / g.pinf;
+        q[QU + d] = 2.0 * sigma * vn - src_n;
+      }
+    } else if (kind == BC_DISTURB && a >= 0 && a < g.n[t1]) {
+      // Disturbance wall (Section 3.2, Eq. (8)): prescribed inward-normal
+      // velocity A sin(2 pi kappa x) at the wall-face centre, (A, kappa)
+      // taken from the boundary parameters.
+      const double *th = g.K + g.doff[face];
+      double vn = th[0] * sin(2.0 * M_PI * g.xm[t1][a] * th[1]);
+      q[QU + d] = 2.0 * sigma * vn - src_n;
+    }
+    if (g.Tw[face] > 0.0) {  // isothermal; adiabatic keeps rho and T
+      double Tg = 2.0 * g.Tw[face] - q[QT];
+      if (!(Tg > 0.0)) atomicOr(g.flags, 1u);
+      q[QT] = Tg;
+      q[QR] = q[QP] / (g.R * Tg);
+      mu = -1.0;
+    }
+  }
+  g.Q[QR][b] = q[QR];
+  g.Q[QU][b] = q[QU];
+  if (nd >= 2) g.Q[QV][b] = q[QV];
+  if (nd >= 3) g.Q[QW][b] = q[QW];
+  g.Q[QP][b] = q[QP];
+  if (g.visc != VISC_NONE) {
+    g.Q[QT][b] = q[QT];
+    g.Q[QMU][b] = mu >= 0.0 ? mu : viscosity(g, q[QT]);
+  }
+}
+
+// Two-launch form (many ghost cells): interior cells, then the ghost cells
+// copied from the interior ones.
+__global__ void __launch_bounds__(256) k_prim_interior(Dev g, const double *U) {
+  prim_interior_body(g, U, blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void __launch_bounds__(256) k_prim_ghost(Dev g) {
+  prim_ghost_body(g, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Cell-centred velocity derivatives d u_phi / d x_t (4th order, index space
 // times the analytic metric) on every cell that a face flux reads them from:
 // position along t interior, the other active positions within two layers.
 // G[3 t + phi] are box arrays.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_grad(Dev g) {
-  const unsigned bl = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (bl >= (unsigned)g.nbox) return;
-  const unsigned N0 = g.N[0], N01 = (unsigned)g.N[0] * g.N[1];
+template <int NDIM>
+__device__ __forceinline__ void grad_body(const Dev &g, unsigned bid, unsigned nblk) {
+  // threads over the cells within two layers of the interior, x-fastest
+  const unsigned bl = xcd_remap(bid, nblk) * blockDim.x + threadIdx.x;
+  const unsigned E0 = g.n[0] + 4, E1 = g.n[1] + 4, E2 = NDIM >= 3 ? g.n[2] + 4 : 1;
+  if (bl >= E0 * E1 * E2) return;
   int p[3];
-  p[2] = (int)(bl / N01) - g.h[2];
-  const unsigned r = bl % N01;
-  p[1] = (int)(r / N0) - g.h[1];
-  p[0] = (int)(r % N0) - g.h[0];
+  const unsigned r = bl / E0;
+  p[0] = (int)(bl % E0) - 2;
+  p[1] = (int)(r % E1) - 2;
+  p[2] = NDIM >= 3 ? (int)(r / E1) - 2 : 0;
   const long b = bidx(g, p[0], p[1], p[2]);
-  const int nd = g.ndim;
-  bool near[3];
-  for (int e = 0; e < 3; ++e) near[e] = e >= nd || (p[e] >= -2 && p[e] < g.n[e] + 2);
-  for (int t = 0; t < nd; ++t) {
-    if (p[t] < 0 || p[t] >= g.n[t]) continue;
-    bool ok = true;
-    for (int e = 0; e < nd; ++e)
-      if (e != t && !near[e]) ok = false;
-    if (!ok) continue;
+  // all stencil loads first, then the derivatives of the axes along which
+  // this cell is interior
+  bool in[NDIM];
+  double v[NDIM][NDIM][4];
+#pragma unroll
+  for (int t = 0; t < NDIM; ++t) {
+    in[t] = p[t] >= 0 && p[t] < g.n[t];
+    if (!in[t]) continue;
     const long st = g.sb[t];
-    const double mct = g.mc[t][p[t]];
-    for (int phi = 0; phi < nd; ++phi) {
+#pragma unroll
+    for (int phi = 0; phi < NDIM; ++phi) {
       const double *A = g.Q[QU + phi];
-      g.G[3 * t + phi][b] = dcell4(A[b - 2 * st], A[b - st], A[b + st], A[b + 2 * st]) * mct;
+      v[t][phi][0] = A[b - 2 * st];
+      v[t][phi][1] = A[b - st];
+      v[t][phi][2] = A[b + st];
+      v[t][phi][3] = A[b + 2 * st];
     }
   }
+#pragma unroll
+  for (int t = 0; t < NDIM; ++t) {
+    if (!in[t]) continue;
+    const double mct = g.mc[t][p[t]];
+#pragma unroll
+    for (int phi = 0; phi < NDIM; ++phi)
+      g.G[3 * t + phi][b] = dcell4(v[t][phi][0], v[t][phi][1], v[t][phi][2], v[t][phi][3]) * mct;
+  }
+}
+
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_grad(Dev g) {
+  grad_body<NDIM>(g, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -360,12 +530,11 @@ __device__ __forceinline__ int slot_of(int q) { return q; }  // QR..QMU map 1:1
 // from LDS.  Coalesced loads, one global read per staged value.
 // ---------------------------------------------------------------------------
 template <int NDIM, bool VISC>
-__global__ void __launch_bounds__(256) k_flux_x(Dev g, int nwmax) {
-  extern __shared__ double lds[];
+__device__ __forceinline__ void flux_x_body(const Dev &g, int nwmax, unsigned bid, double *lds) {
   using S = Slots<NDIM, VISC>;
   const int nf = g.n[0] + 1;
   const unsigned total = (unsigned)g.fcount[0];
-  const unsigned t0 = blockIdx.x * 256u;
+  const unsigned t0 = bid * 256u;
   const unsigned tl = min(t0 + 255u, total - 1u);
   const unsigned r0 = t0 / nf, f0 = t0 % nf;
   const unsigned rl = tl / nf;
@@ -408,20 +577,25 @@ __global__ void __launch_bounds__(256) k_flux_x(Dev g, int nwmax) {
   for (int m = 0; m < 5; ++m) F[m * fc + t] = G[m];
 }
 
+template <int NDIM, bool VISC>
+__global__ void __launch_bounds__(256) k_flux_x(Dev g, int nwmax) {
+  extern __shared__ double lds[];
+  flux_x_body<NDIM, VISC>(g, nwmax, blockIdx.x, lds);
+}
+
 // ---------------------------------------------------------------------------
 // y / z faces: 16 (x) x 16 (faces along D) tiles; the tile's 21 cells along D
 // by 16 along x are staged in LDS per primitive / derivative.
 // ---------------------------------------------------------------------------
 template <int NDIM, int D, bool VISC>
-__global__ void __launch_bounds__(256) k_flux_yz(Dev g) {
+__device__ __forceinline__ void flux_yz_body(const Dev &g, unsigned lin, unsigned ntot,
+                                             unsigned nbx, unsigned nby) {
   using S = Slots<NDIM, VISC>;
   constexpr int TX = 16, TD = 16, TR = TD + 5;
   __shared__ double lds[S::NC][TR][TX];
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
   // tiles along D are consecutive in the remapped order (they share 5 rows)
-  const unsigned nbx = gridDim.x, nby = gridDim.y;
-  const unsigned lin = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
-  const unsigned lg = xcd_remap(lin, nbx * nby * gridDim.z);
+  const unsigned lg = xcd_remap(lin, ntot);
   const unsigned by = lg % nby, rest = lg / nby;
   const int i0 = (int)(rest % nbx) * TX, f0 = (int)by * TD, oc = (int)(rest / nbx);
   const int nD = g.n[D];
@@ -458,6 +632,13 @@ __global__ void __launch_bounds__(256) k_flux_yz(Dev g) {
   const long fc = g.fcount[D];
 #pragma unroll
   for (int m = 0; m < 5; ++m) F[m * fc + t] = G[m];
+}
+
+template <int NDIM, int D, bool VISC>
+__global__ void __launch_bounds__(256) k_flux_yz(Dev g) {
+  const unsigned nbx = gridDim.x, nby = gridDim.y;
+  flux_yz_body<NDIM, D, VISC>(g, blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z),
+                              nbx * nby * gridDim.z, nbx, nby);
 }
 
 // Index of the face left of cell (i, j, k) in direction D's face array.
@@ -568,10 +749,10 @@ __global__ void __launch_bounds__(256) k_force_final(const double *part, int npa
 // TVD-RK3 stage: Uout = a*Un + b*(Uin + dt*R).  With Rout != nullptr the
 // kernel writes R instead (rhs evaluation).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_update(Dev g, const double *Un, const double *Uin,
-                                                double *Uout, double *Rout, const double *dtp,
-                                                double a, double bcoef, const double *force) {
-  const unsigned cu = blockIdx.x * blockDim.x + threadIdx.x;  // ncell < 2^31
+__device__ __forceinline__ void update_body(const Dev &g, const double *Un, const double *Uin,
+                                            double *Uout, double *Rout, const double *dtp,
+                                            double a, double bcoef, const double *force,
+                                            unsigned cu) {  // ncell < 2^31
   if (cu >= (unsigned)g.ncell) return;
   const long c = cu;
   const unsigned n0 = g.n[0], n01 = n0 * (unsigned)g.n[1];
@@ -614,14 +795,21 @@ __global__ void __launch_bounds__(256) k_update(Dev g, const double *Un, const d
   }
 }
 
+__global__ void __launch_bounds__(256) k_update(Dev g, const double *Un, const double *Uin,
+                                                double *Uout, double *Rout, const double *dtp,
+                                                double a, double bcoef, const double *force) {
+  update_body(g, Un, Uin, Uout, Rout, dtp, a, bcoef, force, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // CFL time step: dt = min(dt_max, cfl / max_cells sigma).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_dt_partial(Dev g, const double *U, double *part) {
+__device__ __forceinline__ void dt_partial_body(const Dev &g, const double *U, double *part,
+                                                unsigned bid, unsigned nblk) {
   __shared__ double sh[256];
   double smax = 0.0;
-  for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < g.ncell;
-       c += (long)gridDim.x * blockDim.x) {
+  for (long c = (long)bid * blockDim.x + threadIdx.x; c < g.ncell;
+       c += (long)nblk * blockDim.x) {
     int pos[3] = {(int)(c % g.n[0]), (int)((c / g.n[0]) % g.n[1]),
                   (int)(c / ((long)g.n[0] * g.n[1]))};
     double q[6];
@@ -643,16 +831,25 @@ __global__ void __launch_bounds__(256) k_dt_partial(Dev g, const double *U, doub
     smax = fmax(smax, sig);
   }
   smax = block_max(smax, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = smax;
+  if (threadIdx.x == 0) part[bid] = smax;
 }
 
-__global__ void __launch_bounds__(256) k_dt_final(const double *part, int nparts, double cfl,
-                                                  double dt_max, double *dt) {
+__global__ void __launch_bounds__(256) k_dt_partial(Dev g, const double *U, double *part) {
+  dt_partial_body(g, U, part, blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ void dt_final_body(const double *part, int nparts, double cfl,
+                                              double dt_max, double *dt) {
   __shared__ double sh[256];
   double m = 0.0;
   for (int b = threadIdx.x; b < nparts; b += 256) m = fmax(m, part[b]);
   m = block_max(m, sh);
   if (threadIdx.x == 0) dt[0] = fmin(dt_max, cfl / m);
+}
+
+__global__ void __launch_bounds__(256) k_dt_final(const double *part, int nparts, double cfl,
+                                                  double dt_max, double *dt) {
+  dt_final_body(part, nparts, cfl, dt_max, dt);
 }
 
 // ---------------------------------------------------------------------------
@@ -828,7 +1025,15 @@ hipError_t launch_init_state(const Dev &g, const double *P, double *U, hipStream
   return hipGetLastError();
 }
 hipError_t launch_prim_halo(const Dev &g, const double *U, hipStream_t st) {
-  k_prim_halo<<<grid_for(g.nbox), 256, 0, st>>>(g, U);
+  // few ghost cells: one launch; otherwise interior first, then the ghosts
+  // copied from it (a second launch costs less than ghost threads that
+  // convert their source state themselves)
+  if ((g.nbox - g.ncell) * 10 <= g.nbox) {
+    k_prim_halo<<<grid_for(g.nbox), 256, 0, st>>>(g, U);
+  } else {
+    k_prim_interior<<<grid_for(g.ncell), 256, 0, st>>>(g, U);
+    k_prim_ghost<<<grid_for(g.nbox - g.ncell), 256, 0, st>>>(g);
+  }
   return hipGetLastError();
 }
 static int x_window(const Dev &g) {
@@ -853,7 +1058,11 @@ static hipError_t launch_yz(const Dev &g, hipStream_t st) {
 
 hipError_t launch_grad(const Dev &g, hipStream_t st) {
   if (g.visc == VISC_NONE || g.ndim < 2) return hipSuccess;
-  k_grad<<<grid_for(g.nbox), 256, 0, st>>>(g);
+  const long cells = (long)(g.n[0] + 4) * (g.n[1] + 4) * (g.ndim >= 3 ? g.n[2] + 4 : 1);
+  if (g.ndim == 2)
+    k_grad<2><<<grid_for(cells), 256, 0, st>>>(g);
+  else
+    k_grad<3><<<grid_for(cells), 256, 0, st>>>(g);
   return hipGetLastError();
 }
 
@@ -906,6 +1115,138 @@ hipError_t launch_diag(const Dev &g, const double *U, double *part, double *out,
   k_diag_final<<<1, 256, 0, st>>>(part, (int)nb, out);
   return hipGetLastError();
 }
+// ---------------------------------------------------------------------------
+// Batched step: the same kernels over a table of solves (gridDim.y = solve).
+// A workgroup beyond its solve's own count returns before any barrier.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ const double *stage_in(const BatchEntry &e, int stage) {
+  return stage == 0 ? e.U : (stage == 1 ? e.U1 : e.U2);
+}
+
+__global__ void __launch_bounds__(256) kb_prim_interior(const BatchEntry *tab, int stage) {
+  const BatchEntry &e = tab[blockIdx.y];
+  if (blockIdx.x >= e.nb_prim) return;
+  prim_interior_body(e.g, stage_in(e, stage), blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void __launch_bounds__(256) kb_prim_ghost(const BatchEntry *tab) {
+  const BatchEntry &e = tab[blockIdx.y];
+  if (blockIdx.x >= e.nb_ghost) return;
+  prim_ghost_body(e.g, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <int NDIM>
+__global__ void __launch_bounds__(256) kb_grad(const BatchEntry *tab) {
+  const BatchEntry &e = tab[blockIdx.y];
+  if (blockIdx.x >= e.nb_grad) return;
+  grad_body<NDIM>(e.g, blockIdx.x, e.nb_grad);
+}
+
+template <int NDIM, bool VISC>
+__global__ void __launch_bounds__(256) kb_flux_x(const BatchEntry *tab) {
+  extern __shared__ double lds[];
+  const BatchEntry &e = tab[blockIdx.y];
+  if (blockIdx.x >= e.nb_x) return;
+  flux_x_body<NDIM, VISC>(e.g, e.nwmax, blockIdx.x, lds);
+}
+
+template <int NDIM, int D, bool VISC>
+__global__ void __launch_bounds__(256) kb_flux_yz(const BatchEntry *tab) {
+  const BatchEntry &e = tab[blockIdx.y];
+  if (blockIdx.x >= e.yz_ntot[D]) return;
+  flux_yz_body<NDIM, D, VISC>(e.g, blockIdx.x, e.yz_ntot[D], e.yz_nbx[D], e.yz_nby[D]);
+}
+
+__global__ void __launch_bounds__(256) kb_update(const BatchEntry *tab, int stage) {
+  const BatchEntry &e = tab[blockIdx.y];
+  if (blockIdx.x >= e.nb_upd) return;
+  // Shu-Osher stages: U1 = U + dt R(U); U2 = 3/4 U + 1/4 (U1 + dt R(U1));
+  // U = 1/3 U + 2/3 (U2 + dt R(U2))
+  const double a = stage == 0 ? 0.0 : (stage == 1 ? 0.75 : 1.0 / 3.0);
+  const double b = stage == 0 ? 1.0 : (stage == 1 ? 0.25 : 2.0 / 3.0);
+  double *out = stage == 0 ? e.U1 : (stage == 1 ? e.U2 : e.U);
+  update_body(e.g, e.U, stage_in(e, stage), out, nullptr, e.dt, a, b, nullptr,
+              blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(256) kb_dt_partial(const BatchEntry *tab) {
+  const BatchEntry &e = tab[blockIdx.y];
+  if (blockIdx.x >= e.nb_dt) return;
+  dt_partial_body(e.g, e.U, e.part, blockIdx.x, e.nb_dt);
+}
+
+__global__ void __launch_bounds__(256) kb_dt_final(const BatchEntry *tab, double cfl) {
+  const BatchEntry &e = tab[blockIdx.x];
+  dt_final_body(e.part, (int)e.nb_dt, cfl, 1.0e300, e.dt);
+}
+
+void batch_entry_sizes(BatchEntry &e) {
+  const Dev &g = e.g;
+  e.nb_prim = grid_for(g.ncell);
+  e.nb_ghost = g.nbox > g.ncell ? grid_for(g.nbox - g.ncell) : 0;
+  e.nb_grad = (g.visc != VISC_NONE && g.ndim >= 2)
+                  ? grid_for((long)(g.n[0] + 4) * (g.n[1] + 4) * (g.ndim >= 3 ? g.n[2] + 4 : 1))
+                  : 0;
+  e.nb_x = grid_for(g.fcount[0]);
+  e.nb_upd = grid_for(g.ncell);
+  e.nb_dt = grid_capped(g.ncell, RED_BLOCKS);
+  e.nwmax = x_window(g);
+  for (int D = 0; D < 3; ++D) {
+    e.yz_nbx[D] = e.yz_nby[D] = e.yz_ntot[D] = 0;
+    if (D == 0 || D >= g.ndim) continue;
+    e.yz_nbx[D] = (g.n[0] + 15) / 16;
+    e.yz_nby[D] = (g.n[D] + 1 + 15) / 16;
+    e.yz_ntot[D] = e.yz_nbx[D] * e.yz_nby[D] * (D == 1 ? g.n[2] : g.n[1]);
+  }
+}
+
+template <int NDIM, bool VISC>
+static hipError_t batch_step_t(const BatchEntry *tab, const BatchEntry *h, int n, double cfl,
+                               hipStream_t st) {
+  unsigned mp = 0, mh = 0, mg = 0, mx = 0, mu = 0, md = 0, my[3] = {0, 0, 0};
+  int nw = 0;
+  for (int i = 0; i < n; ++i) {
+    mp = std::max(mp, h[i].nb_prim);
+    mh = std::max(mh, h[i].nb_ghost);
+    mg = std::max(mg, h[i].nb_grad);
+    mx = std::max(mx, h[i].nb_x);
+    mu = std::max(mu, h[i].nb_upd);
+    md = std::max(md, h[i].nb_dt);
+    nw = std::max(nw, h[i].nwmax);
+    for (int D = 1; D < 3; ++D) my[D] = std::max(my[D], h[i].yz_ntot[D]);
+  }
+  const unsigned ny = (unsigned)n;
+  if (cfl > 0.0) {
+    kb_dt_partial<<<dim3(md, ny), 256, 0, st>>>(tab);
+    kb_dt_final<<<ny, 256, 0, st>>>(tab, cfl);
+  }
+  const size_t shm = sizeof(double) * Slots<NDIM, VISC>::NC * nw;
+  for (int stage = 0; stage < 3; ++stage) {
+    kb_prim_interior<<<dim3(mp, ny), 256, 0, st>>>(tab, stage);
+    if (mh) kb_prim_ghost<<<dim3(mh, ny), 256, 0, st>>>(tab);
+    if (VISC && NDIM >= 2) kb_grad<NDIM < 2 ? 2 : NDIM><<<dim3(mg, ny), 256, 0, st>>>(tab);
+    kb_flux_x<NDIM, VISC><<<dim3(mx, ny), 256, shm, st>>>(tab);
+    if (NDIM >= 2) kb_flux_yz<NDIM < 2 ? 2 : NDIM, 1, VISC><<<dim3(my[1], ny), 256, 0, st>>>(tab);
+    if (NDIM >= 3) kb_flux_yz<3, 2, VISC><<<dim3(my[2], ny), 256, 0, st>>>(tab);
+    kb_update<<<dim3(mu, ny), 256, 0, st>>>(tab, stage);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_step(const BatchEntry *tab_dev, const BatchEntry *tab_host, int n,
+                             double cfl, hipStream_t st) {
+  const int nd = tab_host[0].g.ndim;
+  const bool v = tab_host[0].g.visc != VISC_NONE;
+  switch (nd) {
+    case 1: return v ? batch_step_t<1, true>(tab_dev, tab_host, n, cfl, st)
+                     : batch_step_t<1, false>(tab_dev, tab_host, n, cfl, st);
+    case 2: return v ? batch_step_t<2, true>(tab_dev, tab_host, n, cfl, st)
+                     : batch_step_t<2, false>(tab_dev, tab_host, n, cfl, st);
+    case 3: return v ? batch_step_t<3, true>(tab_dev, tab_host, n, cfl, st)
+                     : batch_step_t<3, false>(tab_dev, tab_host, n, cfl, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_cost(const Dev &g, int face, double pref, const double *U, double w,
                        double *J, double *grad, hipStream_t st) {
   k_cost<<<1, 256, 0, st>>>(g, face, pref, U, w, J, grad);

@@ -8,6 +8,27 @@ namespace dcf {
 
 constexpr int RED_BLOCKS = 1024;  // partial-sum slots of the two-pass reductions
 
+// One solve of a batched step: its context, its buffers and the number of
+// workgroups each kernel needs for it.  A device array of these is the tile
+// table of the batched launches (workgroup (x, y) = tile x of solve y).
+struct BatchEntry {
+  Dev g;
+  double *U, *U1, *U2;  // state (advanced in place) and the two stage states
+  double *dt;           // step size (device, one double)
+  double *part;         // reduction partials of the CFL step
+  unsigned nb_prim, nb_ghost, nb_grad, nb_x, nb_upd, nb_dt;
+  unsigned yz_nbx[3], yz_nby[3], yz_ntot[3];  // tile grids of the y and z fluxes
+  int nwmax;            // x-flux LDS window length
+};
+
+// Fills the per-kernel workgroup counts of an entry (host side).
+void batch_entry_sizes(BatchEntry &e);
+// One TVD-RK3 step of every solve in the table (tab_dev: device copy of
+// tab_host), optionally preceded by the CFL step (cfl > 0).  All entries
+// share ndim and the viscous flag and carry no source term.
+hipError_t launch_batch_step(const BatchEntry *tab_dev, const BatchEntry *tab_host, int n,
+                             double cfl, hipStream_t st);
+
 hipError_t launch_metrics(int kind, double lo, double hi, double beta, int n, double *dx,
                           double *idx, double *mc, double *mf, double *xm, hipStream_t st);
 hipError_t launch_init_state(const Dev &g, const double *P, double *U, hipStream_t st);

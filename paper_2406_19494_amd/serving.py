@@ -189,6 +189,9 @@ class Scheduler:
                             raise RuntimeError(f"request {job.spec.rid}: no work in flight "
                                                f"but {job.remaining} remaining")
                         progressed = True
+            flush = getattr(self.b, "flush", None)
+            if flush is not None:
+                flush()
             if not progressed:
                 if not active and not queue and pending and realtime:
                     wait = pending[0].arrival - now()
@@ -373,10 +376,96 @@ class _Job:
         self.events = deque()
 
 
+class BatchedGpuBackend(GpuBackend):
+    """Forward solves of one family (grid dimension, viscous or not, no
+    source) advance together: each epoch is k batched steps, one launch per
+    kernel and stage for all of the family's active solves
+    (dcf_batch_rk3_step), on the family's stream.  Gradient solves run as in
+    GpuBackend.  Solves join and leave a family between epochs."""
+
+    def __init__(self, steps_per_epoch: int = 10, keep_outputs: bool = False, inflight: int = 2,
+                 fault: Optional[Dict[int, str]] = None):
+        super().__init__(steps_per_epoch=steps_per_epoch, graphs=False, keep_outputs=keep_outputs,
+                         inflight=inflight, fault=fault)
+        self.families = {}   # key -> [stream, BatchStepper]
+        self.want = {}       # key -> jobs that asked for an epoch
+
+    @staticmethod
+    def _key(job):
+        c = job.solver.case
+        return (c.ndim, c.visc_law != "none", c.cfl)
+
+    def start(self, spec: RequestSpec):
+        if spec.kind == "gradient":
+            return super().start(spec)
+        torch = self.torch
+        from .solver import BatchStepper, Solver
+        case, P, K = build_case(spec)
+        if case.source != "none":
+            return super().start(spec)
+        if spec.rid in self.fault:
+            P = P.copy()
+            if self.fault[spec.rid] == "nonphysical":
+                P[4].flat[len(P[4].flat) // 2] = -1.0
+        job = _Job(spec)
+        job.solver = Solver(case, K=K, mode=0)
+        key = self._key(job)
+        if key not in self.families:
+            self.families[key] = [torch.cuda.Stream(), BatchStepper()]
+        job.stream = self.families[key][0]
+        job.batched = True
+        job.U = job.solver.init_state(P, stream=job.stream)
+        job.dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+        job.remaining = spec.nsteps
+        job.events = deque()
+        for _ in range(self.inflight):
+            if job.remaining:
+                self.step(job)
+        self.flush()
+        return job
+
+    def step(self, job) -> bool:
+        if not getattr(job, "batched", False):
+            return super().step(job)
+        n = min(self.k, job.spec.nsteps - job.enqueued)
+        if n <= 0:
+            return False
+        self.want.setdefault(self._key(job), []).append((job, n))
+        job.enqueued += n
+        return True
+
+    def flush(self):
+        """Launch the requested epochs: per family, step i of the epoch
+        batches every solve that asked for more than i steps."""
+        torch = self.torch
+        for key, reqs in self.want.items():
+            stream, stepper = self.families.get(key, (None, None))
+            while reqs:
+                # one round: at most one pending epoch per solve
+                seen, rnd, rest = set(), [], []
+                for j, n in reqs:
+                    (rest if id(j) in seen else rnd).append((j, n))
+                    seen.add(id(j))
+                reqs[:] = rest
+                with torch.cuda.stream(stream):
+                    for i in range(max(n for _, n in rnd)):
+                        members = [j for j, n in rnd if n > i]
+                        stepper.step([j.solver for j in members], [j.U for j in members],
+                                     [j.dt for j in members], cfl=key[2], stream=stream)
+                    ev = torch.cuda.Event()
+                    ev.record(stream)
+                for j, n in rnd:
+                    j.events.append((ev, n))
+
+
 def serve(trace, budget_bytes=200e9, max_slots=16, steps_per_epoch=10, graphs=True,
-          keep_outputs=False, realtime=True, fault=None):
-    backend = GpuBackend(steps_per_epoch=steps_per_epoch, graphs=graphs,
-                         keep_outputs=keep_outputs, fault=fault)
+          keep_outputs=False, realtime=True, fault=None, batched=False):
+    if batched:
+        backend = BatchedGpuBackend(steps_per_epoch=steps_per_epoch, keep_outputs=keep_outputs,
+                                    fault=fault)
+    else:
+        backend = GpuBackend(steps_per_epoch=steps_per_epoch, graphs=graphs,
+                             keep_outputs=keep_outputs, fault=fault)
     sch = Scheduler(backend, budget_bytes, max_slots)
     t0 = time.perf_counter()
     res = sch.run(trace, realtime=realtime)

@@ -212,3 +212,27 @@ class Solver:
         B.call("dcf_gradient", self.ctx, _ptr(U0), int(self.nsteps), _ptr(dt), int(self.seg_len),
                _ptr(J), _ptr(gK) if self.nk else None, _ptr(gU), _stream(stream))
         return J, gK[: self.nk], gU
+
+
+class BatchStepper:
+    """One TVD-RK3 step of several solves with one launch per kernel and
+    stage (dcf_batch_rk3_step); keeps the device tile table between calls."""
+
+    def __init__(self):
+        self.table = None
+
+    def step(self, solvers, Us, dts, cfl=None, stream=None):
+        n = len(solvers)
+        if n == 0:
+            return
+        size = C.c_size_t()
+        B.call("dcf_batch_table_bytes", n, C.byref(size))
+        if self.table is None or self.table.numel() < size.value:
+            dev = Us[0].device
+            self.table = torch.empty(max(size.value, 4096), dtype=torch.uint8, device=dev)
+        VP = C.c_void_p * n
+        ctxs = VP(*[s.ctx.value for s in solvers])
+        us = VP(*[U.data_ptr() for U in Us])
+        ds = VP(*[d.data_ptr() for d in dts])
+        B.call("dcf_batch_rk3_step", ctxs, us, ds, n, float(cfl) if cfl else 0.0,
+               _ptr(self.table), self.table.numel(), _stream(stream))

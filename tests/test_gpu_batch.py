@@ -1,0 +1,102 @@
+"""Batched stepping (dcf_batch_rk3_step): one launch per kernel and stage
+over several solves of different sizes gives bitwise the results of the
+solves stepped one by one, and refuses batches it cannot run."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2406_19494_amd import binding as B
+from paper_2406_19494_amd import workloads as W
+from paper_2406_19494_amd.solver import BatchStepper, Solver
+from tests.test_oracle_pins import _tiny_porous
+
+pytestmark = pytest.mark.gpu
+
+EINVAL = {v: k for k, v in B.ERRORS.items()}["EINVAL"]
+EUNSUPPORTED = {v: k for k, v in B.ERRORS.items()}["EUNSUPPORTED"]
+
+
+def _families():
+    tgv = [W.tgv(n) for n in (8, 12, 16)]
+    c = W.Case(name="mix3d", ndim=3, n=(13, 9, 7), lo=(0, 0, 0), hi=(1, 1, 1),
+               stretch=("tanh1", "uniform", "uniform"), beta=(1.5, 0, 0), gamma=1.4, R=1.0,
+               Pr=0.7, visc_law="power", mu_ref=0.005, T_ref=1.0, visc_param=0.7,
+               bc=("zerograd", "zerograd", "wall", "wall", "periodic", "periodic"),
+               T_wall=(0, 0, 1.0, 1.0, 0, 0))
+    f3 = [(cs, P, None) for cs, P in tgv] + [(c, W.random_smooth(c, seed=9, amp=0.2), None)]
+    f1 = [(cs, P, None) for cs, P in (W.sod(200), W.sod(513), W.sod(4096))]
+    cp, Pp, Kp = _tiny_porous()
+    cl, Pl = W.laminar_bl(nx=36, ny=20, amp=0.01, kappa=10.0)
+    cb, Pb, Kb = W.porous_bl(nx=64, ny=32, strip=(16, 48))
+    f2 = [(cp, Pp, Kp), (cl, Pl, None), (cb, Pb, Kb)]
+    return {"3d_viscous": f3, "1d_inviscid": f1, "2d_viscous": f2}
+
+
+FAM = _families()
+
+
+@pytest.mark.parametrize("fam", list(FAM))
+@pytest.mark.parametrize("cfl_mode", ["cfl", "fixed"])
+def test_batch_step_equals_individual_steps(fam, cfl_mode):
+    print(f"[batch] {fam} {cfl_mode}", flush=True)
+    solves = FAM[fam]
+    ref, bat, dts_r, dts_b, Us_r, Us_b = [], [], [], [], [], []
+    for case, P, K in solves:
+        s1 = Solver(case, K=K)
+        s2 = Solver(case, K=K)
+        ref.append(s1)
+        bat.append(s2)
+        U1 = s1.init_state(P)
+        Us_r.append(U1)
+        Us_b.append(U1.clone())
+        d = s1.compute_dt(U1)
+        if cfl_mode == "fixed":
+            d.mul_(0.5)
+        dts_r.append(d)
+        dts_b.append(d.clone())
+    bs = BatchStepper()
+    for step in range(4):
+        for s, U, d in zip(ref, Us_r, dts_r):
+            if cfl_mode == "cfl":
+                s.compute_dt(U, cfl=s.case.cfl, out=d)
+            s.step(U, d)
+        bs.step(bat, Us_b, dts_b, cfl=(bat[0].case.cfl if cfl_mode == "cfl" else None))
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(Us_r, Us_b)):
+        assert torch.equal(a, b), (fam, i, (a - b).abs().max().item())
+    for a, b in zip(dts_r, dts_b):
+        assert torch.equal(a, b)
+    for s in bat:
+        assert s.flags() == 0
+
+
+def _raw_step(solvers, Us, dts, table_bytes=None):
+    n = len(solvers)
+    size = C.c_size_t()
+    B.call("dcf_batch_table_bytes", n, C.byref(size))
+    nbytes = size.value if table_bytes is None else table_bytes
+    table = torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
+    VP = C.c_void_p * n
+    return B.lib().dcf_batch_rk3_step(VP(*[s.ctx.value for s in solvers]),
+                                      VP(*[U.data_ptr() for U in Us]),
+                                      VP(*[d.data_ptr() for d in dts]), n, 0.0,
+                                      C.c_void_p(table.data_ptr()), nbytes, None)
+
+
+def test_batch_rejects_what_it_cannot_run():
+    c3, P3 = W.tgv(8)
+    c1, P1 = W.sod(200)
+    cc, Pc = W.channel(nx=12, ny=10, nz=8)
+    s3, s1, sc = Solver(c3), Solver(c1), Solver(cc)
+    U3, U1, Uc = s3.init_state(P3), s1.init_state(P1), sc.init_state(Pc)
+    d = [torch.full((1,), 1e-4, dtype=torch.float64, device="cuda") for _ in range(3)]
+    assert _raw_step([s3, s1], [U3, U1], d[:2]) == EUNSUPPORTED     # mixed ndim
+    assert _raw_step([s3, sc], [U3, Uc], d[:2]) == EUNSUPPORTED     # source term
+    assert _raw_step([s3, s3], [U3, U3], d[:2]) == EINVAL           # repeated context
+    assert _raw_step([s3], [U3], d[:1], table_bytes=8) == EINVAL    # table too small
+    U0 = U3.clone()
+    assert _raw_step([s3], [U3], d[:1]) == 0
+    torch.cuda.synchronize()
+    assert not torch.equal(U0, U3)

@@ -85,3 +85,35 @@ def test_batched_beats_sequential():
     _, t_seq, _ = S.serve_sequential(trace, realtime=False)
     print(f"[serving] batched {t_batched:.3f} s, sequential {t_seq:.3f} s", flush=True)
     assert t_batched < t_seq
+
+
+def test_batched_kernels_backend_matches_unbatched_alone():
+    # forward solves of one family step together in batched launches; every
+    # result equals the solve served alone by the per-request backend
+    trace = [
+        S.RequestSpec(0, "sod", 300, "forward", 33, 0.0),
+        S.RequestSpec(1, "sod", 1000, "forward", 20, 0.0),
+        S.RequestSpec(2, "sod", 513, "forward", 47, 0.0),
+        S.RequestSpec(3, "tgv", 16, "forward", 25, 0.0),
+        S.RequestSpec(4, "tgv", 24, "forward", 12, 0.0),
+        S.RequestSpec(5, "bl", 1, "forward", 21, 0.0),
+        S.RequestSpec(6, "tgv", 16, "gradient", 8, 0.0),
+    ]
+    mix, _, sch = S.serve(trace, max_slots=7, keep_outputs=True, realtime=False, batched=True)
+    assert sch.peak_active >= 5
+    for spec in trace:
+        alone, _, _ = S.serve([spec], max_slots=1, keep_outputs=True, realtime=False)
+        a, m = alone[spec.rid], mix[spec.rid]
+        assert a.status == m.status == "ok", (spec, a.status, m.status, m.message)
+        for key, va in a.output.items():
+            assert np.array_equal(np.asarray(va), np.asarray(m.output[key])), (spec, key)
+
+
+def test_batched_kernels_backend_isolates_nonphysical():
+    trace = [S.RequestSpec(0, "sod", 300, "forward", 30, 0.0),
+             S.RequestSpec(1, "sod", 400, "forward", 30, 0.0)]
+    res, _, _ = S.serve(trace, max_slots=2, keep_outputs=True, realtime=False, batched=True,
+                        fault={0: "nonphysical"})
+    assert res[0].status == "nonphysical" and res[1].status == "ok"
+    ref, _, _ = S.serve([trace[1]], max_slots=1, keep_outputs=True, realtime=False)
+    assert np.array_equal(ref[1].output["U"], res[1].output["U"])

@@ -237,3 +237,49 @@ def test_gpu_backend_gradient_accounting_terminates():
     else:
         raise AssertionError("did not terminate")
     assert job.solver.units == 137 and job.enqueued_done
+
+
+class _FakeStepper:
+    def __init__(self):
+        self.calls = []
+
+    def step(self, solvers, Us, dts, cfl=None, stream=None):
+        assert len(set(map(id, solvers))) == len(solvers), "a solve twice in one batch"
+        self.calls.append(len(solvers))
+        for s in solvers:
+            s.steps += 1
+
+
+def test_batched_backend_rounds_and_accounting():
+    # forward solves of one family: every batched step holds each solve at
+    # most once, a solve with two pending epochs gets two rounds, and every
+    # solve receives exactly its steps
+    from collections import deque
+    from paper_2406_19494_amd.serving import BatchedGpuBackend, _Job
+    be = BatchedGpuBackend.__new__(BatchedGpuBackend)
+    be.torch, be.k, be.inflight = _FakeTorch, 10, 2
+    stepper = _FakeStepper()
+    be.families = {(1, False, 0.5): [None, stepper]}
+    be.want = {}
+    be._key = lambda job: (1, False, 0.5)
+    jobs = []
+    for rid, n in enumerate((25, 7, 40)):
+        job = _Job(RequestSpec(rid, "sod", 200, "forward", n, 0.0))
+        job.solver, job.stream, job.events, job.batched = _FakeSolver(0), None, deque(), True
+        for _ in range(be.inflight):
+            be.step(job)
+        jobs.append(job)
+    be.flush()
+    for it in range(10000):
+        active = [j for j in jobs if j.remaining or j.events]
+        if not active:
+            break
+        for j in active:
+            if be.poll(j) and j.remaining:
+                be.step(j)
+        be.flush()
+    else:
+        raise AssertionError("did not terminate")
+    for j in jobs:
+        assert j.solver.steps == j.spec.nsteps == j.completed
+    assert max(stepper.calls) == 3
