@@ -119,8 +119,12 @@ dcf_status dcf_state_info(const dcf_ctx *ctx, int *nv, long *ncell, size_t *stat
  * size reported for the same (mode, nsteps, seg_len).  mode 0 = forward
  * (rhs, rk3_step, dt, diagnostics, cost); mode 1 = adds vjp_step; mode 2 =
  * adds the trajectory gradient over exactly `nsteps` steps with checkpoints
- * every `seg_len` steps (dcf_gradient).  nsteps/seg_len are ignored below
- * mode 2.  The library keeps the pointer until the next call. */
+ * every `seg_len` steps (dcf_gradient); mode 3 = as mode 2 and also keeps
+ * the primitive and velocity-derivative boxes of every stage of a segment
+ * from the forward recompute, so the reverse sweep recomputes nothing
+ * (3 seg_len more boxes of memory; bitwise the same gradient).
+ * nsteps/seg_len are ignored below mode 2.  The library keeps the pointer
+ * until the next call. */
 dcf_status dcf_workspace_size(const dcf_ctx *ctx, int mode, int nsteps, int seg_len,
                               size_t *bytes);
 dcf_status dcf_set_workspace(dcf_ctx *ctx, int mode, int nsteps, int seg_len, void *dev,

@@ -586,8 +586,14 @@ __global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, do
   int lo1 = 0, n1 = g.n[t1], lo2 = 0, n2 = g.n[t2];
   if (t1 < d) { lo1 = -g.h[t1]; n1 = g.N[t1]; }
   if (t2 < d) { lo2 = -g.h[t2]; n2 = g.N[t2]; }
-  long col = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= (long)n1 * n2) return;
+  // one thread per column and side when the two sides' source cells cannot
+  // coincide (n >= 6), else one thread per column doing both sides in turn
+  const long ncol = (long)n1 * n2;
+  const bool split = g.n[d] >= 6;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (split ? 2 : 1) * ncol) return;
+  const long col = split ? tid % ncol : tid;
+  const int side_lo = split ? (int)(tid / ncol) : 0, side_hi = split ? side_lo + 1 : 2;
   const int a = lo1 + (int)(col % n1), bq = lo2 + (int)(col / n1);
   auto box = [&](int s) {
     int p[3];
@@ -602,7 +608,7 @@ __global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, do
   constexpr int qs[6] = {QR, QU, NDIM >= 2 ? QV : QP, NDIM == 3 ? QW : (NDIM == 2 ? QP : QT),
                          NDIM == 3 ? QP : QT, QT};
   const int n = g.n[d];
-  for (int side = 0; side < 2; ++side) {
+  for (int side = side_lo; side < side_hi; ++side) {
     const int face = 2 * d + side;
     const int kind = g.bck[face];
     if (kind == BC_DIRICHLET) continue;
@@ -810,14 +816,16 @@ static inline unsigned blocks(long n) { return (unsigned)((n + 255) / 256 > 0 ? 
 static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A0, const double *V, const double *Wb,
                             const double *dt, double a, double b, double *Vb,
                             const double *acc_in, double *acc_out, int fold, double *dJdK,
-                            hipStream_t st) {
+                            hipStream_t st, bool have_box) {
   const bool visc = g.visc != VISC_NONE;
   AdjBuffers A = A0;
   A.Wb = Wb;
   A.dtp = dt;
   A.bcoef = b;
-  DCF_TRY(launch_prim_halo(g, V, st));
-  if (visc && g.ndim >= 2) DCF_TRY(launch_grad(g, st));
+  if (!have_box) {  // the stage's primitive and derivative boxes
+    DCF_TRY(launch_prim_halo(g, V, st));
+    if (visc && g.ndim >= 2) DCF_TRY(launch_grad(g, st));
+  }
   DCF_TRY(launch_fill(A.zero_begin, 0.0, A.zero_count, st));
   for (int D = 0; D < g.ndim; ++D) {
     hipLaunchKernelGGL(conv_kernel(g.ndim, D), dim3(tile_count<-3, 2>(g, D)), dim3(256), 0, st, g,
@@ -838,7 +846,7 @@ static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A0, const double *V,
     long n1 = t1 < d ? g.N[t1] : g.n[t1];
     long n2 = t2 < d ? g.N[t2] : g.n[t2];
     auto hk = g.ndim == 1 ? k_halo_vjp<1> : (g.ndim == 2 ? k_halo_vjp<2> : k_halo_vjp<3>);
-    hk<<<blocks(n1 * n2), 256, 0, st>>>(g, A, d, dJdK);
+    hk<<<blocks((g.n[d] >= 6 ? 2 : 1) * n1 * n2), 256, 0, st>>>(g, A, d, dJdK);
     DCF_TRY(hipGetLastError());
     for (int side = 0; side < 2 && dJdK; ++side) {
       const int face = 2 * d + side;
@@ -854,7 +862,16 @@ static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A0, const double *V,
 
 hipError_t vjp_step(Dev g, const AdjBuffers &A, const double *Un, double *U1, double *U2,
                     const double *dt, const double *lam1, double *lam0, double *dJdK,
-                    hipStream_t st, bool recompute) {
+                    hipStream_t st, bool recompute, const Dev *boxes) {
+  if (boxes) {  // stage boxes cached by the forward recompute (Un, U1, U2)
+    DCF_TRY(stage_vjp(boxes[2], A, U2, lam1, dt, 1.0 / 3.0, 2.0 / 3.0, A.Ub2, nullptr, A.acc, 0,
+                      dJdK, st, true));
+    DCF_TRY(stage_vjp(boxes[1], A, U1, A.Ub2, dt, 0.75, 0.25, A.Ub1, A.acc, A.acc, 0, dJdK, st,
+                      true));
+    DCF_TRY(stage_vjp(boxes[0], A, Un, A.Ub1, dt, 0.0, 1.0, lam0, A.acc, nullptr, 1, dJdK, st,
+                      true));
+    return hipSuccess;
+  }
   if (recompute) {  // the stage states U1, U2 of Un
     DCF_TRY(launch_prim_halo(g, Un, st));
     DCF_TRY(launch_fluxes(g, st));
@@ -864,11 +881,12 @@ hipError_t vjp_step(Dev g, const AdjBuffers &A, const double *Un, double *U1, do
     DCF_TRY(launch_update(g, Un, U1, U2, nullptr, dt, 0.75, 0.25, nullptr, st));
   }
   // stage 3: W = Un/3 + 2/3 (U2 + dt R(U2))
-  DCF_TRY(stage_vjp(g, A, U2, lam1, dt, 1.0 / 3.0, 2.0 / 3.0, A.Ub2, nullptr, A.acc, 0, dJdK, st));
+  DCF_TRY(stage_vjp(g, A, U2, lam1, dt, 1.0 / 3.0, 2.0 / 3.0, A.Ub2, nullptr, A.acc, 0, dJdK, st,
+                    false));
   // stage 2: W = 3/4 Un + 1/4 (U1 + dt R(U1))
-  DCF_TRY(stage_vjp(g, A, U1, A.Ub2, dt, 0.75, 0.25, A.Ub1, A.acc, A.acc, 0, dJdK, st));
+  DCF_TRY(stage_vjp(g, A, U1, A.Ub2, dt, 0.75, 0.25, A.Ub1, A.acc, A.acc, 0, dJdK, st, false));
   // stage 1: W = Un + dt R(Un)
-  DCF_TRY(stage_vjp(g, A, Un, A.Ub1, dt, 0.0, 1.0, lam0, A.acc, nullptr, 1, dJdK, st));
+  DCF_TRY(stage_vjp(g, A, Un, A.Ub1, dt, 0.0, 1.0, lam0, A.acc, nullptr, 1, dJdK, st, false));
   return hipSuccess;
 }
 

@@ -45,8 +45,10 @@ template <class Carver> void carve_adjoint(Carver &cv, const Dev &g, AdjBuffers 
 // lam0 = (dU^{n+1}/dU^n)^T lam1 and dJdK += (dU^{n+1}/dK)^T lam1 (if not
 // null).  With recompute, U1 and U2 are scratch arrays that receive the
 // stage states; without, they must already hold the stage states of Un.
+// With `boxes` (three contexts whose Q and G point at the cached primitive
+// and derivative boxes of Un, U1, U2) nothing of the forward is recomputed.
 hipError_t vjp_step(Dev g, const AdjBuffers &a, const double *Un, double *U1, double *U2,
                     const double *dt, const double *lam1, double *lam0, double *dJdK,
-                    hipStream_t st, bool recompute = true);
+                    hipStream_t st, bool recompute = true, const Dev *boxes = nullptr);
 
 }  // namespace dcf

@@ -67,6 +67,8 @@ struct dcf_ctx {
   double *ckpt = nullptr;  // gradient checkpoints
   double *seg = nullptr;   // per-segment recomputed states
   double *sst = nullptr;   // per-segment stage states U1, U2 of every step
+  double *boxc = nullptr;  // mode 3: primitive + derivative boxes of every stage of a segment
+  int box_arrays = 0;      // box arrays per cached stage
   double *lam_a = nullptr, *lam_b = nullptr, *gbuf = nullptr, *zero_dt = nullptr;
   // incremental gradient state (dcf_gradient_begin / advance / finish)
   struct {
@@ -236,6 +238,15 @@ static size_t carve(dcf_ctx *c, void *base, int mode, int nsteps, int seg_len) {
     c->lam_b = cv.take<double>(nv * ncell);
     c->gbuf = cv.take<double>(nv * ncell);
   }
+  c->boxc = nullptr;
+  c->box_arrays = 0;
+  if (mode >= 3) {
+    int na = NQ;
+    for (int q = 0; q < 9; ++q)
+      if (need_g && q / 3 < g.ndim && q % 3 < g.ndim) ++na;
+    c->box_arrays = na;
+    c->boxc = cv.take<double>((size_t)3 * seg_len * na * nbox);
+  }
   return cv.off;
 }
 
@@ -244,8 +255,8 @@ extern "C" {
 dcf_status dcf_workspace_size(const dcf_ctx *c, int mode, int nsteps, int seg_len,
                               size_t *bytes) {
   if (!c || !bytes) return fail(DCF_EINVAL, "null argument");
-  if (mode < 0 || mode > 2) return fail(DCF_EINVAL, "mode must be 0, 1 or 2");
-  if (mode == 2 && (nsteps < 1 || seg_len < 1))
+  if (mode < 0 || mode > 3) return fail(DCF_EINVAL, "mode must be 0, 1, 2 or 3");
+  if (mode >= 2 && (nsteps < 1 || seg_len < 1))
     return fail(DCF_EINVAL, "gradient workspace needs nsteps >= 1 and seg_len >= 1");
   dcf_ctx tmp = *c;
   *bytes = carve(&tmp, nullptr, mode, nsteps, seg_len);
@@ -256,8 +267,8 @@ dcf_status dcf_set_workspace(dcf_ctx *c, int mode, int nsteps, int seg_len, void
                              size_t bytes) {
   if (!c || !dev) return fail(DCF_EINVAL, "null argument");
   if (((uintptr_t)dev) & 255) return fail(DCF_EINVAL, "workspace must be 256-byte aligned");
-  if (mode < 0 || mode > 2) return fail(DCF_EINVAL, "mode must be 0, 1 or 2");
-  if (mode == 2 && (nsteps < 1 || seg_len < 1))
+  if (mode < 0 || mode > 3) return fail(DCF_EINVAL, "mode must be 0, 1, 2 or 3");
+  if (mode >= 2 && (nsteps < 1 || seg_len < 1))
     return fail(DCF_EINVAL, "gradient workspace needs nsteps >= 1 and seg_len >= 1");
   dcf_ctx tmp = *c;
   size_t need = carve(&tmp, nullptr, mode, nsteps, seg_len);
@@ -267,8 +278,8 @@ dcf_status dcf_set_workspace(dcf_ctx *c, int mode, int nsteps, int seg_len, void
   c->ws = dev;
   c->ws_bytes = bytes;
   c->ws_mode = mode;
-  c->ws_nsteps = mode == 2 ? nsteps : 0;
-  c->ws_seg = mode == 2 ? seg_len : 0;
+  c->ws_nsteps = mode >= 2 ? nsteps : 0;
+  c->ws_seg = mode >= 2 ? seg_len : 0;
   return DCF_OK;
 }
 
@@ -550,6 +561,20 @@ dcf_status dcf_gradient_begin(dcf_ctx *c, const double *U0, int nsteps, const do
 
 // One unit of gradient work: a forward step (with checkpoint and cost), a
 // recomputed step of the current segment, or a reverse step.
+// A copy of the context whose primitive and derivative boxes are the cached
+// ones of stage s of step n of the current segment (workspace mode 3).
+static Dev stage_box(const dcf_ctx *c, int n, int s) {
+  Dev d = c->g;
+  double *p = c->boxc + (size_t)(3 * n + s) * c->box_arrays * d.nboxp;
+  for (int q = 0; q < NQ; ++q, p += d.nboxp) d.Q[q] = p;
+  for (int q = 0; q < 9; ++q)
+    if (c->g.G[q]) {
+      d.G[q] = p;
+      p += d.nboxp;
+    }
+  return d;
+}
+
 static dcf_status gradient_unit(dcf_ctx *c, hipStream_t st) {
   auto &gr = c->gr;
   Dev &g = c->g;
@@ -577,7 +602,19 @@ static dcf_status gradient_unit(dcf_ctx *c, hipStream_t st) {
     double *Ua = c->seg + (long)gr.n * M, *Ub = Ua + M;
     DCF_HIP(launch_copy(Ub, Ua, M, st));
     double *S1 = c->sst + (long)(2 * gr.n) * M, *S2 = S1 + M;
-    if ((s = rk3_stages(c, Ub, gr.dt, st, S1, S2))) return s;
+    if (c->boxc && g.source == SRC_NONE) {  // the same three stages, keeping each stage's boxes
+      const double *in[3] = {Ub, S1, S2};
+      double *out[3] = {S1, S2, Ub};
+      const double a[3] = {0.0, 0.75, 1.0 / 3.0}, b[3] = {1.0, 0.25, 2.0 / 3.0};
+      for (int k = 0; k < 3; ++k) {
+        const Dev gs = stage_box(c, gr.n, k);
+        DCF_HIP(launch_prim_halo(gs, in[k], st));
+        DCF_HIP(launch_fluxes(gs, st));
+        DCF_HIP(launch_update(gs, Ub, in[k], out[k], nullptr, gr.dt, a[k], b[k], nullptr, st));
+      }
+    } else if ((s = rk3_stages(c, Ub, gr.dt, st, S1, S2))) {
+      return s;
+    }
     if (++gr.n == n1 - n0) {
       gr.phase = 2;
       gr.n = n1;
@@ -590,7 +627,12 @@ static dcf_status gradient_unit(dcf_ctx *c, hipStream_t st) {
     DCF_HIP(launch_cost(g, c->cost_face, c->cost_pref, Ucur, w, c->force + 2, gr.lam, st));
     const double *Uprev = c->seg + (long)(n - 1 - n0) * M;
     double *S1 = c->sst + (long)(2 * (n - 1 - n0)) * M, *S2 = S1 + M;
-    if (vjp_step(g, c->adj, Uprev, S1, S2, gr.dt, gr.lam, gr.lam_prev, gr.dJdK, st, false))
+    Dev boxes[3];
+    const bool cached = c->boxc && g.source == SRC_NONE;
+    if (cached)
+      for (int k = 0; k < 3; ++k) boxes[k] = stage_box(c, n - 1 - n0, k);
+    if (vjp_step(g, c->adj, Uprev, S1, S2, gr.dt, gr.lam, gr.lam_prev, gr.dJdK, st, false,
+                 cached ? boxes : nullptr))
       return fail(DCF_EDEVICE, "vjp launch failed");
     double *t = gr.lam;
     gr.lam = gr.lam_prev;

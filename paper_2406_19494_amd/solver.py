@@ -32,7 +32,9 @@ class Solver:
     """A solve on the GPU.
 
     mode: 0 forward, 1 forward + single-step VJP, 2 trajectory gradient with
-    ``nsteps`` steps and checkpoints every ``seg_len`` steps.
+    ``nsteps`` steps and checkpoints every ``seg_len`` steps, 3 as 2 with the
+    stage boxes of a segment kept for the reverse sweep (more memory, no
+    recompute in the reverse sweep).
     """
 
     def __init__(self, case: Case, K=None, mode: int = 0, nsteps: int = 0, seg_len: int = 0,

@@ -89,6 +89,20 @@ def test_dot_product_gpu_vjp_vs_oracle_jvp(name, case, P, K, dt):
 
 
 @pytest.mark.parametrize("which", ["porous", "disturb"])
+def test_cached_stage_boxes_give_the_same_gradient_bitwise(which):
+    case, P, K = _tiny_porous() if which == "porous" else _tiny_disturb()
+    o = Oracle(case, K=K)
+    U0 = torch.as_tensor(o.cons(P), device="cuda")
+    dt = torch.full((1,), 1e-3 if which == "porous" else 2e-4, dtype=torch.float64, device="cuda")
+    out = []
+    for mode in (2, 3):
+        s = Solver(case, K=K, mode=mode, nsteps=7, seg_len=3)
+        out.append(s.gradient(U0, dt))
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("which", ["porous", "disturb"])
 def test_trajectory_gradient_matches_oracle(which):
     case, P, K = _tiny_porous() if which == "porous" else _tiny_disturb()
     print(f"[trajectory gradient] {which}", flush=True)
