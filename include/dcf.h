@@ -176,6 +176,14 @@ dcf_status dcf_compute_dt(dcf_ctx *ctx, const double *U_dev, double cfl, double 
 /* One TVD-RK3 step (Shu-Osher form) in place, with dt read from dt_dev[0]. */
 dcf_status dcf_rk3_step(dcf_ctx *ctx, double *U_dev, const double *dt_dev, void *stream);
 
+/* dcf_rk3_step fused with the CFL step of the new state: the last stage's
+ * update also reduces the signal rates of the cells it writes, and
+ * dt_next_dev[0] = min(dt_max, cfl / max_cells sigma(U^{n+1})), bitwise the
+ * value dcf_compute_dt(U^{n+1}) would give (dt_max <= 0: no cap).  dt_next
+ * may alias dt (the step reads dt before it is overwritten). */
+dcf_status dcf_rk3_step_cfl(dcf_ctx *ctx, double *U_dev, const double *dt_dev, double cfl,
+                            double dt_max, double *dt_next_dev, void *stream);
+
 /* ---- batched stepping (the serving loop's step launches) ---------------- */
 /* Bytes of the device table dcf_batch_rk3_step needs for n solves. */
 dcf_status dcf_batch_table_bytes(int n, size_t *bytes);

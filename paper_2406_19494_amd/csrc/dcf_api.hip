@@ -63,6 +63,7 @@ struct dcf_ctx {
   int ws_mode = -1;
   int ws_nsteps = 0, ws_seg = 0;
   double *U1 = nullptr, *U2 = nullptr, *part = nullptr, *force = nullptr;
+  double *dtpart = nullptr;  // per-block signal rates of the last stage (fused CFL step)
   AdjBuffers adj;
   double *ckpt = nullptr;  // gradient checkpoints
   double *seg = nullptr;   // per-segment recomputed states
@@ -227,6 +228,7 @@ static size_t carve(dcf_ctx *c, void *base, int mode, int nsteps, int seg_len) {
   c->U2 = cv.take<double>(nv * ncell);
   c->part = cv.take<double>(8 * RED_BLOCKS);
   c->force = cv.take<double>(4);
+  c->dtpart = cv.take<double>(update_blocks(g));
   g.flags = cv.take<unsigned>(64);
   if (mode >= 1) carve_adjoint(cv, g, c->adj);
   if (mode >= 2) {
@@ -386,7 +388,8 @@ static dcf_status eval_fluxes(dcf_ctx *c, const double *U, hipStream_t st) {
 
 // One RK3 step in place; the stage states go to U1, U2 (default: scratch).
 static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_t st,
-                             double *U1 = nullptr, double *U2 = nullptr) {
+                             double *U1 = nullptr, double *U2 = nullptr,
+                             double *dtpart = nullptr) {
   Dev &g = c->g;
   if (!U1) U1 = c->U1;
   if (!U2) U2 = c->U2;
@@ -396,7 +399,7 @@ static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_
   if ((s = eval_fluxes(c, U1, st))) return s;
   DCF_HIP(launch_update(g, U, U1, U2, nullptr, dt, 0.75, 0.25, c->force, st));
   if ((s = eval_fluxes(c, U2, st))) return s;
-  DCF_HIP(launch_update(g, U, U2, U, nullptr, dt, 1.0 / 3.0, 2.0 / 3.0, c->force, st));
+  DCF_HIP(launch_update(g, U, U2, U, nullptr, dt, 1.0 / 3.0, 2.0 / 3.0, c->force, st, dtpart));
   return DCF_OK;
 }
 
@@ -478,6 +481,19 @@ dcf_status dcf_batch_rk3_step(dcf_ctx *const *ctxs, double *const *U, double *co
   DCF_HIP(hipMemcpyAsync(table, h.data(), (size_t)n * sizeof(BatchEntry), hipMemcpyHostToDevice,
                          st));
   DCF_HIP(launch_batch_step((const BatchEntry *)table, h.data(), n, cfl, st));
+  return DCF_OK;
+}
+
+dcf_status dcf_rk3_step_cfl(dcf_ctx *c, double *U, const double *dt, double cfl, double dt_max,
+                            double *dt_next, void *stream) {
+  dcf_status s = ready(c, 0);
+  if (s) return s;
+  if (!U || !dt || !dt_next) return fail(DCF_EINVAL, "null array");
+  if (!(cfl > 0.0)) return fail(DCF_EINVAL, "cfl must be > 0");
+  if (!(dt_max > 0.0)) dt_max = 1.0e300;
+  hipStream_t st = (hipStream_t)stream;
+  if ((s = rk3_stages(c, U, dt, st, nullptr, nullptr, c->dtpart))) return s;
+  DCF_HIP(launch_dt_final(c->dtpart, (int)update_blocks(c->g), cfl, dt_max, dt_next, st));
   return DCF_OK;
 }
 

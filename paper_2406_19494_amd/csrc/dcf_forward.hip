@@ -54,6 +54,24 @@ __global__ void k_metrics(int kind, double lo, double hi, double beta, int n, do
 // ---------------------------------------------------------------------------
 // Primitives from conserved variables (Eq. (2), ideal gas).
 // ---------------------------------------------------------------------------
+// From (rho, rho u, rho v, rho w, E) with zeros for unused momenta.
+__device__ __forceinline__ void prim_of_state(const Dev &g, const double *s, double *q) {
+  const int nd = g.ndim;
+  double rho = s[0];
+  double ir = 1.0 / rho;
+  double u = s[1] * ir;
+  double v = nd >= 2 ? s[2] * ir : 0.0;
+  double w = nd >= 3 ? s[3] * ir : 0.0;
+  double E = s[4];
+  double p = (g.gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v + w * w));
+  q[QR] = rho;
+  q[QU] = u;
+  q[QV] = v;
+  q[QW] = w;
+  q[QP] = p;
+  q[QT] = p / (rho * g.R);
+}
+
 __device__ __forceinline__ void cons_to_prim(const Dev &g, const double *U, long c, double *q) {
   const int nd = g.ndim;
   const long nc = g.ncell;
@@ -744,16 +762,37 @@ __global__ void __launch_bounds__(256) k_force_final(const double *part, int npa
   if (threadIdx.x == 0) f[0] = -v[0] / v[1];
 }
 
+// Signal rate of one cell, sum_d (|u_d| + c)/dx_d + 2 nu_eff sum_d 1/dx_d^2
+// (nu_eff = max(4/3, gamma/Pr) mu/rho); dt = cfl / max over cells.
+__device__ __forceinline__ double cell_sigma(const Dev &g, const double *q, const int *pos) {
+  double cs = sqrt(g.gamma * q[QP] / q[QR]);
+  double conv = 0.0, inv2 = 0.0;
+  for (int d = 0; d < g.ndim; ++d) {
+    double id = g.idx[d][pos[d]];
+    conv += (fabs(q[QU + d]) + cs) * id;
+    inv2 += id * id;
+  }
+  double sig = conv;
+  if (g.visc != VISC_NONE) {
+    double mu = viscosity(g, q[QT]);
+    double nu = fmax(4.0 / 3.0, g.gamma / g.Pr) * mu / q[QR];
+    sig += 2.0 * nu * inv2;
+  }
+  if (!(sig < 1.0e300)) sig = 1.0e300;  // non-finite: flagged elsewhere
+  return sig;
+}
+
 // ---------------------------------------------------------------------------
 // Divergence of the face fluxes (Eq. (6)) plus the source, fused with the
 // TVD-RK3 stage: Uout = a*Un + b*(Uin + dt*R).  With Rout != nullptr the
 // kernel writes R instead (rhs evaluation).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void update_body(const Dev &g, const double *Un, const double *Uin,
-                                            double *Uout, double *Rout, const double *dtp,
-                                            double a, double bcoef, const double *force,
-                                            unsigned cu) {  // ncell < 2^31
-  if (cu >= (unsigned)g.ncell) return;
+// One cell's divergence + source + stage update (no barrier inside).
+// Returns the cell's new state's signal rate when `want_sigma`.
+__device__ __forceinline__ double update_cell(const Dev &g, const double *Un, const double *Uin,
+                                              double *Uout, double *Rout, const double *dtp,
+                                              double a, double bcoef, const double *force,
+                                              unsigned cu, bool want_sigma) {
   const long c = cu;
   const unsigned n0 = g.n[0], n01 = n0 * (unsigned)g.n[1];
   const int k = (int)(cu / n01), j = (int)((cu % n01) / n0), i = (int)(cu % n0);
@@ -785,20 +824,47 @@ __device__ __forceinline__ void update_body(const Dev &g, const double *Un, cons
   Rv[nd + 1] = R[4];
   if (Rout) {
     for (int v = 0; v < nd + 2; ++v) Rout[v * nc + c] = Rv[v];
-    return;
+    return 0.0;
   }
   const double dt = dtp[0];
+  double st[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int v = 0; v < nd + 2; ++v) {
     double un = Un[v * nc + c];
     double ui = Uin[v * nc + c];
-    Uout[v * nc + c] = a * un + bcoef * (ui + dt * Rv[v]);
+    double uo = a * un + bcoef * (ui + dt * Rv[v]);
+    Uout[v * nc + c] = uo;
+    st[v == nd + 1 ? 4 : v] = uo;
+  }
+  if (!want_sigma) return 0.0;
+  double q[6];
+  prim_of_state(g, st, q);
+  const int pos[3] = {i, j, k};
+  return cell_sigma(g, q, pos);
+}
+
+// With dtpart (uniform over the launch) every thread of the block reaches
+// the block reduction of the new state's signal rates (the CFL step of the
+// next step); the barrier sits outside any branch on the thread's cell.
+__device__ __forceinline__ void update_body(const Dev &g, const double *Un, const double *Uin,
+                                            double *Uout, double *Rout, const double *dtp,
+                                            double a, double bcoef, const double *force,
+                                            unsigned cu, double *dtpart = nullptr) {
+  double sig = 0.0;
+  if (cu < (unsigned)g.ncell)  // ncell < 2^31
+    sig = update_cell(g, Un, Uin, Uout, Rout, dtp, a, bcoef, force, cu, dtpart != nullptr);
+  if (dtpart) {
+    __shared__ double shx[256];
+    const double m = block_max(sig, shx);
+    if (threadIdx.x == 0) dtpart[blockIdx.x] = m;
   }
 }
 
 __global__ void __launch_bounds__(256) k_update(Dev g, const double *Un, const double *Uin,
                                                 double *Uout, double *Rout, const double *dtp,
-                                                double a, double bcoef, const double *force) {
-  update_body(g, Un, Uin, Uout, Rout, dtp, a, bcoef, force, blockIdx.x * blockDim.x + threadIdx.x);
+                                                double a, double bcoef, const double *force,
+                                                double *dtpart) {
+  update_body(g, Un, Uin, Uout, Rout, dtp, a, bcoef, force, blockIdx.x * blockDim.x + threadIdx.x,
+              dtpart);
 }
 
 // ---------------------------------------------------------------------------
@@ -814,21 +880,7 @@ __device__ __forceinline__ void dt_partial_body(const Dev &g, const double *U, d
                   (int)(c / ((long)g.n[0] * g.n[1]))};
     double q[6];
     cons_to_prim(g, U, c, q);
-    double cs = sqrt(g.gamma * q[QP] / q[QR]);
-    double conv = 0.0, inv2 = 0.0;
-    for (int d = 0; d < g.ndim; ++d) {
-      double id = g.idx[d][pos[d]];
-      conv += (fabs(q[QU + d]) + cs) * id;
-      inv2 += id * id;
-    }
-    double sig = conv;
-    if (g.visc != VISC_NONE) {
-      double mu = viscosity(g, q[QT]);
-      double nu = fmax(4.0 / 3.0, g.gamma / g.Pr) * mu / q[QR];
-      sig += 2.0 * nu * inv2;
-    }
-    if (!(sig < 1.0e300)) sig = 1.0e300;  // non-finite: flagged elsewhere
-    smax = fmax(smax, sig);
+    smax = fmax(smax, cell_sigma(g, q, pos));
   }
   smax = block_max(smax, sh);
   if (threadIdx.x == 0) part[bid] = smax;
@@ -918,42 +970,48 @@ __global__ void __launch_bounds__(256) k_cost(Dev g, int face, double pref, cons
   __shared__ double sh[2 * 256];
   const int d = face / 2, side = face % 2;
   const int t1 = tan1(d), t2 = tan2(d);
-  const int na = g.n[t1], nb = g.n[t2];
-  const long nface = (long)na * nb;
+  const unsigned na = g.n[t1];
+  const unsigned nface = na * (unsigned)g.n[t2];
   const int nd = g.ndim;
   const long nc = g.ncell;
-  // total area (fixed order), then the weighted sum
-  double v[2] = {0.0, 0.0};
-  for (long x = threadIdx.x; x < nface; x += 256) {
-    int a = (int)(x % na), bb = (int)(x / na);
-    double A = 1.0;
+  constexpr int CH = 4;  // faces per thread per round, loads issued together
+  auto cell_of = [&](unsigned x, double &A) {
+    const int a = (int)(x % na), bb = (int)(x / na);
+    A = 1.0;
     if (t1 < nd) A *= g.dx[t1][a];
     if (t2 < nd) A *= g.dx[t2][bb];
     int p[3];
     p[d] = side == 0 ? 0 : g.n[d] - 1;
     p[t1] = a;
     p[t2] = bb;
-    long c = ((long)p[2] * g.n[1] + p[1]) * g.n[0] + p[0];
-    double q[6];
-    cons_to_prim(g, U, c, q);
-    double dp = q[QP] - pref;
-    v[0] += A * dp * dp;
-    v[1] += A;
+    return ((long)p[2] * g.n[1] + p[1]) * g.n[0] + p[0];
+  };
+  // total area (fixed order), then the weighted sum
+  double v[2] = {0.0, 0.0};
+  for (unsigned x0 = threadIdx.x; x0 < nface; x0 += 256u * CH) {
+    double q[CH][6], A[CH];
+    bool ok[CH];
+#pragma unroll
+    for (int r = 0; r < CH; ++r) {
+      const unsigned x = x0 + 256u * r;
+      ok[r] = x < nface;
+      if (ok[r]) cons_to_prim(g, U, cell_of(x, A[r]), q[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < CH; ++r) {
+      if (!ok[r]) continue;
+      double dp = q[r][QP] - pref;
+      v[0] += A[r] * dp * dp;
+      v[1] += A[r];
+    }
   }
   block_sum<2>(v, sh);
   const double area = v[1];
   if (threadIdx.x == 0) J[0] += w * (v[0] / area);
   if (!grad) return;
-  for (long x = threadIdx.x; x < nface; x += 256) {
-    int a = (int)(x % na), bb = (int)(x / na);
-    double A = 1.0;
-    if (t1 < nd) A *= g.dx[t1][a];
-    if (t2 < nd) A *= g.dx[t2][bb];
-    int p[3];
-    p[d] = side == 0 ? 0 : g.n[d] - 1;
-    p[t1] = a;
-    p[t2] = bb;
-    long c = ((long)p[2] * g.n[1] + p[1]) * g.n[0] + p[0];
+  for (unsigned x = threadIdx.x; x < nface; x += 256) {
+    double A;
+    const long c = cell_of(x, A);
     double q[6];
     cons_to_prim(g, U, c, q);
     double s = w * (A / area) * 2.0 * (q[QP] - pref) * (g.gamma - 1.0);
@@ -1097,8 +1155,14 @@ hipError_t launch_force(const Dev &g, double *part, double *force, hipStream_t s
 }
 hipError_t launch_update(const Dev &g, const double *Un, const double *Uin, double *Uout,
                          double *Rout, const double *dt, double a, double b,
-                         const double *force, hipStream_t st) {
-  k_update<<<grid_for(g.ncell), 256, 0, st>>>(g, Un, Uin, Uout, Rout, dt, a, b, force);
+                         const double *force, hipStream_t st, double *dtpart) {
+  k_update<<<grid_for(g.ncell), 256, 0, st>>>(g, Un, Uin, Uout, Rout, dt, a, b, force, dtpart);
+  return hipGetLastError();
+}
+unsigned update_blocks(const Dev &g) { return grid_for(g.ncell); }
+hipError_t launch_dt_final(const double *part, int nparts, double cfl, double dt_max, double *dt,
+                           hipStream_t st) {
+  k_dt_final<<<1, 256, 0, st>>>(part, nparts, cfl, dt_max, dt);
   return hipGetLastError();
 }
 hipError_t launch_dt(const Dev &g, const double *U, double cfl, double dt_max, double *part,

@@ -37,9 +37,14 @@ hipError_t launch_fluxes(const Dev &g, hipStream_t st);
 hipError_t launch_flux_dir(const Dev &g, int D, hipStream_t st);
 hipError_t launch_grad(const Dev &g, hipStream_t st);
 hipError_t launch_force(const Dev &g, double *part, double *force, hipStream_t st);
+// With dtpart (update_blocks(g) doubles) each block also writes the largest
+// signal rate of its cells' new state (the CFL step of the next step).
 hipError_t launch_update(const Dev &g, const double *Un, const double *Uin, double *Uout,
                          double *Rout, const double *dt, double a, double b,
-                         const double *force, hipStream_t st);
+                         const double *force, hipStream_t st, double *dtpart = nullptr);
+unsigned update_blocks(const Dev &g);
+hipError_t launch_dt_final(const double *part, int nparts, double cfl, double dt_max, double *dt,
+                           hipStream_t st);
 hipError_t launch_dt(const Dev &g, const double *U, double cfl, double dt_max, double *part,
                      double *dt, hipStream_t st);
 hipError_t launch_diag(const Dev &g, const double *U, double *part, double *out,

@@ -290,13 +290,14 @@ class GpuBackend:
                 job.remaining = 1
             else:
                 job.remaining = spec.nsteps
+                # the first CFL step; every step then returns the next one
+                job.solver.compute_dt(job.U, cfl=case.cfl, out=job.dt, stream=job.stream)
                 if self.graphs and spec.nsteps >= self.k:
                     job.graph = torch.cuda.CUDAGraph()
                     job.stream.synchronize()
                     with torch.cuda.graph(job.graph, stream=job.stream):
                         for _ in range(self.k):
-                            job.solver.compute_dt(job.U, cfl=case.cfl, out=job.dt)
-                            job.solver.step(job.U, job.dt)
+                            job.solver.step_cfl(job.U, job.dt, cfl=case.cfl)
                     # capture records without running: state unchanged so far
         job.events = deque()
         for _ in range(self.inflight):
@@ -327,8 +328,7 @@ class GpuBackend:
                 else:
                     case = s.case
                     for _ in range(n):
-                        s.compute_dt(job.U, cfl=case.cfl, out=job.dt, stream=job.stream)
-                        s.step(job.U, job.dt, stream=job.stream)
+                        s.step_cfl(job.U, job.dt, cfl=case.cfl, stream=job.stream)
                 job.enqueued += n
             ev = torch.cuda.Event()
             ev.record(job.stream)

@@ -138,6 +138,16 @@ class Solver:
     def step(self, U: torch.Tensor, dt: torch.Tensor, stream=None):
         B.call("dcf_rk3_step", self.ctx, _ptr(U), _ptr(dt), _stream(stream))
 
+    def step_cfl(self, U: torch.Tensor, dt: torch.Tensor, cfl=None, dt_max=0.0, out=None,
+                 stream=None) -> torch.Tensor:
+        """One RK3 step with dt, returning (in `out`, default dt itself) the
+        CFL step of the new state from the last stage's fused reduction."""
+        out = dt if out is None else out
+        B.call("dcf_rk3_step_cfl", self.ctx, _ptr(U), _ptr(dt),
+               float(self.case.cfl if cfl is None else cfl), float(dt_max), _ptr(out),
+               _stream(stream))
+        return out
+
     def run(self, U: torch.Tensor, nsteps: int, dt_fixed: float = 0.0, t_end: float = 0.0,
             cfl=None):
         """Advance U in place.  With dt_fixed > 0 the step is fixed; otherwise

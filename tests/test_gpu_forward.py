@@ -171,3 +171,32 @@ def test_full_size_rhs_parity(which):
     R_or = o.rhs(U_or)
     err = rel_err_per_var(R_gpu, R_or, flux_scale(case, U_or))
     assert np.all(err <= RHS_TOL), (which, err)
+
+
+@pytest.mark.parametrize("which", ["tgv", "channel", "porous_bl", "sod"])
+def test_fused_cfl_step_equals_separate_dt(which):
+    # dcf_rk3_step_cfl: the same new state as dcf_rk3_step, and the next step
+    # bitwise equal to dcf_compute_dt of that state
+    if which == "tgv":
+        case, P = W.tgv(20)
+        K = None
+    elif which == "channel":
+        case, P = W.channel(nx=20, ny=18, nz=11)
+        K = None
+    elif which == "porous_bl":
+        case, P, K = W.porous_bl(nx=80, ny=40, strip=(20, 60))
+    else:
+        case, P = W.sod(300)
+        K = None
+    s = Solver(case, K=K)
+    U1 = s.init_state(P)
+    U2 = U1.clone()
+    dt1 = s.compute_dt(U1)
+    dt2 = dt1.clone()
+    for _ in range(3):
+        s.step(U1, dt1)
+        s.compute_dt(U1, out=dt1)
+        s.step_cfl(U2, dt2)
+    torch.cuda.synchronize()
+    assert torch.equal(U1, U2)
+    assert torch.equal(dt1, dt2)

@@ -189,6 +189,9 @@ class _FakeSolver:
     def step(self, *a, **k):
         self.steps += 1
 
+    def step_cfl(self, *a, **k):
+        self.steps += 1
+
     def gradient_advance(self, n, stream=None):
         self.units = min(self.units_needed, self.units + n)
         return self.units == self.units_needed
