@@ -23,8 +23,15 @@
 
 namespace dcf {
 
-constexpr int TF = 64;  // faces per tile line
-constexpr int TW = 4;   // lines per tile (TF * TW = 256 threads)
+// Tile shape of direction D (TF faces per line x TW lines = 256 threads):
+// x-faces run along the lanes (64 x 4); y and z tiles take 8 neighbouring
+// x-lines so that a cell row is read and written in 64-byte segments
+// (32 x 8, at the price of more faces recomputed at tile edges).
+template <int D> struct TileShape {
+  static constexpr int TF = D == 0 ? 64 : 32;
+  static constexpr int TW = 256 / TF;
+};
+__host__ inline int tile_faces(int D) { return D == 0 ? 64 : 32; }
 
 // ---------------------------------------------------------------------------
 // Reverse of WENO5-JS: g[0..4] += d y / d (a..e) * yb.
@@ -233,8 +240,9 @@ struct Tile {
   bool line_ok;
 };
 
-template <int OLO, int OHI>
-__device__ __forceinline__ Tile make_tile(const Dev &g, int D) {
+template <int OLO, int OHI, int D>
+__device__ __forceinline__ Tile make_tile(const Dev &g) {
+  constexpr int TF = TileShape<D>::TF, TW = TileShape<D>::TW;
   constexpr int SPAN = OHI - OLO;
   constexpr int CPT = TF - SPAN;  // cells completed per tile line
   const int T1 = tan1(D), T2 = tan2(D);
@@ -271,8 +279,9 @@ __device__ __forceinline__ Tile make_tile(const Dev &g, int D) {
 
 template <int OLO, int OHI>
 __host__ inline unsigned tile_count(const Dev &g, int D) {
+  const int TF = tile_faces(D), TW = 256 / TF;
   constexpr int SPAN = OHI - OLO;
-  constexpr int CPT = TF - SPAN;
+  const int CPT = TF - SPAN;
   const int ncell_line = g.n[D] + 1 + SPAN;
   const long tiles_d = (ncell_line + CPT - 1) / CPT;
   const long lines = (long)g.n[tan1(D)] * g.n[tan2(D)];
@@ -286,12 +295,13 @@ __host__ inline unsigned tile_count(const Dev &g, int D) {
 template <int NDIM, int D>
 __global__ void __launch_bounds__(256) k_conv_vjp(Dev g, AdjBuffers A) {
   constexpr int OLO = -3, OHI = 2, NOFF = OHI - OLO + 1, SPAN = OHI - OLO;
+  constexpr int TF = TileShape<D>::TF, TW = TileShape<D>::TW;
   constexpr int NCW = TF + SPAN;  // window cells per line
   constexpr int T1 = tan1(D), T2 = tan2(D);
   constexpr int NC = 5;
   __shared__ double acc[NC][TW][NCW];
   __shared__ double buf[NOFF][TW][TF];  // one component's contributions per face
-  Tile t = make_tile<OLO, OHI>(g, D);
+  Tile t = make_tile<OLO, OHI, D>(g);
   for (int i = threadIdx.x; i < NC * TW * NCW; i += 256) (&acc[0][0][0])[i] = 0.0;
 
   const int f = t.f0 + t.lane_face;
@@ -390,11 +400,12 @@ __global__ void __launch_bounds__(256) k_conv_vjp(Dev g, AdjBuffers A) {
 template <int NDIM, int D>
 __global__ void __launch_bounds__(256) k_visc_vjp(Dev g, AdjBuffers A) {
   constexpr int OLO = -2, OHI = 1, NOFF = OHI - OLO + 1, SPAN = OHI - OLO;
+  constexpr int TF = TileShape<D>::TF, TW = TileShape<D>::TW;
   constexpr int NCW = TF + SPAN;
   constexpr int T1 = tan1(D), T2 = tan2(D);
   constexpr int NC = 9;  // u, v, w, T, mu, G(t1,t1) G(t1,D) G(t2,t2) G(t2,D)
   __shared__ double acc[NC][TW][NCW];
-  Tile t = make_tile<OLO, OHI>(g, D);
+  Tile t = make_tile<OLO, OHI, D>(g);
   for (int i = threadIdx.x; i < NC * TW * NCW; i += 256) (&acc[0][0][0])[i] = 0.0;
   __syncthreads();
 
