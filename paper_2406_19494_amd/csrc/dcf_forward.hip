@@ -674,21 +674,21 @@ __device__ __forceinline__ double cell_volume(const Dev &g, int i, int j, int k)
 // ---------------------------------------------------------------------------
 // Deterministic block reductions (fixed tree for a fixed launch shape).
 // ---------------------------------------------------------------------------
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double *sh /*[NV*256]*/) {
+template <int NV, int BS = 256>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *sh /*[NV*BS]*/) {
   const int t = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < NV; ++q) sh[q * 256 + t] = v[q];
+  for (int q = 0; q < NV; ++q) sh[q * BS + t] = v[q];
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = BS / 2; w > 0; w >>= 1) {
     if (t < w) {
 #pragma unroll
-      for (int q = 0; q < NV; ++q) sh[q * 256 + t] += sh[q * 256 + t + w];
+      for (int q = 0; q < NV; ++q) sh[q * BS + t] += sh[q * BS + t + w];
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < NV; ++q) v[q] = sh[q * 256];
+  for (int q = 0; q < NV; ++q) v[q] = sh[q * BS];
 }
 
 __device__ __forceinline__ double block_max(double v, double *sh) {
@@ -965,16 +965,18 @@ __global__ void __launch_bounds__(256) k_diag_final(const double *part, int npar
 // next to the cost face, accumulated as J += w j; optional gradient
 // g += w dj/dU.  One block; the face has O(n^2) cells.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_cost(Dev g, int face, double pref, const double *U,
-                                              double w, double *J, double *grad) {
-  __shared__ double sh[2 * 256];
+// Wall-pressure cost term and its gradient: one block of 1024 threads, one
+// wall face per thread and round (fixed reduction order: deterministic).
+__global__ void __launch_bounds__(1024) k_cost(Dev g, int face, double pref, const double *U,
+                                               double w, double *J, double *grad) {
+  constexpr int BS = 1024;
+  __shared__ double sh[2 * BS];
   const int d = face / 2, side = face % 2;
   const int t1 = tan1(d), t2 = tan2(d);
   const unsigned na = g.n[t1];
   const unsigned nface = na * (unsigned)g.n[t2];
   const int nd = g.ndim;
   const long nc = g.ncell;
-  constexpr int CH = 4;  // faces per thread per round, loads issued together
   auto cell_of = [&](unsigned x, double &A) {
     const int a = (int)(x % na), bb = (int)(x / na);
     A = 1.0;
@@ -988,28 +990,18 @@ __global__ void __launch_bounds__(256) k_cost(Dev g, int face, double pref, cons
   };
   // total area (fixed order), then the weighted sum
   double v[2] = {0.0, 0.0};
-  for (unsigned x0 = threadIdx.x; x0 < nface; x0 += 256u * CH) {
-    double q[CH][6], A[CH];
-    bool ok[CH];
-#pragma unroll
-    for (int r = 0; r < CH; ++r) {
-      const unsigned x = x0 + 256u * r;
-      ok[r] = x < nface;
-      if (ok[r]) cons_to_prim(g, U, cell_of(x, A[r]), q[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < CH; ++r) {
-      if (!ok[r]) continue;
-      double dp = q[r][QP] - pref;
-      v[0] += A[r] * dp * dp;
-      v[1] += A[r];
-    }
+  for (unsigned x = threadIdx.x; x < nface; x += BS) {
+    double A, q[6];
+    cons_to_prim(g, U, cell_of(x, A), q);
+    double dp = q[QP] - pref;
+    v[0] += A * dp * dp;
+    v[1] += A;
   }
-  block_sum<2>(v, sh);
+  block_sum<2, BS>(v, sh);
   const double area = v[1];
   if (threadIdx.x == 0) J[0] += w * (v[0] / area);
   if (!grad) return;
-  for (unsigned x = threadIdx.x; x < nface; x += 256) {
+  for (unsigned x = threadIdx.x; x < nface; x += BS) {
     double A;
     const long c = cell_of(x, A);
     double q[6];
@@ -1313,7 +1305,7 @@ hipError_t launch_batch_step(const BatchEntry *tab_dev, const BatchEntry *tab_ho
 
 hipError_t launch_cost(const Dev &g, int face, double pref, const double *U, double w,
                        double *J, double *grad, hipStream_t st) {
-  k_cost<<<1, 256, 0, st>>>(g, face, pref, U, w, J, grad);
+  k_cost<<<1, 1024, 0, st>>>(g, face, pref, U, w, J, grad);
   return hipGetLastError();
 }
 
