@@ -397,49 +397,50 @@ __global__ void __launch_bounds__(256) k_prim_ghost(Dev g) {
 // position along t interior, the other active positions within two layers.
 // G[3 t + phi] are box arrays.
 // ---------------------------------------------------------------------------
+// Cells that need d u_phi / d x_t: position along t interior, the other
+// active positions within two layers.  One thread per (cell, t), x-fastest.
+__host__ __device__ __forceinline__ unsigned grad_cells(const Dev &g, int t) {
+  unsigned n = 1;
+  for (int e = 0; e < g.ndim; ++e) n *= e == t ? g.n[e] : g.n[e] + 4;
+  return n;
+}
+
 template <int NDIM>
-__device__ __forceinline__ void grad_body(const Dev &g, unsigned bid, unsigned nblk) {
-  // threads over the cells within two layers of the interior, x-fastest
+__device__ __forceinline__ void grad_body(const Dev &g, int t, unsigned bid, unsigned nblk) {
   const unsigned bl = xcd_remap(bid, nblk) * blockDim.x + threadIdx.x;
-  const unsigned E0 = g.n[0] + 4, E1 = g.n[1] + 4, E2 = NDIM >= 3 ? g.n[2] + 4 : 1;
-  if (bl >= E0 * E1 * E2) return;
+  if (bl >= grad_cells(g, t)) return;
+  unsigned E[3];
+  int o[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    E[e] = e >= NDIM ? 1u : (e == t ? (unsigned)g.n[e] : (unsigned)g.n[e] + 4);
+    o[e] = (e >= NDIM || e == t) ? 0 : -2;
+  }
   int p[3];
-  const unsigned r = bl / E0;
-  p[0] = (int)(bl % E0) - 2;
-  p[1] = (int)(r % E1) - 2;
-  p[2] = NDIM >= 3 ? (int)(r / E1) - 2 : 0;
+  const unsigned r = bl / E[0];
+  p[0] = (int)(bl % E[0]) + o[0];
+  p[1] = (int)(r % E[1]) + o[1];
+  p[2] = (int)(r / E[1]) + o[2];
   const long b = bidx(g, p[0], p[1], p[2]);
-  // all stencil loads first, then the derivatives of the axes along which
-  // this cell is interior
-  bool in[NDIM];
-  double v[NDIM][NDIM][4];
+  const long st = g.sb[t];
+  double v[NDIM][4];
 #pragma unroll
-  for (int t = 0; t < NDIM; ++t) {
-    in[t] = p[t] >= 0 && p[t] < g.n[t];
-    if (!in[t]) continue;
-    const long st = g.sb[t];
-#pragma unroll
-    for (int phi = 0; phi < NDIM; ++phi) {
-      const double *A = g.Q[QU + phi];
-      v[t][phi][0] = A[b - 2 * st];
-      v[t][phi][1] = A[b - st];
-      v[t][phi][2] = A[b + st];
-      v[t][phi][3] = A[b + 2 * st];
-    }
+  for (int phi = 0; phi < NDIM; ++phi) {
+    const double *A = g.Q[QU + phi];
+    v[phi][0] = A[b - 2 * st];
+    v[phi][1] = A[b - st];
+    v[phi][2] = A[b + st];
+    v[phi][3] = A[b + 2 * st];
   }
+  const double mct = g.mc[t][p[t]];
 #pragma unroll
-  for (int t = 0; t < NDIM; ++t) {
-    if (!in[t]) continue;
-    const double mct = g.mc[t][p[t]];
-#pragma unroll
-    for (int phi = 0; phi < NDIM; ++phi)
-      g.G[3 * t + phi][b] = dcell4(v[t][phi][0], v[t][phi][1], v[t][phi][2], v[t][phi][3]) * mct;
-  }
+  for (int phi = 0; phi < NDIM; ++phi)
+    g.G[3 * t + phi][b] = dcell4(v[phi][0], v[phi][1], v[phi][2], v[phi][3]) * mct;
 }
 
 template <int NDIM>
 __global__ void __launch_bounds__(256) k_grad(Dev g) {
-  grad_body<NDIM>(g, blockIdx.x, gridDim.x);
+  grad_body<NDIM>(g, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1108,11 +1109,13 @@ static hipError_t launch_yz(const Dev &g, hipStream_t st) {
 
 hipError_t launch_grad(const Dev &g, hipStream_t st) {
   if (g.visc == VISC_NONE || g.ndim < 2) return hipSuccess;
-  const long cells = (long)(g.n[0] + 4) * (g.n[1] + 4) * (g.ndim >= 3 ? g.n[2] + 4 : 1);
+  unsigned cells = 0;
+  for (int t = 0; t < g.ndim; ++t) cells = std::max(cells, grad_cells(g, t));
+  const dim3 grid(grid_for(cells), g.ndim);
   if (g.ndim == 2)
-    k_grad<2><<<grid_for(cells), 256, 0, st>>>(g);
+    k_grad<2><<<grid, 256, 0, st>>>(g);
   else
-    k_grad<3><<<grid_for(cells), 256, 0, st>>>(g);
+    k_grad<3><<<grid, 256, 0, st>>>(g);
   return hipGetLastError();
 }
 
@@ -1194,7 +1197,7 @@ template <int NDIM>
 __global__ void __launch_bounds__(256) kb_grad(const BatchEntry *tab) {
   const BatchEntry &e = tab[blockIdx.y];
   if (blockIdx.x >= e.nb_grad) return;
-  grad_body<NDIM>(e.g, blockIdx.x, e.nb_grad);
+  grad_body<NDIM>(e.g, blockIdx.z, blockIdx.x, e.nb_grad);
 }
 
 template <int NDIM, bool VISC>
@@ -1239,9 +1242,9 @@ void batch_entry_sizes(BatchEntry &e) {
   const Dev &g = e.g;
   e.nb_prim = grid_for(g.ncell);
   e.nb_ghost = g.nbox > g.ncell ? grid_for(g.nbox - g.ncell) : 0;
-  e.nb_grad = (g.visc != VISC_NONE && g.ndim >= 2)
-                  ? grid_for((long)(g.n[0] + 4) * (g.n[1] + 4) * (g.ndim >= 3 ? g.n[2] + 4 : 1))
-                  : 0;
+  e.nb_grad = 0;
+  if (g.visc != VISC_NONE && g.ndim >= 2)
+    for (int t = 0; t < g.ndim; ++t) e.nb_grad = std::max(e.nb_grad, grid_for(grad_cells(g, t)));
   e.nb_x = grid_for(g.fcount[0]);
   e.nb_upd = grid_for(g.ncell);
   e.nb_dt = grid_capped(g.ncell, RED_BLOCKS);
@@ -1279,7 +1282,8 @@ static hipError_t batch_step_t(const BatchEntry *tab, const BatchEntry *h, int n
   for (int stage = 0; stage < 3; ++stage) {
     kb_prim_interior<<<dim3(mp, ny), 256, 0, st>>>(tab, stage);
     if (mh) kb_prim_ghost<<<dim3(mh, ny), 256, 0, st>>>(tab);
-    if (VISC && NDIM >= 2) kb_grad<NDIM < 2 ? 2 : NDIM><<<dim3(mg, ny), 256, 0, st>>>(tab);
+    if (VISC && NDIM >= 2)
+      kb_grad<NDIM < 2 ? 2 : NDIM><<<dim3(mg, ny, NDIM), 256, 0, st>>>(tab);
     kb_flux_x<NDIM, VISC><<<dim3(mx, ny), 256, shm, st>>>(tab);
     if (NDIM >= 2) kb_flux_yz<NDIM < 2 ? 2 : NDIM, 1, VISC><<<dim3(my[1], ny), 256, 0, st>>>(tab);
     if (NDIM >= 3) kb_flux_yz<3, 2, VISC><<<dim3(my[2], ny), 256, 0, st>>>(tab);

@@ -52,6 +52,12 @@ def test_invalid_arguments_rejected_without_device(dcf):
     # null context on every stateful call
     assert L.dcf_rk3_step(None, None, None, None) == -1
     assert L.dcf_vjp_step(None, None, None, None, None, None, None) == -1
+    assert L.dcf_rk3_step_cfl(None, None, None, 0.5, 0.0, None, None) == -1
+    # batched stepping: sizes and null arguments are checked first
+    nb = C.c_size_t()
+    assert L.dcf_batch_table_bytes(0, C.byref(nb)) == -1
+    assert L.dcf_batch_table_bytes(3, C.byref(nb)) == 0 and nb.value > 0
+    assert L.dcf_batch_rk3_step(None, None, None, 1, 0.0, None, 0, None) == -1
 
 
 def test_product_path_does_not_import_oracle():
