@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -228,7 +229,7 @@ static size_t carve(dcf_ctx *c, void *base, int mode, int nsteps, int seg_len) {
   c->U2 = cv.take<double>(nv * ncell);
   c->part = cv.take<double>(8 * RED_BLOCKS);
   c->force = cv.take<double>(4);
-  c->dtpart = cv.take<double>(update_blocks(g));
+  c->dtpart = cv.take<double>(std::max(update_blocks(g), flux_update_blocks(g)));
   g.flags = cv.take<unsigned>(64);
   if (mode >= 1) carve_adjoint(cv, g, c->adj);
   if (mode >= 2) {
@@ -387,12 +388,27 @@ static dcf_status eval_fluxes(dcf_ctx *c, const double *U, hipStream_t st) {
 }
 
 // One RK3 step in place; the stage states go to U1, U2 (default: scratch).
+// The last direction's fluxes are fused into the stage update where there is
+// no source term (the body force needs every boundary flux first).
+static bool fused_stages(const dcf_ctx *c) { return c->g.ndim >= 2 && c->g.source == SRC_NONE; }
+
 static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_t st,
                              double *U1 = nullptr, double *U2 = nullptr,
                              double *dtpart = nullptr) {
   Dev &g = c->g;
   if (!U1) U1 = c->U1;
   if (!U2) U2 = c->U2;
+  if (fused_stages(c)) {
+    const double *in[3] = {U, U1, U2};
+    double *out[3] = {U1, U2, U};
+    const double a[3] = {0.0, 0.75, 1.0 / 3.0}, b[3] = {1.0, 0.25, 2.0 / 3.0};
+    for (int k = 0; k < 3; ++k) {
+      DCF_HIP(launch_prim_halo(g, in[k], st));
+      DCF_HIP(launch_fluxes_update(g, U, in[k], out[k], dt, a[k], b[k], k == 2 ? dtpart : nullptr,
+                                   st));
+    }
+    return DCF_OK;
+  }
   dcf_status s;
   if ((s = eval_fluxes(c, U, st))) return s;
   DCF_HIP(launch_update(g, U, U, U1, nullptr, dt, 0.0, 1.0, c->force, st));
@@ -493,7 +509,8 @@ dcf_status dcf_rk3_step_cfl(dcf_ctx *c, double *U, const double *dt, double cfl,
   if (!(dt_max > 0.0)) dt_max = 1.0e300;
   hipStream_t st = (hipStream_t)stream;
   if ((s = rk3_stages(c, U, dt, st, nullptr, nullptr, c->dtpart))) return s;
-  DCF_HIP(launch_dt_final(c->dtpart, (int)update_blocks(c->g), cfl, dt_max, dt_next, st));
+  const unsigned nparts = fused_stages(c) ? flux_update_blocks(c->g) : update_blocks(c->g);
+  DCF_HIP(launch_dt_final(c->dtpart, (int)nparts, cfl, dt_max, dt_next, st));
   return DCF_OK;
 }
 
@@ -625,8 +642,12 @@ static dcf_status gradient_unit(dcf_ctx *c, hipStream_t st) {
       for (int k = 0; k < 3; ++k) {
         const Dev gs = stage_box(c, gr.n, k);
         DCF_HIP(launch_prim_halo(gs, in[k], st));
-        DCF_HIP(launch_fluxes(gs, st));
-        DCF_HIP(launch_update(gs, Ub, in[k], out[k], nullptr, gr.dt, a[k], b[k], nullptr, st));
+        if (fused_stages(c)) {
+          DCF_HIP(launch_fluxes_update(gs, Ub, in[k], out[k], gr.dt, a[k], b[k], nullptr, st));
+        } else {
+          DCF_HIP(launch_fluxes(gs, st));
+          DCF_HIP(launch_update(gs, Ub, in[k], out[k], nullptr, gr.dt, a[k], b[k], nullptr, st));
+        }
       }
     } else if ((s = rk3_stages(c, Ub, gr.dt, st, S1, S2))) {
       return s;

@@ -117,166 +117,50 @@ __device__ __forceinline__ int ghost_source(int kind, int side, int m, int n) {
   return side == 0 ? m : n - 1 - m;  // walls mirror
 }
 
-// Single-launch form (used when ghost cells are a small share of the box):
-// threads [0, ncell) convert interior cells (x-fastest, coalesced, one
-// branch for the whole wave); threads [ncell, nbox) fill the ghost cells,
-// converting their source cell's state themselves.
-__device__ __forceinline__ void prim_halo_body(const Dev &g, const double *U, unsigned t) {
-  if (t >= (unsigned)g.nbox) return;
-  const int nd = g.ndim;
-  int p[3];
-  if (t < (unsigned)g.ncell) {
-    const unsigned n0 = g.n[0], n01 = n0 * (unsigned)g.n[1];
-    p[2] = (int)(t / n01);
-    const unsigned rr = t % n01;
-    p[1] = (int)(rr / n0);
-    p[0] = (int)(rr % n0);
-    const long b = bidx(g, p[0], p[1], p[2]);
+// Sources of the ghost chain: the conserved state (the source cell is
+// converted here) or the primitive box once its interior is filled (the
+// source's primitives and mu are copied).
+struct FromState {
+  const double *U;
+  __device__ __forceinline__ void load(const Dev &g, const int *s, double *q, double &mu) const {
+    cons_to_prim(g, U, ((long)s[2] * g.n[1] + s[1]) * g.n[0] + s[0], q);
+    mu = -1.0;
+  }
+  __device__ __forceinline__ double pressure(const Dev &g, const int *w) const {
     double q[6];
-    cons_to_prim(g, U, (long)t, q);
-    if (!(finite_pos(q[QR]) && finite_pos(q[QP]))) atomicOr(g.flags, 1u);
-    g.Q[QR][b] = q[QR];
-    g.Q[QU][b] = q[QU];
-    if (nd >= 2) g.Q[QV][b] = q[QV];
-    if (nd >= 3) g.Q[QW][b] = q[QW];
-    g.Q[QP][b] = q[QP];
+    cons_to_prim(g, U, ((long)w[2] * g.n[1] + w[1]) * g.n[0] + w[0], q);
+    return q[QP];
+  }
+};
+struct FromBox {
+  __device__ __forceinline__ void load(const Dev &g, const int *s, double *q, double &mu) const {
+    const int nd = g.ndim;
+    const long sb = bidx(g, s[0], s[1], s[2]);
+    q[QR] = g.Q[QR][sb];
+    q[QU] = g.Q[QU][sb];
+    q[QV] = nd >= 2 ? g.Q[QV][sb] : 0.0;
+    q[QW] = nd >= 3 ? g.Q[QW][sb] : 0.0;
+    q[QP] = g.Q[QP][sb];
     if (g.visc != VISC_NONE) {
-      g.Q[QT][b] = q[QT];
-      g.Q[QMU][b] = viscosity(g, q[QT]);
-    }
-    return;
-  }
-  ghost_position(g, t - (unsigned)g.ncell, p);
-  const long b = bidx(g, p[0], p[1], p[2]);
-  int s[3] = {p[0], p[1], p[2]};
-  int side[3] = {0, 0, 0};
-  bool gh[3] = {false, false, false};
-  int top = -1;
-  for (int d = 0; d < nd; ++d) {
-    if (p[d] < 0 || p[d] >= g.n[d]) {
-      gh[d] = true;
-      side[d] = p[d] < 0 ? 0 : 1;
-      int m = side[d] == 0 ? -1 - p[d] : p[d] - g.n[d];
-      int kind = g.bck[2 * d + side[d]];
-      if (kind == BC_DIRICHLET)
-        top = d;
-      else
-        s[d] = ghost_source(kind, side[d], m, g.n[d]);
+      q[QT] = g.Q[QT][sb];
+      mu = g.Q[QMU][sb];
+    } else {
+      q[QT] = q[QP] / (q[QR] * g.R);
+      mu = -1.0;
     }
   }
-  double q[6];
-  int start = 0;
-  if (top >= 0) {
-    const int d = top;
-    const int t1 = tan1(d), t2 = tan2(d);
-    int a = t1 < nd ? (t1 < d ? p[t1] : s[t1]) : 0;
-    int bb = t2 < nd ? (t2 < d ? p[t2] : s[t2]) : 0;
-    a = min(max(a, 0), g.n[t1] - 1);
-    bb = min(max(bb, 0), g.n[t2] - 1);
-    const long nt = (long)g.n[t1] * g.n[t2];
-    const long o = (long)bb * g.n[t1] + a;
-    const double *P = g.dir[2 * d + side[d]];
-    q[QR] = P[o];
-    q[QU] = P[nt + o];
-    q[QV] = P[2 * nt + o];
-    q[QW] = P[3 * nt + o];
-    q[QP] = P[4 * nt + o];
-    q[QT] = q[QP] / (q[QR] * g.R);
-    start = top + 1;
-  } else {
-    long c = ((long)s[2] * g.n[1] + s[1]) * g.n[0] + s[0];
-    cons_to_prim(g, U, c, q);
+  __device__ __forceinline__ double pressure(const Dev &g, const int *w) const {
+    return g.Q[QP][bidx(g, w[0], w[1], w[2])];
   }
-  for (int d = start; d < nd; ++d) {
-    if (!gh[d]) continue;
-    const int face = 2 * d + side[d];
-    const int kind = g.bck[face];
-    if (!is_wall(kind)) continue;  // copies keep the value
-    double src_n = q[QU + d];
-    q[QU] = -q[QU];
-    q[QV] = -q[QV];
-    q[QW] = -q[QW];
-    const int t1 = tan1(d), t2 = tan2(d);
-    const int a = t1 < nd ? (t1 < d ? p[t1] : s[t1]) : 0;
-    const int bb = t2 < nd ? (t2 < d ? p[t2] : s[t2]) : 0;
-    const double sigma = side[d] == 0 ? 1.0 : -1.0;
-    if (kind == BC_POROUS && face == g.pface) {
-      if (a >= g.pb && a < g.pe && bb >= 0 && bb < g.n[t2]) {
-        // Darcy transpiration through the porous strip: inward-normal
-        // velocity -K (p_w - p_inf)/p_inf, p_w of the first interior cell.
-        int w[3];
-        w[d] = side[d] == 0 ? 0 : g.n[d] - 1;
-        w[t1] = a;
-        w[t2] = bb;
-        long cw = ((long)w[2] * g.n[1] + w[1]) * g.n[0] + w[0];
-        double qw[6];
-        cons_to_prim(g, U, cw, qw);
-        int kk = bb * (g.pe - g.pb) + (a - g.pb);
-        double vn = -g.K[kk] * (qw[QP] - g.pinf) / g.pinf;
-        q[QU + d] = 2.0 * sigma * vn - src_n;
-      }
-    } else if (kind == BC_DISTURB && a >= 0 && a < g.n[t1]) {
-      // Disturbance wall (Section 3.2, Eq. (8)): prescribed inward-normal
-      // velocity A sin(2 pi kappa x) at the wall-face centre, (A, kappa)
-      // taken from the boundary parameters.
-      const double *th = g.K + g.doff[face];
-      double vn = th[0] * sin(2.0 * M_PI * g.xm[t1][a] * th[1]);
-      q[QU + d] = 2.0 * sigma * vn - src_n;
-    }
-    if (g.Tw[face] > 0.0) {  // isothermal; adiabatic keeps rho and T
-      double Tg = 2.0 * g.Tw[face] - q[QT];
-      if (!(Tg > 0.0)) atomicOr(g.flags, 1u);
-      q[QT] = Tg;
-      q[QR] = q[QP] / (g.R * Tg);
-    }
-  }
-  g.Q[QR][b] = q[QR];
-  g.Q[QU][b] = q[QU];
-  if (nd >= 2) g.Q[QV][b] = q[QV];
-  if (nd >= 3) g.Q[QW][b] = q[QW];
-  g.Q[QP][b] = q[QP];
-  if (g.visc != VISC_NONE) {
-    g.Q[QT][b] = q[QT];
-    g.Q[QMU][b] = viscosity(g, q[QT]);
-  }
-}
+};
 
-__global__ void __launch_bounds__(256) k_prim_halo(Dev g, const double *U) {
-  prim_halo_body(g, U, blockIdx.x * blockDim.x + threadIdx.x);
-}
-
-// Interior cells: primitives of their own conserved state (x-fastest,
-// coalesced).
-__device__ __forceinline__ void prim_interior_body(const Dev &g, const double *U, unsigned t) {
-  if (t >= (unsigned)g.ncell) return;
+// Ghost cell p (box index b) through the halo-fill chain: follow the source
+// cells back to the interior (or to a Dirichlet profile), then apply the
+// per-axis ghost transforms in x, y, z order; mu is recomputed unless the
+// source's is still valid (copied and no transform changed T).
+template <class Src>
+__device__ __forceinline__ void ghost_chain(const Dev &g, const int *p, long b, const Src &src) {
   const int nd = g.ndim;
-  const unsigned n0 = g.n[0], n01 = n0 * (unsigned)g.n[1];
-  const int k = (int)(t / n01), j = (int)((t % n01) / n0), i = (int)(t % n0);
-  const long b = bidx(g, i, j, k);
-  double q[6];
-  cons_to_prim(g, U, (long)t, q);
-  if (!(finite_pos(q[QR]) && finite_pos(q[QP]))) atomicOr(g.flags, 1u);
-  g.Q[QR][b] = q[QR];
-  g.Q[QU][b] = q[QU];
-  if (nd >= 2) g.Q[QV][b] = q[QV];
-  if (nd >= 3) g.Q[QW][b] = q[QW];
-  g.Q[QP][b] = q[QP];
-  if (g.visc != VISC_NONE) {
-    g.Q[QT][b] = q[QT];
-    g.Q[QMU][b] = viscosity(g, q[QT]);
-  }
-}
-
-// Ghost cell number t (after k_prim_interior): follow the chain of sources
-// back to an interior cell (or a Dirichlet profile), copy its primitives from
-// the box and apply the per-axis ghost transforms in x, y, z order; mu is
-// recomputed only where a transform changed T.
-__device__ __forceinline__ void prim_ghost_body(const Dev &g, unsigned t) {
-  if (t >= (unsigned)(g.nbox - g.ncell)) return;
-  const int nd = g.ndim;
-  int p[3];
-  ghost_position(g, t, p);
-  const long b = bidx(g, p[0], p[1], p[2]);
   int s[3] = {p[0], p[1], p[2]};
   int side[3] = {0, 0, 0};
   bool gh[3] = {false, false, false};
@@ -315,19 +199,7 @@ __device__ __forceinline__ void prim_ghost_body(const Dev &g, unsigned t) {
     mu = -1.0;  // recomputed below
     start = top + 1;
   } else {
-    // the source is an interior cell, converted by k_prim_interior
-    const long sb = bidx(g, s[0], s[1], s[2]);
-    q[QR] = g.Q[QR][sb];
-    q[QU] = g.Q[QU][sb];
-    q[QV] = nd >= 2 ? g.Q[QV][sb] : 0.0;
-    q[QW] = nd >= 3 ? g.Q[QW][sb] : 0.0;
-    q[QP] = g.Q[QP][sb];
-    if (g.visc != VISC_NONE) {
-      q[QT] = g.Q[QT][sb];
-      mu = g.Q[QMU][sb];
-    } else {
-      q[QT] = q[QP] / (q[QR] * g.R);
-    }
+    src.load(g, s, q, mu);  // the interior source cell
   }
   for (int d = start; d < nd; ++d) {
     if (!gh[d]) continue;
@@ -350,7 +222,7 @@ __device__ __forceinline__ void prim_ghost_body(const Dev &g, unsigned t) {
         w[d] = side[d] == 0 ? 0 : g.n[d] - 1;
         w[t1] = a;
         w[t2] = bb;
-        const double pw = g.Q[QP][bidx(g, w[0], w[1], w[2])];
+        const double pw = src.pressure(g, w);
         int kk = bb * (g.pe - g.pb) + (a - g.pb);
         double vn = -g.K[kk] * (pw - g.pinf) / g.pinf;
         q[QU + d] = 2.0 * sigma * vn - src_n;
@@ -380,6 +252,61 @@ __device__ __forceinline__ void prim_ghost_body(const Dev &g, unsigned t) {
     g.Q[QT][b] = q[QT];
     g.Q[QMU][b] = mu >= 0.0 ? mu : viscosity(g, q[QT]);
   }
+}
+
+// Interior cells: primitives of their own conserved state (x-fastest,
+// coalesced).
+__device__ __forceinline__ void prim_interior_body(const Dev &g, const double *U, unsigned t) {
+  if (t >= (unsigned)g.ncell) return;
+  const int nd = g.ndim;
+  const unsigned n0 = g.n[0], n01 = n0 * (unsigned)g.n[1];
+  const int k = (int)(t / n01), j = (int)((t % n01) / n0), i = (int)(t % n0);
+  const long b = bidx(g, i, j, k);
+  double q[6];
+  cons_to_prim(g, U, (long)t, q);
+  if (!(finite_pos(q[QR]) && finite_pos(q[QP]))) atomicOr(g.flags, 1u);
+  g.Q[QR][b] = q[QR];
+  g.Q[QU][b] = q[QU];
+  if (nd >= 2) g.Q[QV][b] = q[QV];
+  if (nd >= 3) g.Q[QW][b] = q[QW];
+  g.Q[QP][b] = q[QP];
+  if (g.visc != VISC_NONE) {
+    g.Q[QT][b] = q[QT];
+    g.Q[QMU][b] = viscosity(g, q[QT]);
+  }
+}
+
+// Single-launch form (used when ghost cells are a small share of the box):
+// threads [0, ncell) convert interior cells (x-fastest, coalesced, one
+// branch for the whole wave); threads [ncell, nbox) fill the ghost cells,
+// converting their source cell's state themselves.
+__device__ __forceinline__ void prim_halo_body(const Dev &g, const double *U, unsigned t) {
+  if (t >= (unsigned)g.nbox) return;
+  if (t < (unsigned)g.ncell) {
+    prim_interior_body(g, U, t);
+    return;
+  }
+  int p[3];
+  ghost_position(g, t - (unsigned)g.ncell, p);
+  ghost_chain(g, p, bidx(g, p[0], p[1], p[2]), FromState{U});
+}
+
+__global__ void __launch_bounds__(256) k_prim_halo(Dev g, const double *U) {
+  prim_halo_body(g, U, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+
+// Ghost cell number t (after k_prim_interior): follow the chain of sources
+// back to an interior cell (or a Dirichlet profile), copy its primitives from
+// the box and apply the per-axis ghost transforms in x, y, z order; mu is
+// recomputed only where a transform changed T.
+
+// Ghost cell number t, after k_prim_interior has filled the interior.
+__device__ __forceinline__ void prim_ghost_body(const Dev &g, unsigned t) {
+  if (t >= (unsigned)(g.nbox - g.ncell)) return;
+  int p[3];
+  ghost_position(g, t, p);
+  ghost_chain(g, p, bidx(g, p[0], p[1], p[2]), FromBox{});
 }
 
 // Two-launch form (many ghost cells): interior cells, then the ghost cells
@@ -606,17 +533,22 @@ __global__ void __launch_bounds__(256) k_flux_x(Dev g, int nwmax) {
 // y / z faces: 16 (x) x 16 (faces along D) tiles; the tile's 21 cells along D
 // by 16 along x are staged in LDS per primitive / derivative.
 // ---------------------------------------------------------------------------
-template <int NDIM, int D, bool VISC>
-__device__ __forceinline__ void flux_yz_body(const Dev &g, unsigned lin, unsigned ntot,
-                                             unsigned nbx, unsigned nby) {
+template <int NDIM, bool VISC> struct YzTile {
+  static constexpr int TX = 16, TD = 16, TR = TD + 5;
   using S = Slots<NDIM, VISC>;
-  constexpr int TX = 16, TD = 16, TR = TD + 5;
-  __shared__ double lds[S::NC][TR][TX];
+  double lds[S::NC][TR][TX];
+};
+
+// Stages the tile's stencil cells (rows f0 - 3 .. f0 + 17 along D, x from
+// i0, remaining axis at oc) and computes the flux of face f0 + ty at x
+// i0 + tx into G; returns false for a thread outside the grid.
+template <int NDIM, int D, bool VISC>
+__device__ __forceinline__ bool yz_tile_face(const Dev &g, YzTile<NDIM, VISC> &T, int i0, int f0,
+                                             int oc, double *G) {
+  using Tl = YzTile<NDIM, VISC>;
+  using S = typename Tl::S;
+  constexpr int TX = Tl::TX, TR = Tl::TR;
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  // tiles along D are consecutive in the remapped order (they share 5 rows)
-  const unsigned lg = xcd_remap(lin, ntot);
-  const unsigned by = lg % nby, rest = lg / nby;
-  const int i0 = (int)(rest % nbx) * TX, f0 = (int)by * TD, oc = (int)(rest / nbx);
   const int nD = g.n[D];
   // oc is the remaining axis' index: z for D = 1, y for D = 2
   for (int idx = threadIdx.x; idx < TR * TX; idx += 256) {
@@ -631,20 +563,33 @@ __device__ __forceinline__ void flux_yz_body(const Dev &g, unsigned lin, unsigne
 #pragma unroll
     for (int sl = 0; sl < S::NC; ++sl) {
       if ((sl == QV && NDIM < 2) || (sl == QW && NDIM < 3)) continue;
-      lds[sl][a][x] = slot_array<NDIM, D, VISC>(g, sl)[bx];
+      T.lds[sl][a][x] = slot_array<NDIM, D, VISC>(g, sl)[bx];
     }
   }
   __syncthreads();
   const int i = i0 + tx, f = f0 + ty;
-  if (i >= g.n[0] || f > nD) return;
-  auto P = [&](int q, int o) { return lds[slot_of(q)][ty + 3 + o][tx]; };
-  auto Gv = [&](int kk, int o) { return lds[S::NP + kk][ty + 3 + o][tx]; };
-  double G[5];
+  if (i >= g.n[0] || f > nD) return false;
+  auto P = [&](int q, int o) { return T.lds[slot_of(q)][ty + 3 + o][tx]; };
+  auto Gv = [&](int kk, int o) { return T.lds[S::NP + kk][ty + 3 + o][tx]; };
   face_flux<NDIM, D, VISC>(g, P, Gv, f, G);
   if (!(fabs(G[0]) + fabs(G[4]) < 1.0e300)) atomicOr(g.flags, 1u);  // non-finite flux
+  return true;
+}
+
+template <int NDIM, int D, bool VISC>
+__device__ __forceinline__ void flux_yz_body(const Dev &g, unsigned lin, unsigned ntot,
+                                             unsigned nbx, unsigned nby) {
+  __shared__ YzTile<NDIM, VISC> T;
+  // tiles along D are consecutive in the remapped order (they share 5 rows)
+  const unsigned lg = xcd_remap(lin, ntot);
+  const unsigned by = lg % nby, rest = lg / nby;
+  const int i0 = (int)(rest % nbx) * YzTile<NDIM, VISC>::TX, oc = (int)(rest / nbx);
+  const int f0 = (int)by * YzTile<NDIM, VISC>::TD;
+  double G[5];
+  if (!yz_tile_face<NDIM, D, VISC>(g, T, i0, f0, oc, G)) return;
   int p[3];
-  p[0] = i;
-  p[D] = f;
+  p[0] = i0 + (int)(threadIdx.x % 16);
+  p[D] = f0 + (int)(threadIdx.x / 16);
   p[3 - D] = oc;
   const long t = ((long)p[2] * g.fn[D][1] + p[1]) * g.fn[D][0] + p[0];
   double *F = g.F[D];
@@ -788,18 +733,11 @@ __device__ __forceinline__ double cell_sigma(const Dev &g, const double *q, cons
 // TVD-RK3 stage: Uout = a*Un + b*(Uin + dt*R).  With Rout != nullptr the
 // kernel writes R instead (rhs evaluation).
 // ---------------------------------------------------------------------------
-// One cell's divergence + source + stage update (no barrier inside).
-// Returns the cell's new state's signal rate when `want_sigma`.
-__device__ __forceinline__ double update_cell(const Dev &g, const double *Un, const double *Uin,
-                                              double *Uout, double *Rout, const double *dtp,
-                                              double a, double bcoef, const double *force,
-                                              unsigned cu, bool want_sigma) {
-  const long c = cu;
-  const unsigned n0 = g.n[0], n01 = n0 * (unsigned)g.n[1];
-  const int k = (int)(cu / n01), j = (int)((cu % n01) / n0), i = (int)(cu % n0);
-  const int nd = g.ndim;
-  double R[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int D = 0; D < nd; ++D) {
+// R_m -= (F_D(c+1/2) - F_D(c-1/2)) / dx_D for the directions D < upto,
+// fluxes read from the face arrays (Eq. (6), the divergence).
+__device__ __forceinline__ void flux_divergence(const Dev &g, int i, int j, int k, int upto,
+                                                double *R) {
+  for (int D = 0; D < upto; ++D) {
     long fl = face_index(g, D, i, j, k);
     long fr = fl + (D == 0 ? 1 : (D == 1 ? g.fn[1][0] : (long)g.fn[2][0] * g.fn[2][1]));
     int pos = D == 0 ? i : (D == 1 ? j : k);
@@ -809,6 +747,16 @@ __device__ __forceinline__ double update_cell(const Dev &g, const double *Un, co
 #pragma unroll
     for (int m = 0; m < 5; ++m) R[m] -= (F[m * fc + fr] - F[m * fc + fl]) * id;
   }
+}
+
+// Source, then Uout = a Un + b (Uin + dt R) for cell c at (i, j, k) (or R
+// itself into Rout); returns the new state's signal rate when want_sigma.
+__device__ __forceinline__ double stage_apply(const Dev &g, const double *Un, const double *Uin,
+                                              double *Uout, double *Rout, const double *dtp,
+                                              double a, double bcoef, const double *force,
+                                              long c, int i, int j, int k, double *R,
+                                              bool want_sigma) {
+  const int nd = g.ndim;
   if (g.source == SRC_MASSFLUX) {
     double f = force[0];
     long b = bidx(g, i, j, k);
@@ -843,6 +791,19 @@ __device__ __forceinline__ double update_cell(const Dev &g, const double *Un, co
   return cell_sigma(g, q, pos);
 }
 
+// One cell's divergence + source + stage update (no barrier inside).
+__device__ __forceinline__ double update_cell(const Dev &g, const double *Un, const double *Uin,
+                                              double *Uout, double *Rout, const double *dtp,
+                                              double a, double bcoef, const double *force,
+                                              unsigned cu, bool want_sigma) {
+  const unsigned n0 = g.n[0], n01 = n0 * (unsigned)g.n[1];
+  const int k = (int)(cu / n01), j = (int)((cu % n01) / n0), i = (int)(cu % n0);
+  double R[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  flux_divergence(g, i, j, k, g.ndim, R);
+  return stage_apply(g, Un, Uin, Uout, Rout, dtp, a, bcoef, force, (long)cu, i, j, k, R,
+                     want_sigma);
+}
+
 // With dtpart (uniform over the launch) every thread of the block reaches
 // the block reduction of the new state's signal rates (the CFL step of the
 // next step); the barrier sits outside any branch on the thread's cell.
@@ -866,6 +827,69 @@ __global__ void __launch_bounds__(256) k_update(Dev g, const double *Un, const d
                                                 double *dtpart) {
   update_body(g, Un, Uin, Uout, Rout, dtp, a, bcoef, force, blockIdx.x * blockDim.x + threadIdx.x,
               dtpart);
+}
+
+// ---------------------------------------------------------------------------
+// Faces of the last direction fused with the stage update (no source term):
+// 16 x 16 face tiles advance by 15 cells along D, so the 15 cells between a
+// tile's faces get their whole divergence, the last direction's fluxes from
+// LDS and the other directions' from the face arrays.  The face values and
+// the order of the sums are those of k_flux_yz + k_update.
+// ---------------------------------------------------------------------------
+template <int NDIM, int D, bool VISC>
+__device__ __forceinline__ void flux_update_body(const Dev &g, unsigned lin, unsigned ntot,
+                                                 unsigned nbx, unsigned nby, const double *Un,
+                                                 const double *Uin, double *Uout,
+                                                 const double *dtp, double a, double bcoef,
+                                                 double *dtpart, unsigned bid) {
+  using Tl = YzTile<NDIM, VISC>;
+  __shared__ Tl T;
+  const unsigned lg = xcd_remap(lin, ntot);
+  const unsigned by = lg % nby, rest = lg / nby;
+  const int i0 = (int)(rest % nbx) * Tl::TX, oc = (int)(rest / nbx);
+  const int f0 = (int)by * (Tl::TD - 1);
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double G[5];
+  const bool valid = yz_tile_face<NDIM, D, VISC>(g, T, i0, f0, oc, G);
+  __syncthreads();  // the staged stencil is no longer read: reuse it for the faces
+  double(*fl)[16][16] = reinterpret_cast<double(*)[16][16]>(&T.lds[0][0][0]);
+  if (valid)
+#pragma unroll
+    for (int m = 0; m < 5; ++m) fl[m][ty][tx] = G[m];
+  __syncthreads();
+  double sig = 0.0;
+  const int i = i0 + tx, cD = f0 + ty;
+  if (ty < Tl::TD - 1 && i < g.n[0] && cD < g.n[D]) {
+    int p[3];
+    p[0] = i;
+    p[D] = cD;
+    p[3 - D] = oc;
+    if (NDIM == 2) p[2] = 0;
+    double R[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    flux_divergence(g, p[0], p[1], p[2], D, R);
+    const double id = g.idx[D][cD];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) R[m] -= (fl[m][ty + 1][tx] - fl[m][ty][tx]) * id;
+    const long c = ((long)p[2] * g.n[1] + p[1]) * g.n[0] + p[0];
+    sig = stage_apply(g, Un, Uin, Uout, nullptr, dtp, a, bcoef, nullptr, c, p[0], p[1], p[2], R,
+                      dtpart != nullptr);
+  }
+  if (dtpart) {
+    __shared__ double shx[256];
+    const double m = block_max(sig, shx);
+    if (threadIdx.x == 0) dtpart[bid] = m;
+  }
+}
+
+template <int NDIM, bool VISC>
+__global__ void __launch_bounds__(256) k_flux_update(Dev g, const double *Un, const double *Uin,
+                                                     double *Uout, const double *dtp, double a,
+                                                     double bcoef, double *dtpart) {
+  constexpr int D = NDIM - 1;
+  const unsigned nbx = gridDim.x, nby = gridDim.y;
+  const unsigned lin = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
+  flux_update_body<NDIM, D, VISC>(g, lin, nbx * nby * gridDim.z, nbx, nby, Un, Uin, Uout, dtp,
+                                  a, bcoef, dtpart, lin);
 }
 
 // ---------------------------------------------------------------------------
@@ -1031,6 +1055,13 @@ __global__ void k_fill(double *p, double v, long n) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     p[i] = v;
 }
+// 16-byte stores for a 16-byte aligned array (the last element separately).
+__global__ void k_fill2(double2 *p, double v, long n2, double *tail) {
+  const double2 vv = make_double2(v, v);
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (long)gridDim.x * blockDim.x)
+    p[i] = vv;
+  if (tail && blockIdx.x == 0 && threadIdx.x == 0) *tail = v;
+}
 __global__ void k_copy(double *dst, const double *src, long n) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     dst[i] = src[i];
@@ -1052,7 +1083,11 @@ static inline unsigned grid_capped(long n, int cap) {
 
 hipError_t launch_fill(double *p, double v, long n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  k_fill<<<grid_capped(n, 4096), 256, 0, st>>>(p, v, n);
+  if ((((uintptr_t)p) & 15) == 0 && n >= 2)
+    k_fill2<<<grid_capped(n / 2, 4096), 256, 0, st>>>((double2 *)p, v, n / 2,
+                                                       (n & 1) ? p + n - 1 : nullptr);
+  else
+    k_fill<<<grid_capped(n, 4096), 256, 0, st>>>(p, v, n);
   return hipGetLastError();
 }
 hipError_t launch_copy(double *dst, const double *src, long n, hipStream_t st) {
@@ -1117,6 +1152,39 @@ hipError_t launch_grad(const Dev &g, hipStream_t st) {
   else
     k_grad<3><<<grid, 256, 0, st>>>(g);
   return hipGetLastError();
+}
+
+template <int NDIM, bool VISC>
+static hipError_t launch_fu(const Dev &g, const double *Un, const double *Uin, double *Uout,
+                            const double *dt, double a, double b, double *dtpart,
+                            hipStream_t st) {
+  constexpr int D = NDIM - 1;
+  dim3 grid((g.n[0] + 15) / 16, (g.n[D] + 14) / 15, D == 1 ? g.n[2] : g.n[1]);
+  k_flux_update<NDIM, VISC><<<grid, 256, 0, st>>>(g, Un, Uin, Uout, dt, a, b, dtpart);
+  return hipGetLastError();
+}
+
+unsigned flux_update_blocks(const Dev &g) {
+  if (g.ndim < 2) return 0;
+  const int D = g.ndim - 1;
+  return (unsigned)((g.n[0] + 15) / 16) * (unsigned)((g.n[D] + 14) / 15) *
+         (unsigned)(D == 1 ? g.n[2] : g.n[1]);
+}
+
+hipError_t launch_fluxes_update(const Dev &g, const double *Un, const double *Uin,
+                                double *Uout, const double *dt, double a, double b,
+                                double *dtpart, hipStream_t st) {
+  hipError_t e = launch_grad(g, st);
+  for (int D = 0; D + 1 < g.ndim && e == hipSuccess; ++D) e = launch_flux_dir(g, D, st);
+  if (e != hipSuccess) return e;
+  const bool v = g.visc != VISC_NONE;
+  if (g.ndim == 2)
+    return v ? launch_fu<2, true>(g, Un, Uin, Uout, dt, a, b, dtpart, st)
+             : launch_fu<2, false>(g, Un, Uin, Uout, dt, a, b, dtpart, st);
+  if (g.ndim == 3)
+    return v ? launch_fu<3, true>(g, Un, Uin, Uout, dt, a, b, dtpart, st)
+             : launch_fu<3, false>(g, Un, Uin, Uout, dt, a, b, dtpart, st);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_flux_dir(const Dev &g, int D, hipStream_t st) {

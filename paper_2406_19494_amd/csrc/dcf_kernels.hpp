@@ -43,6 +43,14 @@ hipError_t launch_update(const Dev &g, const double *Un, const double *Uin, doub
                          double *Rout, const double *dt, double a, double b,
                          const double *force, hipStream_t st, double *dtpart = nullptr);
 unsigned update_blocks(const Dev &g);
+// The whole right-hand side and stage update with the last direction's
+// fluxes fused into the update (ndim >= 2, no source term): gradients, the
+// other directions' fluxes, then one kernel for the last direction + update.
+// With dtpart (flux_update_blocks(g) doubles) the CFL partials as above.
+hipError_t launch_fluxes_update(const Dev &g, const double *Un, const double *Uin,
+                                double *Uout, const double *dt, double a, double b,
+                                double *dtpart, hipStream_t st);
+unsigned flux_update_blocks(const Dev &g);
 hipError_t launch_dt_final(const double *part, int nparts, double cfl, double dt_max, double *dt,
                            hipStream_t st);
 hipError_t launch_dt(const Dev &g, const double *U, double cfl, double dt_max, double *part,

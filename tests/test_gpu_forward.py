@@ -200,3 +200,39 @@ def test_fused_cfl_step_equals_separate_dt(which):
     torch.cuda.synchronize()
     assert torch.equal(U1, U2)
     assert torch.equal(dt1, dt2)
+
+
+def test_tgv64_1000_step_history_matches_oracle():
+    # The benchmark configuration itself: TGV 64^3, 1000 TVD-RK3 steps at a
+    # fixed step; kinetic energy and dissipation every 50 steps against the
+    # oracle's history (tests/golden/tgv64_history.txt, written by the
+    # oracle-only script beside it).
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "tgv64_history.txt")
+    rows, dt = [], None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#"):
+                continue
+            parts = line.split()
+            if parts[0] == "dt":
+                dt = float(parts[1])
+            else:
+                rows.append((int(parts[0]), float(parts[2]), float(parts[3])))
+    case, P = W.tgv(64)
+    s = Solver(case)
+    U = s.init_state(P)
+    dtg = torch.full((1,), dt, dtype=torch.float64, device="cuda")
+    worst = 0.0
+    n = 0
+    for step, ek, eps in rows:
+        while n < step:
+            s.step(U, dtg)
+            n += 1
+        d = s.diagnostics(U)
+        e1 = abs(d["ek"] - ek) / abs(ek)
+        e2 = abs(d["eps"] - eps) / abs(eps)
+        worst = max(worst, e1, e2)
+        assert e1 < 1e-8 and e2 < 1e-8, (step, d["ek"], ek, d["eps"], eps)
+    print(f"[tgv64 history] 1000 steps, worst relative deviation {worst:.2e}", flush=True)
+    assert s.flags() == 0
