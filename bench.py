@@ -185,33 +185,54 @@ def adjoint_ratio(steps=20):
     torch.cuda.synchronize()
     f = ev[0].elapsed_time(ev[1]) / steps
     a = ev[1].elapsed_time(ev[2]) / steps
-    # whole checkpointed trajectory gradient (forward sweep with checkpoints,
-    # per-segment recompute with cached stage states, reverse sweep) against
-    # the plain forward trajectory of the same length
+    # whole checkpointed trajectory gradient (forward sweep with checkpoints
+    # and cost, per-segment recompute, reverse sweep), each phase timed with
+    # HIP events between the dcf_gradient_advance calls that run it
     n, seg = 100, 10
     U0 = s.init_state(P)
     traj = {}
     for mode in (2, 3):
         sg = Solver(case, K=K, mode=mode, nsteps=n, seg_len=seg)
-        sg.gradient(U0, dt)
+        sg.gradient(U0, dt)  # warm-up
+        J = torch.zeros(1, dtype=torch.float64, device="cuda")
+        gKt = torch.zeros(sg.nk, dtype=torch.float64, device="cuda")
+        nseg = (n + seg - 1) // seg
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 + 2 * nseg)]
         torch.cuda.synchronize()
-        ev[2].record(stream)
-        sg.gradient(U0, dt)
-        ev[3].record(stream)
+        sg.gradient_begin(U0, dt, J, gKt)
+        evs[0].record(stream)
+        sg.gradient_advance(n)
+        evs[1].record(stream)
+        for k in range(nseg):
+            units = min(seg, n - (nseg - 1 - k) * seg)
+            sg.gradient_advance(units)  # recompute of the segment
+            evs[2 + 2 * k].record(stream)
+            sg.gradient_advance(units)  # reverse steps of the segment
+            evs[3 + 2 * k].record(stream)
+        done = sg.gradient_advance(1)
         torch.cuda.synchronize()
-        g = ev[2].elapsed_time(ev[3])
+        assert done, "gradient did not complete in the expected number of units"
+        sg.gradient_finish()
+        fwd = evs[0].elapsed_time(evs[1])
+        rec = sum(evs[1 + 2 * k].elapsed_time(evs[2 + 2 * k]) for k in range(nseg))
+        rev = sum(evs[2 + 2 * k].elapsed_time(evs[3 + 2 * k]) for k in range(nseg))
+        g = evs[0].elapsed_time(evs[-1])
         traj[f"mode{mode}"] = {"steps": n, "seg_len": seg, "gradient_ms": g,
+                               "forward_sweep_ms": fwd, "recompute_ms": rec, "reverse_ms": rev,
                                "gradient_over_forward": g / (n * f),
-                               "reverse_over_forward": (g - 2 * n * f) / (n * f)}
+                               "reverse_step_over_forward": rev / (n * f)}
         del sg
     return {"workload": "Mach-6 porous boundary layer 1024x256", "forward_ms_per_step": f,
-            "vjp_ms_per_step": a, "adjoint_forward_ratio": a / f,
-            "vjp_step_note": "dcf_vjp_step recomputes the two inner stage states of its step",
+            "vjp_ms_per_step": a, "vjp_step_over_forward": a / f,
+            "adjoint_forward_ratio": traj["mode3"]["reverse_step_over_forward"],
+            "vjp_step_note": "dcf_vjp_step alone recomputes the two inner stage states and "
+                             "every stage's primitive and derivative boxes of its step",
             "trajectory": traj,
-            "trajectory_note": "mode2 recomputes each stage's boxes in the reverse sweep, "
-                               "mode3 keeps them from the segment recompute; "
-                               "reverse_over_forward = (gradient - forward sweep - recompute "
-                               "sweep) / forward"}
+            "trajectory_note": "reverse_step_over_forward: reverse sweep (one VJP of the RK3 "
+                               "step per step, cost adjoint included) over the forward "
+                               "rk3_step, per step; mode2 recomputes each stage's boxes in "
+                               "the reverse sweep, mode3 keeps them from the segment "
+                               "recompute; adjoint_forward_ratio is mode3's"}
 
 
 def main():
@@ -276,60 +297,58 @@ def main():
     ms_step = ms / args.steps
     value = case.ncells * 3 / (ms_step * 1e-3)
 
-    # per-kernel timing (HIP events on the same stream) -> dominant kernel
+    # per-kernel timing (HIP events on the same stream) -> dominant kernel.
+    # A 2D/3D step without source term runs the last direction's fluxes
+    # fused with the stage update (k_flux_update); the unfused pair is timed
+    # too, for the record.
     names = {0: "k_prim_halo", 1: "k_flux_x", 2: "k_flux_yz<y>", 3: "k_flux_yz<z>", 4: "k_update",
-             5: "k_grad"}
-    kt = {}
-    kinds = [0] + list(range(1, case.ndim + 1)) + [4]
-    if case.visc_law != "none" and case.ndim >= 2:
-        kinds.append(5)
-    for w in kinds:
-        kt[w] = s.time_kernel(U, w, reps=20)
-    # dominant kernel: the flux family (one launch per direction) when it
-    # takes the largest share of a stage, reported through its slowest
-    # launch; otherwise the single slowest kernel
+             5: "k_grad", 6: "k_flux_update"}
     visc = case.visc_law != "none"
-    flux_ms = sum(kt[w] for w in range(1, case.ndim + 1))
-    others = {w: v for w, v in kt.items() if not 1 <= w <= case.ndim}
-    if flux_ms >= max(others.values()):
-        dom = max(range(1, case.ndim + 1), key=lambda w: kt[w])
-    else:
-        dom = max(others, key=lambda w: others[w])
-    if 1 <= dom <= 3:
-        D = dom - 1
-        faces = 1
+    fused = case.ndim >= 2 and case.source == "none"
+    step_kinds = [0] + ([5] if visc and case.ndim >= 2 else [])
+    step_kinds += list(range(1, case.ndim)) + [6] if fused else list(range(1, case.ndim + 1)) + [4]
+    kinds = sorted(set(step_kinds) | {case.ndim, 4})
+    kt = {w: s.time_kernel(U, w, reps=20) for w in kinds}
+
+    def faces_of(D):
+        f = 1
         for e in range(3):
-            faces *= case.n[e] + (1 if e == D else 0)
-        flops = FLOPS_PER_FACE[(case.ndim, visc)] * faces
-        achieved = flops / (kt[dom] * 1e-3)
-        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
-                "traffic": measured_traffic(names[dom], args.workload),
-                "kernel": names[dom], "avg_ms": kt[dom],
-                "algorithmic_flops_per_face": FLOPS_PER_FACE[(case.ndim, visc)],
-                "faces_per_launch": faces}
-    else:
-        nbytes = algorithmic_bytes(case, names[dom])
-        achieved = nbytes / (kt[dom] * 1e-3)
-        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
-                "unit": "GB/s", "frac": achieved / PEAK_HBM,
-                "traffic": measured_traffic(names[dom], args.workload),
-                "kernel": names[dom], "avg_ms": kt[dom], "algorithmic_bytes": nbytes}
+            f *= case.n[e] + (1 if e == D else 0)
+        return f
+
+    def flux_dir(w):  # direction whose faces kernel w computes, or None
+        return w - 1 if 1 <= w <= 3 else (case.ndim - 1 if w == 6 else None)
+
+    def kernel_roof(w):
+        # flux kernels (and the fused one, counted by its flux work alone)
+        # against the FP64 vector peak, the others against HBM bandwidth
+        D = flux_dir(w)
+        if D is not None:
+            flops = FLOPS_PER_FACE[(case.ndim, visc)] * faces_of(D)
+            a = flops / (kt[w] * 1e-3)
+            return {"bound": "alu", "achieved": a / 1e12, "peak": PEAK_FP64 / 1e12,
+                    "unit": "TFLOP/s", "frac": a / PEAK_FP64,
+                    "algorithmic_flops_per_face": FLOPS_PER_FACE[(case.ndim, visc)],
+                    "faces_per_launch": faces_of(D)}
+        nbytes = algorithmic_bytes(case, names[w])
+        a = nbytes / (kt[w] * 1e-3)
+        return {"bound": "hbm", "achieved": a / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": a / PEAK_HBM, "algorithmic_bytes": nbytes}
+
+    # dominant kernel: the step's slowest launch
+    dom = max(step_kinds, key=lambda w: kt[w])
+    roof = kernel_roof(dom)
+    roof = {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac")} | {
+        "traffic": measured_traffic(names[dom], args.workload), "kernel": names[dom],
+        "avg_ms": kt[dom]} | {k: v for k, v in roof.items()
+                              if k not in ("bound", "achieved", "peak", "unit", "frac")}
     # every kernel against its own roofline, for the record
     per_kernel = {}
-    for w, v in kt.items():
-        if 1 <= w <= 3:
-            D = w - 1
-            faces = 1
-            for e in range(3):
-                faces *= case.n[e] + (1 if e == D else 0)
-            a = FLOPS_PER_FACE[(case.ndim, visc)] * faces / (v * 1e-3)
-            per_kernel[names[w]] = {"bound": "alu", "frac": a / PEAK_FP64,
-                                    "achieved_tflops": a / 1e12}
-        else:
-            a = algorithmic_bytes(case, names[w]) / (v * 1e-3)
-            per_kernel[names[w]] = {"bound": "hbm", "frac": a / PEAK_HBM,
-                                    "achieved_gbs": a / 1e9}
+    for w in kinds:
+        r = kernel_roof(w)
+        per_kernel[names[w]] = {"bound": r["bound"], "frac": r["frac"],
+                                ("achieved_tflops" if r["bound"] == "alu" else "achieved_gbs"):
+                                    r["achieved"], "in_step": w in step_kinds}
     roof["per_kernel"] = per_kernel
 
     out = {
@@ -349,6 +368,7 @@ def main():
                    "step": "CFL dt + TVD-RK3 (WENO5-JS, HLLC, 4th-order viscous)"},
         "roofline": roof,
         "kernel_ms": {names[k]: v for k, v in kt.items()},
+        "step_kernels": [names[k] for k in step_kinds],
         "source_sha": source_digest(),
         "wall_s": wall,
     }

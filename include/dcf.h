@@ -124,7 +124,9 @@ dcf_status dcf_state_info(const dcf_ctx *ctx, int *nv, long *ncell, size_t *stat
  * from the forward recompute, so the reverse sweep recomputes nothing
  * (3 seg_len more boxes of memory; bitwise the same gradient).
  * nsteps/seg_len are ignored below mode 2.  The library keeps the pointer
- * until the next call. */
+ * until the next call, clears the parts that must start at zero (the call
+ * returns once that is done) and owns the contents from then on: the caller
+ * must not write into the workspace. */
 dcf_status dcf_workspace_size(const dcf_ctx *ctx, int mode, int nsteps, int seg_len,
                               size_t *bytes);
 dcf_status dcf_set_workspace(dcf_ctx *ctx, int mode, int nsteps, int seg_len, void *dev,
@@ -232,8 +234,12 @@ dcf_status dcf_gradient(dcf_ctx *ctx, const double *U0_dev, int nsteps, const do
 /* Times `reps` back-to-back launches of one kernel family on `stream` with
  * HIP events and returns the mean duration in milliseconds (synchronises).
  * which: 0 primitive box + halos, 1/2/3 face fluxes along x/y/z, 4 the
- * divergence + RK stage update.  The inputs it needs (primitive box, face
- * fluxes) are computed from U once before timing. */
+ * divergence + RK stage update, 5 the cell-centred velocity derivatives,
+ * 6 the last direction's fluxes fused with the divergence and stage update
+ * (2D/3D without source term; the kernel dcf_rk3_step runs in place of 3 or
+ * 2 and 4).  The inputs it needs (primitive box, derivatives, face fluxes)
+ * are computed from U once before timing.  DCF_EINVAL for an unknown `which`
+ * or one the case does not have. */
 dcf_status dcf_time_kernel(dcf_ctx *ctx, const double *U_dev, int which, int reps,
                            double *avg_ms, void *stream);
 

@@ -251,7 +251,11 @@ __device__ __forceinline__ Tile make_tile(const Dev &g) {
   const int ncell_line = g.n[D] + 1 + SPAN;     // cells [OLO, n + OHI]
   const int tiles_d = (ncell_line + CPT - 1) / CPT;
   const long lines = (long)nt1 * nt2;
-  long tile = blockIdx.x;
+  // y/z tiles: the two line groups that share each 128-byte row segment (and
+  // the tiles along D of both, which share halo rows) run on one XCD, with
+  // such chunks dealt round robin so that every XCD gets wall and free-stream
+  // regions alike; x tiles keep the hardware order
+  long tile = D == 0 ? blockIdx.x : xcd_chunk_remap(blockIdx.x, gridDim.x, 2u * tiles_d);
   int td = (int)(tile % tiles_d);
   long lg = tile / tiles_d;  // line group
   Tile t;
@@ -299,8 +303,11 @@ __global__ void __launch_bounds__(256) k_conv_vjp(Dev g, AdjBuffers A) {
   constexpr int NCW = TF + SPAN;  // window cells per line
   constexpr int T1 = tan1(D), T2 = tan2(D);
   constexpr int NC = 5;
+  // y/z tiles: a row stride of 36 doubles puts the 8 lines x 4 faces of a
+  // half-wave on distinct LDS banks
+  constexpr int BF = D == 0 ? TF : TF + 4;
   __shared__ double acc[NC][TW][NCW];
-  __shared__ double buf[NOFF][TW][TF];  // one component's contributions per face
+  __shared__ double buf[NOFF][TW][BF];  // one component's contributions per face
   Tile t = make_tile<OLO, OHI, D>(g);
   for (int i = threadIdx.x; i < NC * TW * NCW; i += 256) (&acc[0][0][0])[i] = 0.0;
 
@@ -383,11 +390,23 @@ __global__ void __launch_bounds__(256) k_conv_vjp(Dev g, AdjBuffers A) {
     p[T1] = (int)(ln % g.n[T1]);
     p[T2] = (int)(ln / g.n[T1]);
     const long b = bidx(g, p[0], p[1], p[2]);
-    A.Qb[QR][b] += acc[0][ll][w];
-    A.Qb[QU + D][b] += acc[1][ll][w];
-    if (T1 < NDIM) A.Qb[QU + T1][b] += acc[2][ll][w];
-    if (T2 < NDIM) A.Qb[QU + T2][b] += acc[3][ll][w];
-    A.Qb[QP][b] += acc[4][ll][w];
+    if (D == 0 || cell < 0 || cell >= g.n[D]) {
+      // first writer of this cell in the stage: set every component the
+      // later kernels accumulate into
+      A.Qb[QR][b] = acc[0][ll][w];
+      A.Qb[QU + D][b] = acc[1][ll][w];
+      if (T1 < NDIM) A.Qb[QU + T1][b] = acc[2][ll][w];
+      if (T2 < NDIM) A.Qb[QU + T2][b] = acc[3][ll][w];
+      A.Qb[QP][b] = acc[4][ll][w];
+      A.Qb[QT][b] = 0.0;
+      if (g.visc != VISC_NONE) A.Qb[QMU][b] = 0.0;
+    } else {
+      A.Qb[QR][b] += acc[0][ll][w];
+      A.Qb[QU + D][b] += acc[1][ll][w];
+      if (T1 < NDIM) A.Qb[QU + T1][b] += acc[2][ll][w];
+      if (T2 < NDIM) A.Qb[QU + T2][b] += acc[3][ll][w];
+      A.Qb[QP][b] += acc[4][ll][w];
+    }
   }
 }
 
@@ -402,11 +421,12 @@ __global__ void __launch_bounds__(256) k_visc_vjp(Dev g, AdjBuffers A) {
   constexpr int OLO = -2, OHI = 1, NOFF = OHI - OLO + 1, SPAN = OHI - OLO;
   constexpr int TF = TileShape<D>::TF, TW = TileShape<D>::TW;
   constexpr int NCW = TF + SPAN;
+  constexpr int AS = D == 0 ? NCW : NCW + 1;  // LDS row stride (36 for y/z tiles)
   constexpr int T1 = tan1(D), T2 = tan2(D);
   constexpr int NC = 9;  // u, v, w, T, mu, G(t1,t1) G(t1,D) G(t2,t2) G(t2,D)
-  __shared__ double acc[NC][TW][NCW];
+  __shared__ double acc[NC][TW][AS];
   Tile t = make_tile<OLO, OHI, D>(g);
-  for (int i = threadIdx.x; i < NC * TW * NCW; i += 256) (&acc[0][0][0])[i] = 0.0;
+  for (int i = threadIdx.x; i < NC * TW * AS; i += 256) (&acc[0][0][0])[i] = 0.0;
   __syncthreads();
 
   const int f = t.f0 + t.lane_face;
@@ -528,13 +548,20 @@ __global__ void __launch_bounds__(256) k_visc_vjp(Dev g, AdjBuffers A) {
     if (NDIM >= 3) A.Qb[QW][b] += acc[2][ll][w];
     A.Qb[QT][b] += acc[3][ll][w];
     A.Qb[QMU][b] += acc[4][ll][w];
+    // derivative adjoints: d u_D / d x_t is this kernel's alone (set); the
+    // diagonal d u_t / d x_t is shared with the kernel of every earlier
+    // direction other than t, which covered the cells interior along D
+    const bool ghost = cell < 0 || cell >= g.n[D];
+    constexpr bool sh1 = D >= 2 || (D == 1 && T1 != 0), sh2 = D >= 2 || (D == 1 && T2 != 0);
     if (T1 < NDIM) {
-      A.Gb[3 * T1 + T1][b] += acc[5][ll][w];
-      A.Gb[3 * T1 + D][b] += acc[6][ll][w];
+      double &d1 = A.Gb[3 * T1 + T1][b];
+      d1 = (sh1 && !ghost ? d1 : 0.0) + acc[5][ll][w];
+      A.Gb[3 * T1 + D][b] = acc[6][ll][w];
     }
     if (T2 < NDIM) {
-      A.Gb[3 * T2 + T2][b] += acc[7][ll][w];
-      A.Gb[3 * T2 + D][b] += acc[8][ll][w];
+      double &d2 = A.Gb[3 * T2 + T2][b];
+      d2 = (sh2 && !ghost ? d2 : 0.0) + acc[7][ll][w];
+      A.Gb[3 * T2 + D][b] = acc[8][ll][w];
     }
   }
 }
@@ -619,10 +646,23 @@ __global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, do
   constexpr int qs[6] = {QR, QU, NDIM >= 2 ? QV : QP, NDIM == 3 ? QW : (NDIM == 2 ? QP : QT),
                          NDIM == 3 ? QP : QT, QT};
   const int n = g.n[d];
+  // ghost cells of this column that are ghosts along another axis too (edges
+  // and corners of the box) are written only by the tangential-derivative
+  // adjoint and by the transposes of later axes: this kernel, their last
+  // reader, clears them for the next stage.  Every other cell the adjoint
+  // reads is set afresh each stage by the flux adjoints.
+  const bool edge = a < 0 || a >= g.n[t1] || bq < 0 || bq >= g.n[t2];
   for (int side = side_lo; side < side_hi; ++side) {
     const int face = 2 * d + side;
     const int kind = g.bck[face];
-    if (kind == BC_DIRICHLET) continue;
+    if (kind == BC_DIRICHLET) {  // ghost adjoints discarded
+      if (edge)
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+          for (int i = 0; i < nq; ++i) A.Qb[qs[i]][box(side == 0 ? -1 - m : n + m)] = 0.0;
+      continue;
+    }
     const double sigma = side == 0 ? 1.0 : -1.0;
     long G[3], S[3];
     for (int m = 0; m < 3; ++m) {
@@ -633,17 +673,56 @@ __global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, do
       else src = side == 0 ? m : n - 1 - m;
       S[m] = box(src);
     }
-    // all ghost adjoints of the column first (independent loads) ...
-    double gb[3][6];
+    const bool wall = is_wall(kind);
+    const bool iso = wall && g.Tw[face] > 0.0;
+    const bool porous = kind == BC_POROUS && face == g.pface && a >= g.pb && a < g.pe &&
+                        bq >= 0 && bq < g.n[t2];
+    const bool disturb = kind == BC_DISTURB && dJdK && a >= 0 && a < g.n[t1];
+    const bool merged = kind == BC_ZEROGRAD;  // every layer copies one cell
+    const bool distinct = !merged && n >= 3;  // three distinct sources
+    // every load of the column first (one round trip): ghost adjoints,
+    // source adjoints, ghost states (isothermal wall), wall pressure and
+    // coefficient (porous), position and parameters (disturbance)
+    double gb[3][6], sv[3][6] = {}, rg[3] = {}, pg[3] = {};
 #pragma unroll
     for (int m = 0; m < 3; ++m)
 #pragma unroll
       for (int i = 0; i < nq; ++i) gb[m][i] = A.Qb[qs[i]][G[m]];
-    // ... mapped to contributions to their sources: copies pass through;
-    // walls: p_g = p_s, u_g = -u_s (plus a prescribed normal part that
-    // depends on the state only through the porous p_w below); isothermal:
-    // rho_g = p_g/(R T_g), T_g = 2 T_w - T_s; adiabatic: rho_g = rho_s,
-    // T_g = T_s
+    if (merged) {
+#pragma unroll
+      for (int i = 0; i < nq; ++i) sv[0][i] = A.Qb[qs[i]][S[0]];
+    } else if (distinct) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int i = 0; i < nq; ++i) sv[m][i] = A.Qb[qs[i]][S[m]];
+    }
+    if (iso) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        rg[m] = g.Q[QR][G[m]];
+        pg[m] = g.Q[QP][G[m]];
+      }
+    }
+    int kk = 0;
+    double pw = 0.0, Kk = 0.0, kb0 = 0.0;
+    if (porous) {
+      kk = bq * (g.pe - g.pb) + (a - g.pb);
+      pw = g.Q[QP][S[0]];
+      Kk = g.K[kk];
+      if (dJdK) kb0 = dJdK[kk];
+    }
+    double xd = 0.0, th0 = 0.0, th1 = 0.0;
+    if (disturb) {
+      xd = g.xm[t1][a];
+      th0 = g.K[g.doff[face]];
+      th1 = g.K[g.doff[face] + 1];
+    }
+    // ghost adjoints mapped to contributions to their sources: copies pass
+    // through; walls: p_g = p_s, u_g = -u_s (plus a prescribed normal part
+    // that depends on the state only through the porous p_w below);
+    // isothermal: rho_g = p_g/(R T_g), T_g = 2 T_w - T_s; adiabatic:
+    // rho_g = rho_s, T_g = T_s
     constexpr int iP = nq - 2, iT = nq - 1;
     double cs[3][6];
     double vsum = 0.0;  // sum over the column's ghosts of the normal-velocity adjoint
@@ -656,49 +735,44 @@ __global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, do
         if (c == d) gn[m] = gb[m][1 + c];
 #pragma unroll
       for (int i = 0; i < nq; ++i) cs[m][i] = gb[m][i];
-      if (!is_wall(kind)) continue;
+      if (!wall) continue;
 #pragma unroll
       for (int c = 0; c < nd; ++c) cs[m][1 + c] = -gb[m][1 + c];
-      if (g.Tw[face] > 0.0) {
-        const double rg = g.Q[QR][G[m]], pg = g.Q[QP][G[m]];
+      if (iso) {
         const double rb = gb[m][0];
         cs[m][0] = 0.0;
-        cs[m][iP] = gb[m][iP] + rb * rg / pg;
-        cs[m][iT] = -(gb[m][iT] - rb * rg * rg * g.R / pg);
+        cs[m][iP] = gb[m][iP] + rb * rg[m] / pg[m];
+        cs[m][iT] = -(gb[m][iT] - rb * rg[m] * rg[m] * g.R / pg[m]);
       }
       vsum += gn[m];
     }
-    if (kind == BC_POROUS && face == g.pface && a >= g.pb && a < g.pe && bq >= 0 &&
-        bq < g.n[t2]) {
+    if (porous) {
       // v_g[d] = 2 sigma v_n - v_s[d], v_n = -K (p_w - p_inf)/p_inf; the
       // wall cell W is the source of ghost layer 0
-      const int kk = bq * (g.pe - g.pb) + (a - g.pb);
-      const double pw = g.Q[QP][S[0]];
       double kb = 0.0;
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
         const double vnb = 2.0 * sigma * gn[m];
-        cs[0][iP] += -g.K[kk] / g.pinf * vnb;
+        cs[0][iP] += -Kk / g.pinf * vnb;
         kb += -(pw - g.pinf) / g.pinf * vnb;
       }
-      if (dJdK) dJdK[kk] += kb;
+      if (dJdK) dJdK[kk] = kb0 + kb;
     }
-    // fold into the sources (read all, then write all: distinct sources;
-    // one merged update when every layer copies the same cell)
-    if (kind == BC_ZEROGRAD) {
-#pragma unroll
-      for (int i = 0; i < nq; ++i) A.Qb[qs[i]][S[0]] += (cs[0][i] + cs[1][i]) + cs[2][i];
-    } else if (n >= 3) {
-      double sv[3][6];
+    if (edge)
 #pragma unroll
       for (int m = 0; m < 3; ++m)
 #pragma unroll
-        for (int i = 0; i < nq; ++i) sv[m][i] = A.Qb[qs[i]][S[m]];
+        for (int i = 0; i < nq; ++i) A.Qb[qs[i]][G[m]] = 0.0;
+    // fold into the sources
+    if (merged) {
+#pragma unroll
+      for (int i = 0; i < nq; ++i) A.Qb[qs[i]][S[0]] = sv[0][i] + ((cs[0][i] + cs[1][i]) + cs[2][i]);
+    } else if (distinct) {
 #pragma unroll
       for (int m = 0; m < 3; ++m)
 #pragma unroll
         for (int i = 0; i < nq; ++i) A.Qb[qs[i]][S[m]] = sv[m][i] + cs[m][i];
-    } else {
+    } else {  // n < 3: sources may repeat, accumulate layer by layer
 #pragma unroll
       for (int m = 0; m < 3; ++m)
 #pragma unroll
@@ -708,13 +782,11 @@ __global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, do
       // v_g[d] = 2 sigma A sin(phi) - v_s[d], phi = 2 pi kappa x: per-column
       // partials of dJ/dA and dJ/dkappa, summed over columns by k_disturb_sum
       double dA = 0.0, dk = 0.0;
-      if (a >= 0 && a < g.n[t1]) {
-        const double *th = g.K + g.doff[face];
-        const double x = g.xm[t1][a];
-        const double ph = 2.0 * M_PI * x * th[1];
+      if (disturb) {
+        const double ph = 2.0 * M_PI * xd * th1;
         const double w = 2.0 * sigma * vsum;
         dA = w * sin(ph);
-        dk = w * th[0] * cos(ph) * 2.0 * M_PI * x;
+        dk = w * th0 * cos(ph) * 2.0 * M_PI * xd;
       }
       A.dpart[(2 * side) * A.dcols + col] = dA;
       A.dpart[(2 * side + 1) * A.dcols + col] = dk;
@@ -823,7 +895,9 @@ static inline unsigned blocks(long n) { return (unsigned)((n + 255) / 256 > 0 ? 
   } while (0)
 
 // Reverse of one stage: Vb = b Wb + R'(V)^T (b dt Wb), accumulators as in
-// k_interior_vjp.  Needs g.Q to hold nothing on entry (recomputed here).
+// k_interior_vjp.  Needs g.Q to hold nothing on entry (recomputed here), and
+// the adjoint boxes (Qb, Gb) zero wherever no kernel of a stage writes them
+// (cleared once with the workspace; the kernels keep it so).
 static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A0, const double *V, const double *Wb,
                             const double *dt, double a, double b, double *Vb,
                             const double *acc_in, double *acc_out, int fold, double *dJdK,
@@ -837,7 +911,6 @@ static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A0, const double *V,
     DCF_TRY(launch_prim_halo(g, V, st));
     if (visc && g.ndim >= 2) DCF_TRY(launch_grad(g, st));
   }
-  DCF_TRY(launch_fill(A.zero_begin, 0.0, A.zero_count, st));
   for (int D = 0; D < g.ndim; ++D) {
     hipLaunchKernelGGL(conv_kernel(g.ndim, D), dim3(tile_count<-3, 2>(g, D)), dim3(256), 0, st, g,
                        A);
@@ -883,13 +956,20 @@ hipError_t vjp_step(Dev g, const AdjBuffers &A, const double *Un, double *U1, do
                       true));
     return hipSuccess;
   }
-  if (recompute) {  // the stage states U1, U2 of Un
-    DCF_TRY(launch_prim_halo(g, Un, st));
-    DCF_TRY(launch_fluxes(g, st));
-    DCF_TRY(launch_update(g, Un, Un, U1, nullptr, dt, 0.0, 1.0, nullptr, st));
-    DCF_TRY(launch_prim_halo(g, U1, st));
-    DCF_TRY(launch_fluxes(g, st));
-    DCF_TRY(launch_update(g, Un, U1, U2, nullptr, dt, 0.75, 0.25, nullptr, st));
+  if (recompute) {  // the stage states U1, U2 of Un, as the forward step makes them
+    const bool fused = g.ndim >= 2 && g.source == SRC_NONE;
+    const double *in[2] = {Un, U1};
+    double *out[2] = {U1, U2};
+    const double ca[2] = {0.0, 0.75}, cb[2] = {1.0, 0.25};
+    for (int k = 0; k < 2; ++k) {
+      DCF_TRY(launch_prim_halo(g, in[k], st));
+      if (fused) {
+        DCF_TRY(launch_fluxes_update(g, Un, in[k], out[k], dt, ca[k], cb[k], nullptr, st));
+      } else {
+        DCF_TRY(launch_fluxes(g, st));
+        DCF_TRY(launch_update(g, Un, in[k], out[k], nullptr, dt, ca[k], cb[k], nullptr, st));
+      }
+    }
   }
   // stage 3: W = Un/3 + 2/3 (U2 + dt R(U2))
   DCF_TRY(stage_vjp(g, A, U2, lam1, dt, 1.0 / 3.0, 2.0 / 3.0, A.Ub2, nullptr, A.acc, 0, dJdK, st,

@@ -15,7 +15,8 @@ struct AdjBuffers {
   double bcoef;      // weight b of the stage's V + dt R(V) term
   double *dpart;    // per-column partial sums of dJ/d(A, kappa), 4 per wall column
   long dcols;       // columns per disturbance-face partial array
-  double *zero_begin;  // Qb and Gb are carved back to back: one fill clears both
+  double *zero_begin;  // Qb and Gb are carved back to back: one clear (with the
+                       // workspace) zeroes both
   long zero_count;
 };
 

@@ -278,6 +278,10 @@ dcf_status dcf_set_workspace(dcf_ctx *c, int mode, int nsteps, int seg_len, void
   if (need > bytes) return fail(DCF_ENOMEM, "workspace needs %zu bytes, got %zu", need, bytes);
   carve(c, dev, mode, nsteps, seg_len);
   DCF_HIP(hipMemset(c->g.flags, 0, 64 * sizeof(unsigned)));
+  // the adjoint boxes start at zero; the reverse kernels keep every cell no
+  // stage writes at zero from then on
+  if (mode >= 1) DCF_HIP(hipMemset(c->adj.zero_begin, 0, c->adj.zero_count * sizeof(double)));
+  DCF_HIP(hipStreamSynchronize(nullptr));  // done before work on any stream can use them
   c->ws = dev;
   c->ws_bytes = bytes;
   c->ws_mode = mode;
@@ -724,8 +728,10 @@ dcf_status dcf_time_kernel(dcf_ctx *c, const double *U, int which, int reps, dou
   dcf_status s = ready(c, 0);
   if (s) return s;
   if (!U || !avg_ms || reps < 1) return fail(DCF_EINVAL, "bad argument");
-  if (which < 0 || which > 5 || (which >= 1 && which <= 3 && which > c->g.ndim))
+  if (which < 0 || which > 6 || (which >= 1 && which <= 3 && which > c->g.ndim))
     return fail(DCF_EINVAL, "unknown kernel %d", which);
+  if (which == 6 && !fused_stages(c))
+    return fail(DCF_EINVAL, "no fused flux + update kernel for this case (1D or source term)");
   hipStream_t st = (hipStream_t)stream;
   Dev &g = c->g;
   if ((s = eval_fluxes(c, U, st))) return s;
@@ -739,6 +745,7 @@ dcf_status dcf_time_kernel(dcf_ctx *c, const double *U, int which, int reps, dou
     if (which == 0) e = launch_prim_halo(g, U, st);
     else if (which <= 3) e = launch_flux_dir(g, which - 1, st);
     else if (which == 5) e = launch_grad(g, st);
+    else if (which == 6) e = launch_flux_update_last(g, U, U, c->U1, c->U2, 0.0, 1.0, nullptr, st);
     else e = launch_update(g, U, U, c->U1, nullptr, c->U2, 0.0, 1.0, c->force, st);
     if (e != hipSuccess) return fail(DCF_EDEVICE, "launch: %s", hipGetErrorString(e));
   }

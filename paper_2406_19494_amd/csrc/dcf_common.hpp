@@ -218,6 +218,17 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned L, unsigned nb) {
   return x < rem ? x * (per + 1u) + i : rem * (per + 1u) + (x - rem) * per + i;
 }
 
+// As xcd_remap, but spreading chunks of C consecutive logical tiles round
+// robin over the XCDs (chunk k on XCD k mod 8): tiles of one chunk share an
+// L2 while the work of any region is spread over all XCDs.  Blocks past the
+// last whole round of 8 chunks keep their index.
+__device__ __forceinline__ unsigned xcd_chunk_remap(unsigned P, unsigned nb, unsigned C) {
+  const unsigned full = nb / (8u * C) * (8u * C);
+  if (P >= full) return P;
+  const unsigned x = P % 8u, i = P / 8u;
+  return ((i / C) * 8u + x) * C + i % C;
+}
+
 __host__ __device__ __forceinline__ constexpr int tan1(int d) { return d == 0 ? 1 : 0; }
 __host__ __device__ __forceinline__ constexpr int tan2(int d) { return d == 2 ? 1 : 2; }
 

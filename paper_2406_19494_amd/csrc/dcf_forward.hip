@@ -1171,12 +1171,9 @@ unsigned flux_update_blocks(const Dev &g) {
          (unsigned)(D == 1 ? g.n[2] : g.n[1]);
 }
 
-hipError_t launch_fluxes_update(const Dev &g, const double *Un, const double *Uin,
-                                double *Uout, const double *dt, double a, double b,
-                                double *dtpart, hipStream_t st) {
-  hipError_t e = launch_grad(g, st);
-  for (int D = 0; D + 1 < g.ndim && e == hipSuccess; ++D) e = launch_flux_dir(g, D, st);
-  if (e != hipSuccess) return e;
+hipError_t launch_flux_update_last(const Dev &g, const double *Un, const double *Uin,
+                                   double *Uout, const double *dt, double a, double b,
+                                   double *dtpart, hipStream_t st) {
   const bool v = g.visc != VISC_NONE;
   if (g.ndim == 2)
     return v ? launch_fu<2, true>(g, Un, Uin, Uout, dt, a, b, dtpart, st)
@@ -1185,6 +1182,15 @@ hipError_t launch_fluxes_update(const Dev &g, const double *Un, const double *Ui
     return v ? launch_fu<3, true>(g, Un, Uin, Uout, dt, a, b, dtpart, st)
              : launch_fu<3, false>(g, Un, Uin, Uout, dt, a, b, dtpart, st);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_fluxes_update(const Dev &g, const double *Un, const double *Uin,
+                                double *Uout, const double *dt, double a, double b,
+                                double *dtpart, hipStream_t st) {
+  hipError_t e = launch_grad(g, st);
+  for (int D = 0; D + 1 < g.ndim && e == hipSuccess; ++D) e = launch_flux_dir(g, D, st);
+  if (e != hipSuccess) return e;
+  return launch_flux_update_last(g, Un, Uin, Uout, dt, a, b, dtpart, st);
 }
 
 hipError_t launch_flux_dir(const Dev &g, int D, hipStream_t st) {

@@ -51,6 +51,11 @@ hipError_t launch_fluxes_update(const Dev &g, const double *Un, const double *Ui
                                 double *Uout, const double *dt, double a, double b,
                                 double *dtpart, hipStream_t st);
 unsigned flux_update_blocks(const Dev &g);
+// The last direction's flux + update kernel alone (its gradient and other
+// fluxes already computed).
+hipError_t launch_flux_update_last(const Dev &g, const double *Un, const double *Uin,
+                                   double *Uout, const double *dt, double a, double b,
+                                   double *dtpart, hipStream_t st);
 hipError_t launch_dt_final(const double *part, int nparts, double cfl, double dt_max, double *dt,
                            hipStream_t st);
 hipError_t launch_dt(const Dev &g, const double *U, double cfl, double dt_max, double *part,

@@ -90,3 +90,23 @@ def test_gradient_sized_for_other_trajectory_rejected():
     with pytest.raises(B.DcfError) as ei:
         s.gradient(U, dt)
     assert ei.value.code == -1
+
+
+def test_time_kernel_families_and_unknown_ids():
+    # every kernel family of a 3D viscous case times to a positive duration;
+    # the fused flux + update (6) is refused where the case has none (1D)
+    case, P = W.tgv(16)
+    s = Solver(case)
+    U = s.init_state(P)
+    for w in range(7):
+        assert s.time_kernel(U, w, reps=2) > 0.0
+    L = B.lib()
+    ms = C.c_double()
+    for bad in (-1, 7):
+        assert L.dcf_time_kernel(s.ctx, C.c_void_p(U.data_ptr()), bad, 2, C.byref(ms), None) == -1
+    case1, P1 = W.sod(64)
+    s1 = Solver(case1)
+    U1 = s1.init_state(P1)
+    assert s1.time_kernel(U1, 1, reps=2) > 0.0
+    for bad in (2, 6):
+        assert L.dcf_time_kernel(s1.ctx, C.c_void_p(U1.data_ptr()), bad, 2, C.byref(ms), None) == -1
