@@ -293,33 +293,44 @@ __host__ inline unsigned tile_count(const Dev &g, int D) {
 }
 
 // ---------------------------------------------------------------------------
-// Convective adjoint along D: WENO5-JS + HLLC reversed per face, gathered
-// into Qb (rho, u, v, w, p) over the cells f-3 .. f+2.
+// Adjoint of the fluxes along D, one tile of faces per workgroup:
+//  * convective: WENO5-JS + HLLC reversed per face, contributions to the
+//    cells f-3 .. f+2 (rho, velocity, p);
+//  * dissipative (VISC): the face stress / heat flux reversed to face-level
+//    adjoints, expanded over the cells f-2 .. f+1 into velocity, T, mu and
+//    the adjoint Gb of the cell-centred tangential velocity derivatives.
+// Both share the face adjoint from Wb and one LDS window of cells
+// (f0-3 .. f0+TF+1 per line); the tile writes each completed cell once.
 // ---------------------------------------------------------------------------
-template <int NDIM, int D>
-__global__ void __launch_bounds__(256) k_conv_vjp(Dev g, AdjBuffers A) {
+template <int NDIM, int D, bool VISC>
+__global__ void __launch_bounds__(256) k_dir_vjp(Dev g, AdjBuffers A) {
   constexpr int OLO = -3, OHI = 2, NOFF = OHI - OLO + 1, SPAN = OHI - OLO;
   constexpr int TF = TileShape<D>::TF, TW = TileShape<D>::TW;
   constexpr int NCW = TF + SPAN;  // window cells per line
   constexpr int T1 = tan1(D), T2 = tan2(D);
-  constexpr int NC = 5;
+  // accumulator channels: rho, u, v, w, p (global velocity components), then
+  // T, mu, Gb(T1,T1), Gb(T1,D), Gb(T2,T2), Gb(T2,D) when viscous
+  constexpr int CT = 5, CMU = 6, CG = 7;
+  constexpr int NCH = VISC ? 11 : 5;
   // y/z tiles: a row stride of 36 doubles puts the 8 lines x 4 faces of a
   // half-wave on distinct LDS banks
   constexpr int BF = D == 0 ? TF : TF + 4;
-  __shared__ double acc[NC][TW][NCW];
+  __shared__ double acc[NCH][TW][NCW];
   __shared__ double buf[NOFF][TW][BF];  // one component's contributions per face
   Tile t = make_tile<OLO, OHI, D>(g);
-  for (int i = threadIdx.x; i < NC * TW * NCW; i += 256) (&acc[0][0][0])[i] = 0.0;
+  for (int i = threadIdx.x; i < NCH * TW * NCW; i += 256) (&acc[0][0][0])[i] = 0.0;
 
   const int f = t.f0 + t.lane_face;
   const bool active = t.line_ok && f >= 0 && f <= g.n[D];
   const int qi[5] = {QR, QU + D, QU + T1, QU + T2, QP};
+  constexpr int ch[5] = {0, 1 + D, 1 + T1, 1 + T2, 4};  // face frame -> channel
   double qLb[5] = {0, 0, 0, 0, 0}, qRb[5] = {0, 0, 0, 0, 0};
-  long base = 0, s = g.sb[D];
+  double Fb[5] = {0, 0, 0, 0, 0};
+  long base = 0;
+  const long s = g.sb[D];
   if (active) {
     int pos[3] = {t.line[0], t.line[1], t.line[2]};
     pos[D] = f;
-    double Fb[5];
     face_adjoint(g, A, D, pos, f, Fb);
     base = bidx(g, pos[0], pos[1], pos[2]);
     double qL[5], qR[5];
@@ -339,9 +350,9 @@ __global__ void __launch_bounds__(256) k_conv_vjp(Dev g, AdjBuffers A) {
     double Fr[5] = {Fb[0], Fb[1 + D], Fb[1 + T1], Fb[1 + T2], Fb[4]};
     hllc_vjp(qL, qR, g.gamma, Fr, qLb, qRb);
   }
-  // per component: reverse the two reconstructions, stage the contributions
-  // to cells f-3 .. f+2 in LDS, then gather them per window cell in a fixed
-  // order of faces (deterministic, no atomics)
+  // convective, per component: reverse the two reconstructions, stage the
+  // contributions to cells f-3 .. f+2 in LDS, then gather them per window
+  // cell in a fixed order of faces (deterministic, no atomics)
   for (int m = 0; m < 5; ++m) {
     const bool act = !((m == 2 && T1 >= NDIM) || (m == 3 && T2 >= NDIM));
     if (!act) continue;  // uniform across the block
@@ -372,9 +383,106 @@ __global__ void __launch_bounds__(256) k_conv_vjp(Dev g, AdjBuffers A) {
         const int fl = w - o;  // face (lane) whose offset o lands on window cell w
         if (fl >= 0 && fl < TF) sum += buf[o][ll][fl];
       }
-      acc[m][ll][w] += sum;
+      acc[ch[m]][ll][w] += sum;
     }
     __syncthreads();
+  }
+  if (VISC) {
+    // face-level adjoints of the dissipative flux
+    double ufb[3] = {0, 0, 0}, dnb[3] = {0, 0, 0}, dTb = 0.0, mufb = 0.0;
+    double divtb = 0.0, dtnb[3] = {0, 0, 0};
+    double mfD = 0.0;
+    if (active) {
+      double vel[3][4], Tc[4], muc[4];
+#pragma unroll
+      for (int o = 0; o < 4; ++o) {
+        long cb = base + (o - 2) * s;
+        vel[0][o] = g.Q[QU][cb];
+        vel[1][o] = NDIM >= 2 ? g.Q[QV][cb] : 0.0;
+        vel[2][o] = NDIM >= 3 ? g.Q[QW][cb] : 0.0;
+        Tc[o] = g.Q[QT][cb];
+        muc[o] = g.Q[QMU][cb];
+      }
+      mfD = g.mf[D][f];
+      double muf = interp4(muc[0], muc[1], muc[2], muc[3]);
+      double uf[3], dn[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        uf[c] = interp4(vel[c][0], vel[c][1], vel[c][2], vel[c][3]);
+        dn[c] = dface4(vel[c][0], vel[c][1], vel[c][2], vel[c][3]) * mfD;
+      }
+      double dT = dface4(Tc[0], Tc[1], Tc[2], Tc[3]) * mfD;
+      double divt = 0.0, dtn[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int tt = r == 0 ? T1 : T2;
+        if (tt >= NDIM) continue;
+        // cell-centred tangential derivatives of the recomputed stage (k_grad)
+        const double *Gtt = g.G[3 * tt + tt], *Gtn = g.G[3 * tt + D];
+        double gtt[4], gtn[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+          long cb = base + (o - 2) * s;
+          gtt[o] = Gtt[cb];
+          gtn[o] = Gtn[cb];
+        }
+        divt += interp4(gtt[0], gtt[1], gtt[2], gtt[3]);
+        dtn[tt] = interp4(gtn[0], gtn[1], gtn[2], gtn[3]);
+      }
+      double brk[3] = {0.0, 0.0, 0.0};
+      brk[D] = (4.0 / 3.0) * dn[D] - (2.0 / 3.0) * divt;
+      if (T1 < NDIM) brk[T1] = dtn[T1] + dn[T1];
+      if (T2 < NDIM) brk[T2] = dtn[T2] + dn[T2];
+      double tau[3] = {muf * brk[0], muf * brk[1], muf * brk[2]};
+      const double cpPr = g.cp / g.Pr;
+      double lam = muf * cpPr;
+      // reverse
+      double enb = -Fb[4];
+      double taub[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        taub[c] = -Fb[1 + c] + enb * uf[c];
+        ufb[c] = enb * tau[c];
+      }
+      double lamb = enb * dT;
+      dTb = enb * lam;
+      mufb = lamb * cpPr + taub[0] * brk[0] + taub[1] * brk[1] + taub[2] * brk[2];
+      dnb[D] = taub[D] * muf * (4.0 / 3.0);
+      divtb = -taub[D] * muf * (2.0 / 3.0);
+      if (T1 < NDIM) {
+        dtnb[T1] = taub[T1] * muf;
+        dnb[T1] = taub[T1] * muf;
+      }
+      if (T2 < NDIM) {
+        dtnb[T2] = taub[T2] * muf;
+        dnb[T2] = taub[T2] * muf;
+      }
+    }
+    // cells f-2 .. f+1 are window cells lane_face + 1 .. lane_face + 4; one
+    // offset at a time so that no two faces update a cell together
+    const double I4[4] = {-1.0 / 16.0, 9.0 / 16.0, 9.0 / 16.0, -1.0 / 16.0};
+    const double D4[4] = {1.0 / 24.0, -27.0 / 24.0, 27.0 / 24.0, -1.0 / 24.0};
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      if (active) {
+        const int w = t.lane_face + 1 + o;
+        const int ll = t.lane_line;
+        const double dm = D4[o] * mfD, im = I4[o];
+#pragma unroll
+        for (int c = 0; c < NDIM; ++c) acc[1 + c][ll][w] += ufb[c] * im + dnb[c] * dm;
+        acc[CT][ll][w] += dTb * dm;
+        acc[CMU][ll][w] += mufb * im;
+        if (T1 < NDIM) {
+          acc[CG][ll][w] += divtb * im;
+          acc[CG + 1][ll][w] += dtnb[T1] * im;
+        }
+        if (T2 < NDIM) {
+          acc[CG + 2][ll][w] += divtb * im;
+          acc[CG + 3][ll][w] += dtnb[T2] * im;
+        }
+      }
+      __syncthreads();
+    }
   }
   // write the completed cells: window cell w <-> cell t.f0 + OLO + w
   for (int i = threadIdx.x; i < TW * NCW; i += 256) {
@@ -390,178 +498,41 @@ __global__ void __launch_bounds__(256) k_conv_vjp(Dev g, AdjBuffers A) {
     p[T1] = (int)(ln % g.n[T1]);
     p[T2] = (int)(ln / g.n[T1]);
     const long b = bidx(g, p[0], p[1], p[2]);
-    if (D == 0 || cell < 0 || cell >= g.n[D]) {
+    const bool ghost = cell < 0 || cell >= g.n[D];
+    if (D == 0 || ghost) {
       // first writer of this cell in the stage: set every component the
       // later kernels accumulate into
       A.Qb[QR][b] = acc[0][ll][w];
-      A.Qb[QU + D][b] = acc[1][ll][w];
-      if (T1 < NDIM) A.Qb[QU + T1][b] = acc[2][ll][w];
-      if (T2 < NDIM) A.Qb[QU + T2][b] = acc[3][ll][w];
+#pragma unroll
+      for (int c = 0; c < NDIM; ++c) A.Qb[QU + c][b] = acc[1 + c][ll][w];
       A.Qb[QP][b] = acc[4][ll][w];
-      A.Qb[QT][b] = 0.0;
-      if (g.visc != VISC_NONE) A.Qb[QMU][b] = 0.0;
+      A.Qb[QT][b] = VISC ? acc[CT][ll][w] : 0.0;
+      if (VISC) A.Qb[QMU][b] = acc[CMU][ll][w];
     } else {
       A.Qb[QR][b] += acc[0][ll][w];
-      A.Qb[QU + D][b] += acc[1][ll][w];
-      if (T1 < NDIM) A.Qb[QU + T1][b] += acc[2][ll][w];
-      if (T2 < NDIM) A.Qb[QU + T2][b] += acc[3][ll][w];
+#pragma unroll
+      for (int c = 0; c < NDIM; ++c) A.Qb[QU + c][b] += acc[1 + c][ll][w];
       A.Qb[QP][b] += acc[4][ll][w];
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Dissipative adjoint along D: the face stress/heat flux reversed to
-// face-level adjoints, then expanded over cells f-2 .. f+1 into
-// Qb (u, v, w, T, mu) and into Gb (adjoint of the cell-centred tangential
-// velocity derivatives).
-// ---------------------------------------------------------------------------
-template <int NDIM, int D>
-__global__ void __launch_bounds__(256) k_visc_vjp(Dev g, AdjBuffers A) {
-  constexpr int OLO = -2, OHI = 1, NOFF = OHI - OLO + 1, SPAN = OHI - OLO;
-  constexpr int TF = TileShape<D>::TF, TW = TileShape<D>::TW;
-  constexpr int NCW = TF + SPAN;
-  constexpr int AS = D == 0 ? NCW : NCW + 1;  // LDS row stride (36 for y/z tiles)
-  constexpr int T1 = tan1(D), T2 = tan2(D);
-  constexpr int NC = 9;  // u, v, w, T, mu, G(t1,t1) G(t1,D) G(t2,t2) G(t2,D)
-  __shared__ double acc[NC][TW][AS];
-  Tile t = make_tile<OLO, OHI, D>(g);
-  for (int i = threadIdx.x; i < NC * TW * AS; i += 256) (&acc[0][0][0])[i] = 0.0;
-  __syncthreads();
-
-  const int f = t.f0 + t.lane_face;
-  const bool active = t.line_ok && f >= 0 && f <= g.n[D];
-  // face-level adjoints
-  double ufb[3] = {0, 0, 0}, dnb[3] = {0, 0, 0}, dTb = 0.0, mufb = 0.0;
-  double divtb = 0.0, dtnb[3] = {0, 0, 0};
-  double mfD = 0.0;
-  if (active) {
-    int pos[3] = {t.line[0], t.line[1], t.line[2]};
-    pos[D] = f;
-    double Fb[5];
-    face_adjoint(g, A, D, pos, f, Fb);
-    const long base = bidx(g, pos[0], pos[1], pos[2]);
-    const long s = g.sb[D];
-    double vel[3][4], Tc[4], muc[4];
-#pragma unroll
-    for (int o = 0; o < 4; ++o) {
-      long cb = base + (o - 2) * s;
-      vel[0][o] = g.Q[QU][cb];
-      vel[1][o] = NDIM >= 2 ? g.Q[QV][cb] : 0.0;
-      vel[2][o] = NDIM >= 3 ? g.Q[QW][cb] : 0.0;
-      Tc[o] = g.Q[QT][cb];
-      muc[o] = g.Q[QMU][cb];
-    }
-    mfD = g.mf[D][f];
-    double muf = interp4(muc[0], muc[1], muc[2], muc[3]);
-    double uf[3], dn[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      uf[c] = interp4(vel[c][0], vel[c][1], vel[c][2], vel[c][3]);
-      dn[c] = dface4(vel[c][0], vel[c][1], vel[c][2], vel[c][3]) * mfD;
-    }
-    double dT = dface4(Tc[0], Tc[1], Tc[2], Tc[3]) * mfD;
-    double divt = 0.0, dtn[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int tt = r == 0 ? T1 : T2;
-      if (tt >= NDIM) continue;
-      // cell-centred tangential derivatives of the recomputed stage (k_grad)
-      const double *Gtt = g.G[3 * tt + tt], *Gtn = g.G[3 * tt + D];
-      double gtt[4], gtn[4];
-#pragma unroll
-      for (int o = 0; o < 4; ++o) {
-        long cb = base + (o - 2) * s;
-        gtt[o] = Gtt[cb];
-        gtn[o] = Gtn[cb];
+      if (VISC) {
+        A.Qb[QT][b] += acc[CT][ll][w];
+        A.Qb[QMU][b] += acc[CMU][ll][w];
       }
-      divt += interp4(gtt[0], gtt[1], gtt[2], gtt[3]);
-      dtn[tt] = interp4(gtn[0], gtn[1], gtn[2], gtn[3]);
     }
-    double brk[3] = {0.0, 0.0, 0.0};
-    brk[D] = (4.0 / 3.0) * dn[D] - (2.0 / 3.0) * divt;
-    if (T1 < NDIM) brk[T1] = dtn[T1] + dn[T1];
-    if (T2 < NDIM) brk[T2] = dtn[T2] + dn[T2];
-    double tau[3] = {muf * brk[0], muf * brk[1], muf * brk[2]};
-    const double cpPr = g.cp / g.Pr;
-    double lam = muf * cpPr;
-    // reverse
-    double enb = -Fb[4];
-    double taub[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      taub[c] = -Fb[1 + c] + enb * uf[c];
-      ufb[c] = enb * tau[c];
-    }
-    double lamb = enb * dT;
-    dTb = enb * lam;
-    mufb = lamb * cpPr + taub[0] * brk[0] + taub[1] * brk[1] + taub[2] * brk[2];
-    dnb[D] = taub[D] * muf * (4.0 / 3.0);
-    divtb = -taub[D] * muf * (2.0 / 3.0);
-    if (T1 < NDIM) {
-      dtnb[T1] = taub[T1] * muf;
-      dnb[T1] = taub[T1] * muf;
-    }
-    if (T2 < NDIM) {
-      dtnb[T2] = taub[T2] * muf;
-      dnb[T2] = taub[T2] * muf;
-    }
-  }
-  const double I4[4] = {-1.0 / 16.0, 9.0 / 16.0, 9.0 / 16.0, -1.0 / 16.0};
-  const double D4[4] = {1.0 / 24.0, -27.0 / 24.0, 27.0 / 24.0, -1.0 / 24.0};
-#pragma unroll
-  for (int o = 0; o < NOFF; ++o) {
-    if (active) {
-      const int w = t.lane_face + o;
-      const int ll = t.lane_line;
-      const double dm = D4[o] * mfD, im = I4[o];
-#pragma unroll
-      for (int c = 0; c < NDIM; ++c) acc[c][ll][w] += ufb[c] * im + dnb[c] * dm;
-      acc[3][ll][w] += dTb * dm;
-      acc[4][ll][w] += mufb * im;
+    if (VISC) {
+      // derivative adjoints: d u_D / d x_t is this kernel's alone (set); the
+      // diagonal d u_t / d x_t is shared with the kernel of every earlier
+      // direction other than t, which covered the cells interior along D
+      constexpr bool sh1 = D >= 2 || (D == 1 && T1 != 0), sh2 = D >= 2 || (D == 1 && T2 != 0);
       if (T1 < NDIM) {
-        acc[5][ll][w] += divtb * im;
-        acc[6][ll][w] += dtnb[T1] * im;
+        double &d1 = A.Gb[3 * T1 + T1][b];
+        d1 = (sh1 && !ghost ? d1 : 0.0) + acc[CG][ll][w];
+        A.Gb[3 * T1 + D][b] = acc[CG + 1][ll][w];
       }
       if (T2 < NDIM) {
-        acc[7][ll][w] += divtb * im;
-        acc[8][ll][w] += dtnb[T2] * im;
+        double &d2 = A.Gb[3 * T2 + T2][b];
+        d2 = (sh2 && !ghost ? d2 : 0.0) + acc[CG + 2][ll][w];
+        A.Gb[3 * T2 + D][b] = acc[CG + 3][ll][w];
       }
-    }
-    __syncthreads();
-  }
-  for (int i = threadIdx.x; i < TW * NCW; i += 256) {
-    // x-lines: consecutive threads take consecutive cells of a line;
-    // otherwise consecutive lines (x-neighbours) of one cell position
-    const int ll = D == 0 ? i / NCW : i % TW, w = D == 0 ? i % NCW : i / TW;
-    const int cell = t.f0 + OLO + w;
-    if (cell < t.c0 || cell >= t.c1) continue;
-    long ln = t.lg * TW + ll;
-    if (ln >= (long)g.n[T1] * g.n[T2]) continue;
-    int p[3];
-    p[D] = cell;
-    p[T1] = (int)(ln % g.n[T1]);
-    p[T2] = (int)(ln / g.n[T1]);
-    const long b = bidx(g, p[0], p[1], p[2]);
-    A.Qb[QU][b] += acc[0][ll][w];
-    if (NDIM >= 2) A.Qb[QV][b] += acc[1][ll][w];
-    if (NDIM >= 3) A.Qb[QW][b] += acc[2][ll][w];
-    A.Qb[QT][b] += acc[3][ll][w];
-    A.Qb[QMU][b] += acc[4][ll][w];
-    // derivative adjoints: d u_D / d x_t is this kernel's alone (set); the
-    // diagonal d u_t / d x_t is shared with the kernel of every earlier
-    // direction other than t, which covered the cells interior along D
-    const bool ghost = cell < 0 || cell >= g.n[D];
-    constexpr bool sh1 = D >= 2 || (D == 1 && T1 != 0), sh2 = D >= 2 || (D == 1 && T2 != 0);
-    if (T1 < NDIM) {
-      double &d1 = A.Gb[3 * T1 + T1][b];
-      d1 = (sh1 && !ghost ? d1 : 0.0) + acc[5][ll][w];
-      A.Gb[3 * T1 + D][b] = acc[6][ll][w];
-    }
-    if (T2 < NDIM) {
-      double &d2 = A.Gb[3 * T2 + T2][b];
-      d2 = (sh2 && !ghost ? d2 : 0.0) + acc[7][ll][w];
-      A.Gb[3 * T2 + D][b] = acc[8][ll][w];
     }
   }
 }
@@ -875,15 +846,15 @@ __global__ void __launch_bounds__(256) k_interior_vjp(Dev g, AdjBuffers A, const
 // ---------------------------------------------------------------------------
 using AdjKernel = void (*)(Dev, AdjBuffers);
 
-static AdjKernel conv_kernel(int nd, int D) {
-  if (nd == 1) return k_conv_vjp<1, 0>;
-  if (nd == 2) return D == 0 ? k_conv_vjp<2, 0> : k_conv_vjp<2, 1>;
-  return D == 0 ? k_conv_vjp<3, 0> : (D == 1 ? k_conv_vjp<3, 1> : k_conv_vjp<3, 2>);
-}
-static AdjKernel visc_kernel(int nd, int D) {
-  if (nd == 1) return k_visc_vjp<1, 0>;
-  if (nd == 2) return D == 0 ? k_visc_vjp<2, 0> : k_visc_vjp<2, 1>;
-  return D == 0 ? k_visc_vjp<3, 0> : (D == 1 ? k_visc_vjp<3, 1> : k_visc_vjp<3, 2>);
+static AdjKernel dir_kernel(int nd, int D, bool visc) {
+  if (nd == 1) return visc ? k_dir_vjp<1, 0, true> : k_dir_vjp<1, 0, false>;
+  if (nd == 2) {
+    if (D == 0) return visc ? k_dir_vjp<2, 0, true> : k_dir_vjp<2, 0, false>;
+    return visc ? k_dir_vjp<2, 1, true> : k_dir_vjp<2, 1, false>;
+  }
+  if (D == 0) return visc ? k_dir_vjp<3, 0, true> : k_dir_vjp<3, 0, false>;
+  if (D == 1) return visc ? k_dir_vjp<3, 1, true> : k_dir_vjp<3, 1, false>;
+  return visc ? k_dir_vjp<3, 2, true> : k_dir_vjp<3, 2, false>;
 }
 
 static inline unsigned blocks(long n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
@@ -912,14 +883,9 @@ static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A0, const double *V,
     if (visc && g.ndim >= 2) DCF_TRY(launch_grad(g, st));
   }
   for (int D = 0; D < g.ndim; ++D) {
-    hipLaunchKernelGGL(conv_kernel(g.ndim, D), dim3(tile_count<-3, 2>(g, D)), dim3(256), 0, st, g,
-                       A);
+    hipLaunchKernelGGL(dir_kernel(g.ndim, D, visc), dim3(tile_count<-3, 2>(g, D)), dim3(256), 0,
+                       st, g, A);
     DCF_TRY(hipGetLastError());
-    if (visc) {
-      hipLaunchKernelGGL(visc_kernel(g.ndim, D), dim3(tile_count<-2, 1>(g, D)), dim3(256), 0, st,
-                         g, A);
-      DCF_TRY(hipGetLastError());
-    }
   }
   if (visc) {
     k_tangential_vjp<<<blocks(g.nbox), 256, 0, st>>>(g, A);
