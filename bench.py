@@ -77,25 +77,35 @@ def workload(name):
 
 
 def cpu_baseline(case, P, K, budget_s):
-    """The oracle on the host cores: RK3 steps of the same workload until the
-    time budget is spent (at least one step)."""
-    from oracle.pyoracle import Oracle
-    o = Oracle(case, K=K)
-    U = o.cons(P)
-    t0 = time.perf_counter()
-    steps = 0
-    while True:
-        dt = o.dt(U, case.cfl)
-        U = o.step(U, dt)
-        steps += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    el = time.perf_counter() - t0
+    """The oracle on the host cores: RK3 steps (each with its CFL step) of
+    the same workload until the time budget is spent (at least one step),
+    with all threads, then with one thread for half the budget."""
+    from oracle import pyoracle as O
+    o = O.Oracle(case, K=K)
+
+    def sample(threads, budget):
+        used = O.set_threads(threads)
+        U = o.cons(P)
+        t0 = time.perf_counter()
+        steps = 0
+        while True:
+            dt = o.dt(U, case.cfl)
+            U = o.step(U, dt)
+            steps += 1
+            if time.perf_counter() - t0 > budget:
+                break
+        return case.ncells * 3 * steps / (time.perf_counter() - t0), steps, used, \
+            time.perf_counter() - t0
+
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": case.ncells * 3 * steps / el, "unit": "cell-updates/s per RK stage",
-            "cores": threads, "kind": "oracle",
+    v, steps, used, el = sample(threads, budget_s)
+    v1, steps1, _, el1 = sample(1, budget_s / 2)
+    O.set_threads(threads)
+    return {"value": v, "unit": "cell-updates/s per RK stage", "cores": used, "kind": "oracle",
             "sample": f"{steps} CFL+RK3 steps of the same {case.n[0]}x{case.n[1]}x{case.n[2]} "
-                      f"workload ({el:.1f} s, OpenMP threads={threads})"}
+                      f"workload ({el:.1f} s, OpenMP threads={used})",
+            "single_thread": {"value": v1, "cores": 1,
+                              "sample": f"{steps1} CFL+RK3 steps ({el1:.1f} s, 1 thread)"}}
 
 
 def source_digest():
@@ -131,11 +141,19 @@ def measured_traffic(kernel, workload):
     return 1024.0 * (fk * float(vals["copy_factor_fetch"]) + wk * float(vals["copy_factor_write"]))
 
 
-def serving_bench(M=32, rate=20.0, seed=2024):
+def serving_bench(M=32, rate=20.0, seed=2024, M_low=12, rate_low=2.0, seed_low=2025):
     """Continuous batching vs sequential solves on a seeded trace of forward
     and gradient requests (Sod 200-4096 cells, TGV 32^3/48^3/64^3, porous BL
-    256x64/512x128), 50-400 steps each, Poisson arrivals at `rate`/s."""
+    256x64/512x128), 50-400 steps each, Poisson arrivals at `rate`/s (an
+    overloaded GPU), and a shorter trace at `rate_low`/s whose offered load
+    stays below the GPU's capacity (latency near the service time)."""
     from paper_2406_19494_amd import serving as S
+
+    def offered(trace):
+        work = sum(3.0 * S.cells_of(r) * r.nsteps for r in trace)
+        span = max(r.arrival for r in trace)
+        return work, (work / span if span > 0 else float("nan"))
+
     trace = S.draw_trace(M, rate, seed, steps=(50, 400), tgv=(32, 48, 64), bl=(1, 2))
     res, t_b, sch = S.serve(trace, budget_bytes=200e9, max_slots=16)
     sb = S.summarize(res, t_b)
@@ -143,17 +161,27 @@ def serving_bench(M=32, rate=20.0, seed=2024):
     sk = S.summarize(res_k, t_k)
     res_s, t_s, _ = S.serve_sequential(trace)
     ss = S.summarize(res_s, t_s)
-    work = sum(3.0 * S.cells_of(r) * r.nsteps for r in trace)
+    work, load = offered(trace)
+    low = S.draw_trace(M_low, rate_low, seed_low, steps=(50, 400), tgv=(32, 48, 64), bl=(1, 2))
+    res_l, t_l, _ = S.serve(low, budget_bytes=200e9, max_slots=16)
+    res_ls, t_ls, _ = S.serve_sequential(low)
+    work_l, load_l = offered(low)
     return {"trace": f"{M} requests, Poisson {rate}/s (seed {seed}), steps 50-400, "
                      "sod 200-4096 / tgv 32-64^3 / porous BL 256x64-512x128, 50% gradients",
-            "offered_cell_updates": work,
+            "offered_cell_updates": work, "offered_load_cell_updates_per_s": load,
             "batched": sb, "batched_kernels": sk, "sequential": ss,
             "peak_active": sch.peak_active,
             "throughput_ratio": sb["cell_updates_per_s"] / ss["cell_updates_per_s"],
             "throughput_ratio_batched_kernels": sk["cell_updates_per_s"] / ss["cell_updates_per_s"],
+            "low_rate": {"trace": f"{M_low} requests, Poisson {rate_low}/s (seed {seed_low}), "
+                                  "same mix", "offered_cell_updates": work_l,
+                         "offered_load_cell_updates_per_s": load_l,
+                         "batched": S.summarize(res_l, t_l),
+                         "sequential": S.summarize(res_ls, t_ls)},
             "note": "batched: one stream and hipGraph-captured epochs per request; "
                     "batched_kernels: forward requests of one family share batched step "
-                    "launches (dcf_batch_rk3_step)"}
+                    "launches (dcf_batch_rk3_step); offered load = the trace's cell updates "
+                    "over its arrival span"}
 
 
 def adjoint_ratio(steps=20):
@@ -301,13 +329,16 @@ def main():
     # A 2D/3D step without source term runs the last direction's fluxes
     # fused with the stage update (k_flux_update); the unfused pair is timed
     # too, for the record.
+    # A 3D step launches the x and y fluxes as one grid (k_flux_xy).
     names = {0: "k_prim_halo", 1: "k_flux_x", 2: "k_flux_yz<y>", 3: "k_flux_yz<z>", 4: "k_update",
-             5: "k_grad", 6: "k_flux_update"}
+             5: "k_grad", 6: "k_flux_update", 7: "k_flux_xy"}
     visc = case.visc_law != "none"
     fused = case.ndim >= 2 and case.source == "none"
     step_kinds = [0] + ([5] if visc and case.ndim >= 2 else [])
-    step_kinds += list(range(1, case.ndim)) + [6] if fused else list(range(1, case.ndim + 1)) + [4]
-    kinds = sorted(set(step_kinds) | {case.ndim, 4})
+    step_kinds += [7] if case.ndim == 3 else [1] if case.ndim == 2 else []
+    step_kinds += [6] if fused else [case.ndim, 4] if case.ndim == 3 else list(
+        range(1, case.ndim + 1)) + [4] if case.ndim == 1 else [2, 4]
+    kinds = sorted(set(step_kinds) | set(range(1, case.ndim + 1)) | {4})
     kt = {w: s.time_kernel(U, w, reps=20) for w in kinds}
 
     def faces_of(D):
@@ -316,20 +347,26 @@ def main():
             f *= case.n[e] + (1 if e == D else 0)
         return f
 
-    def flux_dir(w):  # direction whose faces kernel w computes, or None
-        return w - 1 if 1 <= w <= 3 else (case.ndim - 1 if w == 6 else None)
+    def flux_faces(w):  # faces whose fluxes kernel w computes, or None
+        if 1 <= w <= 3:
+            return faces_of(w - 1)
+        if w == 6:
+            return faces_of(case.ndim - 1)
+        if w == 7:
+            return faces_of(0) + faces_of(1)
+        return None
 
     def kernel_roof(w):
         # flux kernels (and the fused one, counted by its flux work alone)
         # against the FP64 vector peak, the others against HBM bandwidth
-        D = flux_dir(w)
-        if D is not None:
-            flops = FLOPS_PER_FACE[(case.ndim, visc)] * faces_of(D)
+        nf = flux_faces(w)
+        if nf is not None:
+            flops = FLOPS_PER_FACE[(case.ndim, visc)] * nf
             a = flops / (kt[w] * 1e-3)
             return {"bound": "alu", "achieved": a / 1e12, "peak": PEAK_FP64 / 1e12,
                     "unit": "TFLOP/s", "frac": a / PEAK_FP64,
                     "algorithmic_flops_per_face": FLOPS_PER_FACE[(case.ndim, visc)],
-                    "faces_per_launch": faces_of(D)}
+                    "faces_per_launch": nf}
         nbytes = algorithmic_bytes(case, names[w])
         a = nbytes / (kt[w] * 1e-3)
         return {"bound": "hbm", "achieved": a / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
@@ -359,6 +396,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "pid_s_per_cell_stage": 1.0 / value,  # wall time x GPUs / (cells x RK stages)
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

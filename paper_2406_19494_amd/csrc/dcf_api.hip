@@ -728,10 +728,12 @@ dcf_status dcf_time_kernel(dcf_ctx *c, const double *U, int which, int reps, dou
   dcf_status s = ready(c, 0);
   if (s) return s;
   if (!U || !avg_ms || reps < 1) return fail(DCF_EINVAL, "bad argument");
-  if (which < 0 || which > 6 || (which >= 1 && which <= 3 && which > c->g.ndim))
+  if (which < 0 || which > 7 || (which >= 1 && which <= 3 && which > c->g.ndim))
     return fail(DCF_EINVAL, "unknown kernel %d", which);
   if (which == 6 && !fused_stages(c))
     return fail(DCF_EINVAL, "no fused flux + update kernel for this case (1D or source term)");
+  if (which == 7 && c->g.ndim != 3)
+    return fail(DCF_EINVAL, "the combined x + y flux launch is for 3D grids");
   hipStream_t st = (hipStream_t)stream;
   Dev &g = c->g;
   if ((s = eval_fluxes(c, U, st))) return s;
@@ -746,6 +748,7 @@ dcf_status dcf_time_kernel(dcf_ctx *c, const double *U, int which, int reps, dou
     else if (which <= 3) e = launch_flux_dir(g, which - 1, st);
     else if (which == 5) e = launch_grad(g, st);
     else if (which == 6) e = launch_flux_update_last(g, U, U, c->U1, c->U2, 0.0, 1.0, nullptr, st);
+    else if (which == 7) e = launch_flux_xy(g, st);
     else e = launch_update(g, U, U, c->U1, nullptr, c->U2, 0.0, 1.0, c->force, st);
     if (e != hipSuccess) return fail(DCF_EDEVICE, "launch: %s", hipGetErrorString(e));
   }

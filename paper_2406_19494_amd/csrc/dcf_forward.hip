@@ -577,9 +577,8 @@ __device__ __forceinline__ bool yz_tile_face(const Dev &g, YzTile<NDIM, VISC> &T
 }
 
 template <int NDIM, int D, bool VISC>
-__device__ __forceinline__ void flux_yz_body(const Dev &g, unsigned lin, unsigned ntot,
-                                             unsigned nbx, unsigned nby) {
-  __shared__ YzTile<NDIM, VISC> T;
+__device__ __forceinline__ void flux_yz_tile(const Dev &g, YzTile<NDIM, VISC> &T, unsigned lin,
+                                             unsigned ntot, unsigned nbx, unsigned nby) {
   // tiles along D are consecutive in the remapped order (they share 5 rows)
   const unsigned lg = xcd_remap(lin, ntot);
   const unsigned by = lg % nby, rest = lg / nby;
@@ -596,6 +595,27 @@ __device__ __forceinline__ void flux_yz_body(const Dev &g, unsigned lin, unsigne
   const long fc = g.fcount[D];
 #pragma unroll
   for (int m = 0; m < 5; ++m) F[m * fc + t] = G[m];
+}
+
+template <int NDIM, int D, bool VISC>
+__device__ __forceinline__ void flux_yz_body(const Dev &g, unsigned lin, unsigned ntot,
+                                             unsigned nbx, unsigned nby) {
+  __shared__ YzTile<NDIM, VISC> T;
+  flux_yz_tile<NDIM, D, VISC>(g, T, lin, ntot, nbx, nby);
+}
+
+// x and y faces of a 3D grid in one launch (the two are independent): the
+// first ny_tiles workgroups take y tiles, the rest x chunks; both kinds
+// share one dynamic LDS buffer.
+template <bool VISC>
+__global__ void __launch_bounds__(256) k_flux_xy(Dev g, int nwmax, unsigned ny_tiles,
+                                                 unsigned nbx, unsigned nby) {
+  extern __shared__ double lds[];
+  if (blockIdx.x < ny_tiles)
+    flux_yz_tile<3, 1, VISC>(g, *reinterpret_cast<YzTile<3, VISC> *>(lds), blockIdx.x, ny_tiles,
+                             nbx, nby);
+  else
+    flux_x_body<3, VISC>(g, nwmax, blockIdx.x - ny_tiles, lds);
 }
 
 template <int NDIM, int D, bool VISC>
@@ -1135,6 +1155,21 @@ static hipError_t launch_x(const Dev &g, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <bool VISC>
+static hipError_t launch_xy(const Dev &g, hipStream_t st) {
+  const int nw = x_window(g);
+  const size_t shm = std::max(sizeof(double) * Slots<3, VISC>::NC * nw, sizeof(YzTile<3, VISC>));
+  const unsigned nbx = (g.n[0] + 15) / 16, nby = (g.n[1] + 1 + 15) / 16;
+  const unsigned ny_tiles = nbx * nby * (unsigned)g.n[2];
+  k_flux_xy<VISC><<<ny_tiles + grid_for(g.fcount[0]), 256, shm, st>>>(g, nw, ny_tiles, nbx, nby);
+  return hipGetLastError();
+}
+
+hipError_t launch_flux_xy(const Dev &g, hipStream_t st) {
+  if (g.ndim != 3) return hipErrorInvalidValue;
+  return g.visc != VISC_NONE ? launch_xy<true>(g, st) : launch_xy<false>(g, st);
+}
+
 template <int NDIM, int D, bool VISC>
 static hipError_t launch_yz(const Dev &g, hipStream_t st) {
   dim3 grid((g.n[0] + 15) / 16, (g.n[D] + 1 + 15) / 16, D == 1 ? g.n[2] : g.n[1]);
@@ -1188,7 +1223,7 @@ hipError_t launch_fluxes_update(const Dev &g, const double *Un, const double *Ui
                                 double *Uout, const double *dt, double a, double b,
                                 double *dtpart, hipStream_t st) {
   hipError_t e = launch_grad(g, st);
-  for (int D = 0; D + 1 < g.ndim && e == hipSuccess; ++D) e = launch_flux_dir(g, D, st);
+  if (e == hipSuccess) e = g.ndim == 3 ? launch_flux_xy(g, st) : launch_flux_dir(g, 0, st);
   if (e != hipSuccess) return e;
   return launch_flux_update_last(g, Un, Uin, Uout, dt, a, b, dtpart, st);
 }
@@ -1208,6 +1243,10 @@ hipError_t launch_flux_dir(const Dev &g, int D, hipStream_t st) {
 hipError_t launch_fluxes(const Dev &g, hipStream_t st) {
   hipError_t e = launch_grad(g, st);
   if (e != hipSuccess) return e;
+  if (g.ndim == 3) {
+    e = launch_flux_xy(g, st);
+    return e != hipSuccess ? e : launch_flux_dir(g, 2, st);
+  }
   for (int D = 0; D < g.ndim; ++D) {
     e = launch_flux_dir(g, D, st);
     if (e != hipSuccess) return e;

@@ -35,6 +35,8 @@ hipError_t launch_init_state(const Dev &g, const double *P, double *U, hipStream
 hipError_t launch_prim_halo(const Dev &g, const double *U, hipStream_t st);
 hipError_t launch_fluxes(const Dev &g, hipStream_t st);
 hipError_t launch_flux_dir(const Dev &g, int D, hipStream_t st);
+// x and y face fluxes of a 3D grid in one launch.
+hipError_t launch_flux_xy(const Dev &g, hipStream_t st);
 hipError_t launch_grad(const Dev &g, hipStream_t st);
 hipError_t launch_force(const Dev &g, double *part, double *force, hipStream_t st);
 // With dtpart (update_blocks(g) doubles) each block also writes the largest
