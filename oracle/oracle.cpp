@@ -45,6 +45,8 @@
 #include <cstring>
 #include <vector>
 
+#include <omp.h>
+
 namespace {
 
 /* ------------------------------------------------------------------------ */
@@ -824,6 +826,11 @@ double orc_gradient(const orc_case *c, const double *K, const double *U0, int ns
   }
   std::memcpy(dJdU0, lam.data(), sizeof(double) * M);
   return J;
+}
+
+int orc_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
 }
 
 } /* extern "C" */

@@ -93,6 +93,10 @@ void orc_vjp_step(const orc_case *c, const double *K, const double *U, double dt
 double orc_gradient(const orc_case *c, const double *K, const double *U0, int nsteps,
                     double dt, double *dJdK, double *dJdU0);
 
+/* OpenMP threads of the per-line loops: n > 0 sets them; returns the number
+ * the next parallel loop will use. */
+int orc_set_threads(int n);
+
 #ifdef __cplusplus
 }
 #endif

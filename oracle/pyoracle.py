@@ -63,6 +63,7 @@ def lib():
             "orc_jvp_step": (None, [P, _dp, _dp, _dp, _dp, C.c_double, _dp, _dp]),
             "orc_vjp_step": (None, [P, _dp, _dp, C.c_double, _dp, _dp, _dp]),
             "orc_gradient": (C.c_double, [P, _dp, _dp, C.c_int, C.c_double, _dp, _dp]),
+            "orc_set_threads": (C.c_int, [C.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -70,6 +71,12 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """OpenMP threads of the oracle's loops (n > 0 sets them); returns the
+    number in use."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def _ptr(a):
