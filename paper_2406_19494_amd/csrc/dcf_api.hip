@@ -65,6 +65,7 @@ struct dcf_ctx {
   int ws_nsteps = 0, ws_seg = 0;
   double *U1 = nullptr, *U2 = nullptr, *part = nullptr, *force = nullptr;
   double *dtpart = nullptr;  // per-block signal rates of the last stage (fused CFL step)
+  BoxOut qalt;               // second primitive box (fused stages alternate the two)
   AdjBuffers adj;
   double *ckpt = nullptr;  // gradient checkpoints
   double *seg = nullptr;   // per-segment recomputed states
@@ -231,6 +232,7 @@ static size_t carve(dcf_ctx *c, void *base, int mode, int nsteps, int seg_len) {
   c->force = cv.take<double>(4);
   c->dtpart = cv.take<double>(std::max(update_blocks(g), flux_update_blocks(g)));
   g.flags = cv.take<unsigned>(64);
+  for (int q = 0; q < NQ; ++q) c->qalt.Q[q] = g.ndim >= 2 ? cv.take<double>(nbox) : nullptr;
   if (mode >= 1) carve_adjoint(cv, g, c->adj);
   if (mode >= 2) {
     int nseg = (nsteps + seg_len - 1) / seg_len;
@@ -406,10 +408,22 @@ static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_
     const double *in[3] = {U, U1, U2};
     double *out[3] = {U1, U2, U};
     const double a[3] = {0.0, 0.75, 1.0 / 3.0}, b[3] = {1.0, 0.25, 2.0 / 3.0};
+    // the stages' primitive boxes alternate between g.Q and qalt: each
+    // stage's update also writes the interior of the next stage's box, which
+    // then only needs its ghosts
+    Dev gs[2] = {g, g};
+    BoxOut bo[2];
+    for (int q = 0; q < NQ; ++q) {
+      gs[1].Q[q] = c->qalt.Q[q];
+      bo[0].Q[q] = g.Q[q];
+      bo[1].Q[q] = c->qalt.Q[q];
+    }
     for (int k = 0; k < 3; ++k) {
-      DCF_HIP(launch_prim_halo(g, in[k], st));
-      DCF_HIP(launch_fluxes_update(g, U, in[k], out[k], dt, a[k], b[k], k == 2 ? dtpart : nullptr,
-                                   st));
+      const Dev &gk = gs[k & 1];
+      if (k == 0) DCF_HIP(launch_prim_halo(gk, in[k], st));
+      else DCF_HIP(launch_prim_ghost(gk, st));
+      DCF_HIP(launch_fluxes_update(gk, U, in[k], out[k], dt, a[k], b[k], k == 2 ? dtpart : nullptr,
+                                   st, k < 2 ? bo[(k + 1) & 1] : BoxOut{}));
     }
     return DCF_OK;
   }
@@ -645,10 +659,20 @@ static dcf_status gradient_unit(dcf_ctx *c, hipStream_t st) {
       const double a[3] = {0.0, 0.75, 1.0 / 3.0}, b[3] = {1.0, 0.25, 2.0 / 3.0};
       for (int k = 0; k < 3; ++k) {
         const Dev gs = stage_box(c, gr.n, k);
-        DCF_HIP(launch_prim_halo(gs, in[k], st));
         if (fused_stages(c)) {
-          DCF_HIP(launch_fluxes_update(gs, Ub, in[k], out[k], gr.dt, a[k], b[k], nullptr, st));
+          // as rk3_stages: each update writes the interior of the next
+          // stage's cached box
+          BoxOut next;
+          if (k < 2) {
+            const Dev gn = stage_box(c, gr.n, k + 1);
+            for (int q = 0; q < NQ; ++q) next.Q[q] = gn.Q[q];
+          }
+          if (k == 0) DCF_HIP(launch_prim_halo(gs, in[k], st));
+          else DCF_HIP(launch_prim_ghost(gs, st));
+          DCF_HIP(launch_fluxes_update(gs, Ub, in[k], out[k], gr.dt, a[k], b[k], nullptr, st,
+                                       next));
         } else {
+          DCF_HIP(launch_prim_halo(gs, in[k], st));
           DCF_HIP(launch_fluxes(gs, st));
           DCF_HIP(launch_update(gs, Ub, in[k], out[k], nullptr, gr.dt, a[k], b[k], nullptr, st));
         }

@@ -65,6 +65,12 @@ struct Dev {
   unsigned *flags;
 };
 
+// Primitive box arrays a kernel writes besides its main output (null Q[0]:
+// none).
+struct BoxOut {
+  double *Q[NQ] = {};
+};
+
 __device__ __forceinline__ bool finite_pos(double x) { return x > 0.0 && x < 1.0e300; }
 
 // Box arrays: interior cell 0 of each row sits on a 128-byte boundary (x

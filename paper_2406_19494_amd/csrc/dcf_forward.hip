@@ -861,7 +861,8 @@ __device__ __forceinline__ void flux_update_body(const Dev &g, unsigned lin, uns
                                                  unsigned nbx, unsigned nby, const double *Un,
                                                  const double *Uin, double *Uout,
                                                  const double *dtp, double a, double bcoef,
-                                                 double *dtpart, unsigned bid) {
+                                                 double *dtpart, unsigned bid,
+                                                 BoxOut qo = BoxOut{}) {
   using Tl = YzTile<NDIM, VISC>;
   __shared__ Tl T;
   const unsigned lg = xcd_remap(lin, ntot);
@@ -893,6 +894,23 @@ __device__ __forceinline__ void flux_update_body(const Dev &g, unsigned lin, uns
     const long c = ((long)p[2] * g.n[1] + p[1]) * g.n[0] + p[0];
     sig = stage_apply(g, Un, Uin, Uout, nullptr, dtp, a, bcoef, nullptr, c, p[0], p[1], p[2], R,
                       dtpart != nullptr);
+    if (qo.Q[0]) {
+      // the new state's primitives, converted from the values just stored
+      // exactly as k_prim_interior converts them
+      double q[6];
+      cons_to_prim(g, Uout, c, q);
+      if (!(finite_pos(q[QR]) && finite_pos(q[QP]))) atomicOr(g.flags, 1u);
+      const long bx = bidx(g, p[0], p[1], p[2]);
+      qo.Q[QR][bx] = q[QR];
+      qo.Q[QU][bx] = q[QU];
+      qo.Q[QV][bx] = q[QV];
+      if (NDIM >= 3) qo.Q[QW][bx] = q[QW];
+      qo.Q[QP][bx] = q[QP];
+      if (VISC) {
+        qo.Q[QT][bx] = q[QT];
+        qo.Q[QMU][bx] = viscosity(g, q[QT]);
+      }
+    }
   }
   if (dtpart) {
     __shared__ double shx[256];
@@ -904,12 +922,12 @@ __device__ __forceinline__ void flux_update_body(const Dev &g, unsigned lin, uns
 template <int NDIM, bool VISC>
 __global__ void __launch_bounds__(256) k_flux_update(Dev g, const double *Un, const double *Uin,
                                                      double *Uout, const double *dtp, double a,
-                                                     double bcoef, double *dtpart) {
+                                                     double bcoef, double *dtpart, BoxOut qo) {
   constexpr int D = NDIM - 1;
   const unsigned nbx = gridDim.x, nby = gridDim.y;
   const unsigned lin = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
   flux_update_body<NDIM, D, VISC>(g, lin, nbx * nby * gridDim.z, nbx, nby, Un, Uin, Uout, dtp,
-                                  a, bcoef, dtpart, lin);
+                                  a, bcoef, dtpart, lin, qo);
 }
 
 // ---------------------------------------------------------------------------
@@ -1192,10 +1210,10 @@ hipError_t launch_grad(const Dev &g, hipStream_t st) {
 template <int NDIM, bool VISC>
 static hipError_t launch_fu(const Dev &g, const double *Un, const double *Uin, double *Uout,
                             const double *dt, double a, double b, double *dtpart,
-                            hipStream_t st) {
+                            const BoxOut &qo, hipStream_t st) {
   constexpr int D = NDIM - 1;
   dim3 grid((g.n[0] + 15) / 16, (g.n[D] + 14) / 15, D == 1 ? g.n[2] : g.n[1]);
-  k_flux_update<NDIM, VISC><<<grid, 256, 0, st>>>(g, Un, Uin, Uout, dt, a, b, dtpart);
+  k_flux_update<NDIM, VISC><<<grid, 256, 0, st>>>(g, Un, Uin, Uout, dt, a, b, dtpart, qo);
   return hipGetLastError();
 }
 
@@ -1208,24 +1226,29 @@ unsigned flux_update_blocks(const Dev &g) {
 
 hipError_t launch_flux_update_last(const Dev &g, const double *Un, const double *Uin,
                                    double *Uout, const double *dt, double a, double b,
-                                   double *dtpart, hipStream_t st) {
+                                   double *dtpart, hipStream_t st, const BoxOut &qo) {
   const bool v = g.visc != VISC_NONE;
   if (g.ndim == 2)
-    return v ? launch_fu<2, true>(g, Un, Uin, Uout, dt, a, b, dtpart, st)
-             : launch_fu<2, false>(g, Un, Uin, Uout, dt, a, b, dtpart, st);
+    return v ? launch_fu<2, true>(g, Un, Uin, Uout, dt, a, b, dtpart, qo, st)
+             : launch_fu<2, false>(g, Un, Uin, Uout, dt, a, b, dtpart, qo, st);
   if (g.ndim == 3)
-    return v ? launch_fu<3, true>(g, Un, Uin, Uout, dt, a, b, dtpart, st)
-             : launch_fu<3, false>(g, Un, Uin, Uout, dt, a, b, dtpart, st);
+    return v ? launch_fu<3, true>(g, Un, Uin, Uout, dt, a, b, dtpart, qo, st)
+             : launch_fu<3, false>(g, Un, Uin, Uout, dt, a, b, dtpart, qo, st);
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_fluxes_update(const Dev &g, const double *Un, const double *Uin,
                                 double *Uout, const double *dt, double a, double b,
-                                double *dtpart, hipStream_t st) {
+                                double *dtpart, hipStream_t st, const BoxOut &qo) {
   hipError_t e = launch_grad(g, st);
   if (e == hipSuccess) e = g.ndim == 3 ? launch_flux_xy(g, st) : launch_flux_dir(g, 0, st);
   if (e != hipSuccess) return e;
-  return launch_flux_update_last(g, Un, Uin, Uout, dt, a, b, dtpart, st);
+  return launch_flux_update_last(g, Un, Uin, Uout, dt, a, b, dtpart, st, qo);
+}
+
+hipError_t launch_prim_ghost(const Dev &g, hipStream_t st) {
+  if (g.nbox > g.ncell) k_prim_ghost<<<grid_for(g.nbox - g.ncell), 256, 0, st>>>(g);
+  return hipGetLastError();
 }
 
 hipError_t launch_flux_dir(const Dev &g, int D, hipStream_t st) {

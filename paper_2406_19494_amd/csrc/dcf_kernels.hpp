@@ -49,15 +49,21 @@ unsigned update_blocks(const Dev &g);
 // fluxes fused into the update (ndim >= 2, no source term): gradients, the
 // other directions' fluxes, then one kernel for the last direction + update.
 // With dtpart (flux_update_blocks(g) doubles) the CFL partials as above.
+// With qo the kernel also writes the new state's primitives (and mu) into
+// the interior of the box qo (same layout as g.Q, another buffer), as
+// k_prim_interior would: the next stage then only fills the ghosts
+// (launch_prim_ghost on a context whose Q is qo).
 hipError_t launch_fluxes_update(const Dev &g, const double *Un, const double *Uin,
                                 double *Uout, const double *dt, double a, double b,
-                                double *dtpart, hipStream_t st);
+                                double *dtpart, hipStream_t st, const BoxOut &qo = BoxOut{});
 unsigned flux_update_blocks(const Dev &g);
 // The last direction's flux + update kernel alone (its gradient and other
 // fluxes already computed).
 hipError_t launch_flux_update_last(const Dev &g, const double *Un, const double *Uin,
                                    double *Uout, const double *dt, double a, double b,
-                                   double *dtpart, hipStream_t st);
+                                   double *dtpart, hipStream_t st, const BoxOut &qo = BoxOut{});
+// Ghost cells of the box from its interior (the interior already filled).
+hipError_t launch_prim_ghost(const Dev &g, hipStream_t st);
 hipError_t launch_dt_final(const double *part, int nparts, double cfl, double dt_max, double *dt,
                            hipStream_t st);
 hipError_t launch_dt(const Dev &g, const double *U, double cfl, double dt_max, double *part,
