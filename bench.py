@@ -39,6 +39,9 @@ def algorithmic_bytes(case, kernel):
     if kernel == "k_prim_halo":
         nq = nd + 2 + (2 if visc else 0)
         return 8 * (case.ncells * case.nv + nbox * nq)
+    if kernel == "k_prim_ghost":  # each ghost reads its source cell's values, writes its own
+        nq = nd + 2 + (2 if visc else 0)
+        return 8 * 2 * nq * (nbox - case.ncells)
     if kernel == "k_grad":
         writes = 0
         for t in range(nd):
@@ -329,12 +332,15 @@ def main():
     # A 2D/3D step without source term runs the last direction's fluxes
     # fused with the stage update (k_flux_update); the unfused pair is timed
     # too, for the record.
-    # A 3D step launches the x and y fluxes as one grid (k_flux_xy).
+    # A 3D step launches the x and y fluxes as one grid (k_flux_xy).  In a
+    # fused step the update of stages 1 and 2 also writes the next stage's
+    # primitive interior, so stages 2 and 3 fill only the ghosts
+    # (k_prim_ghost, 8) where stage 1 runs the whole halo fill (0).
     names = {0: "k_prim_halo", 1: "k_flux_x", 2: "k_flux_yz<y>", 3: "k_flux_yz<z>", 4: "k_update",
-             5: "k_grad", 6: "k_flux_update", 7: "k_flux_xy"}
+             5: "k_grad", 6: "k_flux_update", 7: "k_flux_xy", 8: "k_prim_ghost"}
     visc = case.visc_law != "none"
     fused = case.ndim >= 2 and case.source == "none"
-    step_kinds = [0] + ([5] if visc and case.ndim >= 2 else [])
+    step_kinds = [0] + ([8] if fused else []) + ([5] if visc and case.ndim >= 2 else [])
     step_kinds += [7] if case.ndim == 3 else [1] if case.ndim == 2 else []
     step_kinds += [6] if fused else [case.ndim, 4] if case.ndim == 3 else list(
         range(1, case.ndim + 1)) + [4] if case.ndim == 1 else [2, 4]

@@ -344,8 +344,7 @@ __global__ void __launch_bounds__(256) k_dir_vjp(Dev g, AdjBuffers A) {
       const double *Qm = g.Q[qi[m]];
       double v0 = Qm[base - 3 * s], v1 = Qm[base - 2 * s], v2 = Qm[base - s];
       double v3 = Qm[base], v4 = Qm[base + s], v5 = Qm[base + 2 * s];
-      qL[m] = weno5(v0, v1, v2, v3, v4);
-      qR[m] = weno5(v5, v4, v3, v2, v1);
+      weno5_pair(v0, v1, v2, v3, v4, v5, qL[m], qR[m]);
     }
     double Fr[5] = {Fb[0], Fb[1 + D], Fb[1 + T1], Fb[1 + T2], Fb[4]};
     hllc_vjp(qL, qR, g.gamma, Fr, qLb, qRb);
@@ -434,7 +433,7 @@ __global__ void __launch_bounds__(256) k_dir_vjp(Dev g, AdjBuffers A) {
       if (T1 < NDIM) brk[T1] = dtn[T1] + dn[T1];
       if (T2 < NDIM) brk[T2] = dtn[T2] + dn[T2];
       double tau[3] = {muf * brk[0], muf * brk[1], muf * brk[2]};
-      const double cpPr = g.cp / g.Pr;
+      const double cpPr = g.cpPr;
       double lam = muf * cpPr;
       // reverse
       double enb = -Fb[4];

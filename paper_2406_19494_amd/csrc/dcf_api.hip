@@ -150,6 +150,8 @@ dcf_status dcf_create(const dcf_grid *grid, const dcf_gas *gas, dcf_ctx **out) {
   g.R = gas->R;
   g.Pr = gas->Pr;
   g.cp = gas->gamma * gas->R / (gas->gamma - 1.0);
+  g.gm1i = 1.0 / (gas->gamma - 1.0);
+  g.cpPr = g.cp / gas->Pr;
   g.mu_ref = gas->mu_ref;
   g.T_ref = gas->T_ref;
   g.vparam = gas->visc_param;
@@ -752,7 +754,7 @@ dcf_status dcf_time_kernel(dcf_ctx *c, const double *U, int which, int reps, dou
   dcf_status s = ready(c, 0);
   if (s) return s;
   if (!U || !avg_ms || reps < 1) return fail(DCF_EINVAL, "bad argument");
-  if (which < 0 || which > 7 || (which >= 1 && which <= 3 && which > c->g.ndim))
+  if (which < 0 || which > 8 || (which >= 1 && which <= 3 && which > c->g.ndim))
     return fail(DCF_EINVAL, "unknown kernel %d", which);
   if (which == 6 && !fused_stages(c))
     return fail(DCF_EINVAL, "no fused flux + update kernel for this case (1D or source term)");
@@ -773,6 +775,7 @@ dcf_status dcf_time_kernel(dcf_ctx *c, const double *U, int which, int reps, dou
     else if (which == 5) e = launch_grad(g, st);
     else if (which == 6) e = launch_flux_update_last(g, U, U, c->U1, c->U2, 0.0, 1.0, nullptr, st);
     else if (which == 7) e = launch_flux_xy(g, st);
+    else if (which == 8) e = launch_prim_ghost(g, st);
     else e = launch_update(g, U, U, c->U1, nullptr, c->U2, 0.0, 1.0, c->force, st);
     if (e != hipSuccess) return fail(DCF_EDEVICE, "launch: %s", hipGetErrorString(e));
   }

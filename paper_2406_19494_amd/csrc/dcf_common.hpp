@@ -46,6 +46,7 @@ struct Dev {
   const double *xm[3];   // cell-centre coordinates (midpoint of the two faces)
   // gas
   double gamma, R, Pr, cp, mu_ref, T_ref, vparam;
+  double gm1i, cpPr;     // 1/(gamma - 1) and cp/Pr
   int visc;
   // boundaries
   int bck[6];
@@ -136,13 +137,17 @@ __device__ __forceinline__ double viscosity(const Dev &g, double T) {
 // nonlinear weights alpha_k = d_k / (eps + beta_k)^2 are normalised after
 // multiplying through by the product of the three denominators, which needs
 // one division instead of four.
-__device__ __forceinline__ double weno5(double a, double b, double c, double d, double e) {
+// WENO5-JS of one stencil a..e (reconstruction at the face between c and d)
+// as numerator and denominator of the normalised nonlinear weights, with
+// the candidate values left unscaled (six times the third-order
+// reconstructions): the value is num / (6 den).
+__device__ __forceinline__ void weno5_nd(double a, double b, double c, double d, double e,
+                                         double &num, double &den) {
   const double eps = 1.0e-6;
-  const double sixth = 1.0 / 6.0;
   const double c1312 = 13.0 / 12.0;
-  double q0 = (2.0 * a - 7.0 * b + 11.0 * c) * sixth;
-  double q1 = (-b + 5.0 * c + 2.0 * d) * sixth;
-  double q2 = (2.0 * c + 5.0 * d - e) * sixth;
+  double q0 = 2.0 * a - 7.0 * b + 11.0 * c;
+  double q1 = -b + 5.0 * c + 2.0 * d;
+  double q2 = 2.0 * c + 5.0 * d - e;
   double r0 = a - 2.0 * b + c, s0 = a - 4.0 * b + 3.0 * c;
   double r1 = b - 2.0 * c + d, s1 = b - d;
   double r2 = c - 2.0 * d + e, s2 = 3.0 * c - 4.0 * d + e;
@@ -152,8 +157,22 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
   t0 *= t0;
   t1 *= t1;
   t2 *= t2;
+  // weights d_k / t_k times t0 t1 t2 (no division per weight)
   double w0 = 0.1 * t1 * t2, w1 = 0.6 * t0 * t2, w2 = 0.3 * t0 * t1;
-  return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+  num = w0 * q0 + w1 * q1 + w2 * q2;
+  den = w0 + w1 + w2;
+}
+
+// Both reconstructions at the face between v2 and v3: left-biased from
+// v0..v4, right-biased from v5..v1, sharing one division.
+__device__ __forceinline__ void weno5_pair(double v0, double v1, double v2, double v3, double v4,
+                                           double v5, double &yl, double &yr) {
+  double nl, dl, nr, dr;
+  weno5_nd(v0, v1, v2, v3, v4, nl, dl);
+  weno5_nd(v5, v4, v3, v2, v1, nr, dr);
+  const double r = 1.0 / (6.0 * dl * dr);
+  yl = nl * dr * r;
+  yr = nr * dl * r;
 }
 
 // HLLC flux in the face frame.  q = (rho, u_n, u_t1, u_t2, p) on each side;
@@ -163,8 +182,7 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
 //   U*_K = r [rho (S-u), rho (S-u) S*, rho (S-u) v, rho (S-u) w,
 //             E (S-u) + (S*-u)(rho (S-u) S* + p)].
 __device__ __forceinline__ void hllc(const double *qL, const double *qR, double gamma,
-                                     double *F) {
-  const double gm1i = 1.0 / (gamma - 1.0);
+                                     double gm1i, double *F) {
   double rL = qL[0], uL = qL[1], vL = qL[2], wL = qL[3], pL = qL[4];
   double rR = qR[0], uR = qR[1], vR = qR[2], wR = qR[3], pR = qR[4];
   double EL = pL * gm1i + 0.5 * rL * (uL * uL + vL * vL + wL * wL);

@@ -393,11 +393,10 @@ __device__ __forceinline__ void face_flux(const Dev &g, const PA &P, const GA &G
     }
     double v0 = P(qi[m], -3), v1 = P(qi[m], -2), v2 = P(qi[m], -1);
     double v3 = P(qi[m], 0), v4 = P(qi[m], 1), v5 = P(qi[m], 2);
-    qL[m] = weno5(v0, v1, v2, v3, v4);
-    qR[m] = weno5(v5, v4, v3, v2, v1);
+    weno5_pair(v0, v1, v2, v3, v4, v5, qL[m], qR[m]);
   }
   double Fc[5];
-  hllc(qL, qR, g.gamma, Fc);
+  hllc(qL, qR, g.gamma, g.gm1i, Fc);
   G[0] = Fc[0];
   G[1 + D] = Fc[1];
   G[1 + T1] = Fc[2];
@@ -436,7 +435,7 @@ __device__ __forceinline__ void face_flux(const Dev &g, const PA &P, const GA &G
     tau[D] = muf * ((4.0 / 3.0) * dn[D] - (2.0 / 3.0) * divt);
     if (T1 < NDIM) tau[T1] = muf * (dtn[T1] + dn[T1]);
     if (T2 < NDIM) tau[T2] = muf * (dtn[T2] + dn[T2]);
-    double lam = muf * g.cp / g.Pr;
+    double lam = muf * g.cpPr;
     double en = uf[0] * tau[0] + uf[1] * tau[1] + uf[2] * tau[2] + lam * dT;
     G[1] -= tau[0];
     G[2] -= tau[1];

@@ -99,11 +99,11 @@ def test_time_kernel_families_and_unknown_ids():
     case, P = W.tgv(16)
     s = Solver(case)
     U = s.init_state(P)
-    for w in range(8):
+    for w in range(9):
         assert s.time_kernel(U, w, reps=2) > 0.0
     L = B.lib()
     ms = C.c_double()
-    for bad in (-1, 8):
+    for bad in (-1, 9):
         assert L.dcf_time_kernel(s.ctx, C.c_void_p(U.data_ptr()), bad, 2, C.byref(ms), None) == -1
     case1, P1 = W.sod(64)
     s1 = Solver(case1)
