@@ -144,6 +144,46 @@ def measured_traffic(kernel, workload):
     return 1024.0 * (fk * float(vals["copy_factor_fetch"]) + wk * float(vals["copy_factor_write"]))
 
 
+def step_kernel_ids(case):
+    """dcf_time_kernel ids of the launches one RK3 stage of `case` runs:
+    halo fill (0; 8 = ghosts only, stages 2-3 of a fused step), derivatives
+    (5, viscous 2D/3D), fluxes (7 = x+y of a 3D grid, 1..3 per direction),
+    then the fused last-direction flux + update (6, 2D/3D without source) or
+    the separate update (4)."""
+    visc = case.visc_law != "none"
+    fused = case.ndim >= 2 and case.source == "none"
+    ids = [0] + ([8] if fused else []) + ([5] if visc and case.ndim >= 2 else [])
+    if case.ndim == 3:
+        ids += [7] + ([6] if fused else [3, 4])
+    elif case.ndim == 2:
+        ids += [1] + ([6] if fused else [2, 4])
+    else:
+        ids += [1, 4]
+    return ids
+
+
+def measured_valu(kernel, workload):
+    """FP64 VALU work per launch of `kernel` from the committed counter
+    summary: 64 lanes x (2 FMA + MUL + ADD + TRANS) FP64 instructions
+    (SQ_INSTS_VALU_*_F64 per dispatch; every lane of a wave counted), or
+    None when no summary exists or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    sha, row = None, None
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) >= 2 and parts[0] == "source_sha":
+                sha = parts[1]
+            elif len(parts) == 6 and parts[0] == "valu" and parts[1] == kernel:
+                row = [float(x) for x in parts[2:]]
+    if sha != source_digest() or row is None:
+        return None
+    fma, mul, add, trans = row
+    return 64.0 * (2.0 * fma + mul + add + trans)
+
+
 def serving_bench(M=32, rate=20.0, seed=2024, M_low=12, rate_low=2.0, seed_low=2025):
     """Continuous batching vs sequential solves on a seeded trace of forward
     and gradient requests (Sod 200-4096 cells, TGV 32^3/48^3/64^3, porous BL
@@ -339,11 +379,7 @@ def main():
     names = {0: "k_prim_halo", 1: "k_flux_x", 2: "k_flux_yz<y>", 3: "k_flux_yz<z>", 4: "k_update",
              5: "k_grad", 6: "k_flux_update", 7: "k_flux_xy", 8: "k_prim_ghost"}
     visc = case.visc_law != "none"
-    fused = case.ndim >= 2 and case.source == "none"
-    step_kinds = [0] + ([8] if fused else []) + ([5] if visc and case.ndim >= 2 else [])
-    step_kinds += [7] if case.ndim == 3 else [1] if case.ndim == 2 else []
-    step_kinds += [6] if fused else [case.ndim, 4] if case.ndim == 3 else list(
-        range(1, case.ndim + 1)) + [4] if case.ndim == 1 else [2, 4]
+    step_kinds = step_kernel_ids(case)
     kinds = sorted(set(step_kinds) | set(range(1, case.ndim + 1)) | {4})
     kt = {w: s.time_kernel(U, w, reps=20) for w in kinds}
 
@@ -385,6 +421,13 @@ def main():
         "traffic": measured_traffic(names[dom], args.workload), "kernel": names[dom],
         "avg_ms": kt[dom]} | {k: v for k, v in roof.items()
                               if k not in ("bound", "achieved", "peak", "unit", "frac")}
+    # the same launch against both roofs from the hardware counters: FP64
+    # VALU operations issued and HBM bytes moved, per launch, over its time
+    vf = measured_valu(names[dom], args.workload)
+    roof["valu_fp64_tflops"] = None if vf is None else vf / (kt[dom] * 1e-3) / 1e12
+    roof["valu_frac"] = None if vf is None else vf / (kt[dom] * 1e-3) / PEAK_FP64
+    tr = roof["traffic"]
+    roof["hbm_frac_measured"] = None if tr is None else tr / (kt[dom] * 1e-3) / PEAK_HBM
     # every kernel against its own roofline, for the record
     per_kernel = {}
     for w in kinds:
