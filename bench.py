@@ -20,12 +20,15 @@ PEAK_HBM = 8.0e12       # MI355X HBM3E bytes/s
 
 # Algorithmic FP64 operations per face of the flux kernel (counted from the
 # kernel source: 10 WENO5-JS reconstructions x 69, HLLC star branch 79, 3D
-# viscous/heat flux 183) and algorithmic bytes per face (the primitive
-# values of one cell, 7 x 8 B, read once; 5 x 8 B of flux written).
+# viscous/heat flux 183) and algorithmic bytes per face: the inputs of one
+# cell read once (rho, u, v, w, p, plus T, mu and the 2 (2D) or 4 (3D)
+# tangential derivatives a viscous face reads), 5 x 8 B of flux written.
 FLOPS_PER_FACE = {(1, False): 6 * 69 + 79, (1, True): 6 * 69 + 79 + 40,
                   (2, False): 8 * 69 + 79, (2, True): 8 * 69 + 79 + 101,
                   (3, False): 10 * 69 + 79, (3, True): 10 * 69 + 79 + 183}
-BYTES_PER_FACE = 7 * 8 + 5 * 8
+BYTES_PER_FACE = {(1, False): 5 * 8 + 40, (1, True): 7 * 8 + 40,
+                  (2, False): 5 * 8 + 40, (2, True): 9 * 8 + 40,
+                  (3, False): 5 * 8 + 40, (3, True): 11 * 8 + 40}
 
 
 def algorithmic_bytes(case, kernel):
@@ -399,20 +402,34 @@ def main():
         return None
 
     def kernel_roof(w):
-        # flux kernels (and the fused one, counted by its flux work alone)
-        # against the FP64 vector peak, the others against HBM bandwidth
+        # every launch against the roof that binds it: the larger of the
+        # FP64 lower bound (algorithmic flops / 78.6 TFLOP/s) and the HBM
+        # lower bound (algorithmic bytes / 8 TB/s); the flux kernels have
+        # both, the others only bytes
         nf = flux_faces(w)
+        t = kt[w] * 1e-3
         if nf is not None:
-            flops = FLOPS_PER_FACE[(case.ndim, visc)] * nf
-            a = flops / (kt[w] * 1e-3)
-            return {"bound": "alu", "achieved": a / 1e12, "peak": PEAK_FP64 / 1e12,
-                    "unit": "TFLOP/s", "frac": a / PEAK_FP64,
-                    "algorithmic_flops_per_face": FLOPS_PER_FACE[(case.ndim, visc)],
-                    "faces_per_launch": nf}
+            fpf, bpf = FLOPS_PER_FACE[(case.ndim, visc)], BYTES_PER_FACE[(case.ndim, visc)]
+            flops = fpf * nf
+            if w == 6:
+                # inputs of one cell once (primitives and derivatives), the
+                # other directions' face fluxes, Un and Uin; Uout written
+                cells = case.ncells
+                nbytes = cells * (bpf - 40) + 3 * cells * case.nv * 8
+                nbytes += sum(40 * faces_of(D) for D in range(case.ndim - 1))
+            else:
+                nbytes = bpf * nf
+            t_alu, t_hbm = flops / PEAK_FP64, nbytes / PEAK_HBM
+            out = {"algorithmic_flops_per_face": fpf, "faces_per_launch": nf,
+                   "algorithmic_bytes": nbytes, "alu_frac": t_alu / t, "hbm_frac": t_hbm / t}
+            if t_hbm >= t_alu:
+                return {"bound": "hbm", "achieved": nbytes / t / 1e9, "peak": PEAK_HBM / 1e9,
+                        "unit": "GB/s", "frac": t_hbm / t} | out
+            return {"bound": "alu", "achieved": flops / t / 1e12, "peak": PEAK_FP64 / 1e12,
+                    "unit": "TFLOP/s", "frac": t_alu / t} | out
         nbytes = algorithmic_bytes(case, names[w])
-        a = nbytes / (kt[w] * 1e-3)
-        return {"bound": "hbm", "achieved": a / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "frac": a / PEAK_HBM, "algorithmic_bytes": nbytes}
+        return {"bound": "hbm", "achieved": nbytes / t / 1e9, "peak": PEAK_HBM / 1e9,
+                "unit": "GB/s", "frac": nbytes / t / PEAK_HBM, "algorithmic_bytes": nbytes}
 
     # dominant kernel: the step's slowest launch
     dom = max(step_kinds, key=lambda w: kt[w])
@@ -435,6 +452,9 @@ def main():
         per_kernel[names[w]] = {"bound": r["bound"], "frac": r["frac"],
                                 ("achieved_tflops" if r["bound"] == "alu" else "achieved_gbs"):
                                     r["achieved"], "in_step": w in step_kinds}
+        for k in ("alu_frac", "hbm_frac"):
+            if k in r:
+                per_kernel[names[w]][k] = r[k]
     roof["per_kernel"] = per_kernel
 
     out = {
