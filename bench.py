@@ -154,7 +154,9 @@ def step_kernel_ids(case):
     then the fused last-direction flux + update (6, 2D/3D without source) or
     the separate update (4)."""
     visc = case.visc_law != "none"
-    fused = case.ndim >= 2 and case.source == "none"
+    last = 2 * (case.ndim - 1)
+    fused = case.ndim >= 2 and (case.source == "none" or (
+        case.bc[last] == "periodic" and case.bc[last + 1] == "periodic"))
     ids = [0] + ([8] if fused else []) + ([5] if visc and case.ndim >= 2 else [])
     if case.ndim == 3:
         ids += [7] + ([6] if fused else [3, 4])

@@ -397,8 +397,19 @@ static dcf_status eval_fluxes(dcf_ctx *c, const double *U, hipStream_t st) {
 
 // One RK3 step in place; the stage states go to U1, U2 (default: scratch).
 // The last direction's fluxes are fused into the stage update where there is
-// no source term (the body force needs every boundary flux first).
-static bool fused_stages(const dcf_ctx *c) { return c->g.ndim >= 2 && c->g.source == SRC_NONE; }
+// no source term, or the constant-mass-flux source with a periodic last
+// direction: the body force needs every boundary flux, and a periodic
+// direction's boundary terms vanish, so the force is reduced from the other
+// directions' fluxes before the fused kernel applies it.
+static bool fused_stages(const dcf_ctx *c) {
+  const Dev &g = c->g;
+  if (g.ndim < 2) return false;
+  if (g.source == SRC_NONE) return true;
+  // the body force needs every boundary flux: only the last direction's can
+  // be left to the fused kernel, and only where they cancel (periodic)
+  const int f = 2 * (g.ndim - 1);
+  return g.source == SRC_MASSFLUX && g.bck[f] == BC_PERIODIC && g.bck[f + 1] == BC_PERIODIC;
+}
 
 static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_t st,
                              double *U1 = nullptr, double *U2 = nullptr,
@@ -425,7 +436,8 @@ static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_
       if (k == 0) DCF_HIP(launch_prim_halo(gk, in[k], st));
       else DCF_HIP(launch_prim_ghost(gk, st));
       DCF_HIP(launch_fluxes_update(gk, U, in[k], out[k], dt, a[k], b[k], k == 2 ? dtpart : nullptr,
-                                   st, k < 2 ? bo[(k + 1) & 1] : BoxOut{}));
+                                   st, k < 2 ? bo[(k + 1) & 1] : BoxOut{}, c->part,
+                                   g.source == SRC_MASSFLUX ? c->force : nullptr));
     }
     return DCF_OK;
   }
@@ -773,7 +785,9 @@ dcf_status dcf_time_kernel(dcf_ctx *c, const double *U, int which, int reps, dou
     if (which == 0) e = launch_prim_halo(g, U, st);
     else if (which <= 3) e = launch_flux_dir(g, which - 1, st);
     else if (which == 5) e = launch_grad(g, st);
-    else if (which == 6) e = launch_flux_update_last(g, U, U, c->U1, c->U2, 0.0, 1.0, nullptr, st);
+    else if (which == 6)
+      e = launch_flux_update_last(g, U, U, c->U1, c->U2, 0.0, 1.0, nullptr, st, BoxOut{},
+                                  g.source == SRC_MASSFLUX ? c->force : nullptr);
     else if (which == 7) e = launch_flux_xy(g, st);
     else if (which == 8) e = launch_prim_ghost(g, st);
     else e = launch_update(g, U, U, c->U1, nullptr, c->U2, 0.0, 1.0, c->force, st);

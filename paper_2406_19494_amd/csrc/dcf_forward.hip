@@ -674,7 +674,12 @@ __device__ __forceinline__ double block_max(double v, double *sh) {
 // periodic axis both boundary faces see the same stencil values, so their
 // fluxes are equal and cancel.)  Per-block partial sums of that boundary
 // term and of the volume, over one thread per boundary line.
-__global__ void __launch_bounds__(256) k_force_partial(Dev g, double *part) {
+// Directions D >= ndir are skipped (their faces not computed yet; the
+// caller guarantees that their boundary terms vanish, as for a periodic
+// direction, whose two boundary faces see the same stencil).  The grid and
+// the line-to-thread map do not depend on ndir, so the sums are bitwise
+// those over every direction.
+__global__ void __launch_bounds__(256) k_force_partial(Dev g, double *part, int ndir) {
   __shared__ double sh[2 * 256];
   double v[2] = {0.0, 0.0};
   const int nd = g.ndim;
@@ -688,6 +693,7 @@ __global__ void __launch_bounds__(256) k_force_partial(Dev g, double *part) {
     int D = 0;
     long l = x;
     while (l >= nl[D]) l -= nl[D++];
+    if (D >= ndir) continue;
     const int T1 = tan1(D), T2 = tan2(D);
     const int a = (int)(l % g.n[T1]), b = (int)(l / g.n[T1]);
     double A = 1.0;
@@ -861,7 +867,8 @@ __device__ __forceinline__ void flux_update_body(const Dev &g, unsigned lin, uns
                                                  const double *Uin, double *Uout,
                                                  const double *dtp, double a, double bcoef,
                                                  double *dtpart, unsigned bid,
-                                                 BoxOut qo = BoxOut{}) {
+                                                 BoxOut qo = BoxOut{},
+                                                 const double *force = nullptr) {
   using Tl = YzTile<NDIM, VISC>;
   __shared__ Tl T;
   const unsigned lg = xcd_remap(lin, ntot);
@@ -891,7 +898,7 @@ __device__ __forceinline__ void flux_update_body(const Dev &g, unsigned lin, uns
 #pragma unroll
     for (int m = 0; m < 5; ++m) R[m] -= (fl[m][ty + 1][tx] - fl[m][ty][tx]) * id;
     const long c = ((long)p[2] * g.n[1] + p[1]) * g.n[0] + p[0];
-    sig = stage_apply(g, Un, Uin, Uout, nullptr, dtp, a, bcoef, nullptr, c, p[0], p[1], p[2], R,
+    sig = stage_apply(g, Un, Uin, Uout, nullptr, dtp, a, bcoef, force, c, p[0], p[1], p[2], R,
                       dtpart != nullptr);
     if (qo.Q[0]) {
       // the new state's primitives, converted from the values just stored
@@ -921,12 +928,13 @@ __device__ __forceinline__ void flux_update_body(const Dev &g, unsigned lin, uns
 template <int NDIM, bool VISC>
 __global__ void __launch_bounds__(256) k_flux_update(Dev g, const double *Un, const double *Uin,
                                                      double *Uout, const double *dtp, double a,
-                                                     double bcoef, double *dtpart, BoxOut qo) {
+                                                     double bcoef, double *dtpart, BoxOut qo,
+                                                     const double *force) {
   constexpr int D = NDIM - 1;
   const unsigned nbx = gridDim.x, nby = gridDim.y;
   const unsigned lin = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
   flux_update_body<NDIM, D, VISC>(g, lin, nbx * nby * gridDim.z, nbx, nby, Un, Uin, Uout, dtp,
-                                  a, bcoef, dtpart, lin, qo);
+                                  a, bcoef, dtpart, lin, qo, force);
 }
 
 // ---------------------------------------------------------------------------
@@ -1209,10 +1217,10 @@ hipError_t launch_grad(const Dev &g, hipStream_t st) {
 template <int NDIM, bool VISC>
 static hipError_t launch_fu(const Dev &g, const double *Un, const double *Uin, double *Uout,
                             const double *dt, double a, double b, double *dtpart,
-                            const BoxOut &qo, hipStream_t st) {
+                            const BoxOut &qo, const double *force, hipStream_t st) {
   constexpr int D = NDIM - 1;
   dim3 grid((g.n[0] + 15) / 16, (g.n[D] + 14) / 15, D == 1 ? g.n[2] : g.n[1]);
-  k_flux_update<NDIM, VISC><<<grid, 256, 0, st>>>(g, Un, Uin, Uout, dt, a, b, dtpart, qo);
+  k_flux_update<NDIM, VISC><<<grid, 256, 0, st>>>(g, Un, Uin, Uout, dt, a, b, dtpart, qo, force);
   return hipGetLastError();
 }
 
@@ -1225,24 +1233,29 @@ unsigned flux_update_blocks(const Dev &g) {
 
 hipError_t launch_flux_update_last(const Dev &g, const double *Un, const double *Uin,
                                    double *Uout, const double *dt, double a, double b,
-                                   double *dtpart, hipStream_t st, const BoxOut &qo) {
+                                   double *dtpart, hipStream_t st, const BoxOut &qo,
+                                   const double *force) {
   const bool v = g.visc != VISC_NONE;
   if (g.ndim == 2)
-    return v ? launch_fu<2, true>(g, Un, Uin, Uout, dt, a, b, dtpart, qo, st)
-             : launch_fu<2, false>(g, Un, Uin, Uout, dt, a, b, dtpart, qo, st);
+    return v ? launch_fu<2, true>(g, Un, Uin, Uout, dt, a, b, dtpart, qo, force, st)
+             : launch_fu<2, false>(g, Un, Uin, Uout, dt, a, b, dtpart, qo, force, st);
   if (g.ndim == 3)
-    return v ? launch_fu<3, true>(g, Un, Uin, Uout, dt, a, b, dtpart, qo, st)
-             : launch_fu<3, false>(g, Un, Uin, Uout, dt, a, b, dtpart, qo, st);
+    return v ? launch_fu<3, true>(g, Un, Uin, Uout, dt, a, b, dtpart, qo, force, st)
+             : launch_fu<3, false>(g, Un, Uin, Uout, dt, a, b, dtpart, qo, force, st);
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_fluxes_update(const Dev &g, const double *Un, const double *Uin,
                                 double *Uout, const double *dt, double a, double b,
-                                double *dtpart, hipStream_t st, const BoxOut &qo) {
+                                double *dtpart, hipStream_t st, const BoxOut &qo,
+                                double *part, double *force) {
   hipError_t e = launch_grad(g, st);
   if (e == hipSuccess) e = g.ndim == 3 ? launch_flux_xy(g, st) : launch_flux_dir(g, 0, st);
+  // the body force from the boundary fluxes of the directions before the
+  // last (the last one is periodic: its boundary terms vanish)
+  if (e == hipSuccess && force) e = launch_force(g, part, force, st, g.ndim - 1);
   if (e != hipSuccess) return e;
-  return launch_flux_update_last(g, Un, Uin, Uout, dt, a, b, dtpart, st, qo);
+  return launch_flux_update_last(g, Un, Uin, Uout, dt, a, b, dtpart, st, qo, force);
 }
 
 hipError_t launch_prim_ghost(const Dev &g, hipStream_t st) {
@@ -1275,11 +1288,11 @@ hipError_t launch_fluxes(const Dev &g, hipStream_t st) {
   }
   return hipSuccess;
 }
-hipError_t launch_force(const Dev &g, double *part, double *force, hipStream_t st) {
+hipError_t launch_force(const Dev &g, double *part, double *force, hipStream_t st, int ndir) {
   long lines = 0;
   for (int D = 0; D < g.ndim; ++D) lines += (long)g.n[tan1(D)] * g.n[tan2(D)];
   unsigned nb = grid_capped(lines, RED_BLOCKS);
-  k_force_partial<<<nb, 256, 0, st>>>(g, part);
+  k_force_partial<<<nb, 256, 0, st>>>(g, part, ndir < 0 ? g.ndim : ndir);
   k_force_final<<<1, 256, 0, st>>>(part, (int)nb, force);
   return hipGetLastError();
 }

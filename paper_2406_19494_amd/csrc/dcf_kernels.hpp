@@ -38,7 +38,9 @@ hipError_t launch_flux_dir(const Dev &g, int D, hipStream_t st);
 // x and y face fluxes of a 3D grid in one launch.
 hipError_t launch_flux_xy(const Dev &g, hipStream_t st);
 hipError_t launch_grad(const Dev &g, hipStream_t st);
-hipError_t launch_force(const Dev &g, double *part, double *force, hipStream_t st);
+// Body force of the constant-mass-flux source from the boundary face fluxes
+// of directions D < ndir (default: all; the others must be periodic).
+hipError_t launch_force(const Dev &g, double *part, double *force, hipStream_t st, int ndir = -1);
 // With dtpart (update_blocks(g) doubles) each block also writes the largest
 // signal rate of its cells' new state (the CFL step of the next step).
 hipError_t launch_update(const Dev &g, const double *Un, const double *Uin, double *Uout,
@@ -52,16 +54,20 @@ unsigned update_blocks(const Dev &g);
 // With qo the kernel also writes the new state's primitives (and mu) into
 // the interior of the box qo (same layout as g.Q, another buffer), as
 // k_prim_interior would: the next stage then only fills the ghosts
-// (launch_prim_ghost on a context whose Q is qo).
+// (launch_prim_ghost on a context whose Q is qo).  With force (the
+// constant-mass-flux source; the last direction periodic) the body force is
+// reduced into force (partials in part) before the fused kernel applies it.
 hipError_t launch_fluxes_update(const Dev &g, const double *Un, const double *Uin,
                                 double *Uout, const double *dt, double a, double b,
-                                double *dtpart, hipStream_t st, const BoxOut &qo = BoxOut{});
+                                double *dtpart, hipStream_t st, const BoxOut &qo = BoxOut{},
+                                double *part = nullptr, double *force = nullptr);
 unsigned flux_update_blocks(const Dev &g);
 // The last direction's flux + update kernel alone (its gradient and other
 // fluxes already computed).
 hipError_t launch_flux_update_last(const Dev &g, const double *Un, const double *Uin,
                                    double *Uout, const double *dt, double a, double b,
-                                   double *dtpart, hipStream_t st, const BoxOut &qo = BoxOut{});
+                                   double *dtpart, hipStream_t st, const BoxOut &qo = BoxOut{},
+                                   const double *force = nullptr);
 // Ghost cells of the box from its interior (the interior already filled).
 hipError_t launch_prim_ghost(const Dev &g, hipStream_t st);
 hipError_t launch_dt_final(const double *part, int nparts, double cfl, double dt_max, double *dt,

@@ -22,7 +22,9 @@ def test_step_kernels_of_each_family():
     tgv, _ = W.tgv(8)
     assert bench.step_kernel_ids(tgv) == [0, 8, 5, 7, 6]
     ch, _ = W.channel(16, 8, 8)
-    assert bench.step_kernel_ids(ch) == [0, 5, 7, 3, 4]  # body force: unfused update
+    assert bench.step_kernel_ids(ch) == [0, 8, 5, 7, 6]  # body force, periodic z: fused
+    ch.bc = ch.bc[:4] + ("wall", "wall")
+    assert bench.step_kernel_ids(ch) == [0, 5, 7, 3, 4]  # body force, walls in z: unfused
     bl, _, _ = W.porous_bl(nx=16, ny=8)
     assert bench.step_kernel_ids(bl) == [0, 8, 5, 1, 6]
     sod, _ = W.sod(50)
