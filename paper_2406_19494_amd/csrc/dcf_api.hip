@@ -518,6 +518,9 @@ dcf_status dcf_batch_rk3_step(dcf_ctx *const *ctxs, double *const *U, double *co
       return fail(DCF_EUNSUPPORTED, "solve %d: source terms are not batched", i);
     BatchEntry &e = h[i];
     e.g = g;
+    e.gb = g;
+    if (g.ndim >= 2)
+      for (int q = 0; q < NQ; ++q) e.gb.Q[q] = c->qalt.Q[q];
     e.U = U[i];
     e.U1 = c->U1;
     e.U2 = c->U2;

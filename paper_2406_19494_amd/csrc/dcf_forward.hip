@@ -1375,6 +1375,65 @@ __global__ void __launch_bounds__(256) kb_update(const BatchEntry *tab, int stag
               blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// The fused-step forms (2D/3D): stage s works on the box of g (s even) or gb
+// (s odd); the update of stages 0 and 1 writes the next stage's interior.
+__device__ __forceinline__ const Dev &stage_dev(const BatchEntry &e, int stage) {
+  return (stage & 1) ? e.gb : e.g;
+}
+
+__global__ void __launch_bounds__(256) kb_prim_ghost_s(const BatchEntry *tab, int stage) {
+  const BatchEntry &e = tab[blockIdx.y];
+  if (blockIdx.x >= e.nb_ghost) return;
+  prim_ghost_body(stage_dev(e, stage), blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <int NDIM>
+__global__ void __launch_bounds__(256) kb_grad_s(const BatchEntry *tab, int stage) {
+  const BatchEntry &e = tab[blockIdx.y];
+  if (blockIdx.x >= e.nb_grad) return;
+  grad_body<NDIM>(stage_dev(e, stage), blockIdx.z, blockIdx.x, e.nb_grad);
+}
+
+template <bool VISC>
+__global__ void __launch_bounds__(256) kb_flux_xy(const BatchEntry *tab, int stage) {
+  extern __shared__ double lds[];
+  const BatchEntry &e = tab[blockIdx.y];
+  const unsigned ny_tiles = e.yz_ntot[1];
+  if (blockIdx.x >= ny_tiles + e.nb_x) return;
+  const Dev &g = stage_dev(e, stage);
+  if (blockIdx.x < ny_tiles)
+    flux_yz_tile<3, 1, VISC>(g, *reinterpret_cast<YzTile<3, VISC> *>(lds), blockIdx.x, ny_tiles,
+                             e.yz_nbx[1], e.yz_nby[1]);
+  else
+    flux_x_body<3, VISC>(g, e.nwmax, blockIdx.x - ny_tiles, lds);
+}
+
+template <bool VISC>
+__global__ void __launch_bounds__(256) kb_flux_x_s(const BatchEntry *tab, int stage) {
+  extern __shared__ double lds[];
+  const BatchEntry &e = tab[blockIdx.y];
+  if (blockIdx.x >= e.nb_x) return;
+  flux_x_body<2, VISC>(stage_dev(e, stage), e.nwmax, blockIdx.x, lds);
+}
+
+template <int NDIM, bool VISC>
+__global__ void __launch_bounds__(256) kb_flux_update(const BatchEntry *tab, int stage) {
+  const BatchEntry &e = tab[blockIdx.y];
+  if (blockIdx.x >= e.fu_ntot) return;
+  const double a = stage == 0 ? 0.0 : (stage == 1 ? 0.75 : 1.0 / 3.0);
+  const double b = stage == 0 ? 1.0 : (stage == 1 ? 0.25 : 2.0 / 3.0);
+  double *out = stage == 0 ? e.U1 : (stage == 1 ? e.U2 : e.U);
+  BoxOut qo;
+  if (stage < 2) {
+    const Dev &gn = stage_dev(e, stage + 1);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) qo.Q[q] = gn.Q[q];
+  }
+  flux_update_body<NDIM, NDIM - 1, VISC>(stage_dev(e, stage), blockIdx.x, e.fu_ntot, e.fu_nbx,
+                                         e.fu_nby, e.U, stage_in(e, stage), out, e.dt, a, b,
+                                         nullptr, blockIdx.x, qo);
+}
+
 __global__ void __launch_bounds__(256) kb_dt_partial(const BatchEntry *tab) {
   const BatchEntry &e = tab[blockIdx.y];
   if (blockIdx.x >= e.nb_dt) return;
@@ -1404,6 +1463,13 @@ void batch_entry_sizes(BatchEntry &e) {
     e.yz_nby[D] = (g.n[D] + 1 + 15) / 16;
     e.yz_ntot[D] = e.yz_nbx[D] * e.yz_nby[D] * (D == 1 ? g.n[2] : g.n[1]);
   }
+  e.fu_nbx = e.fu_nby = e.fu_ntot = 0;
+  if (g.ndim >= 2) {
+    const int D = g.ndim - 1;
+    e.fu_nbx = (g.n[0] + 15) / 16;
+    e.fu_nby = (g.n[D] + 14) / 15;
+    e.fu_ntot = e.fu_nbx * e.fu_nby * (D == 1 ? g.n[2] : g.n[1]);
+  }
 }
 
 template <int NDIM, bool VISC>
@@ -1427,6 +1493,24 @@ static hipError_t batch_step_t(const BatchEntry *tab, const BatchEntry *h, int n
     kb_dt_final<<<ny, 256, 0, st>>>(tab, cfl);
   }
   const size_t shm = sizeof(double) * Slots<NDIM, VISC>::NC * nw;
+  if (NDIM >= 2) {
+    // the single-solve step's launch sequence, one launch per kernel for all
+    unsigned mf = 0;
+    for (int i = 0; i < n; ++i) mf = std::max(mf, h[i].fu_ntot);
+    constexpr int ND = NDIM < 2 ? 2 : NDIM;
+    const size_t shm_xy = std::max(shm, sizeof(YzTile<ND, VISC>));
+    for (int stage = 0; stage < 3; ++stage) {
+      if (stage == 0) kb_prim_interior<<<dim3(mp, ny), 256, 0, st>>>(tab, 0);
+      if (mh) kb_prim_ghost_s<<<dim3(mh, ny), 256, 0, st>>>(tab, stage);
+      if (VISC) kb_grad_s<ND><<<dim3(mg, ny, NDIM), 256, 0, st>>>(tab, stage);
+      if (NDIM == 3)
+        kb_flux_xy<VISC><<<dim3(my[1] + mx, ny), 256, shm_xy, st>>>(tab, stage);
+      else
+        kb_flux_x_s<VISC><<<dim3(mx, ny), 256, shm, st>>>(tab, stage);
+      kb_flux_update<ND, VISC><<<dim3(mf, ny), 256, 0, st>>>(tab, stage);
+    }
+    return hipGetLastError();
+  }
   for (int stage = 0; stage < 3; ++stage) {
     kb_prim_interior<<<dim3(mp, ny), 256, 0, st>>>(tab, stage);
     if (mh) kb_prim_ghost<<<dim3(mh, ny), 256, 0, st>>>(tab);

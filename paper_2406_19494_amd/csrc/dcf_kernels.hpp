@@ -13,11 +13,14 @@ constexpr int RED_BLOCKS = 1024;  // partial-sum slots of the two-pass reduction
 // table of the batched launches (workgroup (x, y) = tile x of solve y).
 struct BatchEntry {
   Dev g;
+  Dev gb;               // the same solve with the second primitive box (2D/3D stages
+                        // alternate the two, as the single-solve step does)
   double *U, *U1, *U2;  // state (advanced in place) and the two stage states
   double *dt;           // step size (device, one double)
   double *part;         // reduction partials of the CFL step
   unsigned nb_prim, nb_ghost, nb_grad, nb_x, nb_upd, nb_dt;
   unsigned yz_nbx[3], yz_nby[3], yz_ntot[3];  // tile grids of the y and z fluxes
+  unsigned fu_nbx, fu_nby, fu_ntot;           // tile grid of the fused last-direction kernel
   int nwmax;            // x-flux LDS window length
 };
 
