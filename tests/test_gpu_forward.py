@@ -140,6 +140,38 @@ def test_run_to_run_bitwise_deterministic():
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("which", ["tgv", "channel", "porous_bl"])
+def test_calls_between_steps_do_not_change_them(which):
+    # a step rebuilds its primitive boxes from U (the fused stages alternate
+    # two boxes inside the step), so right-hand sides, diagnostics, CFL steps
+    # or another context's work between steps leave the trajectory bitwise
+    # unchanged
+    if which == "tgv":
+        case, P = W.tgv(16)
+        K = None
+    elif which == "channel":
+        case, P = W.channel(nx=16, ny=24, nz=8)
+        K = None
+    else:
+        case, P, K = W.porous_bl(nx=64, ny=32, strip=(16, 48))
+    outs = []
+    for interleave in (False, True):
+        s = Solver(case, K=K)
+        other = Solver(case, K=K)
+        U = s.init_state(P)
+        V = other.init_state(P)
+        dt = s.compute_dt(U, cfl=0.4)
+        for k in range(4):
+            s.step(U, dt)
+            if interleave:
+                s.rhs(U)
+                s.diagnostics(U)
+                s.compute_dt(U, cfl=0.3)
+                other.step(V, dt)
+        outs.append(U.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_nonphysical_state_is_flagged():
     case, P = W.sod(50)
     P = P.copy()
