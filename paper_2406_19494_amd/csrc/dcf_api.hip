@@ -643,60 +643,78 @@ static Dev stage_box(const dcf_ctx *c, int n, int s) {
   return d;
 }
 
+// Step k of the current segment, keeping what the reverse sweep needs:
+// seg[k+1] from seg[k], the two inner stage states and (mode 3) every
+// stage's primitive and derivative boxes.
+static dcf_status segment_step(dcf_ctx *c, int k, hipStream_t st) {
+  auto &gr = c->gr;
+  Dev &g = c->g;
+  const long M = (long)g.nv * g.ncell;
+  double *Ua = c->seg + (long)k * M, *Ub = Ua + M;
+  DCF_HIP(launch_copy(Ub, Ua, M, st));
+  double *S1 = c->sst + (long)(2 * k) * M, *S2 = S1 + M;
+  if (c->boxc && g.source == SRC_NONE) {  // the same three stages, keeping each stage's boxes
+    const double *in[3] = {Ub, S1, S2};
+    double *out[3] = {S1, S2, Ub};
+    const double a[3] = {0.0, 0.75, 1.0 / 3.0}, b[3] = {1.0, 0.25, 2.0 / 3.0};
+    for (int s = 0; s < 3; ++s) {
+      const Dev gs = stage_box(c, k, s);
+      if (fused_stages(c)) {
+        // as rk3_stages: each update writes the interior of the next
+        // stage's cached box
+        BoxOut next;
+        if (s < 2) {
+          const Dev gn = stage_box(c, k, s + 1);
+          for (int q = 0; q < NQ; ++q) next.Q[q] = gn.Q[q];
+        }
+        if (s == 0) DCF_HIP(launch_prim_halo(gs, in[s], st));
+        else DCF_HIP(launch_prim_ghost(gs, st));
+        DCF_HIP(launch_fluxes_update(gs, Ub, in[s], out[s], gr.dt, a[s], b[s], nullptr, st,
+                                     next));
+      } else {
+        DCF_HIP(launch_prim_halo(gs, in[s], st));
+        DCF_HIP(launch_fluxes(gs, st));
+        DCF_HIP(launch_update(gs, Ub, in[s], out[s], nullptr, gr.dt, a[s], b[s], nullptr, st));
+      }
+    }
+    return DCF_OK;
+  }
+  return rk3_stages(c, Ub, gr.dt, st, S1, S2);
+}
+
 static dcf_status gradient_unit(dcf_ctx *c, hipStream_t st) {
   auto &gr = c->gr;
   Dev &g = c->g;
   const long M = (long)g.nv * g.ncell;
   const double w = 1.0 / gr.nsteps;
   const int nseg = (gr.nsteps + gr.seg_len - 1) / gr.seg_len;
+  const int last0 = (nseg - 1) * gr.seg_len;  // first step of the last segment
   dcf_status s;
   if (gr.phase == 0) {  // forward sweep
     if (gr.n % gr.seg_len == 0)
       DCF_HIP(launch_copy(c->ckpt + (long)(gr.n / gr.seg_len) * M, c->seg, M, st));
-    if ((s = rk3_stages(c, c->seg, gr.dt, st))) return s;
-    DCF_HIP(launch_cost(g, c->cost_face, c->cost_pref, c->seg, w, gr.J, nullptr, st));
+    const double *Unew = c->seg;
+    if (gr.n >= last0) {
+      // the last segment is the first one reversed: its steps keep their
+      // states now, so it needs no recompute (seg[0] holds U^last0)
+      const int k = gr.n - last0;
+      if ((s = segment_step(c, k, st))) return s;
+      Unew = c->seg + (long)(k + 1) * M;
+    } else if ((s = rk3_stages(c, c->seg, gr.dt, st))) {
+      return s;
+    }
+    DCF_HIP(launch_cost(g, c->cost_face, c->cost_pref, Unew, w, gr.J, nullptr, st));
     if (++gr.n == gr.nsteps) {
-      gr.phase = 1;
+      gr.phase = 2;
       gr.sgi = nseg - 1;
-      gr.n = 0;
       DCF_HIP(launch_fill(gr.lam, 0.0, M, st));
-      DCF_HIP(launch_copy(c->seg, c->ckpt + (long)gr.sgi * M, M, st));
     }
     return DCF_OK;
   }
   const int n0 = gr.sgi * gr.seg_len;
   const int n1 = n0 + gr.seg_len < gr.nsteps ? n0 + gr.seg_len : gr.nsteps;
-  if (gr.phase == 1) {  // recompute U^{n0+1} .. U^{n1} of the segment, keeping stage states
-    double *Ua = c->seg + (long)gr.n * M, *Ub = Ua + M;
-    DCF_HIP(launch_copy(Ub, Ua, M, st));
-    double *S1 = c->sst + (long)(2 * gr.n) * M, *S2 = S1 + M;
-    if (c->boxc && g.source == SRC_NONE) {  // the same three stages, keeping each stage's boxes
-      const double *in[3] = {Ub, S1, S2};
-      double *out[3] = {S1, S2, Ub};
-      const double a[3] = {0.0, 0.75, 1.0 / 3.0}, b[3] = {1.0, 0.25, 2.0 / 3.0};
-      for (int k = 0; k < 3; ++k) {
-        const Dev gs = stage_box(c, gr.n, k);
-        if (fused_stages(c)) {
-          // as rk3_stages: each update writes the interior of the next
-          // stage's cached box
-          BoxOut next;
-          if (k < 2) {
-            const Dev gn = stage_box(c, gr.n, k + 1);
-            for (int q = 0; q < NQ; ++q) next.Q[q] = gn.Q[q];
-          }
-          if (k == 0) DCF_HIP(launch_prim_halo(gs, in[k], st));
-          else DCF_HIP(launch_prim_ghost(gs, st));
-          DCF_HIP(launch_fluxes_update(gs, Ub, in[k], out[k], gr.dt, a[k], b[k], nullptr, st,
-                                       next));
-        } else {
-          DCF_HIP(launch_prim_halo(gs, in[k], st));
-          DCF_HIP(launch_fluxes(gs, st));
-          DCF_HIP(launch_update(gs, Ub, in[k], out[k], nullptr, gr.dt, a[k], b[k], nullptr, st));
-        }
-      }
-    } else if ((s = rk3_stages(c, Ub, gr.dt, st, S1, S2))) {
-      return s;
-    }
+  if (gr.phase == 1) {  // recompute U^{n0+1} .. U^{n1} of the segment, keeping stage data
+    if ((s = segment_step(c, gr.n, st))) return s;
     if (++gr.n == n1 - n0) {
       gr.phase = 2;
       gr.n = n1;
