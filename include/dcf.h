@@ -224,8 +224,10 @@ dcf_status dcf_cost_term(dcf_ctx *ctx, const double *U_dev, double w, double *J_
 
 /* J = (1/nsteps) sum_{n=1..nsteps} j(U^n) over a fixed-dt trajectory from U0,
  * and its gradient with respect to K and U0 by checkpointing every seg_len
- * steps and recomputing each segment in reverse (workspace mode 2).  Any
- * output pointer may be NULL except J_dev. */
+ * steps and recomputing each segment in reverse (workspace mode 2 or 3); the
+ * last segment keeps its states from the forward sweep and is not
+ * recomputed (seg_len >= nsteps: no recompute at all).  Any output pointer
+ * may be NULL except J_dev. */
 dcf_status dcf_gradient(dcf_ctx *ctx, const double *U0_dev, int nsteps, const double *dt_dev,
                         int seg_len, double *J_dev, double *dJdK_dev, double *dJdU0_dev,
                         void *stream);
@@ -241,8 +243,7 @@ dcf_status dcf_gradient(dcf_ctx *ctx, const double *U0_dev, int nsteps, const do
  * the step runs in place of 1 and 2), 8 the ghost cells of the primitive box
  * alone (stages 2 and 3 of such a step: the previous stage's update wrote
  * the interior).  The inputs it needs (primitive box, derivatives, face
- * fluxes)
- * are computed from U once before timing.  DCF_EINVAL for an unknown `which`
+ * fluxes) are computed from U once before timing.  DCF_EINVAL for an unknown `which`
  * or one the case does not have. */
 dcf_status dcf_time_kernel(dcf_ctx *ctx, const double *U_dev, int which, int reps,
                            double *avg_ms, void *stream);
@@ -251,7 +252,8 @@ dcf_status dcf_time_kernel(dcf_ctx *ctx, const double *U_dev, int which, int rep
  * solves: begin validates and records the request (same arguments as
  * dcf_gradient, J and dJdK zeroed on `stream`); advance enqueues at most
  * max_units units of work -- a forward step with its checkpoint and cost
- * term, a recomputed step of the current segment, or one reverse step -- and
+ * term, a recomputed step of the current segment, or one reverse step (the
+ * first nsteps units are the forward sweep, after which J is complete) -- and
  * sets *done once the reverse sweep has reached U0; finish copies dJ/dU0
  * (nullable).  Between calls nothing is read back; the host keeps only the
  * position in the trajectory. */
