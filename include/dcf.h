@@ -186,6 +186,15 @@ dcf_status dcf_rk3_step(dcf_ctx *ctx, double *U_dev, const double *dt_dev, void 
 dcf_status dcf_rk3_step_cfl(dcf_ctx *ctx, double *U_dev, const double *dt_dev, double cfl,
                             double dt_max, double *dt_next_dev, void *stream);
 
+/* nsteps calls of dcf_rk3_step_cfl with dt_next = dt, in one call: each
+ * step advances U with dt_dev[0], then dt_dev[0] becomes the CFL step of
+ * the new state.  Bitwise the same U and dt as the separate calls; cheaper,
+ * since a step after the first starts from the primitive box the previous
+ * step's last update wrote (U is not touched in between).  DCF_EINVAL for
+ * nsteps < 1 or cfl <= 0. */
+dcf_status dcf_rk3_steps_cfl(dcf_ctx *ctx, double *U_dev, double *dt_dev, int nsteps, double cfl,
+                             double dt_max, void *stream);
+
 /* ---- batched stepping (the serving loop's step launches) ---------------- */
 /* Bytes of the device table dcf_batch_rk3_step needs for n solves. */
 dcf_status dcf_batch_table_bytes(int n, size_t *bytes);

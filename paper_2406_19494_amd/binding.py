@@ -69,6 +69,7 @@ _SIGS = {
     "dcf_time_kernel": [_vp, _vp, C.c_int, C.c_int, C.POINTER(C.c_double), _vp],
     "dcf_batch_table_bytes": [C.c_int, C.POINTER(C.c_size_t)],
     "dcf_rk3_step_cfl": [_vp, _vp, _vp, C.c_double, C.c_double, _vp, _vp],
+    "dcf_rk3_steps_cfl": [_vp, _vp, _vp, C.c_int, C.c_double, C.c_double, _vp],
     "dcf_batch_rk3_step": [C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.c_int, C.c_double,
                            _vp, C.c_size_t, _vp],
 }

@@ -411,9 +411,16 @@ static bool fused_stages(const dcf_ctx *c) {
   return g.source == SRC_MASSFLUX && g.bck[f] == BC_PERIODIC && g.bck[f + 1] == BC_PERIODIC;
 }
 
+// Fused steps chain their primitive boxes: stage k of a step works on box
+// (base + k) & 1 (0: g.Q, 1: qalt).  With box_ready the interior of the
+// first stage's box already holds the primitives of U (written by the
+// previous step's last update), so only its ghosts are filled; with
+// write_next the last update writes the primitives of the new state into
+// box (base + 1) & 1, the first box of a following step with the other base.
 static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_t st,
                              double *U1 = nullptr, double *U2 = nullptr,
-                             double *dtpart = nullptr) {
+                             double *dtpart = nullptr, int base = 0, bool box_ready = false,
+                             bool write_next = false) {
   Dev &g = c->g;
   if (!U1) U1 = c->U1;
   if (!U2) U2 = c->U2;
@@ -432,11 +439,12 @@ static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_
       bo[1].Q[q] = c->qalt.Q[q];
     }
     for (int k = 0; k < 3; ++k) {
-      const Dev &gk = gs[k & 1];
-      if (k == 0) DCF_HIP(launch_prim_halo(gk, in[k], st));
+      const Dev &gk = gs[(base + k) & 1];
+      if (k == 0 && !box_ready) DCF_HIP(launch_prim_halo(gk, in[k], st));
       else DCF_HIP(launch_prim_ghost(gk, st));
+      const bool next = k < 2 || write_next;
       DCF_HIP(launch_fluxes_update(gk, U, in[k], out[k], dt, a[k], b[k], k == 2 ? dtpart : nullptr,
-                                   st, k < 2 ? bo[(k + 1) & 1] : BoxOut{}, c->part,
+                                   st, next ? bo[(base + k + 1) & 1] : BoxOut{}, c->part,
                                    g.source == SRC_MASSFLUX ? c->force : nullptr));
     }
     return DCF_OK;
@@ -546,6 +554,28 @@ dcf_status dcf_rk3_step_cfl(dcf_ctx *c, double *U, const double *dt, double cfl,
   if ((s = rk3_stages(c, U, dt, st, nullptr, nullptr, c->dtpart))) return s;
   const unsigned nparts = fused_stages(c) ? flux_update_blocks(c->g) : update_blocks(c->g);
   DCF_HIP(launch_dt_final(c->dtpart, (int)nparts, cfl, dt_max, dt_next, st));
+  return DCF_OK;
+}
+
+dcf_status dcf_rk3_steps_cfl(dcf_ctx *c, double *U, double *dt, int nsteps, double cfl,
+                             double dt_max, void *stream) {
+  dcf_status s = ready(c, 0);
+  if (s) return s;
+  if (!U || !dt) return fail(DCF_EINVAL, "null array");
+  if (nsteps < 1) return fail(DCF_EINVAL, "nsteps must be >= 1");
+  if (!(cfl > 0.0)) return fail(DCF_EINVAL, "cfl must be > 0");
+  if (!(dt_max > 0.0)) dt_max = 1.0e300;
+  hipStream_t st = (hipStream_t)stream;
+  const bool fused = fused_stages(c);
+  const unsigned nparts = fused ? flux_update_blocks(c->g) : update_blocks(c->g);
+  for (int n = 0; n < nsteps; ++n) {
+    // U is not touched between the steps of this call: each step after the
+    // first starts from the primitive box the previous one left
+    if ((s = rk3_stages(c, U, dt, st, nullptr, nullptr, c->dtpart, n & 1, fused && n > 0,
+                        fused && n + 1 < nsteps)))
+      return s;
+    DCF_HIP(launch_dt_final(c->dtpart, (int)nparts, cfl, dt_max, dt, st));
+  }
   return DCF_OK;
 }
 

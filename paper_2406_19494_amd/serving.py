@@ -296,8 +296,7 @@ class GpuBackend:
                     job.graph = torch.cuda.CUDAGraph()
                     job.stream.synchronize()
                     with torch.cuda.graph(job.graph, stream=job.stream):
-                        for _ in range(self.k):
-                            job.solver.step_cfl(job.U, job.dt, cfl=case.cfl)
+                        job.solver.steps_cfl(job.U, job.dt, self.k, cfl=case.cfl)
                     # capture records without running: state unchanged so far
         job.events = deque()
         for _ in range(self.inflight):
@@ -326,9 +325,7 @@ class GpuBackend:
                 if job.graph is not None and n == self.k:
                     job.graph.replay()
                 else:
-                    case = s.case
-                    for _ in range(n):
-                        s.step_cfl(job.U, job.dt, cfl=case.cfl, stream=job.stream)
+                    s.steps_cfl(job.U, job.dt, n, cfl=s.case.cfl, stream=job.stream)
                 job.enqueued += n
             ev = torch.cuda.Event()
             ev.record(job.stream)

@@ -148,6 +148,14 @@ class Solver:
                _stream(stream))
         return out
 
+    def steps_cfl(self, U: torch.Tensor, dt: torch.Tensor, nsteps: int, cfl=None, dt_max=0.0,
+                  stream=None) -> torch.Tensor:
+        """nsteps of step_cfl in one call (dt updated in place after each
+        step); bitwise the same, with less work per step."""
+        B.call("dcf_rk3_steps_cfl", self.ctx, _ptr(U), _ptr(dt), int(nsteps),
+               float(self.case.cfl if cfl is None else cfl), float(dt_max), _stream(stream))
+        return dt
+
     def run(self, U: torch.Tensor, nsteps: int, dt_fixed: float = 0.0, t_end: float = 0.0,
             cfl=None):
         """Advance U in place.  With dt_fixed > 0 the step is fixed; otherwise

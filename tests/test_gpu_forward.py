@@ -172,6 +172,38 @@ def test_calls_between_steps_do_not_change_them(which):
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("which", ["tgv", "channel", "porous_bl", "sod"])
+def test_multi_step_call_equals_single_steps(which):
+    # dcf_rk3_steps_cfl: bitwise the state and CFL step of the same number of
+    # dcf_rk3_step_cfl calls (the steps chain their primitive boxes)
+    if which == "tgv":
+        case, P = W.tgv(16)
+        K = None
+    elif which == "channel":
+        case, P = W.channel(nx=16, ny=24, nz=8)
+        K = None
+    elif which == "porous_bl":
+        case, P, K = W.porous_bl(nx=64, ny=32, strip=(16, 48))
+    else:
+        case, P = W.sod(200)
+        K = None
+    out = []
+    for multi in (False, True):
+        s = Solver(case, K=K)
+        U = s.init_state(P)
+        dt = s.compute_dt(U, cfl=case.cfl)
+        if multi:
+            s.steps_cfl(U, dt, 5, cfl=case.cfl)
+            s.steps_cfl(U, dt, 1, cfl=case.cfl)
+        else:
+            for _ in range(6):
+                s.step_cfl(U, dt, cfl=case.cfl)
+        assert s.flags() == 0
+        out.append((U.cpu().numpy(), dt.item()))
+    assert np.array_equal(out[0][0], out[1][0]), which
+    assert out[0][1] == out[1][1]
+
+
 def test_nonphysical_state_is_flagged():
     case, P = W.sod(50)
     P = P.copy()

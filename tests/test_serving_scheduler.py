@@ -192,6 +192,9 @@ class _FakeSolver:
     def step_cfl(self, *a, **k):
         self.steps += 1
 
+    def steps_cfl(self, U, dt, n, *a, **k):
+        self.steps += n
+
     def gradient_advance(self, n, stream=None):
         self.units = min(self.units_needed, self.units + n)
         return self.units == self.units_needed
