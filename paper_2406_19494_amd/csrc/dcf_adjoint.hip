@@ -319,6 +319,11 @@ __global__ void __launch_bounds__(256) k_dir_vjp(Dev g, AdjBuffers A) {
   __shared__ double buf[NOFF][TW][BF];  // one component's contributions per face
   Tile t = make_tile<OLO, OHI, D>(g);
   for (int i = threadIdx.x; i < NCH * TW * NCW; i += 256) (&acc[0][0][0])[i] = 0.0;
+  // x tiles: each wavefront holds the 64 faces of one line and its lanes
+  // are the only writers of that line's window, one lane per cell in the
+  // convective gather, so after this barrier that gather uses lane shuffles
+  // and no barrier
+  if (D == 0) __syncthreads();
 
   const int f = t.f0 + t.lane_face;
   const bool active = t.line_ok && f >= 0 && f <= g.n[D];
@@ -370,6 +375,22 @@ __global__ void __launch_bounds__(256) k_dir_vjp(Dev g, AdjBuffers A) {
       c[3] = gL[3] + gR[2];
       c[4] = gL[4] + gR[1];
       c[5] = gR[0];
+    }
+    if (D == 0) {
+      // window cell w = L (and w = 64 + L for the last SPAN cells) takes
+      // offset o from lane w - o, in the order of the LDS gather below
+      const int L = t.lane_face;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int o = 0; o < NOFF; ++o) {
+        const double v0 = __shfl(c[o], L - o);
+        const double v1 = __shfl(c[o], TF + L - o);
+        if (L >= o) s0 += v0;
+        if (o > L) s1 += v1;
+      }
+      acc[ch[m]][t.lane_line][L] += s0;
+      if (L < SPAN) acc[ch[m]][t.lane_line][TF + L] += s1;
+      continue;
     }
 #pragma unroll
     for (int o = 0; o < NOFF; ++o) buf[o][t.lane_line][t.lane_face] = c[o];
@@ -480,9 +501,11 @@ __global__ void __launch_bounds__(256) k_dir_vjp(Dev g, AdjBuffers A) {
           acc[CG + 3][ll][w] += dtnb[T2] * im;
         }
       }
+      // neighbouring faces update the same cells at consecutive offsets
       __syncthreads();
     }
   }
+  if (D == 0 && !VISC) __syncthreads();  // every line's window complete before the write-out
   // write the completed cells: window cell w <-> cell t.f0 + OLO + w
   for (int i = threadIdx.x; i < TW * NCW; i += 256) {
     // x-lines: consecutive threads take consecutive cells of a line;
