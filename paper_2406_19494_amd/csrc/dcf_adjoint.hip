@@ -98,8 +98,10 @@ __device__ void hllc_vjp(const double *qL, const double *qR, double gamma, const
   double rR = qR[0], uR = qR[1], vR = qR[2], wR = qR[3], pR = qR[4];
   double EL = pL * gm1i + 0.5 * rL * (uL * uL + vL * vL + wL * wL);
   double ER = pR * gm1i + 0.5 * rR * (uR * uR + vR * vR + wR * wR);
-  double cL = sqrt(gamma * pL / rL);
-  double cR = sqrt(gamma * pR / rR);
+  // wave speeds, star speed and star reciprocal in the forward's arithmetic
+  // (same branch decisions)
+  double cL = sound_speed(gamma, rL, pL);
+  double cR = sound_speed(gamma, rR, pR);
   double aL = uL - cL, bL = uR - cR;
   const bool selL = bL < aL;
   double SL = selL ? bL : aL;
@@ -117,11 +119,11 @@ __device__ void hllc_vjp(const double *qL, const double *qR, double gamma, const
   }
   double mL = rL * (SL - uL), mR = rR * (SR - uR);
   double Nn = pR - pL + uL * mL - uR * mR, Dd = mL - mR;
-  double Ss = Nn / Dd;
+  double Ss = Nn * rcp_nr(Dd);
   const bool left = (0.0 <= Ss);
   double r = left ? rL : rR, u = left ? uL : uR, v = left ? vL : vR, w = left ? wL : wR;
   double p = left ? pL : pR, E = left ? EL : ER, S = left ? SL : SR, m = left ? mL : mR;
-  double inv = 1.0 / (S - Ss);
+  double inv = rcp_nr(S - Ss);
   double Us0 = m * inv;
   double A4 = m * Ss + p;
   double N4 = E * (S - u) + (Ss - u) * A4;

@@ -411,16 +411,26 @@ static bool fused_stages(const dcf_ctx *c) {
   return g.source == SRC_MASSFLUX && g.bck[f] == BC_PERIODIC && g.bck[f + 1] == BC_PERIODIC;
 }
 
+// A CFL step reduction left pending by the previous step (nparts partial
+// maxima in dtpart): the next fused step runs it with its first ghost fill.
+struct PendingDt {
+  int nparts;
+  double cfl, dt_max;
+  double *dt;  // the step (also what the stages read)
+};
+
 // Fused steps chain their primitive boxes: stage k of a step works on box
 // (base + k) & 1 (0: g.Q, 1: qalt).  With box_ready the interior of the
 // first stage's box already holds the primitives of U (written by the
 // previous step's last update), so only its ghosts are filled; with
 // write_next the last update writes the primitives of the new state into
 // box (base + 1) & 1, the first box of a following step with the other base.
+// With pend (box_ready only) the first ghost fill also reduces the previous
+// step's partial maxima into dt, before any stage reads it.
 static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_t st,
                              double *U1 = nullptr, double *U2 = nullptr,
                              double *dtpart = nullptr, int base = 0, bool box_ready = false,
-                             bool write_next = false) {
+                             bool write_next = false, const PendingDt *pend = nullptr) {
   Dev &g = c->g;
   if (!U1) U1 = c->U1;
   if (!U2) U2 = c->U2;
@@ -440,8 +450,13 @@ static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_
     }
     for (int k = 0; k < 3; ++k) {
       const Dev &gk = gs[(base + k) & 1];
-      if (k == 0 && !box_ready) DCF_HIP(launch_prim_halo(gk, in[k], st));
-      else DCF_HIP(launch_prim_ghost(gk, st));
+      if (k == 0 && !box_ready)
+        DCF_HIP(launch_prim_halo(gk, in[k], st));
+      else if (k == 0 && pend)
+        DCF_HIP(launch_prim_ghost_dt(gk, c->dtpart, pend->nparts, pend->cfl, pend->dt_max,
+                                     pend->dt, st));
+      else
+        DCF_HIP(launch_prim_ghost(gk, st));
       const bool next = k < 2 || write_next;
       DCF_HIP(launch_fluxes_update(gk, U, in[k], out[k], dt, a[k], b[k], k == 2 ? dtpart : nullptr,
                                    st, next ? bo[(base + k + 1) & 1] : BoxOut{}, c->part,
@@ -568,13 +583,16 @@ dcf_status dcf_rk3_steps_cfl(dcf_ctx *c, double *U, double *dt, int nsteps, doub
   hipStream_t st = (hipStream_t)stream;
   const bool fused = fused_stages(c);
   const unsigned nparts = fused ? flux_update_blocks(c->g) : update_blocks(c->g);
+  const PendingDt pend{(int)nparts, cfl, dt_max, dt};
   for (int n = 0; n < nsteps; ++n) {
     // U is not touched between the steps of this call: each step after the
-    // first starts from the primitive box the previous one left
-    if ((s = rk3_stages(c, U, dt, st, nullptr, nullptr, c->dtpart, n & 1, fused && n > 0,
-                        fused && n + 1 < nsteps)))
+    // first starts from the primitive box the previous one left, and its
+    // first ghost fill finishes the previous step's CFL reduction
+    const bool chained = fused && n + 1 < nsteps;
+    if ((s = rk3_stages(c, U, dt, st, nullptr, nullptr, c->dtpart, n & 1, fused && n > 0, chained,
+                        fused && n > 0 ? &pend : nullptr)))
       return s;
-    DCF_HIP(launch_dt_final(c->dtpart, (int)nparts, cfl, dt_max, dt, st));
+    if (!chained) DCF_HIP(launch_dt_final(c->dtpart, (int)nparts, cfl, dt_max, dt, st));
   }
   return DCF_OK;
 }

@@ -133,44 +133,76 @@ __device__ __forceinline__ double viscosity(const Dev &g, double T) {
   return 0.0;
 }
 
-// WENO5-JS value at the right face of cell c from (a, b, c, d, e).  The
-// nonlinear weights alpha_k = d_k / (eps + beta_k)^2 are normalised after
-// multiplying through by the product of the three denominators, which needs
-// one division instead of four.
-// WENO5-JS of one stencil a..e (reconstruction at the face between c and d)
-// as numerator and denominator of the normalised nonlinear weights, with
-// the candidate values left unscaled (six times the third-order
-// reconstructions): the value is num / (6 den).
-__device__ __forceinline__ void weno5_nd(double a, double b, double c, double d, double e,
-                                         double &num, double &den) {
-  const double eps = 1.0e-6;
-  const double c1312 = 13.0 / 12.0;
-  double q0 = 2.0 * a - 7.0 * b + 11.0 * c;
-  double q1 = -b + 5.0 * c + 2.0 * d;
-  double q2 = 2.0 * c + 5.0 * d - e;
-  double r0 = a - 2.0 * b + c, s0 = a - 4.0 * b + 3.0 * c;
-  double r1 = b - 2.0 * c + d, s1 = b - d;
-  double r2 = c - 2.0 * d + e, s2 = 3.0 * c - 4.0 * d + e;
-  double t0 = eps + (c1312 * r0 * r0 + 0.25 * s0 * s0);
-  double t1 = eps + (c1312 * r1 * r1 + 0.25 * s1 * s1);
-  double t2 = eps + (c1312 * r2 * r2 + 0.25 * s2 * s2);
-  t0 *= t0;
-  t1 *= t1;
-  t2 *= t2;
-  // weights d_k / t_k times t0 t1 t2 (no division per weight)
-  double w0 = 0.1 * t1 * t2, w1 = 0.6 * t0 * t2, w2 = 0.3 * t0 * t1;
-  num = w0 * q0 + w1 * q1 + w2 * q2;
-  den = w0 + w1 + w2;
+// Reciprocal from the hardware estimate refined by two Newton-Raphson steps
+// e = 1 - x r, r <- r + r e (each squares the relative error): within about
+// an ulp of 1/x for normal x, at half the instructions of an IEEE division.
+// Zero or non-finite x gives a non-finite result.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
 }
 
-// Both reconstructions at the face between v2 and v3: left-biased from
-// v0..v4, right-biased from v5..v1, sharing one division.
+// 1/sqrt(x) for normal x > 0, likewise: the hardware estimate and two Newton
+// steps y <- y + y (1 - x y^2) / 2.  Negative x gives NaN.
+__device__ __forceinline__ double rsq_nr(double x) {
+  const double hx = 0.5 * x;
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(y, fma(-hx * y, y, 0.5), y);
+  return fma(y, fma(-hx * y, y, 0.5), y);
+}
+
+// Sound speed sqrt(gamma p / rho), written gamma p / sqrt(gamma p rho) so
+// that it needs no division.
+__device__ __forceinline__ double sound_speed(double gamma, double rho, double p) {
+  const double gp = gamma * p;
+  return gp * rsq_nr(gp * rho);
+}
+
+// WENO5-JS (Section 2.1): both reconstructions at the face between v2 and
+// v3, left-biased from v0..v4 and right-biased from v5..v1.  The nonlinear
+// weights d_k / (eps + beta_k)^2 are normalised after multiplying through by
+// the product of the three denominators, and the two values share one
+// reciprocal: y_L = N_L D_R r, y_R = N_R D_L r with r = 1 / (6 D_L D_R)
+// (the candidates are kept at six times the third-order reconstructions).
+// The mirrored stencils share work: the left stencils (1..3) and (2..4) are
+// the right stencils (3..1) and (4..2), with the same second differences, and
+// the left candidates 1 and 2 equal the right candidates 2 and 1.
 __device__ __forceinline__ void weno5_pair(double v0, double v1, double v2, double v3, double v4,
                                            double v5, double &yl, double &yr) {
-  double nl, dl, nr, dr;
-  weno5_nd(v0, v1, v2, v3, v4, nl, dl);
-  weno5_nd(v5, v4, v3, v2, v1, nr, dr);
-  const double r = 1.0 / (6.0 * dl * dr);
+  const double eps = 1.0e-6;
+  const double c1312 = 13.0 / 12.0;
+  // second differences over cells (0,1,2), (1,2,3), (2,3,4), (3,4,5)
+  const double d0 = v0 - 2.0 * v1 + v2, d1 = v1 - 2.0 * v2 + v3;
+  const double d2 = v2 - 2.0 * v3 + v4, d3 = v3 - 2.0 * v4 + v5;
+  // candidates: qa left 0, qb left 1 = right 2, qc left 2 = right 1, qd right 0
+  const double qa = 2.0 * v0 - 7.0 * v1 + 11.0 * v2;
+  const double qb = -v1 + 5.0 * v2 + 2.0 * v3;
+  const double qc = 2.0 * v2 + 5.0 * v3 - v4;
+  const double qd = 2.0 * v5 - 7.0 * v4 + 11.0 * v3;
+  // first-derivative terms of the smoothness indicators, per side
+  const double sl0 = v0 - 4.0 * v1 + 3.0 * v2, sl1 = v1 - v3, sl2 = 3.0 * v2 - 4.0 * v3 + v4;
+  const double sr0 = v5 - 4.0 * v4 + 3.0 * v3, sr1 = v4 - v2, sr2 = 3.0 * v3 - 4.0 * v2 + v1;
+  // u_k = (eps + beta_k)^2 / d_k, the square of (eps + beta_k) / sqrt(d_k)
+  // with 1 / sqrt(d_k) folded into the constants (d = 0.1, 0.6, 0.3); the
+  // weights d_k / (eps + beta_k)^2 times the product of all three
+  // denominators are then the products of the other two u (the common
+  // factor d_0 d_1 d_2 cancels in the normalisation)
+  constexpr double is1 = 3.162277660168379, is6 = 1.2909944487358056,
+                   is3 = 1.8257418583505538;  // 1 / sqrt(d_k)
+  auto usq = [&](double r, double s, double sc) {
+    const double t = fma(c1312 * sc * r, r, fma(0.25 * sc * s, s, eps * sc));
+    return t * t;
+  };
+  const double ul0 = usq(d0, sl0, is1), ul1 = usq(d1, sl1, is6), ul2 = usq(d2, sl2, is3);
+  const double ur0 = usq(d3, sr0, is1), ur1 = usq(d2, sr1, is6), ur2 = usq(d1, sr2, is3);
+  const double wl0 = ul1 * ul2, wl1 = ul0 * ul2, wl2 = ul0 * ul1;
+  const double wr0 = ur1 * ur2, wr1 = ur0 * ur2, wr2 = ur0 * ur1;
+  const double nl = wl0 * qa + wl1 * qb + wl2 * qc, dl = wl0 + wl1 + wl2;
+  const double nr = wr0 * qd + wr1 * qc + wr2 * qb, dr = wr0 + wr1 + wr2;
+  const double r = rcp_nr(6.0 * dl * dr);
   yl = nl * dr * r;
   yr = nr * dl * r;
 }
@@ -187,12 +219,12 @@ __device__ __forceinline__ void hllc(const double *qL, const double *qR, double 
   double rR = qR[0], uR = qR[1], vR = qR[2], wR = qR[3], pR = qR[4];
   double EL = pL * gm1i + 0.5 * rL * (uL * uL + vL * vL + wL * wL);
   double ER = pR * gm1i + 0.5 * rR * (uR * uR + vR * vR + wR * wR);
-  double cL = sqrt(gamma * pL / rL);
-  double cR = sqrt(gamma * pR / rR);
+  double cL = sound_speed(gamma, rL, pL);
+  double cR = sound_speed(gamma, rR, pR);
   double SL = fmin(uL - cL, uR - cR);
   double SR = fmax(uL + cL, uR + cR);
   double mL = rL * (SL - uL), mR = rR * (SR - uR);
-  double Ss = (pR - pL + uL * mL - uR * mR) / (mL - mR);
+  double Ss = (pR - pL + uL * mL - uR * mR) * rcp_nr(mL - mR);
   if (0.0 <= SL) {
     F[0] = rL * uL;
     F[1] = rL * uL * uL + pL;
@@ -212,7 +244,7 @@ __device__ __forceinline__ void hllc(const double *qL, const double *qR, double 
   const bool left = (0.0 <= Ss);
   double r = left ? rL : rR, u = left ? uL : uR, v = left ? vL : vR, w = left ? wL : wR;
   double p = left ? pL : pR, E = left ? EL : ER, S = left ? SL : SR, m = left ? mL : mR;
-  double inv = 1.0 / (S - Ss);
+  double inv = rcp_nr(S - Ss);
   double Us0 = m * inv;
   double Us4 = (E * (S - u) + (Ss - u) * (m * Ss + p)) * inv;
   double fm = r * u;

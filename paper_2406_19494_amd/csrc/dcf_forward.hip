@@ -974,6 +974,19 @@ __global__ void __launch_bounds__(256) k_dt_final(const double *part, int nparts
   dt_final_body(part, nparts, cfl, dt_max, dt);
 }
 
+// Ghost fill of a primitive box together with the CFL step reduction of the
+// update before it, as workgroup 0 (its partial maxima are complete when the
+// launch starts, and only later launches read the step).  Saves the launch
+// of a one-workgroup kernel per step.
+__global__ void __launch_bounds__(256) k_prim_ghost_dt(Dev g, const double *part, int nparts,
+                                                       double cfl, double dt_max, double *dt) {
+  if (blockIdx.x == 0) {
+    dt_final_body(part, nparts, cfl, dt_max, dt);
+    return;
+  }
+  prim_ghost_body(g, (blockIdx.x - 1) * blockDim.x + threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Diagnostics: volume means of kinetic energy and mu |omega|^2, and the
 // conserved totals.  Needs the primitive box (vorticity from 4th-order
@@ -1306,6 +1319,12 @@ unsigned update_blocks(const Dev &g) { return grid_for(g.ncell); }
 hipError_t launch_dt_final(const double *part, int nparts, double cfl, double dt_max, double *dt,
                            hipStream_t st) {
   k_dt_final<<<1, 256, 0, st>>>(part, nparts, cfl, dt_max, dt);
+  return hipGetLastError();
+}
+hipError_t launch_prim_ghost_dt(const Dev &g, const double *part, int nparts, double cfl,
+                               double dt_max, double *dt, hipStream_t st) {
+  const unsigned nb = g.nbox > g.ncell ? grid_for(g.nbox - g.ncell) : 0u;
+  k_prim_ghost_dt<<<nb + 1, 256, 0, st>>>(g, part, nparts, cfl, dt_max, dt);
   return hipGetLastError();
 }
 hipError_t launch_dt(const Dev &g, const double *U, double cfl, double dt_max, double *part,

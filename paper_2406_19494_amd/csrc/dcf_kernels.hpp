@@ -73,6 +73,10 @@ hipError_t launch_flux_update_last(const Dev &g, const double *Un, const double 
                                    const double *force = nullptr);
 // Ghost cells of the box from its interior (the interior already filled).
 hipError_t launch_prim_ghost(const Dev &g, hipStream_t st);
+// launch_prim_ghost and launch_dt_final in one launch (the reduction reads
+// part as left by earlier launches and writes dt for later ones).
+hipError_t launch_prim_ghost_dt(const Dev &g, const double *part, int nparts, double cfl,
+                               double dt_max, double *dt, hipStream_t st);
 hipError_t launch_dt_final(const double *part, int nparts, double cfl, double dt_max, double *dt,
                            hipStream_t st);
 hipError_t launch_dt(const Dev &g, const double *U, double cfl, double dt_max, double *part,
