@@ -38,35 +38,37 @@ __host__ inline int tile_faces(int D) { return D == 0 ? 64 : 32; }
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void weno5_vjp(double a, double b, double c, double d, double e,
                                           double yb, double *g) {
+  // the forward in the form the face flux evaluates it: t_k = (eps +
+  // beta_k) / sqrt(d_k), u_k = t_k^2, weights w_k = u_i u_j (i, j != k),
+  // candidates q_k at six times the third-order values, y = N / (6 W)
   const double eps = 1.0e-6;
-  const double sixth = 1.0 / 6.0;
   const double c1312 = 13.0 / 12.0;
-  double q0 = (2.0 * a - 7.0 * b + 11.0 * c) * sixth;
-  double q1 = (-b + 5.0 * c + 2.0 * d) * sixth;
-  double q2 = (2.0 * c + 5.0 * d - e) * sixth;
+  constexpr double is1 = 3.162277660168379, is6 = 1.2909944487358056,
+                   is3 = 1.8257418583505538;  // 1 / sqrt(d_k), d = 0.1, 0.6, 0.3
+  double q0 = 2.0 * a - 7.0 * b + 11.0 * c;
+  double q1 = -b + 5.0 * c + 2.0 * d;
+  double q2 = 2.0 * c + 5.0 * d - e;
   double r0 = a - 2.0 * b + c, s0 = a - 4.0 * b + 3.0 * c;
   double r1 = b - 2.0 * c + d, s1 = b - d;
   double r2 = c - 2.0 * d + e, s2 = 3.0 * c - 4.0 * d + e;
-  double e0 = eps + (c1312 * r0 * r0 + 0.25 * s0 * s0);
-  double e1 = eps + (c1312 * r1 * r1 + 0.25 * s1 * s1);
-  double e2 = eps + (c1312 * r2 * r2 + 0.25 * s2 * s2);
-  double t0 = e0 * e0, t1 = e1 * e1, t2 = e2 * e2;
-  double w0 = 0.1 * t1 * t2, w1 = 0.6 * t0 * t2, w2 = 0.3 * t0 * t1;
-  double iW = 1.0 / (w0 + w1 + w2);
-  double y = (w0 * q0 + w1 * q1 + w2 * q2) * iW;
+  double t0 = fma(c1312 * is1 * r0, r0, fma(0.25 * is1 * s0, s0, eps * is1));
+  double t1 = fma(c1312 * is6 * r1, r1, fma(0.25 * is6 * s1, s1, eps * is6));
+  double t2 = fma(c1312 * is3 * r2, r2, fma(0.25 * is3 * s2, s2, eps * is3));
+  double u0 = t0 * t0, u1 = t1 * t1, u2 = t2 * t2;
+  double w0 = u1 * u2, w1 = u0 * u2, w2 = u0 * u1;
+  double iW = rcp_nr(6.0 * (w0 + w1 + w2));
+  double y6 = 6.0 * ((w0 * q0 + w1 * q1 + w2 * q2) * iW);
   double Nb = yb * iW;
   double q0b = Nb * w0, q1b = Nb * w1, q2b = Nb * w2;
-  double w0b = Nb * (q0 - y), w1b = Nb * (q1 - y), w2b = Nb * (q2 - y);
-  double t0b = 0.6 * w1b * t2 + 0.3 * w2b * t1;
-  double t1b = 0.1 * w0b * t2 + 0.3 * w2b * t0;
-  double t2b = 0.1 * w0b * t1 + 0.6 * w1b * t0;
-  double b0b = 2.0 * e0 * t0b, b1b = 2.0 * e1 * t1b, b2b = 2.0 * e2 * t2b;
-  double r0b = 2.0 * c1312 * r0 * b0b, s0b = 0.5 * s0 * b0b;
-  double r1b = 2.0 * c1312 * r1 * b1b, s1b = 0.5 * s1 * b1b;
-  double r2b = 2.0 * c1312 * r2 * b2b, s2b = 0.5 * s2 * b2b;
-  q0b *= sixth;
-  q1b *= sixth;
-  q2b *= sixth;
+  double w0b = Nb * (q0 - y6), w1b = Nb * (q1 - y6), w2b = Nb * (q2 - y6);
+  double u0b = w1b * u2 + w2b * u1;
+  double u1b = w0b * u2 + w2b * u0;
+  double u2b = w0b * u1 + w1b * u0;
+  double t0b = 2.0 * t0 * u0b, t1b = 2.0 * t1 * u1b, t2b = 2.0 * t2 * u2b;
+  // d t_k / d r_k = 2 (13/12) r_k / sqrt(d_k), d t_k / d s_k = s_k / (2 sqrt(d_k))
+  double r0b = (2.0 * c1312 * is1) * r0 * t0b, s0b = (0.5 * is1) * s0 * t0b;
+  double r1b = (2.0 * c1312 * is6) * r1 * t1b, s1b = (0.5 * is6) * s1 * t1b;
+  double r2b = (2.0 * c1312 * is3) * r2 * t2b, s2b = (0.5 * is3) * s2 * t2b;
   g[0] += 2.0 * q0b + r0b + s0b;
   g[1] += -7.0 * q0b - q1b - 2.0 * r0b - 4.0 * s0b + r1b + s1b;
   g[2] += 11.0 * q0b + 5.0 * q1b + 2.0 * q2b + r0b + 3.0 * s0b - 2.0 * r1b + r2b + 3.0 * s2b;
@@ -91,17 +93,17 @@ __device__ __forceinline__ void phys_flux_vjp(const double *q, double gm1i, cons
 
 // Reverse of the HLLC flux (same branch choices as the forward: Davis wave
 // speeds with the left candidate kept on ties, 0 <= S selects the left side).
-__device__ void hllc_vjp(const double *qL, const double *qR, double gamma, const double *Fb,
-                         double *qLb, double *qRb) {
-  const double gm1i = 1.0 / (gamma - 1.0);
+__device__ void hllc_vjp(const double *qL, const double *qR, double gamma, double gm1i,
+                         const double *Fb, double *qLb, double *qRb) {
   double rL = qL[0], uL = qL[1], vL = qL[2], wL = qL[3], pL = qL[4];
   double rR = qR[0], uR = qR[1], vR = qR[2], wR = qR[3], pR = qR[4];
   double EL = pL * gm1i + 0.5 * rL * (uL * uL + vL * vL + wL * wL);
   double ER = pR * gm1i + 0.5 * rR * (uR * uR + vR * vR + wR * wR);
   // wave speeds, star speed and star reciprocal in the forward's arithmetic
   // (same branch decisions)
-  double cL = sound_speed(gamma, rL, pL);
-  double cR = sound_speed(gamma, rR, pR);
+  double yL, yR;  // 1 / (rho c) per side
+  double cL = sound_speed(gamma, rL, pL, yL);
+  double cR = sound_speed(gamma, rR, pR, yR);
   double aL = uL - cL, bL = uR - cR;
   const bool selL = bL < aL;
   double SL = selL ? bL : aL;
@@ -119,7 +121,8 @@ __device__ void hllc_vjp(const double *qL, const double *qR, double gamma, const
   }
   double mL = rL * (SL - uL), mR = rR * (SR - uR);
   double Nn = pR - pL + uL * mL - uR * mR, Dd = mL - mR;
-  double Ss = Nn * rcp_nr(Dd);
+  const double iDd = rcp_nr(Dd);
+  double Ss = Nn * iDd;
   const bool left = (0.0 <= Ss);
   double r = left ? rL : rR, u = left ? uL : uR, v = left ? vL : vR, w = left ? wL : wR;
   double p = left ? pL : pR, E = left ? EL : ER, S = left ? SL : SR, m = left ? mL : mR;
@@ -169,7 +172,7 @@ __device__ void hllc_vjp(const double *qL, const double *qR, double gamma, const
   qKb[4] += pb;
   double mLb = left ? mb : 0.0, mRb = left ? 0.0 : mb;
   double SLb = left ? Sb : 0.0, SRb = left ? 0.0 : Sb;
-  double Nnb = Ssb / Dd, Ddb = -Ssb * Ss / Dd;
+  double Nnb = Ssb * iDd, Ddb = -Ssb * Ss * iDd;
   qRb[4] += Nnb;
   qLb[4] -= Nnb;
   qLb[1] += Nnb * mL;
@@ -197,12 +200,12 @@ __device__ void hllc_vjp(const double *qL, const double *qR, double gamma, const
     qLb[1] += SRb;
     cLb += SRb;
   }
-  // c = sqrt(gamma p / rho)
-  double xLb = cLb / (2.0 * cL), xRb = cRb / (2.0 * cR);
-  qLb[4] += xLb * gamma / rL;
-  qLb[0] -= xLb * gamma * pL / (rL * rL);
-  qRb[4] += xRb * gamma / rR;
-  qRb[0] -= xRb * gamma * pR / (rR * rR);
+  // c = sqrt(gamma p / rho): dc/dp = gamma / (2 rho c) = gamma y / 2 and
+  // dc/drho = -c / (2 rho) = -c^2 y / 2
+  qLb[4] += cLb * (0.5 * gamma) * yL;
+  qLb[0] -= cLb * (0.5 * cL * cL) * yL;
+  qRb[4] += cRb * (0.5 * gamma) * yR;
+  qRb[0] -= cRb * (0.5 * cR * cR) * yR;
 }
 
 // Flux adjoint at face f of direction D from the stage-output adjoint Wb:
@@ -354,7 +357,7 @@ __global__ void __launch_bounds__(256) k_dir_vjp(Dev g, AdjBuffers A) {
       weno5_pair(v0, v1, v2, v3, v4, v5, qL[m], qR[m]);
     }
     double Fr[5] = {Fb[0], Fb[1 + D], Fb[1 + T1], Fb[1 + T2], Fb[4]};
-    hllc_vjp(qL, qR, g.gamma, Fr, qLb, qRb);
+    hllc_vjp(qL, qR, g.gamma, g.gm1i, Fr, qLb, qRb);
   }
   // convective, per component: reverse the two reconstructions, stage the
   // contributions to cells f-3 .. f+2 in LDS, then gather them per window

@@ -154,11 +154,16 @@ __device__ __forceinline__ double rsq_nr(double x) {
   return fma(y, fma(-hx * y, y, 0.5), y);
 }
 
-// Sound speed sqrt(gamma p / rho), written gamma p / sqrt(gamma p rho) so
-// that it needs no division.
-__device__ __forceinline__ double sound_speed(double gamma, double rho, double p) {
+// Sound speed c = sqrt(gamma p / rho), written gamma p y with
+// y = 1 / sqrt(gamma p rho) = 1 / (rho c) so that it needs no division.
+__device__ __forceinline__ double sound_speed(double gamma, double rho, double p, double &y) {
   const double gp = gamma * p;
-  return gp * rsq_nr(gp * rho);
+  y = rsq_nr(gp * rho);
+  return gp * y;
+}
+__device__ __forceinline__ double sound_speed(double gamma, double rho, double p) {
+  double y;
+  return sound_speed(gamma, rho, p, y);
 }
 
 // WENO5-JS (Section 2.1): both reconstructions at the face between v2 and
