@@ -152,8 +152,10 @@ dcf_status dcf_create(const dcf_grid *grid, const dcf_gas *gas, dcf_ctx **out) {
   g.cp = gas->gamma * gas->R / (gas->gamma - 1.0);
   g.gm1i = 1.0 / (gas->gamma - 1.0);
   g.cpPr = g.cp / gas->Pr;
+  g.iR = 1.0 / gas->R;
   g.mu_ref = gas->mu_ref;
   g.T_ref = gas->T_ref;
+  g.iTref = 1.0 / gas->T_ref;
   g.vparam = gas->visc_param;
   g.visc = gas->visc_law;
   for (int f = 0; f < 6; ++f) {

@@ -47,6 +47,7 @@ struct Dev {
   // gas
   double gamma, R, Pr, cp, mu_ref, T_ref, vparam;
   double gm1i, cpPr;     // 1/(gamma - 1) and cp/Pr
+  double iR, iTref;      // 1/R and 1/T_ref
   int visc;
   // boundaries
   int bck[6];
@@ -121,18 +122,6 @@ __host__ __device__ __forceinline__ void ghost_position(const Dev &g, unsigned g
   p[2] = (int)z - g.h[2];
 }
 
-// Dynamic viscosity: power law, or Sutherland's law (Section 3.2).
-__device__ __forceinline__ double viscosity(const Dev &g, double T) {
-  // (T/T_ref)^omega as exp(omega log(T/T_ref)): a few ulp, half the cost of pow
-  if (g.visc == VISC_POWER) return g.mu_ref * exp(g.vparam * log(T / g.T_ref));
-  if (g.visc == VISC_SUTHERLAND) {
-    double t = T / g.T_ref;
-    double s = g.vparam / g.T_ref;
-    return g.mu_ref * t * sqrt(t) * (1.0 + s) / (t + s);
-  }
-  return 0.0;
-}
-
 // Reciprocal from the hardware estimate refined by two Newton-Raphson steps
 // e = 1 - x r, r <- r + r e (each squares the relative error): within about
 // an ulp of 1/x for normal x, at half the instructions of an IEEE division.
@@ -164,6 +153,19 @@ __device__ __forceinline__ double sound_speed(double gamma, double rho, double p
 __device__ __forceinline__ double sound_speed(double gamma, double rho, double p) {
   double y;
   return sound_speed(gamma, rho, p, y);
+}
+
+// Dynamic viscosity: power law, or Sutherland's law (Section 3.2).
+__device__ __forceinline__ double viscosity(const Dev &g, double T) {
+  // (T/T_ref)^omega as exp(omega log(T/T_ref)): a few ulp, half the cost of pow
+  if (g.visc == VISC_POWER) return g.mu_ref * exp(g.vparam * log(T * g.iTref));
+  if (g.visc == VISC_SUTHERLAND) {
+    // t^{3/2} (1 + s) / (t + s) with t^{3/2} = t^2 / sqrt(t)
+    double t = T * g.iTref;
+    double s = g.vparam * g.iTref;
+    return g.mu_ref * (1.0 + s) * (t * t * rsq_nr(t)) * rcp_nr(t + s);
+  }
+  return 0.0;
 }
 
 // WENO5-JS (Section 2.1): both reconstructions at the face between v2 and

@@ -58,7 +58,7 @@ __global__ void k_metrics(int kind, double lo, double hi, double beta, int n, do
 __device__ __forceinline__ void prim_of_state(const Dev &g, const double *s, double *q) {
   const int nd = g.ndim;
   double rho = s[0];
-  double ir = 1.0 / rho;
+  double ir = rcp_nr(rho);
   double u = s[1] * ir;
   double v = nd >= 2 ? s[2] * ir : 0.0;
   double w = nd >= 3 ? s[3] * ir : 0.0;
@@ -69,14 +69,14 @@ __device__ __forceinline__ void prim_of_state(const Dev &g, const double *s, dou
   q[QV] = v;
   q[QW] = w;
   q[QP] = p;
-  q[QT] = p / (rho * g.R);
+  q[QT] = p * ir * g.iR;
 }
 
 __device__ __forceinline__ void cons_to_prim(const Dev &g, const double *U, long c, double *q) {
   const int nd = g.ndim;
   const long nc = g.ncell;
   double rho = U[c];
-  double ir = 1.0 / rho;
+  double ir = rcp_nr(rho);
   double u = U[nc + c] * ir;
   double v = nd >= 2 ? U[2 * nc + c] * ir : 0.0;
   double w = nd >= 3 ? U[3 * nc + c] * ir : 0.0;
@@ -87,7 +87,7 @@ __device__ __forceinline__ void cons_to_prim(const Dev &g, const double *U, long
   q[QV] = v;
   q[QW] = w;
   q[QP] = p;
-  q[QT] = p / (rho * g.R);
+  q[QT] = p * ir * g.iR;
 }
 
 __global__ void k_init_state(Dev g, const double *P, double *U) {
@@ -736,7 +736,8 @@ __global__ void __launch_bounds__(256) k_force_final(const double *part, int npa
 // Signal rate of one cell, sum_d (|u_d| + c)/dx_d + 2 nu_eff sum_d 1/dx_d^2
 // (nu_eff = max(4/3, gamma/Pr) mu/rho); dt = cfl / max over cells.
 __device__ __forceinline__ double cell_sigma(const Dev &g, const double *q, const int *pos) {
-  double cs = sqrt(g.gamma * q[QP] / q[QR]);
+  double y;  // 1 / (rho cs)
+  double cs = sound_speed(g.gamma, q[QR], q[QP], y);
   double conv = 0.0, inv2 = 0.0;
   for (int d = 0; d < g.ndim; ++d) {
     double id = g.idx[d][pos[d]];
@@ -746,7 +747,7 @@ __device__ __forceinline__ double cell_sigma(const Dev &g, const double *q, cons
   double sig = conv;
   if (g.visc != VISC_NONE) {
     double mu = viscosity(g, q[QT]);
-    double nu = fmax(4.0 / 3.0, g.gamma / g.Pr) * mu / q[QR];
+    double nu = fmax(4.0 / 3.0, g.gamma / g.Pr) * mu * (cs * y);  // mu / rho
     sig += 2.0 * nu * inv2;
   }
   if (!(sig < 1.0e300)) sig = 1.0e300;  // non-finite: flagged elsewhere
