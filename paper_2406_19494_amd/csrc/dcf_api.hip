@@ -413,6 +413,18 @@ static bool fused_stages(const dcf_ctx *c) {
   return g.source == SRC_MASSFLUX && g.bck[f] == BC_PERIODIC && g.bck[f + 1] == BC_PERIODIC;
 }
 
+// Every face periodic with at least three cells per active axis (each ghost
+// the image of one interior cell) and viscous: the ghost fill and the
+// velocity derivatives run as one launch.
+static bool periodic_viscous(const dcf_ctx *c) {
+  const Dev &g = c->g;
+  if (g.visc == VISC_NONE || g.ndim < 2) return false;
+  for (int d = 0; d < g.ndim; ++d)
+    if (g.bck[2 * d] != BC_PERIODIC || g.bck[2 * d + 1] != BC_PERIODIC || g.n[d] < 3)
+      return false;
+  return true;
+}
+
 // A CFL step reduction left pending by the previous step (nparts partial
 // maxima in dtpart): the next fused step runs it with its first ghost fill.
 struct PendingDt {
@@ -450,19 +462,27 @@ static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_
       bo[0].Q[q] = g.Q[q];
       bo[1].Q[q] = c->qalt.Q[q];
     }
+    const bool merged = periodic_viscous(c);
     for (int k = 0; k < 3; ++k) {
       const Dev &gk = gs[(base + k) & 1];
-      if (k == 0 && !box_ready)
+      if (merged) {
+        if (k == 0 && !box_ready) DCF_HIP(launch_prim_interior(gk, in[k], st));
+        const PendingDt *pk = k == 0 ? pend : nullptr;
+        DCF_HIP(launch_ghost_grad_periodic(gk, pk ? c->dtpart : nullptr, pk ? pk->nparts : 0,
+                                           pk ? pk->cfl : 0.0, pk ? pk->dt_max : 0.0,
+                                           pk ? pk->dt : nullptr, st));
+      } else if (k == 0 && !box_ready) {
         DCF_HIP(launch_prim_halo(gk, in[k], st));
-      else if (k == 0 && pend)
+      } else if (k == 0 && pend) {
         DCF_HIP(launch_prim_ghost_dt(gk, c->dtpart, pend->nparts, pend->cfl, pend->dt_max,
                                      pend->dt, st));
-      else
+      } else {
         DCF_HIP(launch_prim_ghost(gk, st));
+      }
       const bool next = k < 2 || write_next;
       DCF_HIP(launch_fluxes_update(gk, U, in[k], out[k], dt, a[k], b[k], k == 2 ? dtpart : nullptr,
                                    st, next ? bo[(base + k + 1) & 1] : BoxOut{}, c->part,
-                                   g.source == SRC_MASSFLUX ? c->force : nullptr));
+                                   g.source == SRC_MASSFLUX ? c->force : nullptr, merged));
     }
     return DCF_OK;
   }

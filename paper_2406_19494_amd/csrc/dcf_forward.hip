@@ -370,6 +370,50 @@ __global__ void __launch_bounds__(256) k_grad(Dev g) {
   grad_body<NDIM>(g, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
+// As grad_body on a box whose every face is periodic, with each neighbour
+// read from the interior cell whose periodic image it is (the value the
+// ghost fill copies there): the same operands in the same order, so the same
+// derivatives bitwise, without waiting for the ghost fill.
+__device__ __forceinline__ int wrap_periodic(int x, int n) {
+  return x < 0 ? x + n : (x >= n ? x - n : x);
+}
+template <int NDIM>
+__device__ __forceinline__ void grad_body_periodic(const Dev &g, int t, unsigned bid,
+                                                   unsigned nblk) {
+  const unsigned bl = xcd_remap(bid, nblk) * blockDim.x + threadIdx.x;
+  if (bl >= grad_cells(g, t)) return;
+  unsigned E[3];
+  int o[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    E[e] = e >= NDIM ? 1u : (e == t ? (unsigned)g.n[e] : (unsigned)g.n[e] + 4);
+    o[e] = (e >= NDIM || e == t) ? 0 : -2;
+  }
+  int p[3];
+  const unsigned r = bl / E[0];
+  p[0] = (int)(bl % E[0]) + o[0];
+  p[1] = (int)(r % E[1]) + o[1];
+  p[2] = (int)(r / E[1]) + o[2];
+  int q[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) q[e] = e < NDIM ? wrap_periodic(p[e], g.n[e]) : p[e];
+  const int off[4] = {-2, -1, 1, 2};
+  double v[NDIM][4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int s[3] = {q[0], q[1], q[2]};
+    s[t] = wrap_periodic(p[t] + off[k], g.n[t]);
+    const long sb = bidx(g, s[0], s[1], s[2]);
+#pragma unroll
+    for (int phi = 0; phi < NDIM; ++phi) v[phi][k] = g.Q[QU + phi][sb];
+  }
+  const long b = bidx(g, p[0], p[1], p[2]);
+  const double mct = g.mc[t][p[t]];
+#pragma unroll
+  for (int phi = 0; phi < NDIM; ++phi)
+    g.G[3 * t + phi][b] = dcell4(v[phi][0], v[phi][1], v[phi][2], v[phi][3]) * mct;
+}
+
 // ---------------------------------------------------------------------------
 // Total flux F = F^c - F^d at one face of direction D (Eq. (6)), in the
 // global 5-component layout (mass, x/y/z momentum, energy).  The stencil is
@@ -988,6 +1032,31 @@ __global__ void __launch_bounds__(256) k_prim_ghost_dt(Dev g, const double *part
   prim_ghost_body(g, (blockIdx.x - 1) * blockDim.x + threadIdx.x);
 }
 
+// Ghost fill and velocity derivatives of an all-periodic viscous box in one
+// launch: workgroup 0 finishes the previous step's CFL reduction when part
+// is given (as k_prim_ghost_dt), workgroups [gh0, gr0) fill the ghosts, and
+// the rest compute the derivatives of direction (b - gr0) / nb_grad from
+// interior cells only (gr0 and nb_grad are multiples of 8, so each
+// direction's workgroups meet the XCDs in k_grad's order).
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_ghost_grad_periodic(Dev g, const double *part,
+                                                             int nparts, double cfl,
+                                                             double dt_max, double *dt,
+                                                             unsigned gh0, unsigned gr0,
+                                                             unsigned nb_grad) {
+  const unsigned b = blockIdx.x;
+  if (b < gh0) {
+    if (part) dt_final_body(part, nparts, cfl, dt_max, dt);
+    return;
+  }
+  if (b < gr0) {
+    prim_ghost_body(g, (b - gh0) * blockDim.x + threadIdx.x);
+    return;
+  }
+  const unsigned gb = b - gr0;
+  grad_body_periodic<NDIM>(g, (int)(gb / nb_grad), gb % nb_grad, nb_grad);
+}
+
 // ---------------------------------------------------------------------------
 // Diagnostics: volume means of kinetic energy and mu |omega|^2, and the
 // conserved totals.  Needs the primitive box (vorticity from 4th-order
@@ -1262,8 +1331,8 @@ hipError_t launch_flux_update_last(const Dev &g, const double *Un, const double 
 hipError_t launch_fluxes_update(const Dev &g, const double *Un, const double *Uin,
                                 double *Uout, const double *dt, double a, double b,
                                 double *dtpart, hipStream_t st, const BoxOut &qo,
-                                double *part, double *force) {
-  hipError_t e = launch_grad(g, st);
+                                double *part, double *force, bool grad_done) {
+  hipError_t e = grad_done ? hipSuccess : launch_grad(g, st);
   if (e == hipSuccess) e = g.ndim == 3 ? launch_flux_xy(g, st) : launch_flux_dir(g, 0, st);
   // the body force from the boundary fluxes of the directions before the
   // last (the last one is periodic: its boundary terms vanish)
@@ -1320,6 +1389,28 @@ unsigned update_blocks(const Dev &g) { return grid_for(g.ncell); }
 hipError_t launch_dt_final(const double *part, int nparts, double cfl, double dt_max, double *dt,
                            hipStream_t st) {
   k_dt_final<<<1, 256, 0, st>>>(part, nparts, cfl, dt_max, dt);
+  return hipGetLastError();
+}
+hipError_t launch_prim_interior(const Dev &g, const double *U, hipStream_t st) {
+  k_prim_interior<<<grid_for(g.ncell), 256, 0, st>>>(g, U);
+  return hipGetLastError();
+}
+hipError_t launch_ghost_grad_periodic(const Dev &g, const double *part, int nparts, double cfl,
+                                      double dt_max, double *dt, hipStream_t st) {
+  if (g.visc == VISC_NONE || g.ndim < 2) return hipErrorInvalidValue;
+  unsigned cells = 0;
+  for (int t = 0; t < g.ndim; ++t) cells = std::max(cells, grad_cells(g, t));
+  const unsigned nb_grad = (grid_for(cells) + 7u) & ~7u;
+  const unsigned gh0 = part ? 1u : 0u;
+  const unsigned nb_ghost = g.nbox > g.ncell ? grid_for(g.nbox - g.ncell) : 0u;
+  const unsigned gr0 = (gh0 + nb_ghost + 7u) & ~7u;
+  const unsigned total = gr0 + nb_grad * (unsigned)g.ndim;
+  if (g.ndim == 2)
+    k_ghost_grad_periodic<2><<<total, 256, 0, st>>>(g, part, nparts, cfl, dt_max, dt, gh0, gr0,
+                                                      nb_grad);
+  else
+    k_ghost_grad_periodic<3><<<total, 256, 0, st>>>(g, part, nparts, cfl, dt_max, dt, gh0, gr0,
+                                                      nb_grad);
   return hipGetLastError();
 }
 hipError_t launch_prim_ghost_dt(const Dev &g, const double *part, int nparts, double cfl,

@@ -60,10 +60,12 @@ unsigned update_blocks(const Dev &g);
 // (launch_prim_ghost on a context whose Q is qo).  With force (the
 // constant-mass-flux source; the last direction periodic) the body force is
 // reduced into force (partials in part) before the fused kernel applies it.
+// With grad_done the derivatives are already in g.G (launch_ghost_grad_periodic).
 hipError_t launch_fluxes_update(const Dev &g, const double *Un, const double *Uin,
                                 double *Uout, const double *dt, double a, double b,
                                 double *dtpart, hipStream_t st, const BoxOut &qo = BoxOut{},
-                                double *part = nullptr, double *force = nullptr);
+                                double *part = nullptr, double *force = nullptr,
+                                bool grad_done = false);
 unsigned flux_update_blocks(const Dev &g);
 // The last direction's flux + update kernel alone (its gradient and other
 // fluxes already computed).
@@ -77,6 +79,15 @@ hipError_t launch_prim_ghost(const Dev &g, hipStream_t st);
 // part as left by earlier launches and writes dt for later ones).
 hipError_t launch_prim_ghost_dt(const Dev &g, const double *part, int nparts, double cfl,
                                double dt_max, double *dt, hipStream_t st);
+// The interior cells' primitives alone (the first launch of launch_prim_halo's
+// two-launch form).
+hipError_t launch_prim_interior(const Dev &g, const double *U, hipStream_t st);
+// Every face periodic and viscous (ndim >= 2): launch_prim_ghost and
+// launch_grad in one launch (the derivatives read interior cells only, so
+// they do not wait for the ghosts; bitwise the same values), with the CFL
+// reduction of launch_prim_ghost_dt when part is not null.
+hipError_t launch_ghost_grad_periodic(const Dev &g, const double *part, int nparts, double cfl,
+                                      double dt_max, double *dt, hipStream_t st);
 hipError_t launch_dt_final(const double *part, int nparts, double cfl, double dt_max, double *dt,
                            hipStream_t st);
 hipError_t launch_dt(const Dev &g, const double *U, double cfl, double dt_max, double *part,
