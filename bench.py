@@ -45,6 +45,8 @@ def algorithmic_bytes(case, kernel):
     if kernel == "k_prim_ghost":  # each ghost reads its source cell's values, writes its own
         nq = nd + 2 + (2 if visc else 0)
         return 8 * 2 * nq * (nbox - case.ncells)
+    if kernel == "k_ghost_grad_periodic":  # the ghost fill and the derivatives of one launch
+        return algorithmic_bytes(case, "k_prim_ghost") + algorithmic_bytes(case, "k_grad")
     if kernel == "k_grad":
         writes = 0
         for t in range(nd):
@@ -150,14 +152,20 @@ def measured_traffic(kernel, workload):
 def step_kernel_ids(case):
     """dcf_time_kernel ids of the launches one RK3 stage of `case` runs:
     halo fill (0; 8 = ghosts only, stages 2-3 of a fused step), derivatives
-    (5, viscous 2D/3D), fluxes (7 = x+y of a 3D grid, 1..3 per direction),
+    (5, viscous 2D/3D; 9 = ghosts and derivatives in one launch when every
+    face is periodic), fluxes (7 = x+y of a 3D grid, 1..3 per direction),
     then the fused last-direction flux + update (6, 2D/3D without source) or
     the separate update (4)."""
     visc = case.visc_law != "none"
     last = 2 * (case.ndim - 1)
     fused = case.ndim >= 2 and (case.source == "none" or (
         case.bc[last] == "periodic" and case.bc[last + 1] == "periodic"))
-    ids = [0] + ([8] if fused else []) + ([5] if visc and case.ndim >= 2 else [])
+    periodic = all(case.bc[2 * d] == "periodic" and case.bc[2 * d + 1] == "periodic"
+                   and case.n[d] >= 3 for d in range(case.ndim))
+    if fused and visc and periodic:
+        ids = [0, 9]
+    else:
+        ids = [0] + ([8] if fused else []) + ([5] if visc and case.ndim >= 2 else [])
     if case.ndim == 3:
         ids += [7] + ([6] if fused else [3, 4])
     elif case.ndim == 2:
@@ -383,7 +391,8 @@ def main():
     # primitive interior, so stages 2 and 3 fill only the ghosts
     # (k_prim_ghost, 8) where stage 1 runs the whole halo fill (0).
     names = {0: "k_prim_halo", 1: "k_flux_x", 2: "k_flux_yz<y>", 3: "k_flux_yz<z>", 4: "k_update",
-             5: "k_grad", 6: "k_flux_update", 7: "k_flux_xy", 8: "k_prim_ghost"}
+             5: "k_grad", 6: "k_flux_update", 7: "k_flux_xy", 8: "k_prim_ghost",
+             9: "k_ghost_grad_periodic"}
     visc = case.visc_law != "none"
     step_kinds = step_kernel_ids(case)
     kinds = sorted(set(step_kinds) | set(range(1, case.ndim + 1)) | {4})

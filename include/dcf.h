@@ -251,7 +251,9 @@ dcf_status dcf_gradient(dcf_ctx *ctx, const double *U0_dev, int nsteps, const do
  * 2 and 4), 7 the x and y face fluxes of a 3D grid in one launch (the form
  * the step runs in place of 1 and 2), 8 the ghost cells of the primitive box
  * alone (stages 2 and 3 of such a step: the previous stage's update wrote
- * the interior).  The inputs it needs (primitive box, derivatives, face
+ * the interior), 9 the ghost cells and the velocity derivatives in one launch
+ * (viscous boxes whose every face is periodic: the form such a step runs in
+ * place of 8 and 5).  The inputs it needs (primitive box, derivatives, face
  * fluxes) are computed from U once before timing.  DCF_EINVAL for an unknown `which`
  * or one the case does not have. */
 dcf_status dcf_time_kernel(dcf_ctx *ctx, const double *U_dev, int which, int reps,

@@ -857,8 +857,10 @@ dcf_status dcf_time_kernel(dcf_ctx *c, const double *U, int which, int reps, dou
   dcf_status s = ready(c, 0);
   if (s) return s;
   if (!U || !avg_ms || reps < 1) return fail(DCF_EINVAL, "bad argument");
-  if (which < 0 || which > 8 || (which >= 1 && which <= 3 && which > c->g.ndim))
+  if (which < 0 || which > 9 || (which >= 1 && which <= 3 && which > c->g.ndim))
     return fail(DCF_EINVAL, "unknown kernel %d", which);
+  if (which == 9 && !periodic_viscous(c))
+    return fail(DCF_EINVAL, "the joint ghost + derivative launch is for all-periodic viscous boxes");
   if (which == 6 && !fused_stages(c))
     return fail(DCF_EINVAL, "no fused flux + update kernel for this case (1D or source term)");
   if (which == 7 && c->g.ndim != 3)
@@ -881,6 +883,7 @@ dcf_status dcf_time_kernel(dcf_ctx *c, const double *U, int which, int reps, dou
                                   g.source == SRC_MASSFLUX ? c->force : nullptr);
     else if (which == 7) e = launch_flux_xy(g, st);
     else if (which == 8) e = launch_prim_ghost(g, st);
+    else if (which == 9) e = launch_ghost_grad_periodic(g, nullptr, 0, 0.0, 0.0, nullptr, st);
     else e = launch_update(g, U, U, c->U1, nullptr, c->U2, 0.0, 1.0, c->force, st);
     if (e != hipSuccess) return fail(DCF_EDEVICE, "launch: %s", hipGetErrorString(e));
   }

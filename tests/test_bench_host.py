@@ -20,7 +20,9 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 def test_step_kernels_of_each_family():
     tgv, _ = W.tgv(8)
-    assert bench.step_kernel_ids(tgv) == [0, 8, 5, 7, 6]
+    assert bench.step_kernel_ids(tgv) == [0, 9, 7, 6]  # every face periodic: ghosts + derivatives
+    tgv_inviscid, _ = W.tgv(8, viscous=False)
+    assert bench.step_kernel_ids(tgv_inviscid) == [0, 8, 7, 6]
     ch, _ = W.channel(16, 8, 8)
     assert bench.step_kernel_ids(ch) == [0, 8, 5, 7, 6]  # body force, periodic z: fused
     ch.bc = ch.bc[:4] + ("wall", "wall")

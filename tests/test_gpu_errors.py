@@ -93,21 +93,22 @@ def test_gradient_sized_for_other_trajectory_rejected():
 
 
 def test_time_kernel_families_and_unknown_ids():
-    # every kernel family of a 3D viscous case times to a positive duration;
-    # the fused flux + update (6) and the combined x + y flux launch (7) are
-    # refused where the case has none (1D)
+    # every kernel family of a 3D viscous periodic case times to a positive
+    # duration; the fused flux + update (6), the combined x + y flux launch
+    # (7) and the joint ghost + derivative launch (9) are refused where the
+    # case has none (1D)
     case, P = W.tgv(16)
     s = Solver(case)
     U = s.init_state(P)
-    for w in range(9):
+    for w in range(10):
         assert s.time_kernel(U, w, reps=2) > 0.0
     L = B.lib()
     ms = C.c_double()
-    for bad in (-1, 9):
+    for bad in (-1, 10):
         assert L.dcf_time_kernel(s.ctx, C.c_void_p(U.data_ptr()), bad, 2, C.byref(ms), None) == -1
     case1, P1 = W.sod(64)
     s1 = Solver(case1)
     U1 = s1.init_state(P1)
     assert s1.time_kernel(U1, 1, reps=2) > 0.0
-    for bad in (2, 6, 7):
+    for bad in (2, 6, 7, 9):
         assert L.dcf_time_kernel(s1.ctx, C.c_void_p(U1.data_ptr()), bad, 2, C.byref(ms), None) == -1
