@@ -26,12 +26,26 @@ def _families():
                bc=("zerograd", "zerograd", "wall", "wall", "periodic", "periodic"),
                T_wall=(0, 0, 1.0, 1.0, 0, 0))
     f3 = [(cs, P, None) for cs, P in tgv] + [(c, W.random_smooth(c, seed=9, amp=0.2), None)]
+    # every face periodic and viscous, ragged sizes: the single-solve step runs
+    # the ghost fill and the derivatives as one launch (derivatives read from
+    # interior cells), the batched step as two; both must agree bitwise
+    def periodic(name, ndim, n):
+        return W.Case(name=name, ndim=ndim, n=n, lo=(0, 0, 0), hi=(1.0, 0.8, 0.6),
+                      stretch=("uniform",) * 3, beta=(0, 0, 0), gamma=1.4, R=1.0, Pr=0.7,
+                      visc_law="power", mu_ref=0.01, T_ref=1.0, visc_param=0.7,
+                      bc=("periodic",) * 6)
+    p3 = [periodic("per3d", 3, n) for n in ((13, 9, 7), (5, 17, 3))]
+    p2 = [periodic("per2d", 2, n) for n in ((19, 11, 1), (3, 40, 1))]
     f1 = [(cs, P, None) for cs, P in (W.sod(200), W.sod(513), W.sod(4096))]
     cp, Pp, Kp = _tiny_porous()
     cl, Pl = W.laminar_bl(nx=36, ny=20, amp=0.01, kappa=10.0)
     cb, Pb, Kb = W.porous_bl(nx=64, ny=32, strip=(16, 48))
     f2 = [(cp, Pp, Kp), (cl, Pl, None), (cb, Pb, Kb)]
-    return {"3d_viscous": f3, "1d_inviscid": f1, "2d_viscous": f2}
+    return {"3d_viscous": f3, "1d_inviscid": f1, "2d_viscous": f2,
+            "3d_periodic_viscous": [(c3, W.random_smooth(c3, seed=21 + i, amp=0.2), None)
+                                    for i, c3 in enumerate(p3)],
+            "2d_periodic_viscous": [(c2, W.random_smooth(c2, seed=31 + i, amp=0.2), None)
+                                    for i, c2 in enumerate(p2)]}
 
 
 FAM = _families()
