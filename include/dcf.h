@@ -259,6 +259,23 @@ dcf_status dcf_gradient(dcf_ctx *ctx, const double *U0_dev, int nsteps, const do
 dcf_status dcf_time_kernel(dcf_ctx *ctx, const double *U_dev, int which, int reps,
                            double *avg_ms, void *stream);
 
+/* Launch probe: while armed, every launch of kernel family `which` (the ids of
+ * dcf_time_kernel: 1 x fluxes of a 2D step, 5 derivatives, 6 fused last-
+ * direction flux + update, 7 x + y fluxes of a 3D step, 8 ghost fill of
+ * stages after the first (with the carried CFL reduction where a step
+ * follows another in one call), 9 joint ghost + derivative launch) that the
+ * fused stepping calls (dcf_rk3_step,
+ * dcf_rk3_step_cfl, dcf_rk3_steps_cfl) make is bracketed by a pair of HIP
+ * events recorded on that call's stream, up to max_launches launches (later
+ * ones are not recorded).  The events are created here and owned by the
+ * context.  dcf_probe_end waits for the last recorded event, returns the
+ * number of recorded launches and their mean duration in milliseconds, and
+ * releases the events (a later dcf_probe_begin may arm again).  DCF_EINVAL for
+ * an id that cannot be probed, max_launches outside [1, 2^20], arming twice or
+ * ending an unarmed probe. */
+dcf_status dcf_probe_begin(dcf_ctx *ctx, int which, int max_launches);
+dcf_status dcf_probe_end(dcf_ctx *ctx, int *launches, double *avg_ms);
+
 /* Incremental form of dcf_gradient, for schedulers that interleave many
  * solves: begin validates and records the request (same arguments as
  * dcf_gradient, J and dJdK zeroed on `stream`); advance enqueues at most

@@ -67,6 +67,8 @@ _SIGS = {
     "dcf_gradient_finish": [_vp, _vp, _vp],
     "dcf_flags": [_vp, C.POINTER(C.c_uint), _vp],
     "dcf_time_kernel": [_vp, _vp, C.c_int, C.c_int, C.POINTER(C.c_double), _vp],
+    "dcf_probe_begin": [_vp, C.c_int, C.c_int],
+    "dcf_probe_end": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_double)],
     "dcf_batch_table_bytes": [C.c_int, C.POINTER(C.c_size_t)],
     "dcf_rk3_step_cfl": [_vp, _vp, _vp, C.c_double, C.c_double, _vp, _vp],
     "dcf_rk3_steps_cfl": [_vp, _vp, _vp, C.c_int, C.c_double, C.c_double, _vp],

@@ -73,6 +73,7 @@ struct dcf_ctx {
   double *boxc = nullptr;  // mode 3: primitive + derivative boxes of every stage of a segment
   int box_arrays = 0;      // box arrays per cached stage
   double *lam_a = nullptr, *lam_b = nullptr, *gbuf = nullptr, *zero_dt = nullptr;
+  Probe probe;  // dcf_probe_begin / dcf_probe_end
   // incremental gradient state (dcf_gradient_begin / advance / finish)
   struct {
     bool active = false;
@@ -204,6 +205,10 @@ dcf_status dcf_destroy(dcf_ctx *c) {
   if (!c) return DCF_OK;
   (void)hipDeviceSynchronize();
   if (c->metric_mem) (void)hipFree(c->metric_mem);
+  if (c->probe.ev) {
+    for (int i = 0; i < 2 * c->probe.cap; ++i) (void)hipEventDestroy(c->probe.ev[i]);
+    delete[] c->probe.ev;
+  }
   delete c;
   return DCF_OK;
 }
@@ -463,26 +468,33 @@ static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_
       bo[1].Q[q] = c->qalt.Q[q];
     }
     const bool merged = periodic_viscous(c);
+    Probe &pr = c->probe;
     for (int k = 0; k < 3; ++k) {
       const Dev &gk = gs[(base + k) & 1];
       if (merged) {
         if (k == 0 && !box_ready) DCF_HIP(launch_prim_interior(gk, in[k], st));
         const PendingDt *pk = k == 0 ? pend : nullptr;
+        pr.before(9, st);
         DCF_HIP(launch_ghost_grad_periodic(gk, pk ? c->dtpart : nullptr, pk ? pk->nparts : 0,
                                            pk ? pk->cfl : 0.0, pk ? pk->dt_max : 0.0,
                                            pk ? pk->dt : nullptr, st));
+        pr.after(9, st);
       } else if (k == 0 && !box_ready) {
         DCF_HIP(launch_prim_halo(gk, in[k], st));
       } else if (k == 0 && pend) {
+        pr.before(8, st);
         DCF_HIP(launch_prim_ghost_dt(gk, c->dtpart, pend->nparts, pend->cfl, pend->dt_max,
                                      pend->dt, st));
+        pr.after(8, st);
       } else {
+        pr.before(8, st);
         DCF_HIP(launch_prim_ghost(gk, st));
+        pr.after(8, st);
       }
       const bool next = k < 2 || write_next;
       DCF_HIP(launch_fluxes_update(gk, U, in[k], out[k], dt, a[k], b[k], k == 2 ? dtpart : nullptr,
                                    st, next ? bo[(base + k + 1) & 1] : BoxOut{}, c->part,
-                                   g.source == SRC_MASSFLUX ? c->force : nullptr, merged));
+                                   g.source == SRC_MASSFLUX ? c->force : nullptr, merged, &pr));
     }
     return DCF_OK;
   }
@@ -894,6 +906,51 @@ dcf_status dcf_time_kernel(dcf_ctx *c, const double *U, int which, int reps, dou
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *avg_ms = ms / reps;
+  return DCF_OK;
+}
+
+dcf_status dcf_probe_begin(dcf_ctx *c, int which, int max_launches) {
+  dcf_status s = ready(c, 0);
+  if (s) return s;
+  if (!(which == 1 || (which >= 5 && which <= 9)))
+    return fail(DCF_EINVAL, "kernel %d cannot be probed", which);
+  if (max_launches < 1 || max_launches > (1 << 20)) return fail(DCF_EINVAL, "bad max_launches");
+  if (c->probe.ev) return fail(DCF_EINVAL, "a probe is already armed");
+  hipEvent_t *ev = new hipEvent_t[2 * (size_t)max_launches];
+  for (int i = 0; i < 2 * max_launches; ++i) {
+    const hipError_t e = hipEventCreate(&ev[i]);
+    if (e != hipSuccess) {
+      for (int k = 0; k < i; ++k) (void)hipEventDestroy(ev[k]);
+      delete[] ev;
+      return fail(DCF_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+    }
+  }
+  c->probe.which = which;
+  c->probe.ev = ev;
+  c->probe.cap = max_launches;
+  c->probe.n = 0;
+  return DCF_OK;
+}
+
+dcf_status dcf_probe_end(dcf_ctx *c, int *launches, double *avg_ms) {
+  if (!c) return fail(DCF_EINVAL, "null context");
+  if (!launches || !avg_ms) return fail(DCF_EINVAL, "null argument");
+  Probe &p = c->probe;
+  if (!p.ev) return fail(DCF_EINVAL, "no probe armed");
+  double sum = 0.0;
+  hipError_t err = hipSuccess;
+  if (p.n > 0) err = hipEventSynchronize(p.ev[2 * p.n - 1]);
+  for (int i = 0; i < p.n && err == hipSuccess; ++i) {
+    float ms = 0.f;
+    err = hipEventElapsedTime(&ms, p.ev[2 * i], p.ev[2 * i + 1]);
+    sum += ms;
+  }
+  *launches = p.n;
+  *avg_ms = p.n > 0 ? sum / p.n : 0.0;
+  for (int i = 0; i < 2 * p.cap; ++i) (void)hipEventDestroy(p.ev[i]);
+  delete[] p.ev;
+  p = Probe{};
+  if (err != hipSuccess) return fail(DCF_EDEVICE, "probe events: %s", hipGetErrorString(err));
   return DCF_OK;
 }
 

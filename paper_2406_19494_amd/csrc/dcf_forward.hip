@@ -1331,14 +1331,29 @@ hipError_t launch_flux_update_last(const Dev &g, const double *Un, const double 
 hipError_t launch_fluxes_update(const Dev &g, const double *Un, const double *Uin,
                                 double *Uout, const double *dt, double a, double b,
                                 double *dtpart, hipStream_t st, const BoxOut &qo,
-                                double *part, double *force, bool grad_done) {
-  hipError_t e = grad_done ? hipSuccess : launch_grad(g, st);
-  if (e == hipSuccess) e = g.ndim == 3 ? launch_flux_xy(g, st) : launch_flux_dir(g, 0, st);
+                                double *part, double *force, bool grad_done, Probe *pr) {
+  Probe none;
+  Probe &p = pr ? *pr : none;
+  hipError_t e = hipSuccess;
+  if (!grad_done) {
+    p.before(5, st);
+    e = launch_grad(g, st);
+    p.after(5, st);
+  }
+  if (e == hipSuccess) {
+    const int w = g.ndim == 3 ? 7 : 1;
+    p.before(w, st);
+    e = g.ndim == 3 ? launch_flux_xy(g, st) : launch_flux_dir(g, 0, st);
+    p.after(w, st);
+  }
   // the body force from the boundary fluxes of the directions before the
   // last (the last one is periodic: its boundary terms vanish)
   if (e == hipSuccess && force) e = launch_force(g, part, force, st, g.ndim - 1);
   if (e != hipSuccess) return e;
-  return launch_flux_update_last(g, Un, Uin, Uout, dt, a, b, dtpart, st, qo, force);
+  p.before(6, st);
+  e = launch_flux_update_last(g, Un, Uin, Uout, dt, a, b, dtpart, st, qo, force);
+  p.after(6, st);
+  return e;
 }
 
 hipError_t launch_prim_ghost(const Dev &g, hipStream_t st) {

@@ -60,12 +60,31 @@ unsigned update_blocks(const Dev &g);
 // (launch_prim_ghost on a context whose Q is qo).  With force (the
 // constant-mass-flux source; the last direction periodic) the body force is
 // reduced into force (partials in part) before the fused kernel applies it.
+// HIP event pairs around the launches of one kernel family (the ids of
+// dcf_time_kernel) while armed: before/after record on the launch's stream,
+// up to cap launches.  Host-side bookkeeping only.
+struct Probe {
+  int which = -1;
+  hipEvent_t *ev = nullptr;  // 2 * cap events: start, end of each launch
+  int cap = 0, n = 0;
+  void before(int w, hipStream_t st) {
+    if (w == which && n < cap) (void)hipEventRecord(ev[2 * n], st);
+  }
+  void after(int w, hipStream_t st) {
+    if (w != which || n >= cap) return;
+    (void)hipEventRecord(ev[2 * n + 1], st);
+    ++n;
+  }
+};
+
 // With grad_done the derivatives are already in g.G (launch_ghost_grad_periodic).
+// With pr the grad (5), x+y or x flux (7 / 1) and fused update (6) launches
+// are bracketed by its events.
 hipError_t launch_fluxes_update(const Dev &g, const double *Un, const double *Uin,
                                 double *Uout, const double *dt, double a, double b,
                                 double *dtpart, hipStream_t st, const BoxOut &qo = BoxOut{},
                                 double *part = nullptr, double *force = nullptr,
-                                bool grad_done = false);
+                                bool grad_done = false, Probe *pr = nullptr);
 unsigned flux_update_blocks(const Dev &g);
 // The last direction's flux + update kernel alone (its gradient and other
 // fluxes already computed).

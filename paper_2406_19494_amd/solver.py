@@ -192,6 +192,18 @@ class Solver:
                _stream(stream))
         return ms.value
 
+    def probe_begin(self, which: int, max_launches: int) -> None:
+        """Arm HIP event pairs around the stepping calls' launches of one
+        kernel family (dcf_probe_begin)."""
+        B.call("dcf_probe_begin", self.ctx, int(which), int(max_launches))
+
+    def probe_end(self):
+        """(launches recorded, mean duration in ms) of the armed probe
+        (dcf_probe_end; waits for its last event)."""
+        n, ms = C.c_int(), C.c_double()
+        B.call("dcf_probe_end", self.ctx, C.byref(n), C.byref(ms))
+        return n.value, ms.value
+
     def flags(self, stream=None) -> int:
         f = C.c_uint()
         B.call("dcf_flags", self.ctx, C.byref(f), _stream(stream))

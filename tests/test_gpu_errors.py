@@ -112,3 +112,47 @@ def test_time_kernel_families_and_unknown_ids():
     assert s1.time_kernel(U1, 1, reps=2) > 0.0
     for bad in (2, 6, 7, 9):
         assert L.dcf_time_kernel(s1.ctx, C.c_void_p(U1.data_ptr()), bad, 2, C.byref(ms), None) == -1
+
+
+def test_probe_counts_in_loop_launches_and_changes_nothing():
+    # event pairs around the stepping calls' launches of one kernel family:
+    # one launch per stage, the same state bitwise as an unprobed run
+    print("[probe] tgv 12, porous BL 24x16", flush=True)
+    for case, P, K, ids in ((*W.tgv(12), None, (7, 6, 9)),
+                            (*W.porous_bl(nx=24, ny=16, strip=(6, 18)), (1, 5, 6, 8))):
+        s = Solver(case, K=K)
+        U0 = s.init_state(P)
+        ref = U0.clone()
+        dt_ref = s.compute_dt(ref, cfl=0.4)
+        s.steps_cfl(ref, dt_ref, 4, cfl=0.4)
+        for w in ids:
+            U = U0.clone()
+            dt = s.compute_dt(U, cfl=0.4)
+            s.probe_begin(w, 100)
+            s.steps_cfl(U, dt, 4, cfl=0.4)
+            n, ms = s.probe_end()
+            # ghosts alone (8) run in stages 2-3 and later first stages; the
+            # first stage of the call fills the whole halo
+            assert n == (4 * 3 - 1 if w == 8 else 4 * 3), (case.name, w, n)
+            assert ms > 0.0
+            assert torch.equal(U, ref) and torch.equal(dt, dt_ref), (case.name, w)
+    # capped at max_launches
+    s.probe_begin(6, 5)
+    U = U0.clone()
+    s.steps_cfl(U, s.compute_dt(U, cfl=0.4), 4, cfl=0.4)
+    assert s.probe_end()[0] == 5
+
+
+def test_probe_argument_errors():
+    case, P = W.tgv(8)
+    s = Solver(case)
+    L = B.lib()
+    n, ms = C.c_int(), C.c_double()
+    for bad in (-1, 0, 2, 3, 4, 10):
+        assert L.dcf_probe_begin(s.ctx, bad, 10) == -1
+    assert L.dcf_probe_begin(s.ctx, 7, 0) == -1
+    assert L.dcf_probe_end(s.ctx, C.byref(n), C.byref(ms)) == -1  # nothing armed
+    assert L.dcf_probe_begin(s.ctx, 7, 10) == 0
+    assert L.dcf_probe_begin(s.ctx, 7, 10) == -1  # armed twice
+    assert L.dcf_probe_end(s.ctx, C.byref(n), C.byref(ms)) == 0
+    assert n.value == 0 and ms.value == 0.0
