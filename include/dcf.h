@@ -164,7 +164,7 @@ dcf_status dcf_set_source(dcf_ctx *ctx, int kind);
 dcf_status dcf_set_cost(dcf_ctx *ctx, int face, double p_ref);
 
 /* ---- forward ------------------------------------------------------------ */
-/* U (dev, out) from primitives P (dev). */
+/* U (dev, out) from primitives P (dev), Eq. (2); needs no workspace. */
 dcf_status dcf_init_state(dcf_ctx *ctx, const double *P_dev, double *U_dev, void *stream);
 
 /* R = dU/dt of Eq. (6) including the source; R has the layout of U. */
@@ -177,6 +177,26 @@ dcf_status dcf_compute_dt(dcf_ctx *ctx, const double *U_dev, double cfl, double 
 
 /* One TVD-RK3 step (Shu-Osher form) in place, with dt read from dt_dev[0]. */
 dcf_status dcf_rk3_step(dcf_ctx *ctx, double *U_dev, const double *dt_dev, void *stream);
+
+/* dcf_rk3_step for callers that cannot allocate device memory or be handed
+ * a workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The forward workspace of the step is laid out in a
+ * static scratch array of DCF_NOALLOC_SCRATCH_BYTES bytes that each device
+ * holds from the library's first use on it (dcf_create resolves its address)
+ * until the process ends; the call allocates and frees nothing.  The context
+ * needs no workspace (one it has is left untouched).  flags_dev (nullable
+ * dev, one unsigned): the non-physical flags of the step's kernels are OR-ed
+ * into it (the caller clears it); NULL discards them.  DCF_EBUDGET when the
+ * case needs more than DCF_NOALLOC_SCRATCH_BYTES (its mode-0 workspace size,
+ * dcf_workspace_size).  Results are bitwise those of dcf_rk3_step.  Every
+ * call on one device shares that device's scratch, which keeps the last
+ * call's contents (no buffer in it needs to start at zero: each is written
+ * before it is read within one call): calls that overlap on one device
+ * (other streams or host threads) race and must be serialised by the
+ * caller. */
+#define DCF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+dcf_status dcf_rk3_step_noalloc(dcf_ctx *ctx, double *U_dev, const double *dt_dev,
+                                unsigned *flags_dev, void *stream);
 
 /* dcf_rk3_step fused with the CFL step of the new state: the last stage's
  * update also reduces the signal rates of the cells it writes, and

@@ -58,6 +58,7 @@ _SIGS = {
     "dcf_rhs": [_vp, _vp, _vp, _vp],
     "dcf_compute_dt": [_vp, _vp, C.c_double, C.c_double, _vp, _vp],
     "dcf_rk3_step": [_vp, _vp, _vp, _vp],
+    "dcf_rk3_step_noalloc": [_vp, _vp, _vp, _vp, _vp],
     "dcf_diagnostics": [_vp, _vp, _vp, _vp],
     "dcf_vjp_step": [_vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "dcf_cost_term": [_vp, _vp, C.c_double, _vp, _vp, _vp],

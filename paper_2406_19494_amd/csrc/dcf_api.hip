@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -47,7 +48,20 @@ struct Carver {
     return p;
   }
 };
+
+// Device addresses of `scratch` (below), one per device, resolved by
+// dcf_create with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
 }  // namespace
+
+// Workspace of dcf_rk3_step_noalloc: a fixed array in every device's copy of
+// the code object, held from the first use of the library on a device until
+// the process ends.  Host code never passes `scratch` itself to a kernel (on
+// the host the name is only a stand-in): it uses the per-device address that
+// hipGetSymbolAddress returned.
+static __device__ __align__(256) unsigned char scratch[DCF_NOALLOC_SCRATCH_BYTES];
 
 struct dcf_ctx {
   int device = 0;
@@ -119,9 +133,24 @@ dcf_status dcf_create(const dcf_grid *grid, const dcf_gas *gas, dcf_ctx **out) {
   if (ncell > (1L << 31) - 1 || nboxc > (1L << 32) - 1)
     return fail(DCF_EINVAL, "grid too large");
 
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess || device < 0 || device >= kMaxDevices)
+    return fail(DCF_EDEVICE, "no usable current device");
+  {
+    // the static scratch of dcf_rk3_step_noalloc: its address on this device,
+    // taken once per device with the device current
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+      void *ptr = nullptr;
+      const hipError_t es = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (es != hipSuccess || !ptr)
+        return fail(DCF_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(es));
+      g_scratch_addr[device] = ptr;
+    }
+  }
   dcf_ctx *c = new (std::nothrow) dcf_ctx();
   if (!c) return fail(DCF_ENOMEM, "host allocation failed");
-  (void)hipGetDevice(&c->device);
+  c->device = device;
   c->grid = *grid;
   c->gas = *gas;
   Dev &g = c->g;
@@ -374,7 +403,8 @@ dcf_status dcf_set_cost(dcf_ctx *c, int face, double pref) {
 
 }  // extern "C"
 
-// Checks that the context is complete before anything is enqueued.
+// Checks that the context is complete before anything is enqueued
+// (need_mode -1: no workspace needed).
 static dcf_status ready(dcf_ctx *c, int need_mode) {
   if (!c) return fail(DCF_EINVAL, "null context");
   if (c->ws_mode < need_mode)
@@ -511,7 +541,7 @@ static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_
 extern "C" {
 
 dcf_status dcf_init_state(dcf_ctx *c, const double *P, double *U, void *stream) {
-  dcf_status s = ready(c, 0);
+  dcf_status s = ready(c, -1);
   if (s) return s;
   if (!P || !U) return fail(DCF_EINVAL, "null array");
   DCF_HIP(launch_init_state(c->g, P, U, (hipStream_t)stream));
@@ -544,6 +574,33 @@ dcf_status dcf_rk3_step(dcf_ctx *c, double *U, const double *dt, void *stream) {
   if (s) return s;
   if (!U || !dt) return fail(DCF_EINVAL, "null array");
   return rk3_stages(c, U, dt, (hipStream_t)stream);
+}
+
+dcf_status dcf_rk3_step_noalloc(dcf_ctx *c, double *U, const double *dt, unsigned *flags,
+                                void *stream) {
+  dcf_status s = ready(c, -1);
+  if (s) return s;
+  if (!U || !dt) return fail(DCF_EINVAL, "null array");
+  void *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    base = g_scratch_addr[c->device];
+  }
+  if (!base) return fail(DCF_EDEVICE, "static scratch not resolved on device %d", c->device);
+  // the forward workspace laid out over the scratch, in a copy of the
+  // context: the caller's own workspace (if any) is left alone
+  dcf_ctx tmp = *c;
+  tmp.probe = Probe{};
+  tmp.gr.active = false;
+  const size_t need = carve(&tmp, nullptr, 0, 0, 0);
+  if (need > DCF_NOALLOC_SCRATCH_BYTES)
+    return fail(DCF_EBUDGET, "the step needs %zu bytes of scratch, the static scratch holds %zu",
+                need, (size_t)DCF_NOALLOC_SCRATCH_BYTES);
+  carve(&tmp, base, 0, 0, 0);
+  // every scratch buffer is written before it is read within the step; the
+  // flag word only collects bits (into the caller's word when given)
+  if (flags) tmp.g.flags = flags;
+  return rk3_stages(&tmp, U, dt, (hipStream_t)stream);
 }
 
 dcf_status dcf_batch_table_bytes(int n, size_t *bytes) {

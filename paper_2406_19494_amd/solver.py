@@ -31,7 +31,8 @@ def _stream(stream=None):
 class Solver:
     """A solve on the GPU.
 
-    mode: 0 forward, 1 forward + single-step VJP, 2 trajectory gradient with
+    mode: -1 no workspace (only dcf_rk3_step_noalloc runs), 0 forward, 1
+    forward + single-step VJP, 2 trajectory gradient with
     ``nsteps`` steps and checkpoints every ``seg_len`` steps, 3 as 2 with the
     stage boxes of a segment kept for the reverse sweep (more memory, no
     recompute in the reverse sweep).
@@ -86,10 +87,13 @@ class Solver:
                 None if K is None else (K.cpu().numpy() if torch.is_tensor(K) else K))
             self.set_params(torch.as_tensor(th, dtype=torch.float64, device=self.device))
         self.mode, self.nsteps, self.seg_len = mode, nsteps, seg_len
-        size = C.c_size_t()
-        B.call("dcf_workspace_size", ctx, mode, nsteps, seg_len, C.byref(size))
-        self.workspace = torch.empty(size.value, dtype=torch.uint8, device=self.device)
-        B.call("dcf_set_workspace", ctx, mode, nsteps, seg_len, _ptr(self.workspace), size.value)
+        self.workspace = None
+        if mode >= 0:  # mode -1: no workspace (for dcf_rk3_step_noalloc)
+            size = C.c_size_t()
+            B.call("dcf_workspace_size", ctx, mode, nsteps, seg_len, C.byref(size))
+            self.workspace = torch.empty(size.value, dtype=torch.uint8, device=self.device)
+            B.call("dcf_set_workspace", ctx, mode, nsteps, seg_len, _ptr(self.workspace),
+                   size.value)
         nv, ncell, nbytes = C.c_int(), C.c_long(), C.c_size_t()
         B.call("dcf_state_info", ctx, C.byref(nv), C.byref(ncell), C.byref(nbytes))
         self.nv, self.ncell = nv.value, ncell.value
@@ -222,7 +226,7 @@ class Solver:
         return out
 
     def workspace_bytes(self) -> int:
-        return int(self.workspace.numel())
+        return 0 if self.workspace is None else int(self.workspace.numel())
 
     def gradient_begin(self, U0, dt, J, gK, stream=None):
         B.call("dcf_gradient_begin", self.ctx, _ptr(U0), int(self.nsteps), _ptr(dt),
