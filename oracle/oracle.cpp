@@ -202,6 +202,112 @@ template <class T> void hllc(const T *qL, const T *qR, double gamma, T *F) {
   for (int m = 0; m < 5; ++m) F[m] = Fk[m] + S * (Us[m] - Uk[m]);
 }
 
+/* ------------------------------------------------------------------------ */
+/* TENO6-A (targeted ENO with six points and adaptive dissipation; Fu, Hu &  */
+/* Adams): value at the right face of cell i from v = cells i-2 .. i+3.      */
+/* Steps, in the scheme's order:                                             */
+/*  1. third-order candidates on S0 = {i-1,i,i+1}, S1 = {i,i+1,i+2},          */
+/*     S2 = {i-2,i-1,i} and the fourth-order candidate on S3 = {i..i+3};     */
+/*     linear weights d = (0.45, 0.3, 0.05, 0.2), the combination that is    */
+/*     the sixth-order central reconstruction on the six points;             */
+/*  2. Jiang-Shu smoothness indicators beta_k of the candidates and beta6 of  */
+/*     the six-point polynomial; tau6 = |beta6 - (beta0 + beta2 + 4 beta1)/6| */
+/*  3. scale separation gamma_k = (C + tau6 / (beta_k + eps))^q, C = 1,     */
+/*     q = 6, eps = 1e-40, chi_k = gamma_k / sum gamma;                       */
+/*  4. adaptive cut-off C_T = 10^-floor(b), b = alpha1 - alpha2 (1 - g(m)),   */
+/*     g(m) = (1 - m)^4 (1 + 4 m), m = 1 - min(1, eta / C_r), with eta the    */
+/*     smallest of Ren et al.'s smoothness measures of cells i-1 .. i+2:      */
+/*     eta_j = (|2 D_{j+1/2} D_{j-1/2}| + e) / (D_{j+1/2}^2 + D_{j-1/2}^2 + e),  */
+/*     D_{j+1/2} = v_{j+1} - v_j, e = 0.9 C_r xi^2 / (1 - 0.9 C_r);            */
+/*     alpha1 = 10.5, alpha2 = 3.5, C_r = 0.17, xi = 1e-3 (so C_T runs from   */
+/*     1e-10 in smooth regions to 1e-7 at discontinuities);                  */
+/*  5. sharp cut-off delta_k = 0 if chi_k < C_T else 1, and                   */
+/*     omega_k = d_k delta_k / sum_l d_l delta_l;                             */
+/*  6. the value sum_k omega_k q_k.                                           */
+/* The cut-off decisions are piecewise constant: a Dual carries the          */
+/* derivative of the branch taken.                                           */
+/* ------------------------------------------------------------------------ */
+template <class T> inline T vabs(T x) { return val(x) < 0.0 ? -1.0 * x : x; }
+
+template <class T> T teno6a(const T *v, double *ct_out = nullptr, double *w_out = nullptr) {
+  const T a = v[0], b = v[1], c = v[2], d = v[3], e = v[4], f = v[5];
+  /* 1 */
+  T q[4] = {(-1.0 * b + 5.0 * c + 2.0 * d) / 6.0, (2.0 * c + 5.0 * d - 1.0 * e) / 6.0,
+            (2.0 * a - 7.0 * b + 11.0 * c) / 6.0,
+            (3.0 * c + 13.0 * d - 5.0 * e + 1.0 * f) / 12.0};
+  const double dk[4] = {0.45, 0.3, 0.05, 0.2};
+  /* 2 */
+  T beta[4];
+  {
+    T s1 = b - 2.0 * c + d, t1 = b - d;
+    T s2 = c - 2.0 * d + e, t2 = 3.0 * c - 4.0 * d + e;
+    T s3 = a - 2.0 * b + c, t3 = a - 4.0 * b + 3.0 * c;
+    beta[0] = (13.0 / 12.0) * s1 * s1 + 0.25 * t1 * t1;
+    beta[1] = (13.0 / 12.0) * s2 * s2 + 0.25 * t2 * t2;
+    beta[2] = (13.0 / 12.0) * s3 * s3 + 0.25 * t3 * t3;
+    beta[3] = (c * (2107.0 * c - 9402.0 * d + 7042.0 * e - 1854.0 * f) +
+               d * (11003.0 * d - 17246.0 * e + 4642.0 * f) +
+               e * (7043.0 * e - 3882.0 * f) + 547.0 * f * f) / 240.0;
+  }
+  T beta6 = (271779.0 * a * a +
+             a * (-2380800.0 * b + 4086352.0 * c - 3462252.0 * d + 1458762.0 * e -
+                  245620.0 * f) +
+             b * (5653317.0 * b - 20427884.0 * c + 17905032.0 * d - 7727988.0 * e +
+                  1325006.0 * f) +
+             c * (19510972.0 * c - 35817664.0 * d + 15929912.0 * e - 2792660.0 * f) +
+             d * (17195652.0 * d - 15880404.0 * e + 2863984.0 * f) +
+             e * (3824847.0 * e - 1429976.0 * f) + 139633.0 * f * f) / 120960.0;
+  T tau6 = vabs(beta6 - (beta[0] + beta[2] + 4.0 * beta[1]) / 6.0);
+  /* 3 */
+  T gam[4];
+  T gsum = T(0.0);
+  for (int k = 0; k < 4; ++k) {
+    T r = 1.0 + tau6 / (beta[k] + 1e-40);
+    gam[k] = r * r * r * r * r * r;
+    gsum += gam[k];
+  }
+  /* 4 */
+  const double Cr = 0.17, xi = 1e-3, alpha1 = 10.5, alpha2 = 3.5;
+  const double eps_eta = 0.9 * Cr * xi * xi / (1.0 - 0.9 * Cr);
+  double eta = 1e300;
+  for (int j = 1; j <= 4; ++j) { /* cells i-1 .. i+2 = v[1] .. v[4] */
+    double dm = val(v[j]) - val(v[j - 1]), dp = val(v[j + 1]) - val(v[j]);
+    double ej = (std::fabs(2.0 * dp * dm) + eps_eta) / (dp * dp + dm * dm + eps_eta);
+    eta = std::min(eta, ej);
+  }
+  double m = 1.0 - std::min(1.0, eta / Cr);
+  double gm = std::pow(1.0 - m, 4.0) * (1.0 + 4.0 * m);
+  double bbar = alpha1 - alpha2 * (1.0 - gm);
+  double CT = std::pow(10.0, -std::floor(bbar));
+  if (ct_out) *ct_out = CT;
+  /* 5, 6 */
+  double wsum = 0.0, w[4];
+  for (int k = 0; k < 4; ++k) {
+    double chi = val(gam[k]) / val(gsum);
+    w[k] = chi < CT ? 0.0 : dk[k];
+    wsum += w[k];
+  }
+  T out = T(0.0);
+  for (int k = 0; k < 4; ++k) {
+    if (w_out) w_out[k] = w[k] / wsum;
+    out += (w[k] / wsum) * q[k];
+  }
+  return out;
+}
+
+/* 6th-order central interpolation to a face and derivatives (index space):
+ * face value and face derivative from the six cells around the face, cell
+ * derivative from the cells three either side. */
+template <class T> inline T interp6(T a, T b, T c, T d, T e, T f) {
+  return (3.0 * a - 25.0 * b + 150.0 * c + 150.0 * d - 25.0 * e + 3.0 * f) / 256.0;
+}
+template <class T> inline T dface6(T a, T b, T c, T d, T e, T f) {
+  return (2250.0 * (d - c) - 125.0 * (e - b) + 9.0 * (f - a)) / 1920.0;
+}
+template <class T> inline T dcell6(T m3, T m2, T m1, T p1, T p2, T p3) {
+  return (45.0 * (p1 - m1) - 9.0 * (p2 - m2) + (p3 - m3)) / 60.0;
+}
+
 /* 4th-order central interpolation to a face and derivatives (index space). */
 template <class T> inline T interp4(T a, T b, T c, T d) {
   return (-1.0 * a + 9.0 * b + 9.0 * c - 1.0 * d) / 16.0;
@@ -412,6 +518,9 @@ template <class T> struct Solver {
       r[t] += off;
       return Q[q][bid(r[0], r[1], r[2])];
     };
+    if (c.scheme == ORC_SCHEME_TENO6A)
+      return dcell6(val_at(-3), val_at(-2), val_at(-1), val_at(1), val_at(2), val_at(3)) *
+             ax[t].mc[pos];
     return dcell4(val_at(-2), val_at(-1), val_at(1), val_at(2)) * ax[t].mc[pos];
   }
 
@@ -424,8 +533,23 @@ template <class T> struct Solver {
       const std::vector<T> &A = Q[qi[m]];
       T v0 = A[at(d, f - 3, a, b)], v1 = A[at(d, f - 2, a, b)], v2 = A[at(d, f - 1, a, b)];
       T v3 = A[at(d, f, a, b)], v4 = A[at(d, f + 1, a, b)], v5 = A[at(d, f + 2, a, b)];
-      qL[m] = weno5(v0, v1, v2, v3, v4);
-      qR[m] = weno5(v5, v4, v3, v2, v1);
+      if (c.scheme == ORC_SCHEME_TENO6A) {
+        T six[6] = {v0, v1, v2, v3, v4, v5}, mir[6] = {v5, v4, v3, v2, v1, v0};
+        qL[m] = teno6a(six);
+        qR[m] = teno6a(mir);
+      } else {
+        qL[m] = weno5(v0, v1, v2, v3, v4);
+        qR[m] = weno5(v5, v4, v3, v2, v1);
+      }
+    }
+    if (c.scheme == ORC_SCHEME_TENO6A) {
+      /* interpolation limiter: a side whose reconstructed density or
+       * pressure is not positive takes the first-order state, the primitives
+       * of its own cell */
+      if (!(val(qL[0]) > 0.0 && val(qL[4]) > 0.0))
+        for (int m = 0; m < 5; ++m) qL[m] = Q[qi[m]][at(d, f - 1, a, b)];
+      if (!(val(qR[0]) > 0.0 && val(qR[4]) > 0.0))
+        for (int m = 0; m < 5; ++m) qR[m] = Q[qi[m]][at(d, f, a, b)];
     }
     T Fc[5];
     hllc(qL, qR, c.gamma, Fc);
@@ -435,7 +559,51 @@ template <class T> struct Solver {
     G[1 + t1(d)] = Fc[2];
     G[1 + t2(d)] = Fc[3];
     G[4] = Fc[4];
-    if (viscous()) {
+    if (viscous() && c.scheme == ORC_SCHEME_TENO6A) {
+      /* Dissipative flux, Eqs. (4)-(5) and Fourier's law, 6th-order central
+       * over the six cells f-3 .. f+2. */
+      auto cellq = [&](int q, int s) { return Q[q][at(d, s, a, b)]; };
+      auto fval = [&](int q) {
+        return interp6(cellq(q, f - 3), cellq(q, f - 2), cellq(q, f - 1), cellq(q, f),
+                       cellq(q, f + 1), cellq(q, f + 2));
+      };
+      auto fder = [&](int q) {
+        return dface6(cellq(q, f - 3), cellq(q, f - 2), cellq(q, f - 1), cellq(q, f),
+                      cellq(q, f + 1), cellq(q, f + 2)) * ax[d].mf[f];
+      };
+      T muf = interp6(MU[at(d, f - 3, a, b)], MU[at(d, f - 2, a, b)], MU[at(d, f - 1, a, b)],
+                      MU[at(d, f, a, b)], MU[at(d, f + 1, a, b)], MU[at(d, f + 2, a, b)]);
+      T uf[3] = {fval(1), fval(2), fval(3)};
+      T dn[3] = {fder(1), fder(2), fder(3)};
+      T dT = fder(5);
+      T tau[3] = {T(0.0), T(0.0), T(0.0)};
+      T divt = T(0.0);
+      T dtn[3] = {T(0.0), T(0.0), T(0.0)};
+      const int tt[2] = {t1(d), t2(d)};
+      for (int r = 0; r < 2; ++r) {
+        int t = tt[r];
+        if (t >= nd) continue;
+        T g_tt[6], g_tn[6];
+        for (int o = 0; o < 6; ++o) {
+          g_tt[o] = dtan(1 + t, d, t, f - 3 + o, a, b);
+          g_tn[o] = dtan(1 + d, d, t, f - 3 + o, a, b);
+        }
+        divt += interp6(g_tt[0], g_tt[1], g_tt[2], g_tt[3], g_tt[4], g_tt[5]);
+        dtn[t] = interp6(g_tn[0], g_tn[1], g_tn[2], g_tn[3], g_tn[4], g_tn[5]);
+      }
+      tau[d] = muf * ((4.0 / 3.0) * dn[d] - (2.0 / 3.0) * divt);
+      for (int r = 0; r < 2; ++r) {
+        int t = tt[r];
+        if (t >= nd) continue;
+        tau[t] = muf * (dtn[t] + dn[t]);
+      }
+      T lam = muf * cp / c.Pr;
+      T en = uf[0] * tau[0] + uf[1] * tau[1] + uf[2] * tau[2] + lam * dT;
+      G[1] -= tau[0];
+      G[2] -= tau[1];
+      G[3] -= tau[2];
+      G[4] -= en;
+    } else if (viscous()) {
       /* Dissipative flux, Eqs. (4)-(5) and Fourier's law, 4th-order central. */
       auto cellq = [&](int q, int s) { return Q[q][at(d, s, a, b)]; };
       auto fval = [&](int q) {
@@ -609,6 +777,45 @@ void orc_grid(const orc_case *c, int axis, double *xf, double *dx, double *met_c
 
 double orc_weno5(double a, double b, double c, double d, double e) {
   return weno5<double>(a, b, c, d, e);
+}
+
+double orc_teno6a(const double *v, double *ct_out, double *w_out) {
+  return teno6a<double>(v, ct_out, w_out);
+}
+
+void orc_teno6a_beta(const double *v, double *beta) {
+  /* the smoothness indicators teno6a forms (step 2): beta0..beta3, beta6 */
+  const double a = v[0], b = v[1], c = v[2], d = v[3], e = v[4], f = v[5];
+  double s1 = b - 2.0 * c + d, t1 = b - d;
+  double s2 = c - 2.0 * d + e, t2 = 3.0 * c - 4.0 * d + e;
+  double s3 = a - 2.0 * b + c, t3 = a - 4.0 * b + 3.0 * c;
+  beta[0] = (13.0 / 12.0) * s1 * s1 + 0.25 * t1 * t1;
+  beta[1] = (13.0 / 12.0) * s2 * s2 + 0.25 * t2 * t2;
+  beta[2] = (13.0 / 12.0) * s3 * s3 + 0.25 * t3 * t3;
+  beta[3] = (c * (2107.0 * c - 9402.0 * d + 7042.0 * e - 1854.0 * f) +
+             d * (11003.0 * d - 17246.0 * e + 4642.0 * f) + e * (7043.0 * e - 3882.0 * f) +
+             547.0 * f * f) / 240.0;
+  beta[4] = (271779.0 * a * a +
+             a * (-2380800.0 * b + 4086352.0 * c - 3462252.0 * d + 1458762.0 * e -
+                  245620.0 * f) +
+             b * (5653317.0 * b - 20427884.0 * c + 17905032.0 * d - 7727988.0 * e +
+                  1325006.0 * f) +
+             c * (19510972.0 * c - 35817664.0 * d + 15929912.0 * e - 2792660.0 * f) +
+             d * (17195652.0 * d - 15880404.0 * e + 2863984.0 * f) +
+             e * (3824847.0 * e - 1429976.0 * f) + 139633.0 * f * f) / 120960.0;
+}
+
+void orc_central_stencils(const double *v, double *out) {
+  /* v = point values at offsets -3 .. 3 (v[3] at offset 0): out[0..2] =
+   * 6th-order face value, face derivative (face between offsets 0 and 1,
+   * from offsets -2 .. 3) and cell derivative at offset 0; out[3..5] the
+   * same at 4th order */
+  out[0] = interp6(v[1], v[2], v[3], v[4], v[5], v[6]);
+  out[1] = dface6(v[1], v[2], v[3], v[4], v[5], v[6]);
+  out[2] = dcell6(v[0], v[1], v[2], v[4], v[5], v[6]);
+  out[3] = interp4(v[2], v[3], v[4], v[5]);
+  out[4] = dface4(v[2], v[3], v[4], v[5]);
+  out[5] = dcell4(v[1], v[2], v[4], v[5]);
 }
 
 void orc_hllc(const double *qL, const double *qR, double gamma, double *F) {

@@ -44,6 +44,10 @@ enum {
 enum { ORC_VISC_NONE = 0, ORC_VISC_POWER = 1, ORC_VISC_SUTHERLAND = 2 };
 enum { ORC_STRETCH_UNIFORM = 0, ORC_STRETCH_TANH2 = 1, ORC_STRETCH_TANH1 = 2 };
 enum { ORC_SOURCE_NONE = 0, ORC_SOURCE_MASSFLUX = 1 };
+/* Spatial scheme: WENO5-JS reconstruction with 4th-order central dissipative
+ * fluxes, or the channel scheme of Section 3.1: TENO6-A reconstruction with
+ * the interpolation limiter and 6th-order central dissipative fluxes. */
+enum { ORC_SCHEME_WENO5 = 0, ORC_SCHEME_TENO6A = 1 };
 
 typedef struct {
   int ndim;
@@ -63,6 +67,7 @@ typedef struct {
   double p_inf;          /* reference pressure of the Darcy law and the cost */
   int source;            /* ORC_SOURCE_*                                     */
   int cost_face;         /* face of the wall-pressure cost, -1 for none      */
+  int scheme;            /* ORC_SCHEME_*                                     */
 } orc_case;
 
 int orc_nk(const orc_case *c);
@@ -72,6 +77,17 @@ long orc_nbox(const orc_case *c);
 void orc_grid(const orc_case *c, int axis, double *xf, double *dx, double *met_c,
               double *met_f);
 double orc_weno5(double a, double b, double c, double d, double e);
+/* TENO6-A value at the right face of cell c from (a, b, c, d, e, f) =
+ * cells c-2 .. c+3; ct_out (nullable) receives the cut-off C_T it used and
+ * w_out (nullable, 4) the weights of the candidates (S0 = c-1..c+1,
+ * S1 = c..c+2, S2 = c-2..c, S3 = c..c+3). */
+double orc_teno6a(const double *v, double *ct_out, double *w_out);
+/* Its smoothness indicators beta0, beta1, beta2, beta3, beta6 (out[5]). */
+void orc_teno6a_beta(const double *v, double *beta);
+/* Central stencils of the dissipative fluxes on point values v at offsets
+ * -3 .. 3: 6th-order face value, face derivative (face between offsets 0
+ * and 1) and cell derivative (offset 0), then the same at 4th order. */
+void orc_central_stencils(const double *v, double *out);
 void orc_hllc(const double *qL, const double *qR, double gamma, double *F);
 
 void orc_cons_from_prim(const orc_case *c, const double *P, double *U);

@@ -16,6 +16,7 @@ _BC = {"periodic": 0, "wall": 1, "porous": 2, "zerograd": 3, "dirichlet": 4, "di
 _VISC = {"none": 0, "power": 1, "sutherland": 2}
 _STRETCH = {"uniform": 0, "tanh2": 1, "tanh1": 2}
 _SRC = {"none": 0, "massflux": 1}
+_SCHEME = {"weno5": 0, "teno6a": 1}
 
 _dp = C.POINTER(C.c_double)
 
@@ -29,7 +30,7 @@ class OrcCase(C.Structure):
         ("visc_param", C.c_double), ("bc", C.c_int * 6), ("T_wall", C.c_double * 6),
         ("dirichlet", _dp * 6), ("porous_face", C.c_int), ("porous_begin", C.c_int),
         ("porous_end", C.c_int), ("p_inf", C.c_double), ("source", C.c_int),
-        ("cost_face", C.c_int),
+        ("cost_face", C.c_int), ("scheme", C.c_int),
     ]
 
 
@@ -51,6 +52,9 @@ def lib():
             "orc_grid": (None, [P, C.c_int, _dp, _dp, _dp, _dp]),
             "orc_weno5": (C.c_double, [C.c_double] * 5),
             "orc_hllc": (None, [_dp, _dp, C.c_double, _dp]),
+            "orc_teno6a": (C.c_double, [_dp, _dp, _dp]),
+            "orc_teno6a_beta": (None, [_dp, _dp]),
+            "orc_central_stencils": (None, [_dp, _dp]),
             "orc_cons_from_prim": (None, [P, _dp, _dp]),
             "orc_prims_halo": (None, [P, _dp, _dp, _dp, _dp]),
             "orc_rhs": (None, [P, _dp, _dp, _dp]),
@@ -115,6 +119,7 @@ class Oracle:
         s.p_inf = case.p_inf
         s.source = _SRC[case.source]
         s.cost_face = case.cost_face
+        s.scheme = _SCHEME[getattr(case, "scheme", "weno5")]
         self.s = s
         self.L = lib()
         self.nk = self.L.orc_nk(C.byref(s))
@@ -224,6 +229,33 @@ class Oracle:
 
 def weno5(a, b, c, d, e):
     return lib().orc_weno5(a, b, c, d, e)
+
+
+def teno6a(v):
+    """(value, C_T, weights) of the TENO6-A reconstruction at the right face
+    of the third of six cells."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    ct = C.c_double()
+    w = np.zeros(4)
+    y = lib().orc_teno6a(_ptr(v), C.byref(ct), _ptr(w))
+    return y, ct.value, w
+
+
+def teno6a_beta(v):
+    """(beta0, beta1, beta2, beta3, beta6) of TENO6-A on six cells."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    b = np.zeros(5)
+    lib().orc_teno6a_beta(_ptr(v), _ptr(b))
+    return b
+
+
+def central_stencils(v):
+    """(face value, face derivative, cell derivative) at 6th then 4th order
+    from point values at offsets -3 .. 3."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.zeros(6)
+    lib().orc_central_stencils(_ptr(v), _ptr(out))
+    return out
 
 
 def hllc(qL, qR, gamma=1.4):

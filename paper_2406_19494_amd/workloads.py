@@ -68,6 +68,10 @@ class Case:
     p_inf: float = 1.0
     source: str = "none"
     cost_face: int = -1
+    # spatial scheme: "weno5" (WENO5-JS + 4th-order central dissipative
+    # fluxes) or "teno6a" (TENO6-A with the interpolation limiter + 6th-order
+    # central dissipative fluxes, the channel scheme of Section 3.1)
+    scheme: str = "weno5"
     # run parameters
     cfl: float = 0.5
     dt_fixed: float = 0.0
@@ -226,7 +230,8 @@ def tgv(n: int = 64, Re: float = 1600.0, Ma: float = 0.1, Pr: float = 0.71,
 # --------------------------------------------------------------------------
 def channel(nx: int = 192, ny: int = 128, nz: int = 128, Ma_b: float = 0.5,
             Re_b: float = 3000.0, Pr: float = 0.72, omega: float = 0.7,
-            beta: float = 2.0, amp: float = 0.05, seed: int = 2406) -> Tuple[Case, np.ndarray]:
+            beta: float = 2.0, amp: float = 0.05, seed: int = 2406,
+            scheme: str = "weno5") -> Tuple[Case, np.ndarray]:
     """Bulk velocity, bulk density, wall temperature and half-width are 1.
     Ma_b = U_b / c_w gives R = c_w^2 / gamma with c_w = 1/Ma_b; Re_b = 3000
     gives mu_w = 1/Re_b.  u = 1.5 (1 - y^2) plus amp * U_b * (2 r - 1) on all
@@ -239,7 +244,8 @@ def channel(nx: int = 192, ny: int = 128, nz: int = 128, Ma_b: float = 0.5,
                 stretch=("uniform", "tanh2", "uniform"), beta=(0.0, beta, 0.0), gamma=gamma,
                 R=R, Pr=Pr, visc_law="power", mu_ref=1.0 / Re_b, T_ref=1.0, visc_param=omega,
                 bc=("periodic", "periodic", "wall", "wall", "periodic", "periodic"),
-                T_wall=(0.0, 0.0, 1.0, 1.0, 0.0, 0.0), source="massflux", cfl=0.5, nsteps=500)
+                T_wall=(0.0, 0.0, 1.0, 1.0, 0.0, 0.0), source="massflux", cfl=0.5, nsteps=500,
+                scheme=scheme)
     x, y, z = _mesh(case)
     ncell = nx * ny * nz
     P = _prim(nx, ny, nz)
