@@ -132,6 +132,12 @@ dcf_status dcf_workspace_size(const dcf_ctx *ctx, int mode, int nsteps, int seg_
 dcf_status dcf_set_workspace(dcf_ctx *ctx, int mode, int nsteps, int seg_len, void *dev,
                              size_t bytes);
 
+/* dcf_workspace_size for a grid and gas without a context: host arithmetic
+ * only (no device call, no allocation), for schedulers that size requests
+ * before admitting them.  The same validation as dcf_create. */
+dcf_status dcf_workspace_size_for(const dcf_grid *grid, const dcf_gas *gas, int mode,
+                                  int nsteps, int seg_len, size_t *bytes);
+
 /* Boundary condition of one face (Section 3.2).  Periodic faces must be
  * set in pairs.  Walls mirror the velocity (u_g = -u_mirror, no slip) and
  * the pressure; isothermal walls (T_wall > 0) set T_g = 2 T_wall - T_mirror
@@ -156,11 +162,31 @@ dcf_status dcf_set_bc(dcf_ctx *ctx, int face, const dcf_bc *bc);
 dcf_status dcf_set_params(dcf_ctx *ctx, const double *K_dev, int nK);
 int dcf_num_params(const dcf_ctx *ctx);
 
-/* Source term (Eq. (1), sum_i S_i). */
+/* Spatial scheme.  DCF_SCHEME_WENO5 (default): WENO5-JS reconstruction of
+ * the primitives (Section 2.1, "WENO-type") with 4th-order central
+ * dissipative fluxes.  DCF_SCHEME_TENO6A: the channel scheme of Section 3.1,
+ * TENO6-A reconstruction (sixth-order linear weights, adaptive cut-off) with
+ * the interpolation limiter (a face side whose reconstructed density or
+ * pressure is not positive takes its own cell's primitives) and 6th-order
+ * central dissipative fluxes (tangential derivatives three cells either
+ * side).  Forward calls only: dcf_vjp_step, dcf_gradient and the batched
+ * steps return DCF_EUNSUPPORTED for TENO6-A.  DCF_EINVAL for another value. */
+#define DCF_SCHEME_WENO5 0
+#define DCF_SCHEME_TENO6A 1
+dcf_status dcf_set_scheme(dcf_ctx *ctx, int scheme);
+
+/* Source term (Eq. (1), sum_i S_i): DCF_SOURCE_MASSFLUX is the body force
+ * that holds the bulk momentum of a channel constant (the constant-mass-flux
+ * forcing of Section 3.1's channel), with f = -<R_rhou>_V each stage. */
 dcf_status dcf_set_source(dcf_ctx *ctx, int kind);
 
 /* Wall-pressure cost face: j(U) = sum_i (A_i/A)(p_i - p_ref)^2 over the
- * cells next to `face` (-1 disables). */
+ * cells next to `face` (-1 disables), A_i the wall-face area of cell i and A
+ * their sum.  The paper optimises boundary-condition parameters end to end
+ * against a scalar objective of the flow (Section 1, Section 3.2); this
+ * time-averaged wall-pressure-fluctuation cost (average of j over the steps
+ * of a trajectory, dcf_gradient) is the build's reading of that objective
+ * for the porous-wall boundary layer. */
 dcf_status dcf_set_cost(dcf_ctx *ctx, int face, double p_ref);
 
 /* ---- forward ------------------------------------------------------------ */
@@ -171,12 +197,26 @@ dcf_status dcf_init_state(dcf_ctx *ctx, const double *P_dev, double *U_dev, void
 dcf_status dcf_rhs(dcf_ctx *ctx, const double *U_dev, double *R_dev, void *stream);
 
 /* dt_dev[0] = min(dt_max, cfl / max_cells[sum_d (|u_d|+c)/dx_d
- *             + 2 nu_eff sum_d 1/dx_d^2]), nu_eff = max(4/3, gamma/Pr) mu/rho. */
+ *             + 2 nu_eff sum_d 1/dx_d^2]), nu_eff = max(4/3, gamma/Pr) mu/rho.
+ * The paper's explicit TVD Runge-Kutta integration (Section 2.1, text after
+ * Eq. (6)) needs a stable step but states no rule for it: this convective
+ * plus viscous CFL limit is the build's reading.  DCF_EINVAL for cfl <= 0;
+ * dt_max <= 0 means no cap. */
 dcf_status dcf_compute_dt(dcf_ctx *ctx, const double *U_dev, double cfl, double dt_max,
                           double *dt_dev, void *stream);
 
-/* One TVD-RK3 step (Shu-Osher form) in place, with dt read from dt_dev[0]. */
+/* One TVD-RK3 step (Shu-Osher form; Section 2.1, text after Eq. (6)) in
+ * place, with dt read from dt_dev[0]. */
 dcf_status dcf_rk3_step(dcf_ctx *ctx, double *U_dev, const double *dt_dev, void *stream);
+
+/* dcf_rk3_step that also keeps its two inner stage states:
+ * stages_dev[0..M) = U^(1) = U^n + dt R(U^n) and stages_dev[M..2M) = U^(2) =
+ * 3/4 U^n + 1/4 (U^(1) + dt R(U^(1))), M = nv * ncell (dev, caller-owned,
+ * 2 state arrays, may not overlap U).  Bitwise the same U^{n+1} as
+ * dcf_rk3_step; the stage states are what dcf_vjp_step reads instead of
+ * recomputing them. */
+dcf_status dcf_rk3_step_keep(dcf_ctx *ctx, double *U_dev, const double *dt_dev,
+                             double *stages_dev, void *stream);
 
 /* dcf_rk3_step for callers that cannot allocate device memory or be handed
  * a workspace (code under HIP graph capture, tight serving loops, harnesses
@@ -234,29 +274,58 @@ dcf_status dcf_batch_table_bytes(int n, size_t *bytes);
 dcf_status dcf_batch_rk3_step(dcf_ctx *const *ctxs, double *const *U, double *const *dt, int n,
                               double cfl, void *table, size_t table_bytes, void *stream);
 
+/* The two halves of dcf_batch_rk3_step, so that the step launches can be
+ * captured in a HIP graph and replayed while the batch does not change.
+ * dcf_batch_table_fill validates the batch as dcf_batch_rk3_step does and
+ * writes its table into table_host (host memory of dcf_batch_table_bytes(n)
+ * bytes, 16-byte aligned); host work only.  The caller copies it to device
+ * memory (outside any capture).  dcf_batch_rk3_step_table enqueues the step
+ * launches alone: they read the table from table_dev (dev, a copy of
+ * table_host, which must stay unchanged while launches or graph replays that
+ * use it are pending); table_host is read during the call for the launch
+ * sizes.  It enqueues kernels only (no copy, no allocation), so it may be
+ * captured; the contexts, states and steps named in the table must outlive
+ * every replay.  Bitwise the same results as dcf_batch_rk3_step. */
+dcf_status dcf_batch_table_fill(dcf_ctx *const *ctxs, double *const *U, double *const *dt, int n,
+                                void *table_host, size_t table_bytes);
+dcf_status dcf_batch_rk3_step_table(const void *table_dev, const void *table_host, int n,
+                                    double cfl, void *stream);
+
 /* out_dev[8] = (<rho|u|^2/2>_V, <mu|omega|^2>_V, total mass, total x/y/z
- * momentum, total energy, volume). */
+ * momentum, total energy, volume): the kinetic-energy and dissipation
+ * history of a Taylor-Green vortex and the conserved totals of Eq. (1). */
 dcf_status dcf_diagnostics(dcf_ctx *ctx, const double *U_dev, double *out_dev, void *stream);
 
 /* ---- adjoint ------------------------------------------------------------ */
 /* Vector-Jacobian product of one RK3 step U^n -> U^{n+1} with dt_dev[0]
- * held constant: lam_n = (dU^{n+1}/dU^n)^T lam_np1, and, when dJdK_dev is
- * not NULL, dJdK_dev += (dU^{n+1}/dK)^T lam_np1.  lam_n may not alias
- * lam_np1.  Unsupported with the mass-flux source. */
-dcf_status dcf_vjp_step(dcf_ctx *ctx, const double *Un_dev, const double *dt_dev,
-                        const double *lam_np1_dev, double *lam_n_dev, double *dJdK_dev,
-                        void *stream);
+ * held constant (the reverse-mode derivative through the solver that the
+ * paper's end-to-end optimisation rests on, Section 1; the boundary
+ * parameters of Section 3.2 are differentiable inputs): lam_n =
+ * (dU^{n+1}/dU^n)^T lam_np1, and, when dJdK_dev is not NULL, dJdK_dev +=
+ * (dU^{n+1}/dK)^T lam_np1.  stages_dev (nullable dev): the step's stage
+ * states U^(1), U^(2) as dcf_rk3_step_keep writes them; NULL recomputes them
+ * from U^n (two more right-hand sides).  Branches (HLLC wave-speed cases,
+ * min/max) follow the primal.  lam_n may not alias lam_np1.  Workspace mode
+ * >= 1; DCF_EUNSUPPORTED with the mass-flux source. */
+dcf_status dcf_vjp_step(dcf_ctx *ctx, const double *Un_dev, const double *stages_dev,
+                        const double *dt_dev, const double *lam_np1_dev, double *lam_n_dev,
+                        double *dJdK_dev, void *stream);
 
-/* J_dev[0] += w * j(U); when g_dev is not NULL, g_dev += w * dj/dU. */
+/* J_dev[0] += w * j(U) with j the wall-pressure cost of dcf_set_cost; when
+ * g_dev is not NULL, g_dev += w * dj/dU.  DCF_EINVAL without a cost face. */
 dcf_status dcf_cost_term(dcf_ctx *ctx, const double *U_dev, double w, double *J_dev,
                          double *g_dev, void *stream);
 
 /* J = (1/nsteps) sum_{n=1..nsteps} j(U^n) over a fixed-dt trajectory from U0,
- * and its gradient with respect to K and U0 by checkpointing every seg_len
- * steps and recomputing each segment in reverse (workspace mode 2 or 3); the
- * last segment keeps its states from the forward sweep and is not
- * recomputed (seg_len >= nsteps: no recompute at all).  Any output pointer
- * may be NULL except J_dev. */
+ * and its gradient with respect to K and U0 -- the gradient through a whole
+ * simulated trajectory that end-to-end optimisation needs (Section 1) -- by
+ * checkpointing every seg_len steps and recomputing each segment in reverse
+ * (workspace mode 2 or 3, sized for this seg_len and at least nsteps); the last
+ * segment keeps its states from the forward sweep and is not recomputed
+ * (seg_len >= nsteps: no recompute at all).  Any output pointer may be NULL
+ * except J_dev.  DCF_EINVAL without a cost face, for another seg_len or for
+ * more steps than the workspace holds; DCF_EUNSUPPORTED with the mass-flux
+ * source. */
 dcf_status dcf_gradient(dcf_ctx *ctx, const double *U0_dev, int nsteps, const double *dt_dev,
                         int seg_len, double *J_dev, double *dJdK_dev, double *dJdU0_dev,
                         void *stream);

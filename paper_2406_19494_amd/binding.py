@@ -19,6 +19,7 @@ BC = {"periodic": 0, "wall": 1, "porous": 2, "zerograd": 3, "dirichlet": 4, "dis
 VISC = {"none": 0, "power": 1, "sutherland": 2}
 STRETCH = {"uniform": 0, "tanh2": 1, "tanh1": 2}
 SOURCE = {"none": 0, "massflux": 1}
+SCHEME = {"weno5": 0, "teno6a": 1}
 
 
 class DcfError(RuntimeError):
@@ -50,9 +51,12 @@ _SIGS = {
     "dcf_state_info": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_long), C.POINTER(C.c_size_t)],
     "dcf_workspace_size": [_vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_size_t)],
     "dcf_set_workspace": [_vp, C.c_int, C.c_int, C.c_int, _vp, C.c_size_t],
+    "dcf_workspace_size_for": [C.POINTER(dcf_grid), C.POINTER(dcf_gas), C.c_int, C.c_int,
+                               C.c_int, C.POINTER(C.c_size_t)],
     "dcf_set_bc": [_vp, C.c_int, C.POINTER(dcf_bc)],
     "dcf_set_params": [_vp, _vp, C.c_int],
     "dcf_set_source": [_vp, C.c_int],
+    "dcf_set_scheme": [_vp, C.c_int],
     "dcf_set_cost": [_vp, C.c_int, C.c_double],
     "dcf_init_state": [_vp, _vp, _vp, _vp],
     "dcf_rhs": [_vp, _vp, _vp, _vp],
@@ -60,7 +64,8 @@ _SIGS = {
     "dcf_rk3_step": [_vp, _vp, _vp, _vp],
     "dcf_rk3_step_noalloc": [_vp, _vp, _vp, _vp, _vp],
     "dcf_diagnostics": [_vp, _vp, _vp, _vp],
-    "dcf_vjp_step": [_vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "dcf_vjp_step": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "dcf_rk3_step_keep": [_vp, _vp, _vp, _vp, _vp],
     "dcf_cost_term": [_vp, _vp, C.c_double, _vp, _vp, _vp],
     "dcf_gradient": [_vp, _vp, C.c_int, _vp, C.c_int, _vp, _vp, _vp, _vp],
     "dcf_gradient_begin": [_vp, _vp, C.c_int, _vp, C.c_int, _vp, _vp, _vp],
@@ -75,6 +80,9 @@ _SIGS = {
     "dcf_rk3_steps_cfl": [_vp, _vp, _vp, C.c_int, C.c_double, C.c_double, _vp],
     "dcf_batch_rk3_step": [C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.c_int, C.c_double,
                            _vp, C.c_size_t, _vp],
+    "dcf_batch_table_fill": [C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.c_int, _vp,
+                             C.c_size_t],
+    "dcf_batch_rk3_step_table": [_vp, _vp, C.c_int, C.c_double, _vp],
 }
 
 _lib = None

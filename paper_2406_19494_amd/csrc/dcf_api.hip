@@ -101,13 +101,10 @@ struct dcf_ctx {
   } gr;
 };
 
-extern "C" {
-
-const char *dcf_last_error(void) { return g_last_error.c_str(); }
-
-dcf_status dcf_create(const dcf_grid *grid, const dcf_gas *gas, dcf_ctx **out) {
-  if (!grid || !gas || !out) return fail(DCF_EINVAL, "dcf_create: null argument");
-  *out = nullptr;
+// Validates a grid and a gas and lays out the device-side description of a
+// solve on them (sizes, strides, gas constants, boundaries all periodic; no
+// device memory, no metric arrays yet).
+static dcf_status describe(const dcf_grid *grid, const dcf_gas *gas, Dev &g) {
   if (grid->ndim < 1 || grid->ndim > 3) return fail(DCF_EINVAL, "ndim must be 1, 2 or 3");
   for (int d = 0; d < 3; ++d) {
     if (d < grid->ndim) {
@@ -133,27 +130,6 @@ dcf_status dcf_create(const dcf_grid *grid, const dcf_gas *gas, dcf_ctx **out) {
   if (ncell > (1L << 31) - 1 || nboxc > (1L << 32) - 1)
     return fail(DCF_EINVAL, "grid too large");
 
-  int device = 0;
-  if (hipGetDevice(&device) != hipSuccess || device < 0 || device >= kMaxDevices)
-    return fail(DCF_EDEVICE, "no usable current device");
-  {
-    // the static scratch of dcf_rk3_step_noalloc: its address on this device,
-    // taken once per device with the device current
-    std::lock_guard<std::mutex> lock(g_scratch_mu);
-    if (!g_scratch_addr[device]) {
-      void *ptr = nullptr;
-      const hipError_t es = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
-      if (es != hipSuccess || !ptr)
-        return fail(DCF_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(es));
-      g_scratch_addr[device] = ptr;
-    }
-  }
-  dcf_ctx *c = new (std::nothrow) dcf_ctx();
-  if (!c) return fail(DCF_ENOMEM, "host allocation failed");
-  c->device = device;
-  c->grid = *grid;
-  c->gas = *gas;
-  Dev &g = c->g;
   memset(&g, 0, sizeof g);
   g.ndim = grid->ndim;
   g.nv = grid->ndim + 2;
@@ -195,6 +171,41 @@ dcf_status dcf_create(const dcf_grid *grid, const dcf_gas *gas, dcf_ctx **out) {
   g.pface = -1;
   g.source = SRC_NONE;
 
+  return DCF_OK;
+}
+
+extern "C" {
+
+const char *dcf_last_error(void) { return g_last_error.c_str(); }
+
+dcf_status dcf_create(const dcf_grid *grid, const dcf_gas *gas, dcf_ctx **out) {
+  if (!grid || !gas || !out) return fail(DCF_EINVAL, "dcf_create: null argument");
+  *out = nullptr;
+  Dev g0;
+  dcf_status st0 = describe(grid, gas, g0);
+  if (st0) return st0;
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess || device < 0 || device >= kMaxDevices)
+    return fail(DCF_EDEVICE, "no usable current device");
+  {
+    // the static scratch of dcf_rk3_step_noalloc: its address on this device,
+    // taken once per device with the device current
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+      void *ptr = nullptr;
+      const hipError_t es = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (es != hipSuccess || !ptr)
+        return fail(DCF_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(es));
+      g_scratch_addr[device] = ptr;
+    }
+  }
+  dcf_ctx *c = new (std::nothrow) dcf_ctx();
+  if (!c) return fail(DCF_ENOMEM, "host allocation failed");
+  c->device = device;
+  c->grid = *grid;
+  c->gas = *gas;
+  Dev &g = c->g;
+  g = g0;
   size_t total = 0;
   for (int d = 0; d < 3; ++d) total += 5 * (size_t)(g.n[d] + 1);
   hipError_t e = hipMalloc((void **)&c->metric_mem, total * sizeof(double));
@@ -306,6 +317,19 @@ dcf_status dcf_workspace_size(const dcf_ctx *c, int mode, int nsteps, int seg_le
   return DCF_OK;
 }
 
+dcf_status dcf_workspace_size_for(const dcf_grid *grid, const dcf_gas *gas, int mode,
+                                  int nsteps, int seg_len, size_t *bytes) {
+  if (!grid || !gas || !bytes) return fail(DCF_EINVAL, "null argument");
+  if (mode < 0 || mode > 3) return fail(DCF_EINVAL, "mode must be 0, 1, 2 or 3");
+  if (mode >= 2 && (nsteps < 1 || seg_len < 1))
+    return fail(DCF_EINVAL, "gradient workspace needs nsteps >= 1 and seg_len >= 1");
+  dcf_ctx tmp = dcf_ctx();  // host-side description only
+  dcf_status s = describe(grid, gas, tmp.g);
+  if (s) return s;
+  *bytes = carve(&tmp, nullptr, mode, nsteps, seg_len);
+  return DCF_OK;
+}
+
 dcf_status dcf_set_workspace(dcf_ctx *c, int mode, int nsteps, int seg_len, void *dev,
                              size_t bytes) {
   if (!c || !dev) return fail(DCF_EINVAL, "null argument");
@@ -382,6 +406,14 @@ dcf_status dcf_set_params(dcf_ctx *c, const double *K, int nK) {
   if (nK != c->nK) return fail(DCF_EINVAL, "expected %d porous coefficients, got %d", c->nK, nK);
   if (nK > 0 && !K) return fail(DCF_EINVAL, "null K");
   c->g.K = K;
+  return DCF_OK;
+}
+
+dcf_status dcf_set_scheme(dcf_ctx *c, int scheme) {
+  if (!c) return fail(DCF_EINVAL, "null context");
+  if (scheme != DCF_SCHEME_WENO5 && scheme != DCF_SCHEME_TENO6A)
+    return fail(DCF_EINVAL, "unknown scheme %d", scheme);
+  c->g.scheme = scheme == DCF_SCHEME_TENO6A ? SCHEME_TENO6A : SCHEME_WENO5;
   return DCF_OK;
 }
 
@@ -576,6 +608,17 @@ dcf_status dcf_rk3_step(dcf_ctx *c, double *U, const double *dt, void *stream) {
   return rk3_stages(c, U, dt, (hipStream_t)stream);
 }
 
+dcf_status dcf_rk3_step_keep(dcf_ctx *c, double *U, const double *dt, double *stages,
+                             void *stream) {
+  dcf_status s = ready(c, 0);
+  if (s) return s;
+  if (!U || !dt || !stages) return fail(DCF_EINVAL, "null array");
+  const long M = (long)c->g.nv * c->g.ncell;
+  if (stages + 2 * M > U && U + M > stages)
+    return fail(DCF_EINVAL, "the stage states may not overlap U");
+  return rk3_stages(c, U, dt, (hipStream_t)stream, stages, stages + M);
+}
+
 dcf_status dcf_rk3_step_noalloc(dcf_ctx *c, double *U, const double *dt, unsigned *flags,
                                 void *stream) {
   dcf_status s = ready(c, -1);
@@ -609,15 +652,10 @@ dcf_status dcf_batch_table_bytes(int n, size_t *bytes) {
   return DCF_OK;
 }
 
-dcf_status dcf_batch_rk3_step(dcf_ctx *const *ctxs, double *const *U, double *const *dt, int n,
-                              double cfl, void *table, size_t table_bytes, void *stream) {
-  if (n < 1 || !ctxs || !U || !dt || !table) return fail(DCF_EINVAL, "null argument or n < 1");
-  if (table_bytes < (size_t)n * sizeof(BatchEntry))
-    return fail(DCF_EINVAL, "table needs %zu bytes, got %zu", (size_t)n * sizeof(BatchEntry),
-                table_bytes);
-  if (((uintptr_t)table) & 15) return fail(DCF_EINVAL, "table must be 16-byte aligned");
-  static thread_local std::vector<BatchEntry> h;
-  h.resize(n);
+// Validates a batch and writes its table entries into h (host memory of at
+// least n entries).
+static dcf_status batch_fill(dcf_ctx *const *ctxs, double *const *U, double *const *dt, int n,
+                             BatchEntry *h) {
   for (int i = 0; i < n; ++i) {
     dcf_ctx *c = ctxs[i];
     dcf_status s = ready(c, 0);
@@ -630,7 +668,9 @@ dcf_status dcf_batch_rk3_step(dcf_ctx *const *ctxs, double *const *U, double *co
       return fail(DCF_EUNSUPPORTED, "solve %d: a batch needs one dimension and viscous flag", i);
     if (g.source != SRC_NONE)
       return fail(DCF_EUNSUPPORTED, "solve %d: source terms are not batched", i);
-    BatchEntry &e = h[i];
+    if (g.scheme != SCHEME_WENO5)
+      return fail(DCF_EUNSUPPORTED, "solve %d: batched steps are of the WENO5-JS scheme", i);
+    BatchEntry e;
     e.g = g;
     e.gb = g;
     if (g.ndim >= 2)
@@ -641,11 +681,51 @@ dcf_status dcf_batch_rk3_step(dcf_ctx *const *ctxs, double *const *U, double *co
     e.dt = dt[i];
     e.part = c->part;
     batch_entry_sizes(e);
+    memcpy(&h[i], &e, sizeof e);
   }
+  return DCF_OK;
+}
+
+dcf_status dcf_batch_rk3_step(dcf_ctx *const *ctxs, double *const *U, double *const *dt, int n,
+                              double cfl, void *table, size_t table_bytes, void *stream) {
+  if (n < 1 || !ctxs || !U || !dt || !table) return fail(DCF_EINVAL, "null argument or n < 1");
+  if (table_bytes < (size_t)n * sizeof(BatchEntry))
+    return fail(DCF_EINVAL, "table needs %zu bytes, got %zu", (size_t)n * sizeof(BatchEntry),
+                table_bytes);
+  if (((uintptr_t)table) & 15) return fail(DCF_EINVAL, "table must be 16-byte aligned");
+  static thread_local std::vector<BatchEntry> h;
+  h.resize(n);
+  dcf_status s = batch_fill(ctxs, U, dt, n, h.data());
+  if (s) return s;
   hipStream_t st = (hipStream_t)stream;
   DCF_HIP(hipMemcpyAsync(table, h.data(), (size_t)n * sizeof(BatchEntry), hipMemcpyHostToDevice,
                          st));
   DCF_HIP(launch_batch_step((const BatchEntry *)table, h.data(), n, cfl, st));
+  return DCF_OK;
+}
+
+dcf_status dcf_batch_table_fill(dcf_ctx *const *ctxs, double *const *U, double *const *dt, int n,
+                                void *table_host, size_t table_bytes) {
+  if (n < 1 || !ctxs || !U || !dt || !table_host)
+    return fail(DCF_EINVAL, "null argument or n < 1");
+  if (table_bytes < (size_t)n * sizeof(BatchEntry))
+    return fail(DCF_EINVAL, "table needs %zu bytes, got %zu", (size_t)n * sizeof(BatchEntry),
+                table_bytes);
+  if (((uintptr_t)table_host) & 15) return fail(DCF_EINVAL, "table must be 16-byte aligned");
+  return batch_fill(ctxs, U, dt, n, (BatchEntry *)table_host);
+}
+
+dcf_status dcf_batch_rk3_step_table(const void *table_dev, const void *table_host, int n,
+                                    double cfl, void *stream) {
+  if (n < 1 || !table_dev || !table_host) return fail(DCF_EINVAL, "null argument or n < 1");
+  if ((((uintptr_t)table_dev) | ((uintptr_t)table_host)) & 15)
+    return fail(DCF_EINVAL, "tables must be 16-byte aligned");
+  const BatchEntry *h = (const BatchEntry *)table_host;
+  for (int i = 0; i < n; ++i)
+    if (h[i].g.ndim != h[0].g.ndim || (h[i].g.visc != VISC_NONE) != (h[0].g.visc != VISC_NONE) ||
+        h[i].g.ndim < 1 || h[i].g.ndim > 3)
+      return fail(DCF_EINVAL, "table entry %d is not a filled entry of this batch", i);
+  DCF_HIP(launch_batch_step((const BatchEntry *)table_dev, h, n, cfl, (hipStream_t)stream));
   return DCF_OK;
 }
 
@@ -724,15 +804,23 @@ dcf_status dcf_flags(dcf_ctx *c, unsigned *flags_host, void *stream) {
   return DCF_OK;
 }
 
-dcf_status dcf_vjp_step(dcf_ctx *c, const double *Un, const double *dt, const double *lam1,
-                        double *lam0, double *dJdK, void *stream) {
+dcf_status dcf_vjp_step(dcf_ctx *c, const double *Un, const double *stages, const double *dt,
+                        const double *lam1, double *lam0, double *dJdK, void *stream) {
   dcf_status s = ready(c, 1);
   if (s) return s;
   if (!Un || !dt || !lam1 || !lam0) return fail(DCF_EINVAL, "null array");
   if (lam0 == lam1) return fail(DCF_EINVAL, "lam_n may not alias lam_np1");
   if (c->g.source != SRC_NONE)
     return fail(DCF_EUNSUPPORTED, "adjoint of the mass-flux source is not implemented");
-  return vjp_step(c->g, c->adj, Un, c->U1, c->U2, dt, lam1, lam0, dJdK, (hipStream_t)stream)
+  if (c->g.scheme != SCHEME_WENO5)
+    return fail(DCF_EUNSUPPORTED, "the adjoint is of the WENO5-JS scheme only");
+  const long M = (long)c->g.nv * c->g.ncell;
+  // with the caller's stage states the VJP only reads them (the stage
+  // kernels take non-const pointers for the recompute case)
+  double *S1 = stages ? const_cast<double *>(stages) : c->U1;
+  double *S2 = stages ? const_cast<double *>(stages) + M : c->U2;
+  return vjp_step(c->g, c->adj, Un, S1, S2, dt, lam1, lam0, dJdK, (hipStream_t)stream,
+                  stages == nullptr)
              ? fail(DCF_EDEVICE, "vjp launch failed")
              : DCF_OK;
 }
@@ -741,13 +829,15 @@ dcf_status dcf_gradient_begin(dcf_ctx *c, const double *U0, int nsteps, const do
                               int seg_len, double *J, double *dJdK, void *stream) {
   dcf_status s = ready(c, 2);
   if (s) return s;
-  if (c->ws_nsteps != nsteps || c->ws_seg != seg_len)
-    return fail(DCF_EINVAL, "workspace was sized for nsteps=%d seg_len=%d, not %d/%d",
+  if (nsteps < 1 || nsteps > c->ws_nsteps || c->ws_seg != seg_len)
+    return fail(DCF_EINVAL, "workspace was sized for up to nsteps=%d with seg_len=%d, not %d/%d",
                 c->ws_nsteps, c->ws_seg, nsteps, seg_len);
   if (!U0 || !dt || !J) return fail(DCF_EINVAL, "null array");
   if (c->cost_face < 0) return fail(DCF_EINVAL, "no cost face set (dcf_set_cost)");
   if (c->g.source != SRC_NONE)
     return fail(DCF_EUNSUPPORTED, "adjoint of the mass-flux source is not implemented");
+  if (c->g.scheme != SCHEME_WENO5)
+    return fail(DCF_EUNSUPPORTED, "the adjoint is of the WENO5-JS scheme only");
   hipStream_t st = (hipStream_t)stream;
   const long M = (long)c->g.nv * c->g.ncell;
   auto &gr = c->gr;

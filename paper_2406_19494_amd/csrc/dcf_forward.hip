@@ -325,23 +325,30 @@ __global__ void __launch_bounds__(256) k_prim_ghost(Dev g) {
 // G[3 t + phi] are box arrays.
 // ---------------------------------------------------------------------------
 // Cells that need d u_phi / d x_t: position along t interior, the other
-// active positions within two layers.  One thread per (cell, t), x-fastest.
+// active positions within the layers the face stencils reach (two for the
+// 4th-order dissipative fluxes, three for the 6th-order ones).  One thread
+// per (cell, t), x-fastest.
+__host__ __device__ __forceinline__ int grad_halo(const Dev &g) {
+  return g.scheme == SCHEME_TENO6A ? 3 : 2;
+}
 __host__ __device__ __forceinline__ unsigned grad_cells(const Dev &g, int t) {
   unsigned n = 1;
-  for (int e = 0; e < g.ndim; ++e) n *= e == t ? g.n[e] : g.n[e] + 4;
+  const int w = 2 * grad_halo(g);
+  for (int e = 0; e < g.ndim; ++e) n *= e == t ? g.n[e] : g.n[e] + w;
   return n;
 }
 
-template <int NDIM>
+template <int NDIM, int SCH = SCHEME_WENO5>
 __device__ __forceinline__ void grad_body(const Dev &g, int t, unsigned bid, unsigned nblk) {
+  constexpr int HW = SCH == SCHEME_TENO6A ? 3 : 2;  // layers of the other axes
   const unsigned bl = xcd_remap(bid, nblk) * blockDim.x + threadIdx.x;
   if (bl >= grad_cells(g, t)) return;
   unsigned E[3];
   int o[3];
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
-    E[e] = e >= NDIM ? 1u : (e == t ? (unsigned)g.n[e] : (unsigned)g.n[e] + 4);
-    o[e] = (e >= NDIM || e == t) ? 0 : -2;
+    E[e] = e >= NDIM ? 1u : (e == t ? (unsigned)g.n[e] : (unsigned)g.n[e] + 2 * HW);
+    o[e] = (e >= NDIM || e == t) ? 0 : -HW;
   }
   int p[3];
   const unsigned r = bl / E[0];
@@ -350,6 +357,25 @@ __device__ __forceinline__ void grad_body(const Dev &g, int t, unsigned bid, uns
   p[2] = (int)(r / E[1]) + o[2];
   const long b = bidx(g, p[0], p[1], p[2]);
   const long st = g.sb[t];
+  const double mct = g.mc[t][p[t]];
+  if (SCH == SCHEME_TENO6A) {
+    double v[NDIM][6];
+#pragma unroll
+    for (int phi = 0; phi < NDIM; ++phi) {
+      const double *A = g.Q[QU + phi];
+      v[phi][0] = A[b - 3 * st];
+      v[phi][1] = A[b - 2 * st];
+      v[phi][2] = A[b - st];
+      v[phi][3] = A[b + st];
+      v[phi][4] = A[b + 2 * st];
+      v[phi][5] = A[b + 3 * st];
+    }
+#pragma unroll
+    for (int phi = 0; phi < NDIM; ++phi)
+      g.G[3 * t + phi][b] =
+          dcell6(v[phi][0], v[phi][1], v[phi][2], v[phi][3], v[phi][4], v[phi][5]) * mct;
+    return;
+  }
   double v[NDIM][4];
 #pragma unroll
   for (int phi = 0; phi < NDIM; ++phi) {
@@ -359,15 +385,14 @@ __device__ __forceinline__ void grad_body(const Dev &g, int t, unsigned bid, uns
     v[phi][2] = A[b + st];
     v[phi][3] = A[b + 2 * st];
   }
-  const double mct = g.mc[t][p[t]];
 #pragma unroll
   for (int phi = 0; phi < NDIM; ++phi)
     g.G[3 * t + phi][b] = dcell4(v[phi][0], v[phi][1], v[phi][2], v[phi][3]) * mct;
 }
 
-template <int NDIM>
+template <int NDIM, int SCH = SCHEME_WENO5>
 __global__ void __launch_bounds__(256) k_grad(Dev g) {
-  grad_body<NDIM>(g, blockIdx.y, blockIdx.x, gridDim.x);
+  grad_body<NDIM, SCH>(g, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 // As grad_body on a box whose every face is periodic, with each neighbour
@@ -377,17 +402,18 @@ __global__ void __launch_bounds__(256) k_grad(Dev g) {
 __device__ __forceinline__ int wrap_periodic(int x, int n) {
   return x < 0 ? x + n : (x >= n ? x - n : x);
 }
-template <int NDIM>
+template <int NDIM, int SCH = SCHEME_WENO5>
 __device__ __forceinline__ void grad_body_periodic(const Dev &g, int t, unsigned bid,
                                                    unsigned nblk) {
+  constexpr int HW = SCH == SCHEME_TENO6A ? 3 : 2;
   const unsigned bl = xcd_remap(bid, nblk) * blockDim.x + threadIdx.x;
   if (bl >= grad_cells(g, t)) return;
   unsigned E[3];
   int o[3];
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
-    E[e] = e >= NDIM ? 1u : (e == t ? (unsigned)g.n[e] : (unsigned)g.n[e] + 4);
-    o[e] = (e >= NDIM || e == t) ? 0 : -2;
+    E[e] = e >= NDIM ? 1u : (e == t ? (unsigned)g.n[e] : (unsigned)g.n[e] + 2 * HW);
+    o[e] = (e >= NDIM || e == t) ? 0 : -HW;
   }
   int p[3];
   const unsigned r = bl / E[0];
@@ -397,12 +423,12 @@ __device__ __forceinline__ void grad_body_periodic(const Dev &g, int t, unsigned
   int q[3];
 #pragma unroll
   for (int e = 0; e < 3; ++e) q[e] = e < NDIM ? wrap_periodic(p[e], g.n[e]) : p[e];
-  const int off[4] = {-2, -1, 1, 2};
-  double v[NDIM][4];
+  constexpr int NO = 2 * HW;  // neighbours -HW .. -1, 1 .. HW
+  double v[NDIM][NO];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < NO; ++k) {
     int s[3] = {q[0], q[1], q[2]};
-    s[t] = wrap_periodic(p[t] + off[k], g.n[t]);
+    s[t] = wrap_periodic(p[t] + (k < HW ? k - HW : k - HW + 1), g.n[t]);
     const long sb = bidx(g, s[0], s[1], s[2]);
 #pragma unroll
     for (int phi = 0; phi < NDIM; ++phi) v[phi][k] = g.Q[QU + phi][sb];
@@ -410,8 +436,14 @@ __device__ __forceinline__ void grad_body_periodic(const Dev &g, int t, unsigned
   const long b = bidx(g, p[0], p[1], p[2]);
   const double mct = g.mc[t][p[t]];
 #pragma unroll
-  for (int phi = 0; phi < NDIM; ++phi)
-    g.G[3 * t + phi][b] = dcell4(v[phi][0], v[phi][1], v[phi][2], v[phi][3]) * mct;
+  for (int phi = 0; phi < NDIM; ++phi) {
+    double dv;
+    if constexpr (HW == 3)
+      dv = dcell6(v[phi][0], v[phi][1], v[phi][2], v[phi][3], v[phi][4], v[phi][5]);
+    else
+      dv = dcell4(v[phi][0], v[phi][1], v[phi][2], v[phi][3]);
+    g.G[3 * t + phi][b] = dv * mct;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -423,7 +455,7 @@ __device__ __forceinline__ void grad_body_periodic(const Dev &g, int t, unsigned
 // + 0: d u_t / d t, k = 2 r + 1: d u_D / d t, r over the active tangential
 // axes).
 // ---------------------------------------------------------------------------
-template <int NDIM, int D, bool VISC, class PA, class GA>
+template <int NDIM, int D, bool VISC, int SCH, class PA, class GA>
 __device__ __forceinline__ void face_flux(const Dev &g, const PA &P, const GA &Gv, int f,
                                           double *G) {
   constexpr int T1 = tan1(D), T2 = tan2(D);
@@ -437,7 +469,22 @@ __device__ __forceinline__ void face_flux(const Dev &g, const PA &P, const GA &G
     }
     double v0 = P(qi[m], -3), v1 = P(qi[m], -2), v2 = P(qi[m], -1);
     double v3 = P(qi[m], 0), v4 = P(qi[m], 1), v5 = P(qi[m], 2);
-    weno5_pair(v0, v1, v2, v3, v4, v5, qL[m], qR[m]);
+    if (SCH == SCHEME_TENO6A)
+      teno6a_pair(v0, v1, v2, v3, v4, v5, qL[m], qR[m]);
+    else
+      weno5_pair(v0, v1, v2, v3, v4, v5, qL[m], qR[m]);
+  }
+  if (SCH == SCHEME_TENO6A) {
+    // interpolation limiter: a side whose reconstructed density or pressure
+    // is not positive takes its own cell's primitives (first order)
+    if (!(qL[0] > 0.0 && qL[4] > 0.0))
+#pragma unroll
+      for (int m = 0; m < 5; ++m)
+        qL[m] = ((m == 2 && T1 >= NDIM) || (m == 3 && T2 >= NDIM)) ? 0.0 : P(qi[m], -1);
+    if (!(qR[0] > 0.0 && qR[4] > 0.0))
+#pragma unroll
+      for (int m = 0; m < 5; ++m)
+        qR[m] = ((m == 2 && T1 >= NDIM) || (m == 3 && T2 >= NDIM)) ? 0.0 : P(qi[m], 0);
   }
   double Fc[5];
   hllc(qL, qR, g.gamma, g.gm1i, Fc);
@@ -446,7 +493,54 @@ __device__ __forceinline__ void face_flux(const Dev &g, const PA &P, const GA &G
   G[1 + T1] = Fc[2];
   G[1 + T2] = Fc[3];
   G[4] = Fc[4];
-  if (VISC) {
+  if (VISC && SCH == SCHEME_TENO6A) {
+    // Dissipative flux (Eqs. (4)-(5), Fourier's law) from 6th-order central
+    // interpolation / differences over the cells at offsets -3 .. 2.
+    double vel[3][6], Tc[6], muc[6];
+#pragma unroll
+    for (int o = 0; o < 6; ++o) {
+      vel[0][o] = P(QU, o - 3);
+      vel[1][o] = NDIM >= 2 ? P(QV, o - 3) : 0.0;
+      vel[2][o] = NDIM >= 3 ? P(QW, o - 3) : 0.0;
+      Tc[o] = P(QT, o - 3);
+      muc[o] = P(QMU, o - 3);
+    }
+    const double mfD = g.mf[D][f];
+    auto i6 = [](const double *x) { return interp6(x[0], x[1], x[2], x[3], x[4], x[5]); };
+    auto d6 = [](const double *x) { return dface6(x[0], x[1], x[2], x[3], x[4], x[5]); };
+    double muf = i6(muc);
+    double uf[3], dn[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      uf[c] = i6(vel[c]);
+      dn[c] = d6(vel[c]) * mfD;
+    }
+    double dT = d6(Tc) * mfD;
+    double divt = 0.0, dtn[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int tt = r == 0 ? T1 : T2;
+      if (tt >= NDIM) continue;
+      double gt[6], gn[6];
+#pragma unroll
+      for (int o = 0; o < 6; ++o) {
+        gt[o] = Gv(2 * r, o - 3);
+        gn[o] = Gv(2 * r + 1, o - 3);
+      }
+      divt += i6(gt);
+      dtn[tt] = i6(gn);
+    }
+    double tau[3] = {0.0, 0.0, 0.0};
+    tau[D] = muf * ((4.0 / 3.0) * dn[D] - (2.0 / 3.0) * divt);
+    if (T1 < NDIM) tau[T1] = muf * (dtn[T1] + dn[T1]);
+    if (T2 < NDIM) tau[T2] = muf * (dtn[T2] + dn[T2]);
+    double lam = muf * g.cpPr;
+    double en = uf[0] * tau[0] + uf[1] * tau[1] + uf[2] * tau[2] + lam * dT;
+    G[1] -= tau[0];
+    G[2] -= tau[1];
+    G[3] -= tau[2];
+    G[4] -= en;
+  } else if (VISC) {
     // Dissipative flux (Eqs. (4)-(5), Fourier's law) from 4th-order central
     // interpolation / differences over the cells at offsets -2 .. 1.
     double vel[3][4], Tc[4], muc[4];
@@ -518,7 +612,7 @@ __device__ __forceinline__ int slot_of(int q) { return q; }  // QR..QMU map 1:1
 // 3 + 2 cells) are staged in LDS once, then every thread computes one face
 // from LDS.  Coalesced loads, one global read per staged value.
 // ---------------------------------------------------------------------------
-template <int NDIM, bool VISC>
+template <int NDIM, bool VISC, int SCH = SCHEME_WENO5>
 __device__ __forceinline__ void flux_x_body(const Dev &g, int nwmax, unsigned bid, double *lds) {
   using S = Slots<NDIM, VISC>;
   const int nf = g.n[0] + 1;
@@ -558,7 +652,7 @@ __device__ __forceinline__ void flux_x_body(const Dev &g, int nwmax, unsigned bi
   auto P = [&](int q, int o) { return lds[slot_of(q) * nwmax + w0 + o]; };
   auto Gv = [&](int kk, int o) { return lds[(S::NP + kk) * nwmax + w0 + o]; };
   double G[5];
-  face_flux<NDIM, 0, VISC>(g, P, Gv, f, G);
+  face_flux<NDIM, 0, VISC, SCH>(g, P, Gv, f, G);
   if (!(fabs(G[0]) + fabs(G[4]) < 1.0e300)) atomicOr(g.flags, 1u);  // non-finite flux
   double *F = g.F[0];
   const long fc = g.fcount[0];
@@ -566,10 +660,10 @@ __device__ __forceinline__ void flux_x_body(const Dev &g, int nwmax, unsigned bi
   for (int m = 0; m < 5; ++m) F[m * fc + t] = G[m];
 }
 
-template <int NDIM, bool VISC>
+template <int NDIM, bool VISC, int SCH = SCHEME_WENO5>
 __global__ void __launch_bounds__(256) k_flux_x(Dev g, int nwmax) {
   extern __shared__ double lds[];
-  flux_x_body<NDIM, VISC>(g, nwmax, blockIdx.x, lds);
+  flux_x_body<NDIM, VISC, SCH>(g, nwmax, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -585,7 +679,7 @@ template <int NDIM, bool VISC> struct YzTile {
 // Stages the tile's stencil cells (rows f0 - 3 .. f0 + 17 along D, x from
 // i0, remaining axis at oc) and computes the flux of face f0 + ty at x
 // i0 + tx into G; returns false for a thread outside the grid.
-template <int NDIM, int D, bool VISC>
+template <int NDIM, int D, bool VISC, int SCH = SCHEME_WENO5>
 __device__ __forceinline__ bool yz_tile_face(const Dev &g, YzTile<NDIM, VISC> &T, int i0, int f0,
                                              int oc, double *G) {
   using Tl = YzTile<NDIM, VISC>;
@@ -614,12 +708,12 @@ __device__ __forceinline__ bool yz_tile_face(const Dev &g, YzTile<NDIM, VISC> &T
   if (i >= g.n[0] || f > nD) return false;
   auto P = [&](int q, int o) { return T.lds[slot_of(q)][ty + 3 + o][tx]; };
   auto Gv = [&](int kk, int o) { return T.lds[S::NP + kk][ty + 3 + o][tx]; };
-  face_flux<NDIM, D, VISC>(g, P, Gv, f, G);
+  face_flux<NDIM, D, VISC, SCH>(g, P, Gv, f, G);
   if (!(fabs(G[0]) + fabs(G[4]) < 1.0e300)) atomicOr(g.flags, 1u);  // non-finite flux
   return true;
 }
 
-template <int NDIM, int D, bool VISC>
+template <int NDIM, int D, bool VISC, int SCH = SCHEME_WENO5>
 __device__ __forceinline__ void flux_yz_tile(const Dev &g, YzTile<NDIM, VISC> &T, unsigned lin,
                                              unsigned ntot, unsigned nbx, unsigned nby) {
   // tiles along D are consecutive in the remapped order (they share 5 rows)
@@ -628,7 +722,7 @@ __device__ __forceinline__ void flux_yz_tile(const Dev &g, YzTile<NDIM, VISC> &T
   const int i0 = (int)(rest % nbx) * YzTile<NDIM, VISC>::TX, oc = (int)(rest / nbx);
   const int f0 = (int)by * YzTile<NDIM, VISC>::TD;
   double G[5];
-  if (!yz_tile_face<NDIM, D, VISC>(g, T, i0, f0, oc, G)) return;
+  if (!yz_tile_face<NDIM, D, VISC, SCH>(g, T, i0, f0, oc, G)) return;
   int p[3];
   p[0] = i0 + (int)(threadIdx.x % 16);
   p[D] = f0 + (int)(threadIdx.x / 16);
@@ -640,37 +734,37 @@ __device__ __forceinline__ void flux_yz_tile(const Dev &g, YzTile<NDIM, VISC> &T
   for (int m = 0; m < 5; ++m) F[m * fc + t] = G[m];
 }
 
-template <int NDIM, int D, bool VISC>
+template <int NDIM, int D, bool VISC, int SCH = SCHEME_WENO5>
 __device__ __forceinline__ void flux_yz_body(const Dev &g, unsigned lin, unsigned ntot,
                                              unsigned nbx, unsigned nby) {
   __shared__ YzTile<NDIM, VISC> T;
-  flux_yz_tile<NDIM, D, VISC>(g, T, lin, ntot, nbx, nby);
+  flux_yz_tile<NDIM, D, VISC, SCH>(g, T, lin, ntot, nbx, nby);
 }
 
 // x and y faces of a 3D grid in one launch (the two are independent): the
 // first ny_tiles workgroups take y tiles, the rest x chunks; both kinds
 // share one dynamic LDS buffer.
-template <bool VISC>
+template <bool VISC, int SCH = SCHEME_WENO5>
 __global__ void __launch_bounds__(256) k_flux_xy(Dev g, int nwmax, unsigned ny_tiles,
                                                  unsigned nbx, unsigned nby, int remap_x) {
   extern __shared__ double lds[];
   if (blockIdx.x < ny_tiles)
-    flux_yz_tile<3, 1, VISC>(g, *reinterpret_cast<YzTile<3, VISC> *>(lds), blockIdx.x, ny_tiles,
-                             nbx, nby);
+    flux_yz_tile<3, 1, VISC, SCH>(g, *reinterpret_cast<YzTile<3, VISC> *>(lds), blockIdx.x,
+                                  ny_tiles, nbx, nby);
   else {
     // x chunks: with remap_x in contiguous ranges per XCD (z slabs, as the
     // y tiles and the derivative launch before), so that a chunk finds what
     // that launch left in its XCD's L2; plain order otherwise
     const unsigned c = blockIdx.x - ny_tiles;
-    flux_x_body<3, VISC>(g, nwmax, remap_x ? xcd_remap(c, gridDim.x - ny_tiles) : c, lds);
+    flux_x_body<3, VISC, SCH>(g, nwmax, remap_x ? xcd_remap(c, gridDim.x - ny_tiles) : c, lds);
   }
 }
 
-template <int NDIM, int D, bool VISC>
+template <int NDIM, int D, bool VISC, int SCH = SCHEME_WENO5>
 __global__ void __launch_bounds__(256) k_flux_yz(Dev g) {
   const unsigned nbx = gridDim.x, nby = gridDim.y;
-  flux_yz_body<NDIM, D, VISC>(g, blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z),
-                              nbx * nby * gridDim.z, nbx, nby);
+  flux_yz_body<NDIM, D, VISC, SCH>(g, blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z),
+                                   nbx * nby * gridDim.z, nbx, nby);
 }
 
 // Index of the face left of cell (i, j, k) in direction D's face array.
@@ -911,7 +1005,7 @@ __global__ void __launch_bounds__(256) k_update(Dev g, const double *Un, const d
 // LDS and the other directions' from the face arrays.  The face values and
 // the order of the sums are those of k_flux_yz + k_update.
 // ---------------------------------------------------------------------------
-template <int NDIM, int D, bool VISC>
+template <int NDIM, int D, bool VISC, int SCH = SCHEME_WENO5>
 __device__ __forceinline__ void flux_update_body(const Dev &g, unsigned lin, unsigned ntot,
                                                  unsigned nbx, unsigned nby, const double *Un,
                                                  const double *Uin, double *Uout,
@@ -927,7 +1021,7 @@ __device__ __forceinline__ void flux_update_body(const Dev &g, unsigned lin, uns
   const int f0 = (int)by * (Tl::TD - 1);
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   double G[5];
-  const bool valid = yz_tile_face<NDIM, D, VISC>(g, T, i0, f0, oc, G);
+  const bool valid = yz_tile_face<NDIM, D, VISC, SCH>(g, T, i0, f0, oc, G);
   __syncthreads();  // the staged stencil is no longer read: reuse it for the faces
   double(*fl)[16][16] = reinterpret_cast<double(*)[16][16]>(&T.lds[0][0][0]);
   if (valid)
@@ -975,7 +1069,7 @@ __device__ __forceinline__ void flux_update_body(const Dev &g, unsigned lin, uns
   }
 }
 
-template <int NDIM, bool VISC>
+template <int NDIM, bool VISC, int SCH = SCHEME_WENO5>
 __global__ void __launch_bounds__(256) k_flux_update(Dev g, const double *Un, const double *Uin,
                                                      double *Uout, const double *dtp, double a,
                                                      double bcoef, double *dtpart, BoxOut qo,
@@ -983,8 +1077,8 @@ __global__ void __launch_bounds__(256) k_flux_update(Dev g, const double *Un, co
   constexpr int D = NDIM - 1;
   const unsigned nbx = gridDim.x, nby = gridDim.y;
   const unsigned lin = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
-  flux_update_body<NDIM, D, VISC>(g, lin, nbx * nby * gridDim.z, nbx, nby, Un, Uin, Uout, dtp,
-                                  a, bcoef, dtpart, lin, qo, force);
+  flux_update_body<NDIM, D, VISC, SCH>(g, lin, nbx * nby * gridDim.z, nbx, nby, Un, Uin, Uout,
+                                       dtp, a, bcoef, dtpart, lin, qo, force);
 }
 
 // ---------------------------------------------------------------------------
@@ -1043,7 +1137,7 @@ __global__ void __launch_bounds__(256) k_prim_ghost_dt(Dev g, const double *part
 // the rest compute the derivatives of direction (b - gr0) / nb_grad from
 // interior cells only (gr0 and nb_grad are multiples of 8, so each
 // direction's workgroups meet the XCDs in k_grad's order).
-template <int NDIM>
+template <int NDIM, int SCH = SCHEME_WENO5>
 __global__ void __launch_bounds__(256) k_ghost_grad_periodic(Dev g, const double *part,
                                                              int nparts, double cfl,
                                                              double dt_max, double *dt,
@@ -1059,7 +1153,7 @@ __global__ void __launch_bounds__(256) k_ghost_grad_periodic(Dev g, const double
     return;
   }
   const unsigned gb = b - gr0;
-  grad_body_periodic<NDIM>(g, (int)(gb / nb_grad), gb % nb_grad, nb_grad);
+  grad_body_periodic<NDIM, SCH>(g, (int)(gb / nb_grad), gb % nb_grad, nb_grad);
 }
 
 // ---------------------------------------------------------------------------
@@ -1264,7 +1358,10 @@ template <int NDIM, bool VISC>
 static hipError_t launch_x(const Dev &g, hipStream_t st) {
   const int nw = x_window(g);
   const size_t shm = sizeof(double) * Slots<NDIM, VISC>::NC * nw;
-  k_flux_x<NDIM, VISC><<<grid_for(g.fcount[0]), 256, shm, st>>>(g, nw);
+  if (g.scheme == SCHEME_TENO6A)
+    k_flux_x<NDIM, VISC, SCHEME_TENO6A><<<grid_for(g.fcount[0]), 256, shm, st>>>(g, nw);
+  else
+    k_flux_x<NDIM, VISC><<<grid_for(g.fcount[0]), 256, shm, st>>>(g, nw);
   return hipGetLastError();
 }
 
@@ -1278,8 +1375,12 @@ static hipError_t launch_xy(const Dev &g, hipStream_t st) {
   // in the 256 MB Infinity Cache (TGV 64^3: +1.3 % per step); on larger boxes
   // the plain order measured faster (channel 192x128x128: -0.5 % with it)
   const int remap_x = (double)g.nboxp * 8.0 * (NQ + 9) < 256.0 * 1024.0 * 1024.0;
-  k_flux_xy<VISC><<<ny_tiles + grid_for(g.fcount[0]), 256, shm, st>>>(g, nw, ny_tiles, nbx, nby,
-                                                                        remap_x);
+  if (g.scheme == SCHEME_TENO6A)
+    k_flux_xy<VISC, SCHEME_TENO6A><<<ny_tiles + grid_for(g.fcount[0]), 256, shm, st>>>(
+        g, nw, ny_tiles, nbx, nby, remap_x);
+  else
+    k_flux_xy<VISC><<<ny_tiles + grid_for(g.fcount[0]), 256, shm, st>>>(g, nw, ny_tiles, nbx,
+                                                                          nby, remap_x);
   return hipGetLastError();
 }
 
@@ -1291,7 +1392,10 @@ hipError_t launch_flux_xy(const Dev &g, hipStream_t st) {
 template <int NDIM, int D, bool VISC>
 static hipError_t launch_yz(const Dev &g, hipStream_t st) {
   dim3 grid((g.n[0] + 15) / 16, (g.n[D] + 1 + 15) / 16, D == 1 ? g.n[2] : g.n[1]);
-  k_flux_yz<NDIM, D, VISC><<<grid, 256, 0, st>>>(g);
+  if (g.scheme == SCHEME_TENO6A)
+    k_flux_yz<NDIM, D, VISC, SCHEME_TENO6A><<<grid, 256, 0, st>>>(g);
+  else
+    k_flux_yz<NDIM, D, VISC><<<grid, 256, 0, st>>>(g);
   return hipGetLastError();
 }
 
@@ -1300,10 +1404,14 @@ hipError_t launch_grad(const Dev &g, hipStream_t st) {
   unsigned cells = 0;
   for (int t = 0; t < g.ndim; ++t) cells = std::max(cells, grad_cells(g, t));
   const dim3 grid(grid_for(cells), g.ndim);
-  if (g.ndim == 2)
-    k_grad<2><<<grid, 256, 0, st>>>(g);
-  else
-    k_grad<3><<<grid, 256, 0, st>>>(g);
+  const bool t6 = g.scheme == SCHEME_TENO6A;
+  if (g.ndim == 2) {
+    if (t6) k_grad<2, SCHEME_TENO6A><<<grid, 256, 0, st>>>(g);
+    else k_grad<2><<<grid, 256, 0, st>>>(g);
+  } else {
+    if (t6) k_grad<3, SCHEME_TENO6A><<<grid, 256, 0, st>>>(g);
+    else k_grad<3><<<grid, 256, 0, st>>>(g);
+  }
   return hipGetLastError();
 }
 
@@ -1313,7 +1421,12 @@ static hipError_t launch_fu(const Dev &g, const double *Un, const double *Uin, d
                             const BoxOut &qo, const double *force, hipStream_t st) {
   constexpr int D = NDIM - 1;
   dim3 grid((g.n[0] + 15) / 16, (g.n[D] + 14) / 15, D == 1 ? g.n[2] : g.n[1]);
-  k_flux_update<NDIM, VISC><<<grid, 256, 0, st>>>(g, Un, Uin, Uout, dt, a, b, dtpart, qo, force);
+  if (g.scheme == SCHEME_TENO6A)
+    k_flux_update<NDIM, VISC, SCHEME_TENO6A><<<grid, 256, 0, st>>>(g, Un, Uin, Uout, dt, a, b,
+                                                                   dtpart, qo, force);
+  else
+    k_flux_update<NDIM, VISC><<<grid, 256, 0, st>>>(g, Un, Uin, Uout, dt, a, b, dtpart, qo,
+                                                    force);
   return hipGetLastError();
 }
 
@@ -1430,12 +1543,22 @@ hipError_t launch_ghost_grad_periodic(const Dev &g, const double *part, int npar
   const unsigned nb_ghost = g.nbox > g.ncell ? grid_for(g.nbox - g.ncell) : 0u;
   const unsigned gr0 = (gh0 + nb_ghost + 7u) & ~7u;
   const unsigned total = gr0 + nb_grad * (unsigned)g.ndim;
-  if (g.ndim == 2)
-    k_ghost_grad_periodic<2><<<total, 256, 0, st>>>(g, part, nparts, cfl, dt_max, dt, gh0, gr0,
-                                                      nb_grad);
-  else
-    k_ghost_grad_periodic<3><<<total, 256, 0, st>>>(g, part, nparts, cfl, dt_max, dt, gh0, gr0,
-                                                      nb_grad);
+  const bool t6 = g.scheme == SCHEME_TENO6A;
+  if (g.ndim == 2) {
+    if (t6)
+      k_ghost_grad_periodic<2, SCHEME_TENO6A><<<total, 256, 0, st>>>(g, part, nparts, cfl, dt_max,
+                                                                     dt, gh0, gr0, nb_grad);
+    else
+      k_ghost_grad_periodic<2><<<total, 256, 0, st>>>(g, part, nparts, cfl, dt_max, dt, gh0, gr0,
+                                                        nb_grad);
+  } else {
+    if (t6)
+      k_ghost_grad_periodic<3, SCHEME_TENO6A><<<total, 256, 0, st>>>(g, part, nparts, cfl, dt_max,
+                                                                     dt, gh0, gr0, nb_grad);
+    else
+      k_ghost_grad_periodic<3><<<total, 256, 0, st>>>(g, part, nparts, cfl, dt_max, dt, gh0, gr0,
+                                                        nb_grad);
+  }
   return hipGetLastError();
 }
 hipError_t launch_prim_ghost_dt(const Dev &g, const double *part, int nparts, double cfl,

@@ -113,6 +113,12 @@ def build_case(spec: RequestSpec):
     return _CASES[key]
 
 
+def register_case(family: str, size: int, case, P, K=None):
+    """Serve requests of (family, size) with this case, initial primitives
+    and boundary parameters instead of the family's built-in one."""
+    _CASES[(family, size)] = (case, P, K)
+
+
 def seg_len_for(nsteps: int) -> int:
     """Checkpoint spacing ~ sqrt(n) (memory ~ 2 sqrt(n) states)."""
     return max(1, int(round(math.sqrt(nsteps))))
@@ -216,12 +222,35 @@ def summarize(results: Dict[int, RequestResult], makespan: float) -> dict:
     }
 
 
+class _Entry:
+    """A pooled solve: its context and workspace (Solver) and the device
+    state and step arrays the requests that use it write into.  Entries are
+    kept between requests of the same family, size and kind, so that
+    retiring a request frees nothing (no device-wide synchronisation) and the
+    next such request reuses the memory and, for forward requests, the
+    captured epoch graph."""
+
+    def __init__(self, key, solver, U, dt, nbytes):
+        self.key = key
+        self.solver = solver
+        self.U = U
+        self.dt = dt
+        self.nbytes = nbytes
+        self.graph = None      # forward: k-step epoch captured on first use
+
+
 class GpuBackend:
-    """Runs requests with the HIP library: one stream per slot, hipGraph
-    replays for forward epochs, incremental gradients for gradient epochs."""
+    """Runs requests with the HIP library: each request on one of a few
+    streams (the box has 4 hardware queues), forward epochs as replays of a
+    hipGraph of k CFL steps, gradient epochs as units of the library's
+    incremental checkpointed gradient.  Solves are pooled per (family, size,
+    kind); gradient workspaces are sized for the longest trajectory
+    (`grad_cap` steps, checkpoints every round(sqrt(grad_cap)) steps), so
+    every gradient request of a family and size fits one."""
 
     def __init__(self, steps_per_epoch: int = 10, graphs: bool = True, keep_outputs: bool = False,
-                 inflight: int = 2, fault: Optional[Dict[int, str]] = None):
+                 inflight: int = 2, fault: Optional[Dict[int, str]] = None, nstreams: int = 4,
+                 grad_cap: int = 2000, budget_bytes: float = math.inf):
         import torch
         self.torch = torch
         self.k = steps_per_epoch
@@ -229,75 +258,122 @@ class GpuBackend:
         self.keep = keep_outputs
         self.inflight = inflight
         self.fault = fault or {}
+        self.grad_cap = grad_cap
+        self.grad_seg = seg_len_for(grad_cap)
+        self.budget = budget_bytes
+        self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        self._rr = 0
+        self.pool: Dict[tuple, list] = {}   # idle entries per key
+        self.idle_bytes = 0.0
+        self.live_bytes = 0.0
+        self._fp: Dict[tuple, float] = {}
 
     # -- sizes --------------------------------------------------------------
-    def footprint(self, spec: RequestSpec) -> float:
-        from . import binding as B
-        import ctypes as C
-        case, P, K = build_case(spec)
-        from .solver import Solver
-        # measure with a context (no workspace yet): state + workspace + dt/J
-        mode = 2 if spec.kind == "gradient" else 0
-        seg = seg_len_for(spec.nsteps) if mode == 2 else 0
-        key = (spec.family, spec.size, mode, spec.nsteps if mode == 2 else 0)
-        cache = getattr(self, "_fp", {})
-        self._fp = cache
-        if key not in cache:
-            g = B.dcf_grid()
-            g.ndim = case.ndim
-            for d in range(3):
-                g.n[d], g.lo[d], g.hi[d] = case.n[d], case.lo[d], case.hi[d]
-                g.stretch[d], g.beta[d] = B.STRETCH[case.stretch[d]], case.beta[d]
-            gas = B.dcf_gas(case.gamma, case.R, case.Pr, B.VISC[case.visc_law], case.mu_ref,
-                            case.T_ref, case.visc_param)
-            ctx = C.c_void_p()
-            B.call("dcf_create", C.byref(g), C.byref(gas), C.byref(ctx))
-            size = C.c_size_t()
-            B.call("dcf_workspace_size", ctx, mode, spec.nsteps if mode == 2 else 0, seg,
-                   C.byref(size))
-            B.lib().dcf_destroy(ctx)
-            state = 8 * case.nv * case.ncells
-            extra = 2 * state if mode == 2 else 0   # U0 copy and dJ/dU0
-            cache[key] = float(size.value + state + extra)
-        return cache[key]
+    def _key(self, spec: RequestSpec):
+        return (spec.family, spec.size, spec.kind)
 
-    # -- lifecycle ------------------------------------------------------------
-    def start(self, spec: RequestSpec):
+    def footprint(self, spec: RequestSpec) -> float:
+        """Device bytes of a request: workspace (from the library's size
+        formula, no context created), state, step, and for gradients the
+        initial state, J, dJ/dtheta and dJ/dU0."""
+        from .solver import workspace_bytes_for
+        key = self._key(spec)
+        if key not in self._fp:
+            case, P, K = build_case(spec)
+            state = 8 * case.nv * case.ncells
+            if spec.kind == "gradient":
+                ws = workspace_bytes_for(case, 2, self.grad_cap, self.grad_seg)
+                extra = 2 * state
+            else:
+                ws = workspace_bytes_for(case, 0)
+                extra = 0
+            self._fp[key] = float(ws + state + extra + 4096)
+        return self._fp[key]
+
+    # -- pool -----------------------------------------------------------------
+    def _entry(self, spec: RequestSpec) -> _Entry:
         torch = self.torch
         from .solver import Solver
+        key = self._key(spec)
+        free = self.pool.get(key)
+        if free:
+            e = free.pop()
+            self.idle_bytes -= e.nbytes
+            self.live_bytes += e.nbytes
+            return e
+        nbytes = self.footprint(spec)
+        # idle entries of other keys give their memory back when a new one
+        # would not fit beside them (the only place a context is destroyed
+        # while serving)
+        for k2 in list(self.pool):
+            while self.pool[k2] and self.live_bytes + self.idle_bytes + nbytes > self.budget:
+                old = self.pool[k2].pop()
+                self.idle_bytes -= old.nbytes
+                del old
+        case, P, K = build_case(spec)
+        if spec.kind == "gradient":
+            solver = Solver(case, K=K, mode=2, nsteps=self.grad_cap, seg_len=self.grad_seg)
+        else:
+            solver = Solver(case, K=K, mode=0)
+        # written (init_state, compute_dt) before anything reads them
+        U = solver.empty_state()
+        dt = torch.empty(1, dtype=torch.float64, device="cuda")
+        e = _Entry(key, solver, U, dt, nbytes)
+        self.live_bytes += nbytes
+        return e
+
+    def _release(self, e: _Entry):
+        self.pool.setdefault(e.key, []).append(e)
+        self.live_bytes -= e.nbytes
+        self.idle_bytes += e.nbytes
+
+    def _stream(self):
+        st = self.streams[self._rr % len(self.streams)]
+        self._rr += 1
+        return st
+
+    # -- lifecycle ------------------------------------------------------------
+    def _init_job(self, spec: RequestSpec, stream):
         case, P, K = build_case(spec)
         if spec.rid in self.fault:
             P = P.copy()
             if self.fault[spec.rid] == "nonphysical":
                 P[4].flat[len(P[4].flat) // 2] = -1.0
         job = _Job(spec)
-        job.stream = torch.cuda.Stream()
+        job.entry = self._entry(spec)
+        job.solver, job.U, job.dt = job.entry.solver, job.entry.U, job.entry.dt
+        job.stream = stream
+        job.solver.init_state(P, stream=stream, out=job.U)
+        return job
+
+    def start(self, spec: RequestSpec):
+        torch = self.torch
+        job = self._init_job(spec, self._stream())
+        s, case = job.solver, job.solver.case
         with torch.cuda.stream(job.stream):
             if spec.kind == "gradient":
-                job.solver = Solver(case, K=K, mode=2, nsteps=spec.nsteps,
-                                    seg_len=seg_len_for(spec.nsteps))
-            else:
-                job.solver = Solver(case, K=K, mode=0)
-            job.U = job.solver.init_state(P, stream=job.stream)
-            job.dt = torch.empty(1, dtype=torch.float64, device="cuda")
-            if spec.kind == "gradient":
                 # the trajectory's step is fixed at the initial CFL step
-                job.solver.compute_dt(job.U, cfl=case.cfl, out=job.dt, stream=job.stream)
+                s.compute_dt(job.U, cfl=case.cfl, out=job.dt, stream=job.stream)
                 job.J = torch.zeros(1, dtype=torch.float64, device="cuda")
-                job.gK = torch.zeros(max(job.solver.nk, 1), dtype=torch.float64, device="cuda")
+                job.gK = torch.zeros(max(s.nk, 1), dtype=torch.float64, device="cuda")
                 job.gU = torch.empty_like(job.U)
-                job.solver.gradient_begin(job.U, job.dt, job.J, job.gK, stream=job.stream)
+                s.gradient_begin(job.U, job.dt, job.J, job.gK, stream=job.stream,
+                                 nsteps=spec.nsteps)
                 job.remaining = 1
             else:
                 job.remaining = spec.nsteps
                 # the first CFL step; every step then returns the next one
-                job.solver.compute_dt(job.U, cfl=case.cfl, out=job.dt, stream=job.stream)
-                if self.graphs and spec.nsteps >= self.k:
-                    job.graph = torch.cuda.CUDAGraph()
-                    job.stream.synchronize()
-                    with torch.cuda.graph(job.graph, stream=job.stream):
-                        job.solver.steps_cfl(job.U, job.dt, self.k, cfl=case.cfl)
-                    # capture records without running: state unchanged so far
+                s.compute_dt(job.U, cfl=case.cfl, out=job.dt, stream=job.stream)
+                e = job.entry
+                if self.graphs and spec.nsteps >= self.k and e.graph is None:
+                    # capture records without running (state unchanged so
+                    # far); capture_begin/end directly, without the device
+                    # synchronisation and cache release of torch.cuda.graph
+                    e.graph = torch.cuda.CUDAGraph()
+                    e.graph.capture_begin()
+                    s.steps_cfl(job.U, job.dt, self.k, cfl=case.cfl, stream=job.stream)
+                    e.graph.capture_end()
+                job.graph = e.graph if self.graphs else None
         job.events = deque()
         for _ in range(self.inflight):
             if job.remaining:
@@ -348,21 +424,25 @@ class GpuBackend:
         return True
 
     def finish(self, job, res: RequestResult):
+        # every epoch of the job has completed (poll): reading its flags and
+        # outputs waits on nothing else
         flags = job.solver.flags(stream=job.stream)
         res.status = "ok" if flags == 0 else "nonphysical"
         if self.keep and res.status == "ok":
             if job.spec.kind == "gradient":
                 res.output = {"J": job.J.item(), "dJdK": job.gK.cpu().numpy()[: job.solver.nk],
-                              "dJdU0": job.gU.cpu().numpy()}
+                              "dJdU0": job.gU.cpu().numpy(), "dt": job.dt.item()}
             else:
                 res.output = {"U": job.U.cpu().numpy()}
-        job.solver = job.U = job.graph = None
+        self._release(job.entry)
+        job.solver = job.U = job.graph = job.entry = None
 
 
 class _Job:
     def __init__(self, spec):
         self.spec = spec
         self.solver = None
+        self.entry = None
         self.graph = None
         self.U = self.dt = self.J = self.gK = self.gU = None
         self.remaining = spec.nsteps
@@ -371,48 +451,54 @@ class _Job:
         self.enqueued_done = False
         self.footprint = 0.0
         self.events = deque()
+        self.batched = False
+
+
+class _Family:
+    """Forward solves of one family on one stream: the current batch plan
+    and the hipGraph of k batched steps captured for it."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.members = ()
+        self.plan = None
+        self.graph = None
+        self.retired = deque(maxlen=4)  # previous (plan, graph) pairs kept alive a while
 
 
 class BatchedGpuBackend(GpuBackend):
     """Forward solves of one family (grid dimension, viscous or not, no
-    source) advance together: each epoch is k batched steps, one launch per
-    kernel and stage for all of the family's active solves
-    (dcf_batch_rk3_step), on the family's stream.  Gradient solves run as in
-    GpuBackend.  Solves join and leave a family between epochs."""
+    source) advance together: an epoch is one replay of a hipGraph of k
+    batched steps (one launch per kernel and stage for all members,
+    dcf_batch_rk3_step_table over a device table written outside the
+    capture), on the family's stream.  The graph is captured again only when
+    the members change; a member with fewer than k steps left runs them
+    eagerly.  Gradient solves run as in GpuBackend."""
 
     def __init__(self, steps_per_epoch: int = 10, keep_outputs: bool = False, inflight: int = 2,
-                 fault: Optional[Dict[int, str]] = None):
+                 fault: Optional[Dict[int, str]] = None, budget_bytes: float = math.inf):
         super().__init__(steps_per_epoch=steps_per_epoch, graphs=False, keep_outputs=keep_outputs,
-                         inflight=inflight, fault=fault)
-        self.families = {}   # key -> [stream, BatchStepper]
-        self.want = {}       # key -> jobs that asked for an epoch
+                         inflight=inflight, fault=fault, budget_bytes=budget_bytes)
+        self.families: Dict[tuple, _Family] = {}
+        self.want: Dict[tuple, list] = {}
+        self.recaptures = 0
 
     @staticmethod
-    def _key(job):
-        c = job.solver.case
-        return (c.ndim, c.visc_law != "none", c.cfl)
+    def _fkey(case):
+        return (case.ndim, case.visc_law != "none", case.cfl)
 
     def start(self, spec: RequestSpec):
-        if spec.kind == "gradient":
+        case, _, _ = build_case(spec)
+        if spec.kind == "gradient" or case.source != "none":
             return super().start(spec)
         torch = self.torch
-        from .solver import BatchStepper, Solver
-        case, P, K = build_case(spec)
-        if case.source != "none":
-            return super().start(spec)
-        if spec.rid in self.fault:
-            P = P.copy()
-            if self.fault[spec.rid] == "nonphysical":
-                P[4].flat[len(P[4].flat) // 2] = -1.0
-        job = _Job(spec)
-        job.solver = Solver(case, K=K, mode=0)
-        key = self._key(job)
-        if key not in self.families:
-            self.families[key] = [torch.cuda.Stream(), BatchStepper()]
-        job.stream = self.families[key][0]
+        fk = self._fkey(case)
+        if fk not in self.families:
+            self.families[fk] = _Family(torch.cuda.Stream())
+        fam = self.families[fk]
+        job = self._init_job(spec, fam.stream)
         job.batched = True
-        job.U = job.solver.init_state(P, stream=job.stream)
-        job.dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+        job.fkey = fk
         job.remaining = spec.nsteps
         job.events = deque()
         for _ in range(self.inflight):
@@ -422,21 +508,44 @@ class BatchedGpuBackend(GpuBackend):
         return job
 
     def step(self, job) -> bool:
-        if not getattr(job, "batched", False):
+        if not job.batched:
             return super().step(job)
         n = min(self.k, job.spec.nsteps - job.enqueued)
         if n <= 0:
             return False
-        self.want.setdefault(self._key(job), []).append((job, n))
+        self.want.setdefault(job.fkey, []).append((job, n))
         job.enqueued += n
         return True
 
-    def flush(self):
-        """Launch the requested epochs: per family, step i of the epoch
-        batches every solve that asked for more than i steps."""
+    def _graph_for(self, fam: _Family, jobs, cfl):
         torch = self.torch
-        for key, reqs in self.want.items():
-            stream, stepper = self.families.get(key, (None, None))
+        from .solver import BatchPlan
+        members = tuple(id(j.entry) for j in jobs)
+        if members == fam.members and fam.graph is not None:
+            return fam.graph
+        if fam.plan is not None:
+            fam.retired.append((fam.plan, fam.graph))
+        plan = BatchPlan([j.solver for j in jobs], [j.U for j in jobs], [j.dt for j in jobs],
+                         stream=fam.stream)
+        # the table copy precedes the replays on the family stream; the
+        # capture itself records launches only
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(fam.stream):
+            graph.capture_begin()
+            for _ in range(self.k):
+                plan.step(cfl=cfl, stream=fam.stream)
+            graph.capture_end()
+        fam.members, fam.plan, fam.graph = members, plan, graph
+        self.recaptures += 1
+        return graph
+
+    def flush(self):
+        """Launch the requested epochs: per family, the members that asked
+        for a full epoch replay the family's graph together; shorter final
+        epochs run eagerly (a CFL step, then that many fused CFL steps)."""
+        torch = self.torch
+        for fk, reqs in self.want.items():
+            fam = self.families.get(fk)
             while reqs:
                 # one round: at most one pending epoch per solve
                 seen, rnd, rest = set(), [], []
@@ -444,25 +553,35 @@ class BatchedGpuBackend(GpuBackend):
                     (rest if id(j) in seen else rnd).append((j, n))
                     seen.add(id(j))
                 reqs[:] = rest
-                with torch.cuda.stream(stream):
-                    for i in range(max(n for _, n in rnd)):
-                        members = [j for j, n in rnd if n > i]
-                        stepper.step([j.solver for j in members], [j.U for j in members],
-                                     [j.dt for j in members], cfl=key[2], stream=stream)
+                full = [j for j, n in rnd if n == self.k]
+                part = [(j, n) for j, n in rnd if n < self.k]
+                with torch.cuda.stream(fam.stream):
+                    if full:
+                        full.sort(key=lambda j: id(j.entry))
+                        self._graph_for(fam, full, fk[2]).replay()
+                    for j, n in part:
+                        s = j.solver
+                        s.compute_dt(j.U, cfl=s.case.cfl, out=j.dt, stream=fam.stream)
+                        s.steps_cfl(j.U, j.dt, n, cfl=s.case.cfl, stream=fam.stream)
                     ev = torch.cuda.Event()
-                    ev.record(stream)
+                    ev.record(fam.stream)
                 for j, n in rnd:
                     j.events.append((ev, n))
 
 
 def serve(trace, budget_bytes=200e9, max_slots=16, steps_per_epoch=10, graphs=True,
-          keep_outputs=False, realtime=True, fault=None, batched=False):
-    if batched:
-        backend = BatchedGpuBackend(steps_per_epoch=steps_per_epoch, keep_outputs=keep_outputs,
-                                    fault=fault)
-    else:
-        backend = GpuBackend(steps_per_epoch=steps_per_epoch, graphs=graphs,
-                             keep_outputs=keep_outputs, fault=fault)
+          keep_outputs=False, realtime=True, fault=None, batched=False, backend=None):
+    """Serve a trace; returns (results, makespan in s, scheduler).  A backend
+    may be passed in to keep its pooled solves between calls."""
+    if backend is None:
+        if batched:
+            backend = BatchedGpuBackend(steps_per_epoch=steps_per_epoch,
+                                        keep_outputs=keep_outputs, fault=fault,
+                                        budget_bytes=budget_bytes)
+        else:
+            backend = GpuBackend(steps_per_epoch=steps_per_epoch, graphs=graphs,
+                                 keep_outputs=keep_outputs, fault=fault,
+                                 budget_bytes=budget_bytes)
     sch = Scheduler(backend, budget_bytes, max_slots)
     t0 = time.perf_counter()
     res = sch.run(trace, realtime=realtime)
@@ -470,7 +589,8 @@ def serve(trace, budget_bytes=200e9, max_slots=16, steps_per_epoch=10, graphs=Tr
     return res, time.perf_counter() - t0, sch
 
 
-def serve_sequential(trace, steps_per_epoch=10, graphs=True, keep_outputs=False, realtime=True):
+def serve_sequential(trace, steps_per_epoch=10, graphs=True, keep_outputs=False, realtime=True,
+                     backend=None):
     """Baseline: the same trace FIFO, one solve at a time on the same GPU."""
     return serve(trace, budget_bytes=float("inf"), max_slots=1, steps_per_epoch=steps_per_epoch,
-                 graphs=graphs, keep_outputs=keep_outputs, realtime=realtime)
+                 graphs=graphs, keep_outputs=keep_outputs, realtime=realtime, backend=backend)

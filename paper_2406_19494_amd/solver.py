@@ -73,6 +73,7 @@ class Solver:
                                                             case.p_inf)
             B.call("dcf_set_bc", ctx, f, C.byref(bc))
         B.call("dcf_set_source", ctx, B.SOURCE[case.source])
+        B.call("dcf_set_scheme", ctx, B.SCHEME[getattr(case, "scheme", "weno5")])
         if case.cost_face >= 0:
             B.call("dcf_set_cost", ctx, case.cost_face, case.p_inf)
         self.nk = L.dcf_num_params(ctx)
@@ -121,10 +122,16 @@ class Solver:
         self.K = K
         B.call("dcf_set_params", self.ctx, _ptr(K), int(K.numel()))
 
-    def init_state(self, P, stream=None) -> torch.Tensor:
-        Pt = torch.as_tensor(np.ascontiguousarray(P), dtype=torch.float64, device=self.device)
-        U = self.empty_state()
-        B.call("dcf_init_state", self.ctx, _ptr(Pt), _ptr(U), _stream(stream))
+    def init_state(self, P, stream=None, out=None) -> torch.Tensor:
+        """Conserved state from primitives P (into `out` when given).  The
+        staged copy of P is made on the stream that reads it, so that its
+        memory is not handed out again while the conversion is pending."""
+        st = torch.cuda.current_stream() if stream is None else stream
+        with torch.cuda.stream(st):
+            Pt = torch.as_tensor(np.ascontiguousarray(P), dtype=torch.float64,
+                                 device=self.device)
+            U = self.empty_state() if out is None else out
+            B.call("dcf_init_state", self.ctx, _ptr(Pt), _ptr(U), _stream(st))
         return U
 
     # -------------------------------------------------------------- forward
@@ -141,6 +148,12 @@ class Solver:
 
     def step(self, U: torch.Tensor, dt: torch.Tensor, stream=None):
         B.call("dcf_rk3_step", self.ctx, _ptr(U), _ptr(dt), _stream(stream))
+
+    def step_keep(self, U: torch.Tensor, dt: torch.Tensor, stages: torch.Tensor, stream=None):
+        """One RK3 step that also writes its stage states U(1), U(2) into
+        `stages` (shape (2,) + U.shape)."""
+        assert stages.numel() == 2 * U.numel()
+        B.call("dcf_rk3_step_keep", self.ctx, _ptr(U), _ptr(dt), _ptr(stages), _stream(stream))
 
     def step_cfl(self, U: torch.Tensor, dt: torch.Tensor, cfl=None, dt_max=0.0, out=None,
                  stream=None) -> torch.Tensor:
@@ -219,17 +232,22 @@ class Solver:
         B.call("dcf_cost_term", self.ctx, _ptr(U), float(w), _ptr(J), _ptr(grad), _stream(stream))
         return J
 
-    def vjp_step(self, Un, dt, lam, dJdK=None, stream=None) -> torch.Tensor:
+    def vjp_step(self, Un, dt, lam, dJdK=None, stages=None, stream=None) -> torch.Tensor:
+        """lam_n of one step; `stages` (2 state arrays from step_keep) spares
+        the VJP the recompute of the stage states."""
         out = torch.empty_like(lam)
-        B.call("dcf_vjp_step", self.ctx, _ptr(Un), _ptr(dt), _ptr(lam), _ptr(out), _ptr(dJdK),
-               _stream(stream))
+        B.call("dcf_vjp_step", self.ctx, _ptr(Un), _ptr(stages), _ptr(dt), _ptr(lam), _ptr(out),
+               _ptr(dJdK), _stream(stream))
         return out
 
     def workspace_bytes(self) -> int:
         return 0 if self.workspace is None else int(self.workspace.numel())
 
-    def gradient_begin(self, U0, dt, J, gK, stream=None):
-        B.call("dcf_gradient_begin", self.ctx, _ptr(U0), int(self.nsteps), _ptr(dt),
+    def gradient_begin(self, U0, dt, J, gK, stream=None, nsteps=None):
+        """Start a trajectory gradient of `nsteps` steps (default: the size
+        the workspace was made for; fewer fit the same workspace)."""
+        n = self.nsteps if nsteps is None else int(nsteps)
+        B.call("dcf_gradient_begin", self.ctx, _ptr(U0), n, _ptr(dt),
                int(self.seg_len), _ptr(J), _ptr(gK) if self.nk else None, _stream(stream))
 
     def gradient_advance(self, max_units: int, stream=None) -> bool:
@@ -248,6 +266,62 @@ class Solver:
         B.call("dcf_gradient", self.ctx, _ptr(U0), int(self.nsteps), _ptr(dt), int(self.seg_len),
                _ptr(J), _ptr(gK) if self.nk else None, _ptr(gU), _stream(stream))
         return J, gK[: self.nk], gU
+
+
+def grid_gas(case: Case):
+    """The C structs of a case's grid and gas."""
+    g = B.dcf_grid()
+    g.ndim = case.ndim
+    for d in range(3):
+        g.n[d] = case.n[d]
+        g.lo[d] = case.lo[d]
+        g.hi[d] = case.hi[d]
+        g.stretch[d] = B.STRETCH[case.stretch[d]]
+        g.beta[d] = case.beta[d]
+    gas = B.dcf_gas(case.gamma, case.R, case.Pr, B.VISC[case.visc_law], case.mu_ref,
+                    case.T_ref, case.visc_param)
+    return g, gas
+
+
+def workspace_bytes_for(case: Case, mode: int, nsteps: int = 0, seg_len: int = 0) -> int:
+    """Workspace size of a solve without creating one (host arithmetic in the
+    library, dcf_workspace_size_for)."""
+    g, gas = grid_gas(case)
+    size = C.c_size_t()
+    B.call("dcf_workspace_size_for", C.byref(g), C.byref(gas), int(mode), int(nsteps),
+           int(seg_len), C.byref(size))
+    return size.value
+
+
+class BatchPlan:
+    """A fixed batch of solves stepped together: the device table is written
+    once (outside any graph capture); step() enqueues launches only
+    (dcf_batch_rk3_step_table), so it can be captured and replayed while the
+    batch stays the same."""
+
+    def __init__(self, solvers, Us, dts, stream=None):
+        n = len(solvers)
+        size = C.c_size_t()
+        B.call("dcf_batch_table_bytes", n, C.byref(size))
+        dev = Us[0].device
+        self.n = n
+        self.host = torch.empty(size.value, dtype=torch.uint8, pin_memory=True)
+        VP = C.c_void_p * n
+        B.call("dcf_batch_table_fill", VP(*[s.ctx.value for s in solvers]),
+               VP(*[U.data_ptr() for U in Us]), VP(*[d.data_ptr() for d in dts]), n,
+               C.c_void_p(self.host.data_ptr()), size.value)
+        s = torch.cuda.current_stream() if stream is None else stream
+        with torch.cuda.stream(s):
+            # allocated on the stream whose launches read it: freed memory
+            # is handed out again only in that stream's order
+            self.dev = torch.empty(size.value, dtype=torch.uint8, device=dev)
+            self.dev.copy_(self.host, non_blocking=True)
+        # keep the members alive while the plan (or a graph of it) exists
+        self.members = (list(solvers), list(Us), list(dts))
+
+    def step(self, cfl=None, stream=None):
+        B.call("dcf_batch_rk3_step_table", _ptr(self.dev), C.c_void_p(self.host.data_ptr()),
+               self.n, float(cfl) if cfl else 0.0, _stream(stream))
 
 
 class BatchStepper:

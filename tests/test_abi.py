@@ -51,7 +51,9 @@ def test_invalid_arguments_rejected_without_device(dcf):
     assert L.dcf_create(None, C.byref(gas), C.byref(ctx)) == -1
     # null context on every stateful call
     assert L.dcf_rk3_step(None, None, None, None) == -1
-    assert L.dcf_vjp_step(None, None, None, None, None, None, None) == -1
+    assert L.dcf_vjp_step(None, None, None, None, None, None, None, None) == -1
+    assert L.dcf_rk3_step_keep(None, None, None, None, None) == -1
+    assert L.dcf_rk3_step_noalloc(None, None, None, None, None) == -1
     assert L.dcf_rk3_step_cfl(None, None, None, 0.5, 0.0, None, None) == -1
     # batched stepping: sizes and null arguments are checked first
     nb = C.c_size_t()

@@ -59,3 +59,37 @@ def test_trajectory_cost_matches_gradient_and_optimises():
     Js = [h[0] for h in hist]
     print("[optimise] J history", Js, flush=True)
     assert Js[-1] < Js[0]
+
+
+def test_projected_adam_matches_oracle_driven_iterations():
+    # Three projected-Adam iterations on the porous coefficients of a tiny
+    # boundary layer: driven by the GPU's trajectory gradient
+    # (optimize_porous) and, step for step in numpy, by the oracle's dense
+    # adjoint gradient; the parameter vectors agree to 1e-10.
+    case, P, K = _tiny_porous()
+    nsteps, dt_v, lr, k_max, b1, b2 = 4, 1e-3, 0.02, 1.0, 0.9, 0.999
+    o0 = Oracle(case, K=K)
+    U0 = o0.cons(P)
+    s = Solver(case, K=K, mode=2, nsteps=nsteps, seg_len=2)
+    dt = torch.full((1,), dt_v, dtype=torch.float64, device="cuda")
+    # four gradients: the parameters before each of three updates and after
+    # the third
+    hist = optimize_porous(s, torch.as_tensor(U0, device="cuda"), dt, K, iters=4, lr=lr,
+                           k_max=k_max, betas=(b1, b2))
+    th = np.array(K, dtype=np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    for it in range(1, 5):
+        J_or, g, _ = Oracle(case, K=th).gradient(U0, nsteps, dt_v)
+        J_gpu, th_gpu = hist[it - 1]
+        assert abs(J_gpu - J_or) <= 1e-12 * abs(J_or), (it, J_gpu, J_or)
+        assert np.abs(th_gpu.cpu().numpy() - th).max() <= 1e-10 * np.abs(th).max(), it
+        if it == 4:
+            break
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g * g
+        mh = m / (1 - b1 ** it)
+        vh = v / (1 - b2 ** it)
+        th = th - lr * mh / (np.sqrt(vh) + 1e-30)
+        th[: case.n_porous] = np.clip(th[: case.n_porous], 0.0, k_max)
+    print(f"[adam vs oracle] J {[h[0] for h in hist]}", flush=True)

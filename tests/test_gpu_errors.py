@@ -44,7 +44,7 @@ def test_workspace_too_small_and_unset():
     # mode-0 workspace cannot run the adjoint
     lam = torch.zeros_like(U)
     dt = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
-    rc = L.dcf_vjp_step(ctx, C.c_void_p(U.data_ptr()), C.c_void_p(dt.data_ptr()),
+    rc = L.dcf_vjp_step(ctx, C.c_void_p(U.data_ptr()), None, C.c_void_p(dt.data_ptr()),
                         C.c_void_p(lam.data_ptr()), C.c_void_p(R.data_ptr()), None, None)
     assert rc == -2
     L.dcf_destroy(ctx)

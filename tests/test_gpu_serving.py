@@ -1,6 +1,7 @@
 """GPU serving: each request's result is the same alone and in the mix
-(bitwise), graph replays equal eager steps, a non-physical request is isolated,
-and batched serving beats sequential solves on throughput."""
+(bitwise) and matches the oracle, graph replays equal eager steps, a
+non-physical request is isolated, and batched serving beats sequential solves
+on throughput."""
 import numpy as np
 import pytest
 import torch
@@ -117,3 +118,59 @@ def test_batched_kernels_backend_isolates_nonphysical():
     assert res[0].status == "nonphysical" and res[1].status == "ok"
     ref, _, _ = S.serve([trace[1]], max_slots=1, keep_outputs=True, realtime=False)
     assert np.array_equal(ref[1].output["U"], res[1].output["U"])
+
+
+def test_served_results_match_oracle():
+    # forward and gradient requests served together (per-request streams and
+    # family-batched graph epochs), each output against the oracle: forward
+    # states after their CFL steps, gradients (J, dJ/dK, dJ/dU0) over the
+    # fixed-step trajectory the request ran
+    from oracle.pyoracle import Oracle
+    from tests.test_oracle_pins import _tiny_porous
+    case, P, K = _tiny_porous()
+    S.register_case("bl", 0, case, P, K)
+    # a Sod tube whose cost (wall pressure at the x- end against 0.9) is
+    # nonzero from the first step
+    sod, Ps = W.sod(40)
+    sod.cost_face, sod.p_inf = 0, 0.9
+    S.register_case("sod", 41, sod, Ps, None)
+    trace = [
+        S.RequestSpec(0, "sod", 40, "forward", 23, 0.0),
+        S.RequestSpec(1, "sod", 64, "forward", 17, 0.0),
+        S.RequestSpec(2, "tgv", 8, "forward", 12, 0.0),
+        S.RequestSpec(3, "bl", 0, "forward", 14, 0.0),
+        S.RequestSpec(4, "sod", 41, "gradient", 6, 0.0),
+        S.RequestSpec(5, "bl", 0, "gradient", 5, 0.0),
+    ]
+    for batched in (False, True):
+        res, _, _ = S.serve(trace, max_slots=6, keep_outputs=True, realtime=False,
+                            batched=batched)
+        for spec in trace:
+            r = res[spec.rid]
+            assert r.status == "ok", (spec, r.status, r.message)
+            c, Pc, Kc = S.build_case(spec)
+            o = Oracle(c, K=Kc)
+            U0 = o.cons(Pc)
+            if spec.kind == "forward":
+                U_or = U0.copy()
+                for _ in range(spec.nsteps):
+                    U_or = o.step(U_or, o.dt(U_or, c.cfl))
+                err = np.abs(r.output["U"] - U_or).max(axis=(1, 2, 3)) / \
+                    np.abs(U_or).max(axis=(1, 2, 3))
+                assert np.all(err <= 1e-10), (batched, spec, err)
+            else:
+                dt = r.output["dt"]
+                assert abs(dt - o.dt(U0, c.cfl)) <= 1e-13 * dt
+                J, gk, gu = o.gradient(U0, spec.nsteps, dt)
+                assert J > 0.0
+                assert abs(r.output["J"] - J) <= 1e-12 * abs(J), (batched, spec)
+                if o.nk:
+                    assert np.abs(r.output["dJdK"] - gk).max() <= 1e-10 * np.abs(gk).max()
+                # per variable, in units of the change of J under a relative
+                # change of the state: max|d gu_v| max|U_v| against the
+                # largest max|gu_v'| max|U_v'| (a component the cost hardly
+                # feels, such as the density at rest, is held to that scale)
+                um = np.abs(U0).max(axis=(1, 2, 3))
+                ref = (np.abs(gu).max(axis=(1, 2, 3)) * um).max()
+                err = np.abs(r.output["dJdU0"] - gu).max(axis=(1, 2, 3)) * um / ref
+                assert np.all(err <= 1e-10), (batched, spec, err)

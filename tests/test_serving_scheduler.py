@@ -257,21 +257,34 @@ class _FakeStepper:
 
 
 def test_batched_backend_rounds_and_accounting():
-    # forward solves of one family: every batched step holds each solve at
-    # most once, a solve with two pending epochs gets two rounds, and every
-    # solve receives exactly its steps
+    # forward solves of one family: every graph epoch holds each solve at most
+    # once, a solve with two pending epochs gets two rounds, the short final
+    # epoch runs eagerly, and every solve receives exactly its steps
     from collections import deque
-    from paper_2406_19494_amd.serving import BatchedGpuBackend, _Job
+    from paper_2406_19494_amd.serving import BatchedGpuBackend, _Family, _Job
     be = BatchedGpuBackend.__new__(BatchedGpuBackend)
     be.torch, be.k, be.inflight = _FakeTorch, 10, 2
-    stepper = _FakeStepper()
-    be.families = {(1, False, 0.5): [None, stepper]}
+    fk = (1, False, 0.5)
+    be.families = {fk: _Family(None)}
     be.want = {}
-    be._key = lambda job: (1, False, 0.5)
+    calls = []
+
+    class _Graph:
+        def __init__(self, jobs):
+            self.jobs = jobs
+
+        def replay(self):
+            assert len(set(map(id, self.jobs))) == len(self.jobs), "a solve twice in one epoch"
+            calls.append(len(self.jobs))
+            for j in self.jobs:
+                j.solver.steps += be.k
+
+    be._graph_for = lambda fam, jobs, cfl: _Graph(list(jobs))
     jobs = []
     for rid, n in enumerate((25, 7, 40)):
         job = _Job(RequestSpec(rid, "sod", 200, "forward", n, 0.0))
         job.solver, job.stream, job.events, job.batched = _FakeSolver(0), None, deque(), True
+        job.fkey, job.entry = fk, object()
         for _ in range(be.inflight):
             be.step(job)
         jobs.append(job)
@@ -288,4 +301,4 @@ def test_batched_backend_rounds_and_accounting():
         raise AssertionError("did not terminate")
     for j in jobs:
         assert j.solver.steps == j.spec.nsteps == j.completed
-    assert max(stepper.calls) == 3
+    assert max(calls) == 2  # the 25- and 40-step solves share full epochs
