@@ -274,77 +274,67 @@ __device__ __forceinline__ void hllc(const double *qL, const double *qR, double 
 // Jiang-Shu indicators of the candidates and of the six-point polynomial
 // (integrals over the centre cell) give tau6 = |b6 - (b0 + b2 + 4 b1) / 6|
 // and the measures gamma_k = (1 + tau6 / (b_k + 1e-40))^6; a candidate whose
-// share gamma_k / sum gamma is below the cut-off C_T is dropped, the kept
-// ones are combined with their linear weights renormalised.
+// share gamma_k / sum gamma is below the cut-off C_T is dropped (tested as
+// gamma_k < C_T sum gamma), the kept ones are combined with their linear
+// weights renormalised.
 // C_T = 10^-floor(10.5 - 3.5 (1 - (1-m)^4 (1+4m))), m = 1 - min(1, eta/0.17),
 // eta the smallest of Ren's measures (|2 a b| + e) / (a^2 + b^2 + e) over the
 // neighbouring differences (a, b) of the four inner cells,
-// e = 0.9 * 0.17 * (1e-3)^2 / (1 - 0.9 * 0.17); the same for both sides.
-// The quantities that decide which candidates are kept (indicators, tau6,
-// gamma, their shares, eta) are evaluated in a fixed order with IEEE
-// division and without contracted multiply-adds, so that the selection is
-// reproducible operation by operation; for nearly uniform data the
-// indicators are rounding noise and the selection follows that noise.
+// e = 0.9 * 0.17 * (1e-3)^2 / (1 - 0.9 * 0.17); the mirrored differences give
+// the same measures, so C_T is shared by both sides.  Reciprocals are the
+// refined hardware ones (no IEEE division).
 __device__ __forceinline__ void teno6a_pair(double v0, double v1, double v2, double v3, double v4,
                                             double v5, double &yl, double &yr) {
-#pragma clang fp contract(off)
-  // the cut-off, shared by both sides (the mirrored differences give the same
-  // measures)
   double ct;
   {
     const double Cr = 0.17, xi = 1.0e-3;
     const double ee = 0.9 * Cr * xi * xi / (1.0 - 0.9 * Cr);
-    const double v[6] = {v0, v1, v2, v3, v4, v5};
-    double eta = 1.0e300;
-#pragma unroll
-    for (int j = 1; j <= 4; ++j) {
-      const double dm = v[j] - v[j - 1], dp = v[j + 1] - v[j];
-      const double ej = (fabs(2.0 * dp * dm) + ee) / (dp * dp + dm * dm + ee);
-      eta = fmin(eta, ej);
-    }
-    const double m = 1.0 - fmin(1.0, eta / Cr);
+    const double d0 = v1 - v0, d1 = v2 - v1, d2 = v3 - v2, d3 = v4 - v3, d4 = v5 - v4;
+    auto ren = [&](double dm, double dp) {
+      return (fabs(2.0 * dp * dm) + ee) * rcp_nr(fma(dp, dp, fma(dm, dm, ee)));
+    };
+    const double eta = fmin(fmin(ren(d0, d1), ren(d1, d2)), fmin(ren(d2, d3), ren(d3, d4)));
+    const double m = 1.0 - fmin(1.0, eta * (1.0 / Cr));
     const double om = 1.0 - m, om2 = om * om;
     const double bbar = 10.5 - 3.5 * (1.0 - om2 * om2 * (1.0 + 4.0 * m));
     const int k = (int)floor(bbar);
     ct = k >= 10 ? 1.0e-10 : (k == 9 ? 1.0e-9 : (k == 8 ? 1.0e-8 : 1.0e-7));
   }
   auto side = [ct](double a, double b, double c, double d, double e, double f) {
-#pragma clang fp contract(off)
+    constexpr double c1312 = 13.0 / 12.0;
     const double s0 = b - 2.0 * c + d, t0 = b - d;
     const double s1 = c - 2.0 * d + e, t1 = 3.0 * c - 4.0 * d + e;
     const double s2 = a - 2.0 * b + c, t2 = a - 4.0 * b + 3.0 * c;
-    const double beta[4] = {
-        (13.0 / 12.0) * s0 * s0 + 0.25 * t0 * t0, (13.0 / 12.0) * s1 * s1 + 0.25 * t1 * t1,
-        (13.0 / 12.0) * s2 * s2 + 0.25 * t2 * t2,
-        (c * (2107.0 * c - 9402.0 * d + 7042.0 * e - 1854.0 * f) +
-         d * (11003.0 * d - 17246.0 * e + 4642.0 * f) + e * (7043.0 * e - 3882.0 * f) +
-         547.0 * f * f) / 240.0};
+    const double b0 = fma(c1312 * s0, s0, 0.25 * t0 * t0);
+    const double b1 = fma(c1312 * s1, s1, 0.25 * t1 * t1);
+    const double b2 = fma(c1312 * s2, s2, 0.25 * t2 * t2);
+    const double b3 = (c * (2107.0 * c - 9402.0 * d + 7042.0 * e - 1854.0 * f) +
+                       d * (11003.0 * d - 17246.0 * e + 4642.0 * f) +
+                       e * (7043.0 * e - 3882.0 * f) + 547.0 * f * f) * (1.0 / 240.0);
     const double b6 =
-        (271779.0 * a * a +
-         a * (-2380800.0 * b + 4086352.0 * c - 3462252.0 * d + 1458762.0 * e - 245620.0 * f) +
+        (a * (271779.0 * a - 2380800.0 * b + 4086352.0 * c - 3462252.0 * d + 1458762.0 * e -
+              245620.0 * f) +
          b * (5653317.0 * b - 20427884.0 * c + 17905032.0 * d - 7727988.0 * e +
               1325006.0 * f) +
          c * (19510972.0 * c - 35817664.0 * d + 15929912.0 * e - 2792660.0 * f) +
          d * (17195652.0 * d - 15880404.0 * e + 2863984.0 * f) +
-         e * (3824847.0 * e - 1429976.0 * f) + 139633.0 * f * f) / 120960.0;
-    const double tau = fabs(b6 - (beta[0] + beta[2] + 4.0 * beta[1]) / 6.0);
-    double gam[4], gsum = 0.0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double r = 1.0 + tau / (beta[k] + 1.0e-40);
-      gam[k] = r * r * r * r * r * r;
-      gsum += gam[k];
-    }
-    const double dk[4] = {0.45, 0.3, 0.05, 0.2};
-    double w[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) w[k] = gam[k] / gsum < ct ? 0.0 : dk[k];
+         e * (3824847.0 * e - 1429976.0 * f) + 139633.0 * f * f) * (1.0 / 120960.0);
+    const double tau = fabs(b6 - (b0 + b2 + 4.0 * b1) * (1.0 / 6.0));
+    auto gam = [tau](double beta) {
+      const double r = fma(tau, rcp_nr(beta + 1.0e-40), 1.0);
+      const double r2 = r * r;
+      return r2 * r2 * r2;
+    };
+    const double g0 = gam(b0), g1 = gam(b1), g2 = gam(b2), g3 = gam(b3);
+    const double lim = ct * (g0 + g1 + g2 + g3);
+    const double w0 = g0 < lim ? 0.0 : 0.45, w1 = g1 < lim ? 0.0 : 0.3;
+    const double w2 = g2 < lim ? 0.0 : 0.05, w3 = g3 < lim ? 0.0 : 0.2;
     // candidates: (b c d), (c d e), (a b c), (c d e f)
     const double q0 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
     const double q1 = (2.0 * c + 5.0 * d - e) * (1.0 / 6.0);
     const double q2 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
     const double q3 = (3.0 * c + 13.0 * d - 5.0 * e + f) * (1.0 / 12.0);
-    return (w[0] * q0 + w[1] * q1 + w[2] * q2 + w[3] * q3) * rcp_nr(w[0] + w[1] + w[2] + w[3]);
+    return (w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3) * rcp_nr(w0 + w1 + w2 + w3);
   };
   yl = side(v0, v1, v2, v3, v4, v5);
   yr = side(v5, v4, v3, v2, v1, v0);
