@@ -125,6 +125,27 @@ def test_failed_start_is_isolated():
     assert s["completed"] == 2 and s["failed"] == 1
 
 
+class StallingBackend(FakeBackend):
+    """A backend whose solve still counts steps left but has nothing more to
+    enqueue and no epoch in flight: the state in which a polling loop would
+    spin for ever."""
+
+    def step(self, job):
+        if job.remaining <= 10:
+            job.events = 0
+            return False
+        return super().step(job)
+
+
+def test_stalled_solve_raises_instead_of_spinning():
+    clock = FakeClock()
+    be = StallingBackend(clock)
+    sch = Scheduler(be, budget_bytes=1e9, max_slots=4, clock=clock, idle_sleep=0)
+    with pytest.raises(RuntimeError, match="no work in flight"):
+        sch.run(_trace([10], steps=30))
+    assert clock.t < 10.0  # raised within the simulated seconds, not after a spin
+
+
 def test_trace_is_seeded_and_in_range():
     a = draw_trace(50, 20.0, seed=3)
     b = draw_trace(50, 20.0, seed=3)
