@@ -35,14 +35,14 @@ BYTES_PER_CELL_STAGE = {1: 64.0, 2: 85.3, 3: 106.7}
 # kernel source (10 WENO5-JS reconstructions x 69, HLLC star branch 79, 3D
 # viscous/heat flux 183), used where no unit figure above applies (1D/2D,
 # inviscid), and algorithmic bytes per face: the inputs of one cell read
-# once (rho, u, v, w, p, plus T, mu and the 2 (2D) or 4 (3D) tangential
-# derivatives a viscous face reads), 5 x 8 B of flux written.
+# once (rho, u, v, w, p, plus T and mu when viscous; the tangential velocity
+# derivatives are computed from the velocities), 5 x 8 B of flux written.
 FLOPS_PER_FACE = {(1, False): 6 * 69 + 79, (1, True): 6 * 69 + 79 + 40,
                   (2, False): 8 * 69 + 79, (2, True): 8 * 69 + 79 + 101,
                   (3, False): 10 * 69 + 79, (3, True): 10 * 69 + 79 + 183}
 BYTES_PER_FACE = {(1, False): 5 * 8 + 40, (1, True): 7 * 8 + 40,
-                  (2, False): 5 * 8 + 40, (2, True): 9 * 8 + 40,
-                  (3, False): 5 * 8 + 40, (3, True): 11 * 8 + 40}
+                  (2, False): 5 * 8 + 40, (2, True): 7 * 8 + 40,
+                  (3, False): 5 * 8 + 40, (3, True): 7 * 8 + 40}
 
 
 def flops_per_face(case):
@@ -72,17 +72,6 @@ def algorithmic_bytes(case, kernel):
     if kernel == "k_prim_ghost":  # each ghost reads its source cell's values, writes its own
         nq = nd + 2 + (2 if visc else 0)
         return 8 * 2 * nq * (nbox - case.ncells)
-    if kernel == "k_ghost_grad_periodic":  # the ghost fill and the derivatives of one launch
-        return algorithmic_bytes(case, "k_prim_ghost") + algorithmic_bytes(case, "k_grad")
-    if kernel == "k_grad":
-        writes = 0
-        for t in range(nd):
-            cnt = case.n[t]
-            for e in range(nd):
-                if e != t:
-                    cnt *= case.n[e] + 4
-            writes += nd * cnt
-        return 8 * (nbox * nd + writes)
     if kernel == "k_update":
         faces = 0
         for D in range(nd):
@@ -183,21 +172,15 @@ def measured_traffic(kernel, workload):
 
 def step_kernel_ids(case):
     """dcf_time_kernel ids of the launches one RK3 stage of `case` runs:
-    halo fill (0; 8 = ghosts only, stages 2-3 of a fused step), derivatives
-    (5, viscous 2D/3D; 9 = ghosts and derivatives in one launch when every
-    face is periodic), fluxes (7 = x+y of a 3D grid, 1..3 per direction),
+    halo fill (0; 8 = ghosts only, stages 2-3 of a fused step), fluxes (7 =
+    x+y of a 3D grid, 1..3 per direction; on 2D and 3D grids they compute the
+    velocity derivatives they need themselves, so no derivative launch),
     then the fused last-direction flux + update (6, 2D/3D without source) or
     the separate update (4)."""
-    visc = case.visc_law != "none"
     last = 2 * (case.ndim - 1)
     fused = case.ndim >= 2 and (case.source == "none" or (
         case.bc[last] == "periodic" and case.bc[last + 1] == "periodic"))
-    periodic = all(case.bc[2 * d] == "periodic" and case.bc[2 * d + 1] == "periodic"
-                   and case.n[d] >= 3 for d in range(case.ndim))
-    if fused and visc and periodic:
-        ids = [0, 9]
-    else:
-        ids = [0] + ([8] if fused else []) + ([5] if visc and case.ndim >= 2 else [])
+    ids = [0] + ([8] if fused else [])
     if case.ndim == 3:
         ids += [7] + ([6] if fused else [3, 4])
     elif case.ndim == 2:
@@ -490,8 +473,7 @@ def main():
     # only the ghosts (k_prim_ghost, 8; the first step of a call runs the
     # whole halo fill, 0).  The unfused kernels are timed too, for the record.
     names = {0: "k_prim_halo", 1: "k_flux_x", 2: "k_flux_yz<y>", 3: "k_flux_yz<z>", 4: "k_update",
-             5: "k_grad", 6: "k_flux_update", 7: "k_flux_xy", 8: "k_prim_ghost",
-             9: "k_ghost_grad_periodic"}
+             6: "k_flux_update", 7: "k_flux_xy", 8: "k_prim_ghost"}
     step_kinds = step_kernel_ids(case)
     kinds = sorted(set(step_kinds) | set(range(1, case.ndim + 1)) | {4})
     kt = {w: s.time_kernel(U, w, reps=20) for w in kinds}  # back-to-back launches
@@ -502,7 +484,7 @@ def main():
     # timed value above runs without events).
     probed = {}
     for w in step_kinds:
-        if w in (1, 5, 6, 7, 8, 9):
+        if w in (1, 6, 7, 8):
             s.probe_begin(w, 4 * args.steps + 8)
             s.steps_cfl(U, dt, args.steps, cfl=case.cfl)
             torch.cuda.synchronize()
@@ -539,8 +521,8 @@ def main():
             bpf = BYTES_PER_FACE[(case.ndim, visc)]
             flops = fpf * nf
             if w == 6:
-                # inputs of one cell once (primitives and derivatives), the
-                # other directions' face fluxes, Un and Uin; Uout written
+                # inputs of one cell once (primitives), the other
+                # directions' face fluxes, Un and Uin; Uout written
                 cells = case.ncells
                 nbytes = cells * (bpf - 40) + 3 * cells * case.nv * 8
                 nbytes += sum(40 * faces_of(D) for D in range(case.ndim - 1))

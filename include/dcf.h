@@ -120,9 +120,9 @@ dcf_status dcf_state_info(const dcf_ctx *ctx, int *nv, long *ncell, size_t *stat
  * (rhs, rk3_step, dt, diagnostics, cost); mode 1 = adds vjp_step; mode 2 =
  * adds the trajectory gradient over exactly `nsteps` steps with checkpoints
  * every `seg_len` steps (dcf_gradient); mode 3 = as mode 2 and also keeps
- * the primitive and velocity-derivative boxes of every stage of a segment
- * from the forward recompute, so the reverse sweep recomputes nothing
- * (3 seg_len more boxes of memory; bitwise the same gradient).
+ * the primitive box of every stage of a segment from the forward recompute,
+ * so the reverse sweep recomputes nothing of the forward (3 seg_len more
+ * boxes of memory; bitwise the same gradient).
  * nsteps/seg_len are ignored below mode 2.  The library keeps the pointer
  * until the next call, clears the parts that must start at zero (the call
  * returns once that is done) and owns the contents from then on: the caller
@@ -340,20 +340,19 @@ dcf_status dcf_gradient(dcf_ctx *ctx, const double *U0_dev, int nsteps, const do
  * 2 and 4), 7 the x and y face fluxes of a 3D grid in one launch (the form
  * the step runs in place of 1 and 2), 8 the ghost cells of the primitive box
  * alone (stages 2 and 3 of such a step: the previous stage's update wrote
- * the interior), 9 the ghost cells and the velocity derivatives in one launch
- * (viscous boxes whose every face is periodic: the form such a step runs in
- * place of 8 and 5).  The inputs it needs (primitive box, derivatives, face
- * fluxes) are computed from U once before timing.  DCF_EINVAL for an unknown `which`
- * or one the case does not have. */
+ * the interior).  5 and 9 are not used: the flux kernels compute the
+ * cell-centred velocity derivatives while staging their tiles (no separate
+ * derivative launch).  The inputs it needs (primitive box, face fluxes) are
+ * computed from U once before timing.  DCF_EINVAL for an unknown `which` or
+ * one the case does not have. */
 dcf_status dcf_time_kernel(dcf_ctx *ctx, const double *U_dev, int which, int reps,
                            double *avg_ms, void *stream);
 
 /* Launch probe: while armed, every launch of kernel family `which` (the ids of
- * dcf_time_kernel: 1 x fluxes of a 2D step, 5 derivatives, 6 fused last-
- * direction flux + update, 7 x + y fluxes of a 3D step, 8 ghost fill of
- * stages after the first (with the carried CFL reduction where a step
- * follows another in one call), 9 joint ghost + derivative launch) that the
- * fused stepping calls (dcf_rk3_step,
+ * dcf_time_kernel: 1 x fluxes of a 2D step, 6 fused last-direction flux +
+ * update, 7 x + y fluxes of a 3D step, 8 ghost fill of stages after the
+ * first (with the carried CFL reduction where a step follows another in one
+ * call)) that the fused stepping calls (dcf_rk3_step,
  * dcf_rk3_step_cfl, dcf_rk3_steps_cfl) make is bracketed by a pair of HIP
  * events recorded on that call's stream, up to max_launches launches (later
  * ones are not recorded).  The events are created here and owned by the

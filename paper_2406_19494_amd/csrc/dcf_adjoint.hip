@@ -243,10 +243,14 @@ struct Tile {
   int lane_line, lane_face;
   long lg;      // line group of the tile
   bool line_ok;
+  bool valid;   // the workgroup has a tile
 };
 
+// P: the workgroup's index among the nb workgroups of direction D (the
+// hardware index modulo 8 must equal P modulo 8: the XCD order below assumes
+// it); t.valid is false for workgroups beyond the direction's tile count
 template <int OLO, int OHI, int D>
-__device__ __forceinline__ Tile make_tile(const Dev &g) {
+__device__ __forceinline__ Tile make_tile(const Dev &g, unsigned P, unsigned nb) {
   constexpr int TF = TileShape<D>::TF, TW = TileShape<D>::TW;
   constexpr int SPAN = OHI - OLO;
   constexpr int CPT = TF - SPAN;  // cells completed per tile line
@@ -260,10 +264,11 @@ __device__ __forceinline__ Tile make_tile(const Dev &g) {
   // the tiles along D of both, which share halo rows) run on one XCD, with
   // such chunks dealt round robin so that every XCD gets wall and free-stream
   // regions alike; x tiles keep the hardware order
-  long tile = D == 0 ? blockIdx.x : xcd_chunk_remap(blockIdx.x, gridDim.x, 2u * tiles_d);
+  long tile = D == 0 ? P : xcd_chunk_remap(P, nb, 2u * tiles_d);
   int td = (int)(tile % tiles_d);
   long lg = tile / tiles_d;  // line group
   Tile t;
+  t.valid = tile < (long)tiles_d * ((lines + TW - 1) / TW);
   const int tid = threadIdx.x;
   if (D == 0) {
     t.lane_face = tid % TF;
@@ -307,22 +312,46 @@ __host__ inline unsigned tile_count(const Dev &g, int D) {
 // Both share the face adjoint from Wb and one LDS window of cells
 // (f0-3 .. f0+TF+1 per line); the tile writes each completed cell once.
 // ---------------------------------------------------------------------------
-template <int NDIM, int D, bool VISC>
-__global__ void __launch_bounds__(256) k_dir_vjp(Dev g, AdjBuffers A) {
-  constexpr int OLO = -3, OHI = 2, NOFF = OHI - OLO + 1, SPAN = OHI - OLO;
-  constexpr int TF = TileShape<D>::TF, TW = TileShape<D>::TW;
-  constexpr int NCW = TF + SPAN;  // window cells per line
+// LDS of one tile: the accumulators (NCH channels x TW lines x NCW window
+// cells) and, along y and z, the staging rows of the convective gather.
+template <int NDIM, int D, bool VISC> struct DirLds {
+  static constexpr int TF = TileShape<D>::TF, TW = TileShape<D>::TW;
+  static constexpr int NOFF = 6, NCW = TF + 5;
+  static constexpr int CP = 1 + NDIM, CT = 2 + NDIM, CMU = 3 + NDIM, CG = 4 + NDIM;
+  static constexpr int NCH = VISC ? CG + 2 * (NDIM - 1) : CP + 1;
+  static constexpr int BF = D == 0 ? TF : TF + 4;
+  static constexpr int ACC = NCH * TW * NCW;
+  static constexpr int BUF = D == 0 ? 0 : NOFF * TW * BF;
+  static constexpr int SIZE = ACC + BUF;  // doubles
+};
+
+// One tile of direction D.  SIDE: the tile writes its completed cells' Qb
+// contributions to the side arrays Qby (set, never added) instead of adding
+// them to Qb, so that it can run concurrently with the x tiles that set Qb;
+// k_tangential_vjp (ghost cells) and k_interior_vjp (interior cells) add the
+// two.
+template <int NDIM, int D, bool VISC, bool SIDE>
+__device__ __forceinline__ void dir_vjp_tile(const Dev &g, const AdjBuffers &A, unsigned P,
+                                             unsigned nb, double *lds) {
+  using L = DirLds<NDIM, D, VISC>;
+  constexpr int OLO = -3, OHI = 2, NOFF = L::NOFF, SPAN = OHI - OLO;
+  constexpr int TF = L::TF, TW = L::TW;
+  constexpr int NCW = L::NCW;  // window cells per line
   constexpr int T1 = tan1(D), T2 = tan2(D);
-  // accumulator channels: rho, u, v, w, p (global velocity components), then
-  // T, mu, Gb(T1,T1), Gb(T1,D), Gb(T2,T2), Gb(T2,D) when viscous
-  constexpr int CT = 5, CMU = 6, CG = 7;
-  constexpr int NCH = VISC ? 11 : 5;
+  // accumulator channels, active axes only: rho, the NDIM global velocity
+  // components, p, then T, mu and Gb(T1,T1), Gb(T1,D) (Gb(T2,T2), Gb(T2,D))
+  // for each active tangential axis when viscous.  In 2D this is 8 channels,
+  // which keeps a y tile within a fifth of the CU's LDS (5 blocks per CU).
+  constexpr int CP = L::CP, CT = L::CT, CMU = L::CMU, CG = L::CG;
+  constexpr int NCH = L::NCH;
   // y/z tiles: a row stride of 36 doubles puts the 8 lines x 4 faces of a
   // half-wave on distinct LDS banks
-  constexpr int BF = D == 0 ? TF : TF + 4;
-  __shared__ double acc[NCH][TW][NCW];
-  __shared__ double buf[NOFF][TW][BF];  // one component's contributions per face
-  Tile t = make_tile<OLO, OHI, D>(g);
+  constexpr int BF = L::BF;
+  auto acc = reinterpret_cast<double (*)[TW][NCW]>(lds);
+  auto buf = reinterpret_cast<double (*)[TW][BF]>(lds + L::ACC);
+  static_assert(NCH * TW * NCW == L::ACC, "accumulator layout");
+  Tile t = make_tile<OLO, OHI, D>(g, P, nb);
+  if (!t.valid) return;  // uniform across the workgroup
   for (int i = threadIdx.x; i < NCH * TW * NCW; i += 256) (&acc[0][0][0])[i] = 0.0;
   // x tiles: each wavefront holds the 64 faces of one line and its lanes
   // are the only writers of that line's window, one lane per cell in the
@@ -333,7 +362,7 @@ __global__ void __launch_bounds__(256) k_dir_vjp(Dev g, AdjBuffers A) {
   const int f = t.f0 + t.lane_face;
   const bool active = t.line_ok && f >= 0 && f <= g.n[D];
   const int qi[5] = {QR, QU + D, QU + T1, QU + T2, QP};
-  constexpr int ch[5] = {0, 1 + D, 1 + T1, 1 + T2, 4};  // face frame -> channel
+  constexpr int ch[5] = {0, 1 + D, 1 + T1, 1 + T2, CP};  // face frame -> channel (active m)
   double qLb[5] = {0, 0, 0, 0, 0}, qRb[5] = {0, 0, 0, 0, 0};
   double Fb[5] = {0, 0, 0, 0, 0};
   long base = 0;
@@ -412,7 +441,7 @@ __global__ void __launch_bounds__(256) k_dir_vjp(Dev g, AdjBuffers A) {
     }
     __syncthreads();
   }
-  if (VISC) {
+  if constexpr (VISC) {
     // face-level adjoints of the dissipative flux
     double ufb[3] = {0, 0, 0}, dnb[3] = {0, 0, 0}, dTb = 0.0, mufb = 0.0;
     double divtb = 0.0, dtnb[3] = {0, 0, 0};
@@ -442,14 +471,18 @@ __global__ void __launch_bounds__(256) k_dir_vjp(Dev g, AdjBuffers A) {
       for (int r = 0; r < 2; ++r) {
         const int tt = r == 0 ? T1 : T2;
         if (tt >= NDIM) continue;
-        // cell-centred tangential derivatives of the recomputed stage (k_grad)
-        const double *Gtt = g.G[3 * tt + tt], *Gtn = g.G[3 * tt + D];
+        // cell-centred tangential derivatives d u_tt / d x_tt and d u_D /
+        // d x_tt of the stage's primitive box, with the operands and
+        // arithmetic of the forward flux kernels (the same values bitwise)
+        const double *Ut = g.Q[QU + tt], *Ud = g.Q[QU + D];
+        const long stt = g.sb[tt];
+        const double mct = g.mc[tt][t.line[tt]];
         double gtt[4], gtn[4];
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
           long cb = base + (o - 2) * s;
-          gtt[o] = Gtt[cb];
-          gtn[o] = Gtn[cb];
+          gtt[o] = dcell4(Ut[cb - 2 * stt], Ut[cb - stt], Ut[cb + stt], Ut[cb + 2 * stt]) * mct;
+          gtn[o] = dcell4(Ud[cb - 2 * stt], Ud[cb - stt], Ud[cb + stt], Ud[cb + 2 * stt]) * mct;
         }
         divt += interp4(gtt[0], gtt[1], gtt[2], gtt[3]);
         dtn[tt] = interp4(gtn[0], gtn[1], gtn[2], gtn[3]);
@@ -497,11 +530,11 @@ __global__ void __launch_bounds__(256) k_dir_vjp(Dev g, AdjBuffers A) {
         for (int c = 0; c < NDIM; ++c) acc[1 + c][ll][w] += ufb[c] * im + dnb[c] * dm;
         acc[CT][ll][w] += dTb * dm;
         acc[CMU][ll][w] += mufb * im;
-        if (T1 < NDIM) {
+        if constexpr (T1 < NDIM) {
           acc[CG][ll][w] += divtb * im;
           acc[CG + 1][ll][w] += dtnb[T1] * im;
         }
-        if (T2 < NDIM) {
+        if constexpr (T2 < NDIM) {
           acc[CG + 2][ll][w] += divtb * im;
           acc[CG + 3][ll][w] += dtnb[T2] * im;
         }
@@ -526,36 +559,51 @@ __global__ void __launch_bounds__(256) k_dir_vjp(Dev g, AdjBuffers A) {
     p[T2] = (int)(ln / g.n[T1]);
     const long b = bidx(g, p[0], p[1], p[2]);
     const bool ghost = cell < 0 || cell >= g.n[D];
-    if (D == 0 || ghost) {
+    if constexpr (SIDE) {
+      A.Qby[QR][b] = acc[0][ll][w];
+#pragma unroll
+      for (int c = 0; c < NDIM; ++c) A.Qby[QU + c][b] = acc[1 + c][ll][w];
+      A.Qby[QP][b] = acc[CP][ll][w];
+      if constexpr (VISC) {
+        A.Qby[QT][b] = acc[CT][ll][w];
+        A.Qby[QMU][b] = acc[CMU][ll][w];
+      } else {
+        A.Qby[QT][b] = 0.0;
+      }
+    } else if (D == 0 || ghost) {
       // first writer of this cell in the stage: set every component the
       // later kernels accumulate into
       A.Qb[QR][b] = acc[0][ll][w];
 #pragma unroll
       for (int c = 0; c < NDIM; ++c) A.Qb[QU + c][b] = acc[1 + c][ll][w];
-      A.Qb[QP][b] = acc[4][ll][w];
-      A.Qb[QT][b] = VISC ? acc[CT][ll][w] : 0.0;
-      if (VISC) A.Qb[QMU][b] = acc[CMU][ll][w];
+      A.Qb[QP][b] = acc[CP][ll][w];
+      if constexpr (VISC) {
+        A.Qb[QT][b] = acc[CT][ll][w];
+        A.Qb[QMU][b] = acc[CMU][ll][w];
+      } else {
+        A.Qb[QT][b] = 0.0;
+      }
     } else {
       A.Qb[QR][b] += acc[0][ll][w];
 #pragma unroll
       for (int c = 0; c < NDIM; ++c) A.Qb[QU + c][b] += acc[1 + c][ll][w];
-      A.Qb[QP][b] += acc[4][ll][w];
-      if (VISC) {
+      A.Qb[QP][b] += acc[CP][ll][w];
+      if constexpr (VISC) {
         A.Qb[QT][b] += acc[CT][ll][w];
         A.Qb[QMU][b] += acc[CMU][ll][w];
       }
     }
-    if (VISC) {
+    if constexpr (VISC) {
       // derivative adjoints: d u_D / d x_t is this kernel's alone (set); the
       // diagonal d u_t / d x_t is shared with the kernel of every earlier
       // direction other than t, which covered the cells interior along D
       constexpr bool sh1 = D >= 2 || (D == 1 && T1 != 0), sh2 = D >= 2 || (D == 1 && T2 != 0);
-      if (T1 < NDIM) {
+      if constexpr (T1 < NDIM) {
         double &d1 = A.Gb[3 * T1 + T1][b];
         d1 = (sh1 && !ghost ? d1 : 0.0) + acc[CG][ll][w];
         A.Gb[3 * T1 + D][b] = acc[CG + 1][ll][w];
       }
-      if (T2 < NDIM) {
+      if constexpr (T2 < NDIM) {
         double &d2 = A.Gb[3 * T2 + T2][b];
         d2 = (sh2 && !ghost ? d2 : 0.0) + acc[CG + 2][ll][w];
         A.Gb[3 * T2 + D][b] = acc[CG + 3][ll][w];
@@ -564,9 +612,46 @@ __global__ void __launch_bounds__(256) k_dir_vjp(Dev g, AdjBuffers A) {
   }
 }
 
+// One direction per launch (1D, 3D).
+template <int NDIM, int D, bool VISC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NDIM == 2 ? 5 : 4)))
+k_dir_vjp(Dev g, AdjBuffers A) {
+  __shared__ double lds[DirLds<NDIM, D, VISC>::SIZE];
+  dir_vjp_tile<NDIM, D, VISC, false>(g, A, blockIdx.x, gridDim.x, lds);
+}
+
+// 2D: the x and y tiles of a stage in one launch, so that the two directions'
+// tiles share the CUs (each alone leaves the FP64 units idle while its
+// workgroups wait on memory).  Workgroups are dealt in groups of 8, x and y
+// alternating while both have tiles left: group c of a direction holds its
+// tiles 8c .. 8c+7, so that a tile's index modulo 8 is its hardware index
+// modulo 8 (its XCD) as in a launch of its own.  The y tiles write their cell
+// contributions to Qby; the x tiles set Qb.
+template <bool VISC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+k_dir_vjp_xy(Dev g, AdjBuffers A, unsigned nx, unsigned ny) {
+  constexpr int SX = DirLds<2, 0, VISC>::SIZE, SY = DirLds<2, 1, VISC>::SIZE;
+  __shared__ double lds[SX > SY ? SX : SY];
+  const unsigned grp = blockIdx.x / 8u, r = blockIdx.x % 8u;
+  const unsigned cx = (nx + 7u) / 8u, cy = (ny + 7u) / 8u, cm = cx < cy ? cx : cy;
+  unsigned dir, ci;
+  if (grp < 2u * cm) {
+    dir = grp % 2u;
+    ci = grp / 2u;
+  } else {
+    dir = cx > cy ? 0u : 1u;
+    ci = grp - cm;
+  }
+  const unsigned P = ci * 8u + r;
+  if (dir == 0u) dir_vjp_tile<2, 0, VISC, false>(g, A, P, 8u * cx, lds);
+  else dir_vjp_tile<2, 1, VISC, true>(g, A, P, 8u * cy, lds);
+}
+
 // ---------------------------------------------------------------------------
 // Gather of the tangential-derivative adjoints (transpose of the
-// cell-centred 4th-order difference along t), then mu'(T) folding.
+// cell-centred 4th-order difference along t), then mu'(T) folding: on the
+// ghost cells in a launch of their own (the halo transposes read them), on
+// the interior cells inside k_interior_vjp.
 // ---------------------------------------------------------------------------
 // d mu / dT from T and mu(T): omega mu / T (power law), mu (1.5/t - 1/(t+s))
 // / T_ref with t = T/T_ref, s = S/T_ref (Sutherland).
@@ -580,69 +665,167 @@ __device__ __forceinline__ double dviscosity(const Dev &g, double T, double mu) 
   return 0.0;
 }
 
-__global__ void __launch_bounds__(256) k_tangential_vjp(Dev g, AdjBuffers A) {
-  const unsigned bl = blockIdx.x * blockDim.x + threadIdx.x;  // nbox < 2^32
-  if (bl >= (unsigned)g.nbox) return;
-  const unsigned N0 = g.N[0], N01 = N0 * (unsigned)g.N[1];
-  int p[3];
-  p[0] = (int)(bl % N0) - g.h[0];
-  p[1] = (int)((bl % N01) / N0) - g.h[1];
-  p[2] = (int)(bl / N01) - g.h[2];
-  const long b = bidx(g, p[0], p[1], p[2]);
-  const int nd = g.ndim;
-  if (A.Gb[0] != nullptr) {
-    for (int phi = 0; phi < nd; ++phi) {
-      double add = 0.0;
-      for (int t = 0; t < nd; ++t) {
-        const double *G = A.Gb[3 * t + phi];
-        const long st = g.sb[t];
-        // y = x + k along t contributes coef(k) * mc(y) * G(y)
-        const int ks[4] = {-1, 1, -2, 2};
-        const double cf[4] = {8.0 / 12.0, -8.0 / 12.0, -1.0 / 12.0, 1.0 / 12.0};
-        for (int r = 0; r < 4; ++r) {
-          int yt = p[t] + ks[r];
-          if (yt < 0 || yt >= g.n[t]) continue;
-          add += cf[r] * g.mc[t][yt] * G[b + ks[r] * st];
-        }
-      }
-      A.Qb[QU + phi][b] += add;
+// Gather of the tangential-derivative adjoints at box cell p: y = x + k along
+// t contributes coef(k) mc(y) Gb(y); the metric factors of the (at most
+// four) neighbours along each axis are shared by the NDIM velocity components.
+template <int NDIM>
+__device__ __forceinline__ void tangential_gather(const Dev &g, const AdjBuffers &A, const int *p,
+                                                  long b, double *add) {
+  constexpr int ks[4] = {-1, 1, -2, 2};
+  constexpr double cf[4] = {8.0 / 12.0, -8.0 / 12.0, -1.0 / 12.0, 1.0 / 12.0};
+#pragma unroll
+  for (int phi = 0; phi < NDIM; ++phi) add[phi] = 0.0;
+#pragma unroll
+  for (int t = 0; t < NDIM; ++t) {
+    const long st = g.sb[t];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int yt = p[t] + ks[r];
+      if (yt < 0 || yt >= g.n[t]) continue;
+      const double w = cf[r] * g.mc[t][yt];
+#pragma unroll
+      for (int phi = 0; phi < NDIM; ++phi) add[phi] += w * A.Gb[3 * t + phi][b + ks[r] * st];
     }
+  }
+}
+
+// Adjoint components carried through the halo fill: rho, the active
+// velocities, p, T (mu-bar is folded into T-bar first).
+template <int NDIM> struct HaloQ {
+  static constexpr int nq = NDIM + 3;
+  static constexpr int qs[6] = {QR, QU, NDIM >= 2 ? QV : QP,
+                                NDIM == 3 ? QW : (NDIM == 2 ? QP : QT), NDIM == 3 ? QP : QT, QT};
+};
+
+// Ghost cell number t (0 <= t < nbox - ncell) -> its box position: the z
+// ghost planes, then the y ghost rows of the interior planes, then the x
+// ghost cells of the interior rows (x fastest within each part).
+__device__ __forceinline__ void ghost_cell(const Dev &g, long t, int *p) {
+  const long N0 = g.N[0], N1 = g.N[1];
+  const int h0 = g.h[0], h1 = g.h[1], h2 = g.h[2];
+  const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+  const long cz = 2L * h2 * N0 * N1;
+  if (t < cz) {
+    const long pl = t / (N0 * N1), rem = t % (N0 * N1);
+    p[2] = pl < h2 ? (int)pl - h2 : n2 + (int)pl - h2;
+    p[1] = (int)(rem / N0) - h1;
+    p[0] = (int)(rem % N0) - h0;
+    return;
+  }
+  t -= cz;
+  const long cy = 2L * h1 * N0 * n2;
+  if (t < cy) {
+    const long row = t / N0;
+    const int rr = (int)(row % (2 * h1));
+    p[2] = (int)(row / (2 * h1));
+    p[1] = rr < h1 ? rr - h1 : n1 + rr - h1;
+    p[0] = (int)(t % N0) - h0;
+    return;
+  }
+  t -= cy;
+  const int c = (int)(t % (2 * h0));
+  const long line = t / (2 * h0);
+  p[2] = (int)(line / n1);
+  p[1] = (int)(line % n1);
+  p[0] = c < h0 ? c - h0 : n0 + c - h0;
+}
+
+// Ghost cells, before the halo transposes read them: the y tiles' side
+// arrays (2D; on the y ghosts interior along x, which no x tile writes, they
+// are the whole value), the tangential gather, and mu'(T) folded into T.
+// Interior cells take the same three steps in k_interior_vjp.
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_tangential_vjp(Dev g, AdjBuffers A) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.nbox - g.ncell) return;
+  int p[3];
+  ghost_cell(g, t, p);
+  const long b = bidx(g, p[0], p[1], p[2]);
+  if constexpr (NDIM == 2) {
+    if (p[0] >= 0 && p[0] < g.n[0]) {  // a y ghost (x ghosts: x tiles only)
+#pragma unroll
+      for (int i = 0; i < HaloQ<2>::nq; ++i) {
+        const int q = HaloQ<2>::qs[i];
+        A.Qb[q][b] = 0.0 + A.Qby[q][b];
+      }
+      if (g.visc != VISC_NONE) A.Qb[QMU][b] = 0.0 + A.Qby[QMU][b];
+    }
+  }
+  if (NDIM >= 2 && A.Gb[0] != nullptr) {
+    double add[NDIM];
+    tangential_gather<NDIM>(g, A, p, b, add);
+#pragma unroll
+    for (int phi = 0; phi < NDIM; ++phi) A.Qb[QU + phi][b] += add[phi];
   }
   if (g.visc != VISC_NONE) A.Qb[QT][b] += dviscosity(g, g.Q[QT][b], g.Q[QMU][b]) * A.Qb[QMU][b];
 }
 
-// ---------------------------------------------------------------------------
-// Transpose of the halo fill along axis d: one thread per column (both
-// sides, all three layers), folding ghost adjoints into their sources.
-// ---------------------------------------------------------------------------
+// Source cell of ghost layer m (0 nearest the face) on side `side` of an axis
+// of n cells: the cell the forward halo fill copies (and mirrors) into it.
+__device__ __forceinline__ int halo_source(int kind, int side, int m, int n) {
+  if (kind == BC_PERIODIC) return side == 0 ? n - 1 - m : m;
+  if (kind == BC_ZEROGRAD) return side == 0 ? 0 : n - 1;
+  return side == 0 ? m : n - 1 - m;
+}
+
+// A ghost adjoint mapped to its contribution to the source: copies pass
+// through; walls: p_g = p_s, u_g = -u_s (plus a prescribed normal part that
+// depends on the state only through the porous p_w, taken separately);
+// isothermal: rho_g = p_g / (R T_g), T_g = 2 T_w - T_s; adiabatic:
+// rho_g = rho_s, T_g = T_s.  rg, pg: the ghost's density and pressure.
 template <int NDIM>
-__global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, double *dJdK) {
-  constexpr int nd = NDIM;
+__device__ __forceinline__ void ghost_transform(const Dev &g, bool wall, bool iso,
+                                                const double *gbm, double rg, double pg,
+                                                double *cs) {
+  constexpr int nq = HaloQ<NDIM>::nq, iP = nq - 2, iT = nq - 1;
+#pragma unroll
+  for (int i = 0; i < nq; ++i) cs[i] = gbm[i];
+  if (!wall) return;
+#pragma unroll
+  for (int c = 0; c < NDIM; ++c) cs[1 + c] = -gbm[1 + c];
+  if (iso) {
+    const double rb = gbm[0];
+    cs[0] = 0.0;
+    cs[iP] = gbm[iP] + rb * rg / pg;
+    cs[iT] = -(gbm[iT] - rb * rg * rg * g.R / pg);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Transpose of the halo fill along axis d, folding ghost adjoints (complete
+// after k_tangential_vjp) into their sources, axes in the order z, y, x.
+// When the two sides' sources cannot coincide (n >= 6) a thread takes one
+// ghost layer of one side of a column (its ghost and its source are its own
+// cells); the zero-gradient copy (three layers, one source) and the porous /
+// disturbance terms (which sum the three layers' normal-velocity adjoints)
+// are taken by the layer-0 thread.  Short axes (n < 6) keep one thread per
+// column doing both sides and every layer in turn.
+// ---------------------------------------------------------------------------
+__host__ inline long halo_vjp_threads(const Dev &g, int d) {
+  const int t1 = tan1(d), t2 = tan2(d);
+  const long n1 = t1 < d ? g.N[t1] : g.n[t1];
+  const long n2 = t2 < d ? g.N[t2] : g.n[t2];
+  return (g.n[d] >= 6 ? 6 : 1) * n1 * n2;
+}
+
+template <int NDIM>
+__global__ void __launch_bounds__(64) k_halo_vjp(Dev g, AdjBuffers A, int d, double *dJdK) {
+  using H = HaloQ<NDIM>;
+  constexpr int nq = H::nq, iP = nq - 2;
   const int t1 = tan1(d), t2 = tan2(d);
   int lo1 = 0, n1 = g.n[t1], lo2 = 0, n2 = g.n[t2];
   if (t1 < d) { lo1 = -g.h[t1]; n1 = g.N[t1]; }
   if (t2 < d) { lo2 = -g.h[t2]; n2 = g.N[t2]; }
-  // one thread per column and side when the two sides' source cells cannot
-  // coincide (n >= 6), else one thread per column doing both sides in turn
   const long ncol = (long)n1 * n2;
   const bool split = g.n[d] >= 6;
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= (split ? 2 : 1) * ncol) return;
+  if (tid >= (split ? 6 : 1) * ncol) return;
+  // thread -> (column, side, layer): columns fastest, then side, then layer
   const long col = split ? tid % ncol : tid;
-  const int side_lo = split ? (int)(tid / ncol) : 0, side_hi = split ? side_lo + 1 : 2;
+  const int r = split ? (int)(tid / ncol) : 0;
+  const int side_lo = split ? r % 2 : 0, side_hi = split ? side_lo + 1 : 2;
+  const int mlo = split ? r / 2 : 0, mhi = split ? mlo + 1 : 3;
   const int a = lo1 + (int)(col % n1), bq = lo2 + (int)(col / n1);
-  auto box = [&](int s) {
-    int p[3];
-    p[d] = s;
-    p[t1] = a;
-    p[t2] = bq;
-    return bidx(g, p[0], p[1], p[2]);
-  };
-  // adjoint components carried through the halo fill: rho, active
-  // velocities, p, T (mu-bar was folded into T-bar before)
-  constexpr int nq = NDIM + 3;
-  constexpr int qs[6] = {QR, QU, NDIM >= 2 ? QV : QP, NDIM == 3 ? QW : (NDIM == 2 ? QP : QT),
-                         NDIM == 3 ? QP : QT, QT};
   const int n = g.n[d];
   // ghost cells of this column that are ghosts along another axis too (edges
   // and corners of the box) are written only by the tangential-derivative
@@ -653,54 +836,78 @@ __global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, do
   for (int side = side_lo; side < side_hi; ++side) {
     const int face = 2 * d + side;
     const int kind = g.bck[face];
+    const bool merged = kind == BC_ZEROGRAD;  // every layer copies one cell
+    const bool distinct = !merged && n >= 3;  // three distinct sources
+    // layers of this side that this thread folds
+    int m0 = mlo, m1 = mhi;
+    if (!distinct && kind != BC_DIRICHLET) {
+      if (m0 > 0) continue;  // the layer-0 thread folds the whole column
+      m1 = 3;
+    }
+    auto mine = [&](int m) { return m >= m0 && m < m1; };
+    int pG[3][3];
+    long G[3], S[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const int gd = side == 0 ? -1 - m : n + m, sd = halo_source(kind, side, m, n);
+      int ps[3];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {  // no dynamic register index
+        pG[m][e] = e == d ? gd : (e == t1 ? a : bq);
+        ps[e] = e == d ? sd : pG[m][e];
+      }
+      G[m] = bidx(g, pG[m][0], pG[m][1], pG[m][2]);
+      S[m] = bidx(g, ps[0], ps[1], ps[2]);
+    }
     if (kind == BC_DIRICHLET) {  // ghost adjoints discarded
       if (edge)
 #pragma unroll
         for (int m = 0; m < 3; ++m)
+          if (mine(m))
 #pragma unroll
-          for (int i = 0; i < nq; ++i) A.Qb[qs[i]][box(side == 0 ? -1 - m : n + m)] = 0.0;
+            for (int i = 0; i < nq; ++i) A.Qb[H::qs[i]][G[m]] = 0.0;
       continue;
     }
     const double sigma = side == 0 ? 1.0 : -1.0;
-    long G[3], S[3];
-    for (int m = 0; m < 3; ++m) {
-      G[m] = box(side == 0 ? -1 - m : n + m);
-      int src;
-      if (kind == BC_PERIODIC) src = side == 0 ? n - 1 - m : m;
-      else if (kind == BC_ZEROGRAD) src = side == 0 ? 0 : n - 1;
-      else src = side == 0 ? m : n - 1 - m;
-      S[m] = box(src);
-    }
     const bool wall = is_wall(kind);
     const bool iso = wall && g.Tw[face] > 0.0;
+    // porous and disturbance columns are never edge columns, so the layer-0
+    // thread reads the other layers' ghosts while no thread clears them
     const bool porous = kind == BC_POROUS && face == g.pface && a >= g.pb && a < g.pe &&
-                        bq >= 0 && bq < g.n[t2];
-    const bool disturb = kind == BC_DISTURB && dJdK && a >= 0 && a < g.n[t1];
-    const bool merged = kind == BC_ZEROGRAD;  // every layer copies one cell
-    const bool distinct = !merged && n >= 3;  // three distinct sources
-    // every load of the column first (one round trip): ghost adjoints,
-    // source adjoints, ghost states (isothermal wall), wall pressure and
-    // coefficient (porous), position and parameters (disturbance)
-    double gb[3][6], sv[3][6] = {}, rg[3] = {}, pg[3] = {};
+                        bq >= 0 && bq < g.n[t2] && m0 == 0;
+    const bool disturb = kind == BC_DISTURB && dJdK && a >= 0 && a < g.n[t1] && m0 == 0;
+    const bool allgn = porous || disturb;  // needs every layer's normal-velocity adjoint
+    double gb[3][6] = {}, sv[3][6] = {}, rg[3] = {}, pg[3] = {}, gn[3] = {};
 #pragma unroll
-    for (int m = 0; m < 3; ++m)
+    for (int m = 0; m < 3; ++m) {
+      if (mine(m)) {
 #pragma unroll
-      for (int i = 0; i < nq; ++i) gb[m][i] = A.Qb[qs[i]][G[m]];
+        for (int i = 0; i < nq; ++i) gb[m][i] = A.Qb[H::qs[i]][G[m]];
+        gn[m] = gb[m][1];  // gb[m][1 + d], without a dynamic register index
+#pragma unroll
+        for (int c = 1; c < NDIM; ++c)
+          if (c == d) gn[m] = gb[m][1 + c];
+      } else if (allgn) {
+        gn[m] = A.Qb[QU + d][G[m]];
+      }
+    }
     if (merged) {
 #pragma unroll
-      for (int i = 0; i < nq; ++i) sv[0][i] = A.Qb[qs[i]][S[0]];
+      for (int i = 0; i < nq; ++i) sv[0][i] = A.Qb[H::qs[i]][S[0]];
     } else if (distinct) {
 #pragma unroll
       for (int m = 0; m < 3; ++m)
+        if (mine(m))
 #pragma unroll
-        for (int i = 0; i < nq; ++i) sv[m][i] = A.Qb[qs[i]][S[m]];
+          for (int i = 0; i < nq; ++i) sv[m][i] = A.Qb[H::qs[i]][S[m]];
     }
     if (iso) {
 #pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        rg[m] = g.Q[QR][G[m]];
-        pg[m] = g.Q[QP][G[m]];
-      }
+      for (int m = 0; m < 3; ++m)
+        if (mine(m)) {
+          rg[m] = g.Q[QR][G[m]];
+          pg[m] = g.Q[QP][G[m]];
+        }
     }
     int kk = 0;
     double pw = 0.0, Kk = 0.0, kb0 = 0.0;
@@ -716,33 +923,12 @@ __global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, do
       th0 = g.K[g.doff[face]];
       th1 = g.K[g.doff[face] + 1];
     }
-    // ghost adjoints mapped to contributions to their sources: copies pass
-    // through; walls: p_g = p_s, u_g = -u_s (plus a prescribed normal part
-    // that depends on the state only through the porous p_w below);
-    // isothermal: rho_g = p_g/(R T_g), T_g = 2 T_w - T_s; adiabatic:
-    // rho_g = rho_s, T_g = T_s
-    constexpr int iP = nq - 2, iT = nq - 1;
-    double cs[3][6];
+    double cs[3][6] = {};
     double vsum = 0.0;  // sum over the column's ghosts of the normal-velocity adjoint
-    double gn[3];       // the normal-velocity adjoint of each ghost layer
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      gn[m] = gb[m][1];
-#pragma unroll
-      for (int c = 1; c < nd; ++c)
-        if (c == d) gn[m] = gb[m][1 + c];
-#pragma unroll
-      for (int i = 0; i < nq; ++i) cs[m][i] = gb[m][i];
-      if (!wall) continue;
-#pragma unroll
-      for (int c = 0; c < nd; ++c) cs[m][1 + c] = -gb[m][1 + c];
-      if (iso) {
-        const double rb = gb[m][0];
-        cs[m][0] = 0.0;
-        cs[m][iP] = gb[m][iP] + rb * rg[m] / pg[m];
-        cs[m][iT] = -(gb[m][iT] - rb * rg[m] * rg[m] * g.R / pg[m]);
-      }
-      vsum += gn[m];
+      if (wall) vsum += gn[m];
+      if (mine(m)) ghost_transform<NDIM>(g, wall, iso, gb[m], rg[m], pg[m], cs[m]);
     }
     if (porous) {
       // v_g[d] = 2 sigma v_n - v_s[d], v_n = -K (p_w - p_inf)/p_inf; the
@@ -759,24 +945,27 @@ __global__ void __launch_bounds__(256) k_halo_vjp(Dev g, AdjBuffers A, int d, do
     if (edge)
 #pragma unroll
       for (int m = 0; m < 3; ++m)
+        if (mine(m))
 #pragma unroll
-        for (int i = 0; i < nq; ++i) A.Qb[qs[i]][G[m]] = 0.0;
+          for (int i = 0; i < nq; ++i) A.Qb[H::qs[i]][G[m]] = 0.0;
     // fold into the sources
     if (merged) {
 #pragma unroll
-      for (int i = 0; i < nq; ++i) A.Qb[qs[i]][S[0]] = sv[0][i] + ((cs[0][i] + cs[1][i]) + cs[2][i]);
+      for (int i = 0; i < nq; ++i)
+        A.Qb[H::qs[i]][S[0]] = sv[0][i] + ((cs[0][i] + cs[1][i]) + cs[2][i]);
     } else if (distinct) {
 #pragma unroll
       for (int m = 0; m < 3; ++m)
+        if (mine(m))
 #pragma unroll
-        for (int i = 0; i < nq; ++i) A.Qb[qs[i]][S[m]] = sv[m][i] + cs[m][i];
+          for (int i = 0; i < nq; ++i) A.Qb[H::qs[i]][S[m]] = sv[m][i] + cs[m][i];
     } else {  // n < 3: sources may repeat, accumulate layer by layer
 #pragma unroll
       for (int m = 0; m < 3; ++m)
 #pragma unroll
-        for (int i = 0; i < nq; ++i) A.Qb[qs[i]][S[m]] += cs[m][i];
+        for (int i = 0; i < nq; ++i) A.Qb[H::qs[i]][S[m]] += cs[m][i];
     }
-    if (kind == BC_DISTURB && dJdK) {
+    if (kind == BC_DISTURB && dJdK && m0 == 0) {
       // v_g[d] = 2 sigma A sin(phi) - v_s[d], phi = 2 pi kappa x: per-column
       // partials of dJ/dA and dJ/dkappa, summed over columns by k_disturb_sum
       double dA = 0.0, dk = 0.0;
@@ -822,18 +1011,42 @@ __global__ void __launch_bounds__(256) k_disturb_sum(const double *part, long co
 // acc_out = acc_in + a Wb (the Un adjoint accumulator); with fold != 0 the
 // accumulator is added into Vb instead (last stage, V = Un).
 // ---------------------------------------------------------------------------
+template <int NDIM>
 __global__ void __launch_bounds__(256) k_interior_vjp(Dev g, AdjBuffers A, const double *V,
                                                       const double *Wb, double a, double b,
                                                       double *Vb, const double *acc_in,
                                                       double *acc_out, int fold) {
+  constexpr int nd = NDIM;
   const unsigned cu = blockIdx.x * blockDim.x + threadIdx.x;  // ncell < 2^31
   if (cu >= (unsigned)g.ncell) return;
   const long c = cu;
   const long nc = g.ncell;
-  const int nd = g.ndim;
   const unsigned n0 = g.n[0], n01 = n0 * (unsigned)g.n[1];
   const int k = (int)(cu / n01), j = (int)((cu % n01) / n0), i = (int)(cu % n0);
   const long bx = bidx(g, i, j, k);
+  // the primitive adjoint of the cell: the flux adjoints' (x tiles plus, in
+  // 2D, the y tiles' side arrays) with the halo transposes' contributions,
+  // the tangential gather, and mu'(T) folded into T
+  double rb = A.Qb[QR][bx], pb = A.Qb[QP][bx], Tb = A.Qb[QT][bx];
+  double ub[3] = {A.Qb[QU][bx], nd >= 2 ? A.Qb[QV][bx] : 0.0, nd >= 3 ? A.Qb[QW][bx] : 0.0};
+  const bool visc = g.visc != VISC_NONE;
+  double mub = visc ? A.Qb[QMU][bx] : 0.0;
+  if constexpr (NDIM == 2) {
+    rb += A.Qby[QR][bx];
+    ub[0] += A.Qby[QU][bx];
+    ub[1] += A.Qby[QV][bx];
+    pb += A.Qby[QP][bx];
+    Tb += A.Qby[QT][bx];
+    if (visc) mub += A.Qby[QMU][bx];
+  }
+  if (NDIM >= 2 && A.Gb[0] != nullptr) {
+    const int pc[3] = {i, j, k};
+    double add[NDIM];
+    tangential_gather<NDIM>(g, A, pc, bx, add);
+#pragma unroll
+    for (int phi = 0; phi < NDIM; ++phi) ub[phi] += add[phi];
+  }
+  if (visc) Tb += dviscosity(g, g.Q[QT][bx], g.Q[QMU][bx]) * mub;
   double rho = V[c];
   double ir = 1.0 / rho;
   double u[3] = {V[nc + c] * ir, nd >= 2 ? V[2 * nc + c] * ir : 0.0,
@@ -842,18 +1055,18 @@ __global__ void __launch_bounds__(256) k_interior_vjp(Dev g, AdjBuffers A, const
   double k2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   double p = (g.gamma - 1.0) * (E - 0.5 * rho * k2);
   double T = p / (rho * g.R);
-  double rb = A.Qb[QR][bx], pb = A.Qb[QP][bx], Tb = A.Qb[QT][bx];
-  double ub[3] = {A.Qb[QU][bx], nd >= 2 ? A.Qb[QV][bx] : 0.0, nd >= 3 ? A.Qb[QW][bx] : 0.0};
   pb += Tb / (rho * g.R);
   rb -= Tb * T * ir;
   const double gm1 = g.gamma - 1.0;
   double Ub[5];
   Ub[0] = rb + gm1 * 0.5 * k2 * pb;
+#pragma unroll
   for (int d = 0; d < nd; ++d) {
     Ub[1 + d] = ub[d] * ir - gm1 * u[d] * pb;
     Ub[0] -= ub[d] * u[d] * ir;
   }
   Ub[nd + 1] = gm1 * pb;
+#pragma unroll
   for (int v = 0; v < nd + 2; ++v) {
     const long x = (long)v * nc + c;
     double w = Wb[x];
@@ -875,10 +1088,6 @@ using AdjKernel = void (*)(Dev, AdjBuffers);
 
 static AdjKernel dir_kernel(int nd, int D, bool visc) {
   if (nd == 1) return visc ? k_dir_vjp<1, 0, true> : k_dir_vjp<1, 0, false>;
-  if (nd == 2) {
-    if (D == 0) return visc ? k_dir_vjp<2, 0, true> : k_dir_vjp<2, 0, false>;
-    return visc ? k_dir_vjp<2, 1, true> : k_dir_vjp<2, 1, false>;
-  }
   if (D == 0) return visc ? k_dir_vjp<3, 0, true> : k_dir_vjp<3, 0, false>;
   if (D == 1) return visc ? k_dir_vjp<3, 1, true> : k_dir_vjp<3, 1, false>;
   return visc ? k_dir_vjp<3, 2, true> : k_dir_vjp<3, 2, false>;
@@ -891,6 +1100,23 @@ static inline unsigned blocks(long n) { return (unsigned)((n + 255) / 256 > 0 ? 
     hipError_t e_ = (x);              \
     if (e_ != hipSuccess) return e_;  \
   } while (0)
+
+// dJ/d(A, kappa) of the disturbance faces of axis d from the per-column
+// partials its halo transpose wrote.
+static hipError_t disturb_sums(const Dev &g, const AdjBuffers &A, int d, double *dJdK,
+                               hipStream_t st) {
+  if (!dJdK) return hipSuccess;
+  const int t1 = tan1(d), t2 = tan2(d);
+  const long n1 = t1 < d ? g.N[t1] : g.n[t1];
+  const long n2 = t2 < d ? g.N[t2] : g.n[t2];
+  for (int side = 0; side < 2; ++side) {
+    const int face = 2 * d + side;
+    if (g.bck[face] != BC_DISTURB) continue;
+    k_disturb_sum<<<1, 256, 0, st>>>(A.dpart + 2 * side * A.dcols, n1 * n2, dJdK + g.doff[face]);
+    DCF_TRY(hipGetLastError());
+  }
+  return hipSuccess;
+}
 
 // Reverse of one stage: Vb = b Wb + R'(V)^T (b dt Wb), accumulators as in
 // k_interior_vjp.  Needs g.Q to hold nothing on entry (recomputed here), and
@@ -905,35 +1131,36 @@ static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A0, const double *V,
   A.Wb = Wb;
   A.dtp = dt;
   A.bcoef = b;
-  if (!have_box) {  // the stage's primitive and derivative boxes
-    DCF_TRY(launch_prim_halo(g, V, st));
-    if (visc && g.ndim >= 2) DCF_TRY(launch_grad(g, st));
-  }
-  for (int D = 0; D < g.ndim; ++D) {
-    hipLaunchKernelGGL(dir_kernel(g.ndim, D, visc), dim3(tile_count<-3, 2>(g, D)), dim3(256), 0,
-                       st, g, A);
+  if (!have_box) DCF_TRY(launch_prim_halo(g, V, st));  // the stage's primitive box
+  if (g.ndim == 2) {
+    const unsigned nx = tile_count<-3, 2>(g, 0), ny = tile_count<-3, 2>(g, 1);
+    const unsigned nblk = 8u * ((nx + 7u) / 8u + (ny + 7u) / 8u);
+    auto k = visc ? k_dir_vjp_xy<true> : k_dir_vjp_xy<false>;
+    k<<<nblk, 256, 0, st>>>(g, A, nx, ny);
     DCF_TRY(hipGetLastError());
-  }
-  if (visc) {
-    k_tangential_vjp<<<blocks(g.nbox), 256, 0, st>>>(g, A);
-    DCF_TRY(hipGetLastError());
-  }
-  for (int d = g.ndim - 1; d >= 0; --d) {
-    const int t1 = tan1(d), t2 = tan2(d);
-    long n1 = t1 < d ? g.N[t1] : g.n[t1];
-    long n2 = t2 < d ? g.N[t2] : g.n[t2];
-    auto hk = g.ndim == 1 ? k_halo_vjp<1> : (g.ndim == 2 ? k_halo_vjp<2> : k_halo_vjp<3>);
-    hk<<<blocks((g.n[d] >= 6 ? 2 : 1) * n1 * n2), 256, 0, st>>>(g, A, d, dJdK);
-    DCF_TRY(hipGetLastError());
-    for (int side = 0; side < 2 && dJdK; ++side) {
-      const int face = 2 * d + side;
-      if (g.bck[face] != BC_DISTURB) continue;
-      k_disturb_sum<<<1, 256, 0, st>>>(A.dpart + 2 * side * A.dcols, n1 * n2,
-                                       dJdK + g.doff[face]);
+  } else {
+    for (int D = 0; D < g.ndim; ++D) {
+      hipLaunchKernelGGL(dir_kernel(g.ndim, D, visc), dim3(tile_count<-3, 2>(g, D)), dim3(256),
+                         0, st, g, A);
       DCF_TRY(hipGetLastError());
     }
   }
-  k_interior_vjp<<<blocks(g.ncell), 256, 0, st>>>(g, A, V, Wb, a, b, Vb, acc_in, acc_out, fold);
+  if ((visc || g.ndim == 2) && g.nbox > g.ncell) {  // 2D: also the y tiles' side arrays
+    auto tk = g.ndim == 1 ? k_tangential_vjp<1>
+                          : (g.ndim == 2 ? k_tangential_vjp<2> : k_tangential_vjp<3>);
+    tk<<<blocks(g.nbox - g.ncell), 256, 0, st>>>(g, A);
+    DCF_TRY(hipGetLastError());
+  }
+  // the halo transposes, axes z, y, x
+  for (int d = g.ndim - 1; d >= 0; --d) {
+    auto hk = g.ndim == 1 ? k_halo_vjp<1> : (g.ndim == 2 ? k_halo_vjp<2> : k_halo_vjp<3>);
+    const long nt = halo_vjp_threads(g, d);
+    hk<<<(unsigned)((nt + 63) / 64), 64, 0, st>>>(g, A, d, dJdK);
+    DCF_TRY(hipGetLastError());
+    DCF_TRY(disturb_sums(g, A, d, dJdK, st));
+  }
+  auto ik = g.ndim == 1 ? k_interior_vjp<1> : (g.ndim == 2 ? k_interior_vjp<2> : k_interior_vjp<3>);
+  ik<<<blocks(g.ncell), 256, 0, st>>>(g, A, V, Wb, a, b, Vb, acc_in, acc_out, fold);
   return hipGetLastError();
 }
 

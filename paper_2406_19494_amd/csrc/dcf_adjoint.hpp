@@ -9,6 +9,8 @@ namespace dcf {
 struct AdjBuffers {
   double *Qb[NQ];   // adjoint of the primitive box (rho, u, v, w, p, T, mu)
   double *Gb[9];    // adjoint of cell-centred velocity derivatives d u_phi / d x_t (3 t + phi)
+  double *Qby[NQ];  // 2D: the y-direction tiles' Qb contributions (no w), added to Qb's
+                    // on ghost and interior cells; every cell read is written each stage
   double *Ub1, *Ub2, *acc;  // stage adjoints and the running lambda^n accumulator
   const double *Wb;  // stage-output adjoint of the stage being reversed
   const double *dtp; // step size (device)
@@ -30,6 +32,8 @@ template <class Carver> void carve_adjoint(Carver &cv, const Dev &g, AdjBuffers 
                                                            : nullptr;
   a.zero_begin = a.Qb[0];
   a.zero_count = (long)((cv.off - off0) / sizeof(double));
+  for (int q = 0; q < NQ; ++q)
+    a.Qby[q] = (g.ndim == 2 && q != QW) ? cv.template take<double>(g.nboxp) : nullptr;
   a.Ub1 = cv.template take<double>((long)g.nv * g.ncell);
   a.Ub2 = cv.template take<double>((long)g.nv * g.ncell);
   a.acc = cv.template take<double>((long)g.nv * g.ncell);
@@ -47,7 +51,7 @@ template <class Carver> void carve_adjoint(Carver &cv, const Dev &g, AdjBuffers 
 // null).  With recompute, U1 and U2 are scratch arrays that receive the
 // stage states; without, they must already hold the stage states of Un.
 // With `boxes` (three contexts whose Q and G point at the cached primitive
-// and derivative boxes of Un, U1, U2) nothing of the forward is recomputed.
+// boxes of Un, U1, U2) nothing of the forward is recomputed.
 hipError_t vjp_step(Dev g, const AdjBuffers &a, const double *Un, double *U1, double *U2,
                     const double *dt, const double *lam1, double *lam0, double *dJdK,
                     hipStream_t st, bool recompute = true, const Dev *boxes = nullptr);

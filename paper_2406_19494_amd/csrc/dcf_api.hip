@@ -84,7 +84,7 @@ struct dcf_ctx {
   double *ckpt = nullptr;  // gradient checkpoints
   double *seg = nullptr;   // per-segment recomputed states
   double *sst = nullptr;   // per-segment stage states U1, U2 of every step
-  double *boxc = nullptr;  // mode 3: primitive + derivative boxes of every stage of a segment
+  double *boxc = nullptr;  // mode 3: primitive boxes of every stage of a segment
   int box_arrays = 0;      // box arrays per cached stage
   double *lam_a = nullptr, *lam_b = nullptr, *gbuf = nullptr, *zero_dt = nullptr;
   Probe probe;  // dcf_probe_begin / dcf_probe_end
@@ -272,9 +272,6 @@ static size_t carve(dcf_ctx *c, void *base, int mode, int nsteps, int seg_len) {
   const long nbox = g.nboxp, ncell = g.ncell, nv = g.nv;
   for (int q = 0; q < NQ; ++q) g.Q[q] = cv.take<double>(nbox);
   for (int D = 0; D < 3; ++D) g.F[D] = D < g.ndim ? cv.take<double>(5 * g.fcount[D]) : nullptr;
-  const bool need_g = g.visc != VISC_NONE && g.ndim >= 2;
-  for (int q = 0; q < 9; ++q)
-    g.G[q] = (need_g && q / 3 < g.ndim && q % 3 < g.ndim) ? cv.take<double>(nbox) : nullptr;
   c->U1 = cv.take<double>(nv * ncell);
   c->U2 = cv.take<double>(nv * ncell);
   c->part = cv.take<double>(8 * RED_BLOCKS);
@@ -295,11 +292,8 @@ static size_t carve(dcf_ctx *c, void *base, int mode, int nsteps, int seg_len) {
   c->boxc = nullptr;
   c->box_arrays = 0;
   if (mode >= 3) {
-    int na = NQ;
-    for (int q = 0; q < 9; ++q)
-      if (need_g && q / 3 < g.ndim && q % 3 < g.ndim) ++na;
-    c->box_arrays = na;
-    c->boxc = cv.take<double>((size_t)3 * seg_len * na * nbox);
+    c->box_arrays = NQ;
+    c->boxc = cv.take<double>((size_t)3 * seg_len * NQ * nbox);
   }
   return cv.off;
 }
@@ -480,18 +474,6 @@ static bool fused_stages(const dcf_ctx *c) {
   return g.source == SRC_MASSFLUX && g.bck[f] == BC_PERIODIC && g.bck[f + 1] == BC_PERIODIC;
 }
 
-// Every face periodic with at least three cells per active axis (each ghost
-// the image of one interior cell) and viscous: the ghost fill and the
-// velocity derivatives run as one launch.
-static bool periodic_viscous(const dcf_ctx *c) {
-  const Dev &g = c->g;
-  if (g.visc == VISC_NONE || g.ndim < 2) return false;
-  for (int d = 0; d < g.ndim; ++d)
-    if (g.bck[2 * d] != BC_PERIODIC || g.bck[2 * d + 1] != BC_PERIODIC || g.n[d] < 3)
-      return false;
-  return true;
-}
-
 // A CFL step reduction left pending by the previous step (nparts partial
 // maxima in dtpart): the next fused step runs it with its first ghost fill.
 struct PendingDt {
@@ -529,19 +511,10 @@ static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_
       bo[0].Q[q] = g.Q[q];
       bo[1].Q[q] = c->qalt.Q[q];
     }
-    const bool merged = periodic_viscous(c);
     Probe &pr = c->probe;
     for (int k = 0; k < 3; ++k) {
       const Dev &gk = gs[(base + k) & 1];
-      if (merged) {
-        if (k == 0 && !box_ready) DCF_HIP(launch_prim_interior(gk, in[k], st));
-        const PendingDt *pk = k == 0 ? pend : nullptr;
-        pr.before(9, st);
-        DCF_HIP(launch_ghost_grad_periodic(gk, pk ? c->dtpart : nullptr, pk ? pk->nparts : 0,
-                                           pk ? pk->cfl : 0.0, pk ? pk->dt_max : 0.0,
-                                           pk ? pk->dt : nullptr, st));
-        pr.after(9, st);
-      } else if (k == 0 && !box_ready) {
+      if (k == 0 && !box_ready) {
         DCF_HIP(launch_prim_halo(gk, in[k], st));
       } else if (k == 0 && pend) {
         pr.before(8, st);
@@ -556,7 +529,7 @@ static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_
       const bool next = k < 2 || write_next;
       DCF_HIP(launch_fluxes_update(gk, U, in[k], out[k], dt, a[k], b[k], k == 2 ? dtpart : nullptr,
                                    st, next ? bo[(base + k + 1) & 1] : BoxOut{}, c->part,
-                                   g.source == SRC_MASSFLUX ? c->force : nullptr, merged, &pr));
+                                   g.source == SRC_MASSFLUX ? c->force : nullptr, &pr));
     }
     return DCF_OK;
   }
@@ -858,23 +831,18 @@ dcf_status dcf_gradient_begin(dcf_ctx *c, const double *U0, int nsteps, const do
 
 // One unit of gradient work: a forward step (with checkpoint and cost), a
 // recomputed step of the current segment, or a reverse step.
-// A copy of the context whose primitive and derivative boxes are the cached
+// A copy of the context whose primitive box is the cached
 // ones of stage s of step n of the current segment (workspace mode 3).
 static Dev stage_box(const dcf_ctx *c, int n, int s) {
   Dev d = c->g;
   double *p = c->boxc + (size_t)(3 * n + s) * c->box_arrays * d.nboxp;
   for (int q = 0; q < NQ; ++q, p += d.nboxp) d.Q[q] = p;
-  for (int q = 0; q < 9; ++q)
-    if (c->g.G[q]) {
-      d.G[q] = p;
-      p += d.nboxp;
-    }
   return d;
 }
 
 // Step k of the current segment, keeping what the reverse sweep needs:
 // seg[k+1] from seg[k], the two inner stage states and (mode 3) every
-// stage's primitive and derivative boxes.
+// stage's primitive box.
 static dcf_status segment_step(dcf_ctx *c, int k, hipStream_t st) {
   auto &gr = c->gr;
   Dev &g = c->g;
@@ -1018,8 +986,9 @@ dcf_status dcf_time_kernel(dcf_ctx *c, const double *U, int which, int reps, dou
   if (!U || !avg_ms || reps < 1) return fail(DCF_EINVAL, "bad argument");
   if (which < 0 || which > 9 || (which >= 1 && which <= 3 && which > c->g.ndim))
     return fail(DCF_EINVAL, "unknown kernel %d", which);
-  if (which == 9 && !periodic_viscous(c))
-    return fail(DCF_EINVAL, "the joint ghost + derivative launch is for all-periodic viscous boxes");
+  if (which == 5 || which == 9)
+    return fail(DCF_EINVAL, "kernel %d does not exist: the flux kernels compute the velocity "
+                            "derivatives while staging", which);
   if (which == 6 && !fused_stages(c))
     return fail(DCF_EINVAL, "no fused flux + update kernel for this case (1D or source term)");
   if (which == 7 && c->g.ndim != 3)
@@ -1036,13 +1005,11 @@ dcf_status dcf_time_kernel(dcf_ctx *c, const double *U, int which, int reps, dou
     hipError_t e = hipSuccess;
     if (which == 0) e = launch_prim_halo(g, U, st);
     else if (which <= 3) e = launch_flux_dir(g, which - 1, st);
-    else if (which == 5) e = launch_grad(g, st);
     else if (which == 6)
       e = launch_flux_update_last(g, U, U, c->U1, c->U2, 0.0, 1.0, nullptr, st, BoxOut{},
                                   g.source == SRC_MASSFLUX ? c->force : nullptr);
     else if (which == 7) e = launch_flux_xy(g, st);
     else if (which == 8) e = launch_prim_ghost(g, st);
-    else if (which == 9) e = launch_ghost_grad_periodic(g, nullptr, 0, 0.0, 0.0, nullptr, st);
     else e = launch_update(g, U, U, c->U1, nullptr, c->U2, 0.0, 1.0, c->force, st);
     if (e != hipSuccess) return fail(DCF_EDEVICE, "launch: %s", hipGetErrorString(e));
   }
@@ -1059,7 +1026,7 @@ dcf_status dcf_time_kernel(dcf_ctx *c, const double *U, int which, int reps, dou
 dcf_status dcf_probe_begin(dcf_ctx *c, int which, int max_launches) {
   dcf_status s = ready(c, 0);
   if (s) return s;
-  if (!(which == 1 || (which >= 5 && which <= 9)))
+  if (!(which == 1 || (which >= 6 && which <= 8)))
     return fail(DCF_EINVAL, "kernel %d cannot be probed", which);
   if (max_launches < 1 || max_launches > (1 << 20)) return fail(DCF_EINVAL, "bad max_launches");
   if (c->probe.ev) return fail(DCF_EINVAL, "a probe is already armed");

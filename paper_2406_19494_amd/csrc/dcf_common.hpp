@@ -61,7 +61,6 @@ struct Dev {
   int source;
   // workspace
   double *Q[NQ];         // primitive box arrays
-  double *G[9];          // cell-centred velocity derivatives d u_phi/d x_t, index 3 t + phi
   double *F[3];          // face fluxes per direction, 5 components each
   long fcount[3];        // faces per direction (component stride of F)
   int fn[3][3];          // face-array extents per direction

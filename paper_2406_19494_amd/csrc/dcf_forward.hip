@@ -319,134 +319,6 @@ __global__ void __launch_bounds__(256) k_prim_ghost(Dev g) {
 }
 
 // ---------------------------------------------------------------------------
-// Cell-centred velocity derivatives d u_phi / d x_t (4th order, index space
-// times the analytic metric) on every cell that a face flux reads them from:
-// position along t interior, the other active positions within two layers.
-// G[3 t + phi] are box arrays.
-// ---------------------------------------------------------------------------
-// Cells that need d u_phi / d x_t: position along t interior, the other
-// active positions within the layers the face stencils reach (two for the
-// 4th-order dissipative fluxes, three for the 6th-order ones).  One thread
-// per (cell, t), x-fastest.
-__host__ __device__ __forceinline__ int grad_halo(const Dev &g) {
-  return g.scheme == SCHEME_TENO6A ? 3 : 2;
-}
-__host__ __device__ __forceinline__ unsigned grad_cells(const Dev &g, int t) {
-  unsigned n = 1;
-  const int w = 2 * grad_halo(g);
-  for (int e = 0; e < g.ndim; ++e) n *= e == t ? g.n[e] : g.n[e] + w;
-  return n;
-}
-
-template <int NDIM, int SCH = SCHEME_WENO5>
-__device__ __forceinline__ void grad_body(const Dev &g, int t, unsigned bid, unsigned nblk) {
-  constexpr int HW = SCH == SCHEME_TENO6A ? 3 : 2;  // layers of the other axes
-  const unsigned bl = xcd_remap(bid, nblk) * blockDim.x + threadIdx.x;
-  if (bl >= grad_cells(g, t)) return;
-  unsigned E[3];
-  int o[3];
-#pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    E[e] = e >= NDIM ? 1u : (e == t ? (unsigned)g.n[e] : (unsigned)g.n[e] + 2 * HW);
-    o[e] = (e >= NDIM || e == t) ? 0 : -HW;
-  }
-  int p[3];
-  const unsigned r = bl / E[0];
-  p[0] = (int)(bl % E[0]) + o[0];
-  p[1] = (int)(r % E[1]) + o[1];
-  p[2] = (int)(r / E[1]) + o[2];
-  const long b = bidx(g, p[0], p[1], p[2]);
-  const long st = g.sb[t];
-  const double mct = g.mc[t][p[t]];
-  if (SCH == SCHEME_TENO6A) {
-    double v[NDIM][6];
-#pragma unroll
-    for (int phi = 0; phi < NDIM; ++phi) {
-      const double *A = g.Q[QU + phi];
-      v[phi][0] = A[b - 3 * st];
-      v[phi][1] = A[b - 2 * st];
-      v[phi][2] = A[b - st];
-      v[phi][3] = A[b + st];
-      v[phi][4] = A[b + 2 * st];
-      v[phi][5] = A[b + 3 * st];
-    }
-#pragma unroll
-    for (int phi = 0; phi < NDIM; ++phi)
-      g.G[3 * t + phi][b] =
-          dcell6(v[phi][0], v[phi][1], v[phi][2], v[phi][3], v[phi][4], v[phi][5]) * mct;
-    return;
-  }
-  double v[NDIM][4];
-#pragma unroll
-  for (int phi = 0; phi < NDIM; ++phi) {
-    const double *A = g.Q[QU + phi];
-    v[phi][0] = A[b - 2 * st];
-    v[phi][1] = A[b - st];
-    v[phi][2] = A[b + st];
-    v[phi][3] = A[b + 2 * st];
-  }
-#pragma unroll
-  for (int phi = 0; phi < NDIM; ++phi)
-    g.G[3 * t + phi][b] = dcell4(v[phi][0], v[phi][1], v[phi][2], v[phi][3]) * mct;
-}
-
-template <int NDIM, int SCH = SCHEME_WENO5>
-__global__ void __launch_bounds__(256) k_grad(Dev g) {
-  grad_body<NDIM, SCH>(g, blockIdx.y, blockIdx.x, gridDim.x);
-}
-
-// As grad_body on a box whose every face is periodic, with each neighbour
-// read from the interior cell whose periodic image it is (the value the
-// ghost fill copies there): the same operands in the same order, so the same
-// derivatives bitwise, without waiting for the ghost fill.
-__device__ __forceinline__ int wrap_periodic(int x, int n) {
-  return x < 0 ? x + n : (x >= n ? x - n : x);
-}
-template <int NDIM, int SCH = SCHEME_WENO5>
-__device__ __forceinline__ void grad_body_periodic(const Dev &g, int t, unsigned bid,
-                                                   unsigned nblk) {
-  constexpr int HW = SCH == SCHEME_TENO6A ? 3 : 2;
-  const unsigned bl = xcd_remap(bid, nblk) * blockDim.x + threadIdx.x;
-  if (bl >= grad_cells(g, t)) return;
-  unsigned E[3];
-  int o[3];
-#pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    E[e] = e >= NDIM ? 1u : (e == t ? (unsigned)g.n[e] : (unsigned)g.n[e] + 2 * HW);
-    o[e] = (e >= NDIM || e == t) ? 0 : -HW;
-  }
-  int p[3];
-  const unsigned r = bl / E[0];
-  p[0] = (int)(bl % E[0]) + o[0];
-  p[1] = (int)(r % E[1]) + o[1];
-  p[2] = (int)(r / E[1]) + o[2];
-  int q[3];
-#pragma unroll
-  for (int e = 0; e < 3; ++e) q[e] = e < NDIM ? wrap_periodic(p[e], g.n[e]) : p[e];
-  constexpr int NO = 2 * HW;  // neighbours -HW .. -1, 1 .. HW
-  double v[NDIM][NO];
-#pragma unroll
-  for (int k = 0; k < NO; ++k) {
-    int s[3] = {q[0], q[1], q[2]};
-    s[t] = wrap_periodic(p[t] + (k < HW ? k - HW : k - HW + 1), g.n[t]);
-    const long sb = bidx(g, s[0], s[1], s[2]);
-#pragma unroll
-    for (int phi = 0; phi < NDIM; ++phi) v[phi][k] = g.Q[QU + phi][sb];
-  }
-  const long b = bidx(g, p[0], p[1], p[2]);
-  const double mct = g.mc[t][p[t]];
-#pragma unroll
-  for (int phi = 0; phi < NDIM; ++phi) {
-    double dv;
-    if constexpr (HW == 3)
-      dv = dcell6(v[phi][0], v[phi][1], v[phi][2], v[phi][3], v[phi][4], v[phi][5]);
-    else
-      dv = dcell4(v[phi][0], v[phi][1], v[phi][2], v[phi][3]);
-    g.G[3 * t + phi][b] = dv * mct;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Total flux F = F^c - F^d at one face of direction D (Eq. (6)), in the
 // global 5-component layout (mass, x/y/z momentum, energy).  The stencil is
 // read through accessors: P(q, o) is primitive q of the cell at offset o from
@@ -583,28 +455,39 @@ __device__ __forceinline__ void face_flux(const Dev &g, const PA &P, const GA &G
 }
 
 // LDS slots: primitives rho,u,v,w,p,T,mu then the tangential derivatives.
+// LDS slots of a flux tile: the primitives (rho, u, v, w, p, and T, mu when
+// viscous), then the 2 (2D) or 4 (3D) cell-centred tangential velocity
+// derivatives the dissipative flux needs, computed while staging.
 template <int NDIM, bool VISC> struct Slots {
   static constexpr int NP = VISC ? 7 : 5;
   static constexpr int NG = VISC ? 2 * (NDIM - 1) : 0;
   static constexpr int NC = NP + NG;
 };
 
-// Box array (and G index) behind LDS slot `sl` of direction D.
-template <int NDIM, int D, bool VISC>
-__device__ __forceinline__ const double *slot_array(const Dev &g, int sl) {
-  constexpr int T1 = tan1(D), T2 = tan2(D);
-  if (sl < 5) return g.Q[sl];
-  if (VISC) {
-    if (sl == 5) return g.Q[QT];
-    if (sl == 6) return g.Q[QMU];
-    const int k = sl - 7, r = k / 2;
-    const int t = r == 0 ? T1 : T2;
-    return g.G[3 * t + ((k & 1) ? D : t)];
-  }
-  return nullptr;
-}
-
 __device__ __forceinline__ int slot_of(int q) { return q; }  // QR..QMU map 1:1
+
+// Staged value of LDS slot `sl` of direction D at box cell b, position p: a
+// primitive, or (sl >= NP) the derivative d u_phi / d x_t (slots NP + 2r +
+// {0, 1}: t the r-th tangential axis, phi = t, then phi = D), 4th order
+// (6th for the TENO6-A scheme) in index space times the analytic metric.  A
+// staged cell's tangential positions are interior, so the stencil stays in
+// the box (three ghost layers).
+template <int NDIM, int D, bool VISC, int SCH>
+__device__ __forceinline__ double stage_value(const Dev &g, int sl, long b, const int *p) {
+  constexpr int NP = Slots<NDIM, VISC>::NP;
+  if (sl < NP) return g.Q[sl][b];  // QR..QMU map 1:1
+  constexpr int T1 = tan1(D), T2 = tan2(D);
+  const int k = sl - NP, t = (k / 2) == 0 ? T1 : T2;
+  const int phi = (k & 1) ? D : t;
+  const double *A = g.Q[QU + phi];
+  const long st = g.sb[t];
+  const double mct = g.mc[t][p[t]];
+  if (SCH == SCHEME_TENO6A)
+    return dcell6(A[b - 3 * st], A[b - 2 * st], A[b - st], A[b + st], A[b + 2 * st],
+                  A[b + 3 * st]) *
+           mct;
+  return dcell4(A[b - 2 * st], A[b - st], A[b + st], A[b + 2 * st]) * mct;
+}
 
 // ---------------------------------------------------------------------------
 // x faces: the face index space ((k ny + j) (nx+1) + f) is cut into chunks of
@@ -637,10 +520,11 @@ __device__ __forceinline__ void flux_x_body(const Dev &g, int nwmax, unsigned bi
     const unsigned r = r0 + seg;
     const int j = (int)(r % ny), k = (int)(r / ny);
     const long bx = bidx(g, xc, j, k);
+    const int pc[3] = {xc, j, k};
 #pragma unroll
     for (int sl = 0; sl < S::NC; ++sl) {
       if ((sl == QV && NDIM < 2) || (sl == QW && NDIM < 3)) continue;
-      lds[sl * nwmax + w] = slot_array<NDIM, 0, VISC>(g, sl)[bx];
+      lds[sl * nwmax + w] = stage_value<NDIM, 0, VISC, SCH>(g, sl, bx, pc);
     }
   }
   __syncthreads();
@@ -700,7 +584,7 @@ __device__ __forceinline__ bool yz_tile_face(const Dev &g, YzTile<NDIM, VISC> &T
 #pragma unroll
     for (int sl = 0; sl < S::NC; ++sl) {
       if ((sl == QV && NDIM < 2) || (sl == QW && NDIM < 3)) continue;
-      T.lds[sl][a][x] = slot_array<NDIM, D, VISC>(g, sl)[bx];
+      T.lds[sl][a][x] = stage_value<NDIM, D, VISC, SCH>(g, sl, bx, p);
     }
   }
   __syncthreads();
@@ -1131,31 +1015,6 @@ __global__ void __launch_bounds__(256) k_prim_ghost_dt(Dev g, const double *part
   prim_ghost_body(g, (blockIdx.x - 1) * blockDim.x + threadIdx.x);
 }
 
-// Ghost fill and velocity derivatives of an all-periodic viscous box in one
-// launch: workgroup 0 finishes the previous step's CFL reduction when part
-// is given (as k_prim_ghost_dt), workgroups [gh0, gr0) fill the ghosts, and
-// the rest compute the derivatives of direction (b - gr0) / nb_grad from
-// interior cells only (gr0 and nb_grad are multiples of 8, so each
-// direction's workgroups meet the XCDs in k_grad's order).
-template <int NDIM, int SCH = SCHEME_WENO5>
-__global__ void __launch_bounds__(256) k_ghost_grad_periodic(Dev g, const double *part,
-                                                             int nparts, double cfl,
-                                                             double dt_max, double *dt,
-                                                             unsigned gh0, unsigned gr0,
-                                                             unsigned nb_grad) {
-  const unsigned b = blockIdx.x;
-  if (b < gh0) {
-    if (part) dt_final_body(part, nparts, cfl, dt_max, dt);
-    return;
-  }
-  if (b < gr0) {
-    prim_ghost_body(g, (b - gh0) * blockDim.x + threadIdx.x);
-    return;
-  }
-  const unsigned gb = b - gr0;
-  grad_body_periodic<NDIM, SCH>(g, (int)(gb / nb_grad), gb % nb_grad, nb_grad);
-}
-
 // ---------------------------------------------------------------------------
 // Diagnostics: volume means of kinetic energy and mu |omega|^2, and the
 // conserved totals.  Needs the primitive box (vorticity from 4th-order
@@ -1399,22 +1258,6 @@ static hipError_t launch_yz(const Dev &g, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_grad(const Dev &g, hipStream_t st) {
-  if (g.visc == VISC_NONE || g.ndim < 2) return hipSuccess;
-  unsigned cells = 0;
-  for (int t = 0; t < g.ndim; ++t) cells = std::max(cells, grad_cells(g, t));
-  const dim3 grid(grid_for(cells), g.ndim);
-  const bool t6 = g.scheme == SCHEME_TENO6A;
-  if (g.ndim == 2) {
-    if (t6) k_grad<2, SCHEME_TENO6A><<<grid, 256, 0, st>>>(g);
-    else k_grad<2><<<grid, 256, 0, st>>>(g);
-  } else {
-    if (t6) k_grad<3, SCHEME_TENO6A><<<grid, 256, 0, st>>>(g);
-    else k_grad<3><<<grid, 256, 0, st>>>(g);
-  }
-  return hipGetLastError();
-}
-
 template <int NDIM, bool VISC>
 static hipError_t launch_fu(const Dev &g, const double *Un, const double *Uin, double *Uout,
                             const double *dt, double a, double b, double *dtpart,
@@ -1454,21 +1297,13 @@ hipError_t launch_flux_update_last(const Dev &g, const double *Un, const double 
 hipError_t launch_fluxes_update(const Dev &g, const double *Un, const double *Uin,
                                 double *Uout, const double *dt, double a, double b,
                                 double *dtpart, hipStream_t st, const BoxOut &qo,
-                                double *part, double *force, bool grad_done, Probe *pr) {
+                                double *part, double *force, Probe *pr) {
   Probe none;
   Probe &p = pr ? *pr : none;
-  hipError_t e = hipSuccess;
-  if (!grad_done) {
-    p.before(5, st);
-    e = launch_grad(g, st);
-    p.after(5, st);
-  }
-  if (e == hipSuccess) {
-    const int w = g.ndim == 3 ? 7 : 1;
-    p.before(w, st);
-    e = g.ndim == 3 ? launch_flux_xy(g, st) : launch_flux_dir(g, 0, st);
-    p.after(w, st);
-  }
+  const int w = g.ndim == 3 ? 7 : 1;
+  p.before(w, st);
+  hipError_t e = g.ndim == 3 ? launch_flux_xy(g, st) : launch_flux_dir(g, 0, st);
+  p.after(w, st);
   // the body force from the boundary fluxes of the directions before the
   // last (the last one is periodic: its boundary terms vanish)
   if (e == hipSuccess && force) e = launch_force(g, part, force, st, g.ndim - 1);
@@ -1497,8 +1332,7 @@ hipError_t launch_flux_dir(const Dev &g, int D, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 hipError_t launch_fluxes(const Dev &g, hipStream_t st) {
-  hipError_t e = launch_grad(g, st);
-  if (e != hipSuccess) return e;
+  hipError_t e;
   if (g.ndim == 3) {
     e = launch_flux_xy(g, st);
     return e != hipSuccess ? e : launch_flux_dir(g, 2, st);
@@ -1531,34 +1365,6 @@ hipError_t launch_dt_final(const double *part, int nparts, double cfl, double dt
 }
 hipError_t launch_prim_interior(const Dev &g, const double *U, hipStream_t st) {
   k_prim_interior<<<grid_for(g.ncell), 256, 0, st>>>(g, U);
-  return hipGetLastError();
-}
-hipError_t launch_ghost_grad_periodic(const Dev &g, const double *part, int nparts, double cfl,
-                                      double dt_max, double *dt, hipStream_t st) {
-  if (g.visc == VISC_NONE || g.ndim < 2) return hipErrorInvalidValue;
-  unsigned cells = 0;
-  for (int t = 0; t < g.ndim; ++t) cells = std::max(cells, grad_cells(g, t));
-  const unsigned nb_grad = (grid_for(cells) + 7u) & ~7u;
-  const unsigned gh0 = part ? 1u : 0u;
-  const unsigned nb_ghost = g.nbox > g.ncell ? grid_for(g.nbox - g.ncell) : 0u;
-  const unsigned gr0 = (gh0 + nb_ghost + 7u) & ~7u;
-  const unsigned total = gr0 + nb_grad * (unsigned)g.ndim;
-  const bool t6 = g.scheme == SCHEME_TENO6A;
-  if (g.ndim == 2) {
-    if (t6)
-      k_ghost_grad_periodic<2, SCHEME_TENO6A><<<total, 256, 0, st>>>(g, part, nparts, cfl, dt_max,
-                                                                     dt, gh0, gr0, nb_grad);
-    else
-      k_ghost_grad_periodic<2><<<total, 256, 0, st>>>(g, part, nparts, cfl, dt_max, dt, gh0, gr0,
-                                                        nb_grad);
-  } else {
-    if (t6)
-      k_ghost_grad_periodic<3, SCHEME_TENO6A><<<total, 256, 0, st>>>(g, part, nparts, cfl, dt_max,
-                                                                     dt, gh0, gr0, nb_grad);
-    else
-      k_ghost_grad_periodic<3><<<total, 256, 0, st>>>(g, part, nparts, cfl, dt_max, dt, gh0, gr0,
-                                                        nb_grad);
-  }
   return hipGetLastError();
 }
 hipError_t launch_prim_ghost_dt(const Dev &g, const double *part, int nparts, double cfl,
@@ -1600,13 +1406,6 @@ __global__ void __launch_bounds__(256) kb_prim_ghost(const BatchEntry *tab) {
   prim_ghost_body(e.g, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-template <int NDIM>
-__global__ void __launch_bounds__(256) kb_grad(const BatchEntry *tab) {
-  const BatchEntry &e = tab[blockIdx.y];
-  if (blockIdx.x >= e.nb_grad) return;
-  grad_body<NDIM>(e.g, blockIdx.z, blockIdx.x, e.nb_grad);
-}
-
 template <int NDIM, bool VISC>
 __global__ void __launch_bounds__(256) kb_flux_x(const BatchEntry *tab) {
   extern __shared__ double lds[];
@@ -1644,13 +1443,6 @@ __global__ void __launch_bounds__(256) kb_prim_ghost_s(const BatchEntry *tab, in
   const BatchEntry &e = tab[blockIdx.y];
   if (blockIdx.x >= e.nb_ghost) return;
   prim_ghost_body(stage_dev(e, stage), blockIdx.x * blockDim.x + threadIdx.x);
-}
-
-template <int NDIM>
-__global__ void __launch_bounds__(256) kb_grad_s(const BatchEntry *tab, int stage) {
-  const BatchEntry &e = tab[blockIdx.y];
-  if (blockIdx.x >= e.nb_grad) return;
-  grad_body<NDIM>(stage_dev(e, stage), blockIdx.z, blockIdx.x, e.nb_grad);
 }
 
 template <bool VISC>
@@ -1708,9 +1500,6 @@ void batch_entry_sizes(BatchEntry &e) {
   const Dev &g = e.g;
   e.nb_prim = grid_for(g.ncell);
   e.nb_ghost = g.nbox > g.ncell ? grid_for(g.nbox - g.ncell) : 0;
-  e.nb_grad = 0;
-  if (g.visc != VISC_NONE && g.ndim >= 2)
-    for (int t = 0; t < g.ndim; ++t) e.nb_grad = std::max(e.nb_grad, grid_for(grad_cells(g, t)));
   e.nb_x = grid_for(g.fcount[0]);
   e.nb_upd = grid_for(g.ncell);
   e.nb_dt = grid_capped(g.ncell, RED_BLOCKS);
@@ -1734,12 +1523,11 @@ void batch_entry_sizes(BatchEntry &e) {
 template <int NDIM, bool VISC>
 static hipError_t batch_step_t(const BatchEntry *tab, const BatchEntry *h, int n, double cfl,
                                hipStream_t st) {
-  unsigned mp = 0, mh = 0, mg = 0, mx = 0, mu = 0, md = 0, my[3] = {0, 0, 0};
+  unsigned mp = 0, mh = 0, mx = 0, mu = 0, md = 0, my[3] = {0, 0, 0};
   int nw = 0;
   for (int i = 0; i < n; ++i) {
     mp = std::max(mp, h[i].nb_prim);
     mh = std::max(mh, h[i].nb_ghost);
-    mg = std::max(mg, h[i].nb_grad);
     mx = std::max(mx, h[i].nb_x);
     mu = std::max(mu, h[i].nb_upd);
     md = std::max(md, h[i].nb_dt);
@@ -1761,7 +1549,6 @@ static hipError_t batch_step_t(const BatchEntry *tab, const BatchEntry *h, int n
     for (int stage = 0; stage < 3; ++stage) {
       if (stage == 0) kb_prim_interior<<<dim3(mp, ny), 256, 0, st>>>(tab, 0);
       if (mh) kb_prim_ghost_s<<<dim3(mh, ny), 256, 0, st>>>(tab, stage);
-      if (VISC) kb_grad_s<ND><<<dim3(mg, ny, NDIM), 256, 0, st>>>(tab, stage);
       if (NDIM == 3)
         kb_flux_xy<VISC><<<dim3(my[1] + mx, ny), 256, shm_xy, st>>>(tab, stage);
       else
@@ -1773,8 +1560,6 @@ static hipError_t batch_step_t(const BatchEntry *tab, const BatchEntry *h, int n
   for (int stage = 0; stage < 3; ++stage) {
     kb_prim_interior<<<dim3(mp, ny), 256, 0, st>>>(tab, stage);
     if (mh) kb_prim_ghost<<<dim3(mh, ny), 256, 0, st>>>(tab);
-    if (VISC && NDIM >= 2)
-      kb_grad<NDIM < 2 ? 2 : NDIM><<<dim3(mg, ny, NDIM), 256, 0, st>>>(tab);
     kb_flux_x<NDIM, VISC><<<dim3(mx, ny), 256, shm, st>>>(tab);
     if (NDIM >= 2) kb_flux_yz<NDIM < 2 ? 2 : NDIM, 1, VISC><<<dim3(my[1], ny), 256, 0, st>>>(tab);
     if (NDIM >= 3) kb_flux_yz<3, 2, VISC><<<dim3(my[2], ny), 256, 0, st>>>(tab);

@@ -18,7 +18,7 @@ struct BatchEntry {
   double *U, *U1, *U2;  // state (advanced in place) and the two stage states
   double *dt;           // step size (device, one double)
   double *part;         // reduction partials of the CFL step
-  unsigned nb_prim, nb_ghost, nb_grad, nb_x, nb_upd, nb_dt;
+  unsigned nb_prim, nb_ghost, nb_x, nb_upd, nb_dt;
   unsigned yz_nbx[3], yz_nby[3], yz_ntot[3];  // tile grids of the y and z fluxes
   unsigned fu_nbx, fu_nby, fu_ntot;           // tile grid of the fused last-direction kernel
   int nwmax;            // x-flux LDS window length
@@ -40,7 +40,6 @@ hipError_t launch_fluxes(const Dev &g, hipStream_t st);
 hipError_t launch_flux_dir(const Dev &g, int D, hipStream_t st);
 // x and y face fluxes of a 3D grid in one launch.
 hipError_t launch_flux_xy(const Dev &g, hipStream_t st);
-hipError_t launch_grad(const Dev &g, hipStream_t st);
 // Body force of the constant-mass-flux source from the boundary face fluxes
 // of directions D < ndir (default: all; the others must be periodic).
 hipError_t launch_force(const Dev &g, double *part, double *force, hipStream_t st, int ndir = -1);
@@ -51,8 +50,9 @@ hipError_t launch_update(const Dev &g, const double *Un, const double *Uin, doub
                          const double *force, hipStream_t st, double *dtpart = nullptr);
 unsigned update_blocks(const Dev &g);
 // The whole right-hand side and stage update with the last direction's
-// fluxes fused into the update (ndim >= 2, no source term): gradients, the
-// other directions' fluxes, then one kernel for the last direction + update.
+// fluxes fused into the update (ndim >= 2, no source term): the other
+// directions' fluxes, then one kernel for the last direction + update (the
+// flux kernels compute the velocity derivatives they need while staging).
 // With dtpart (flux_update_blocks(g) doubles) the CFL partials as above.
 // With qo the kernel also writes the new state's primitives (and mu) into
 // the interior of the box qo (same layout as g.Q, another buffer), as
@@ -77,16 +77,15 @@ struct Probe {
   }
 };
 
-// With grad_done the derivatives are already in g.G (launch_ghost_grad_periodic).
-// With pr the grad (5), x+y or x flux (7 / 1) and fused update (6) launches
-// are bracketed by its events.
+// With pr the x+y or x flux (7 / 1) and fused update (6) launches are
+// bracketed by its events.
 hipError_t launch_fluxes_update(const Dev &g, const double *Un, const double *Uin,
                                 double *Uout, const double *dt, double a, double b,
                                 double *dtpart, hipStream_t st, const BoxOut &qo = BoxOut{},
                                 double *part = nullptr, double *force = nullptr,
-                                bool grad_done = false, Probe *pr = nullptr);
+                                Probe *pr = nullptr);
 unsigned flux_update_blocks(const Dev &g);
-// The last direction's flux + update kernel alone (its gradient and other
+// The last direction's flux + update kernel alone (the other directions'
 // fluxes already computed).
 hipError_t launch_flux_update_last(const Dev &g, const double *Un, const double *Uin,
                                    double *Uout, const double *dt, double a, double b,
@@ -101,12 +100,6 @@ hipError_t launch_prim_ghost_dt(const Dev &g, const double *part, int nparts, do
 // The interior cells' primitives alone (the first launch of launch_prim_halo's
 // two-launch form).
 hipError_t launch_prim_interior(const Dev &g, const double *U, hipStream_t st);
-// Every face periodic and viscous (ndim >= 2): launch_prim_ghost and
-// launch_grad in one launch (the derivatives read interior cells only, so
-// they do not wait for the ghosts; bitwise the same values), with the CFL
-// reduction of launch_prim_ghost_dt when part is not null.
-hipError_t launch_ghost_grad_periodic(const Dev &g, const double *part, int nparts, double cfl,
-                                      double dt_max, double *dt, hipStream_t st);
 hipError_t launch_dt_final(const double *part, int nparts, double cfl, double dt_max, double *dt,
                            hipStream_t st);
 hipError_t launch_dt(const Dev &g, const double *U, double cfl, double dt_max, double *part,

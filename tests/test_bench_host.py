@@ -19,16 +19,18 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 
 def test_step_kernels_of_each_family():
+    # (2D/3D flux kernels compute the velocity derivatives themselves: no
+    # derivative launch in a step)
     tgv, _ = W.tgv(8)
-    assert bench.step_kernel_ids(tgv) == [0, 9, 7, 6]  # every face periodic: ghosts + derivatives
+    assert bench.step_kernel_ids(tgv) == [0, 8, 7, 6]
     tgv_inviscid, _ = W.tgv(8, viscous=False)
     assert bench.step_kernel_ids(tgv_inviscid) == [0, 8, 7, 6]
     ch, _ = W.channel(16, 8, 8)
-    assert bench.step_kernel_ids(ch) == [0, 8, 5, 7, 6]  # body force, periodic z: fused
+    assert bench.step_kernel_ids(ch) == [0, 8, 7, 6]  # body force, periodic z: fused
     ch.bc = ch.bc[:4] + ("wall", "wall")
-    assert bench.step_kernel_ids(ch) == [0, 5, 7, 3, 4]  # body force, walls in z: unfused
+    assert bench.step_kernel_ids(ch) == [0, 7, 3, 4]  # body force, walls in z: unfused
     bl, _, _ = W.porous_bl(nx=16, ny=8)
-    assert bench.step_kernel_ids(bl) == [0, 8, 5, 1, 6]
+    assert bench.step_kernel_ids(bl) == [0, 8, 1, 6]
     sod, _ = W.sod(50)
     assert bench.step_kernel_ids(sod) == [0, 1, 4]
 
@@ -50,7 +52,7 @@ def test_counter_summaries_parse_or_are_absent():
     # the committed summaries either match the kernel sources (numbers) or
     # are reported as missing (None), never a parse error
     for w in ("tgv64", "channel"):
-        for k in ("k_flux_xy", "k_flux_update", "k_grad", "k_prim_halo"):
+        for k in ("k_flux_xy", "k_flux_update", "k_prim_halo"):
             t = bench.measured_traffic(k, w)
             v = bench.measured_valu(k, w)
             assert t is None or t > 0

@@ -94,18 +94,21 @@ def test_gradient_sized_for_other_trajectory_rejected():
 
 def test_time_kernel_families_and_unknown_ids():
     # every kernel family of a 3D viscous periodic case times to a positive
-    # duration; the fused flux + update (6), the combined x + y flux launch
-    # (7) and the joint ghost + derivative launch (9) are refused where the
-    # case has none (1D)
+    # duration; ids 5 and 9 (no derivative launch exists: the flux kernels
+    # compute the velocity derivatives while staging) are refused; the fused
+    # flux + update (6) and the combined x + y flux launch (7) are refused
+    # where the case has none (1D)
     case, P = W.tgv(16)
-    s = Solver(case)
-    U = s.init_state(P)
-    for w in range(10):
-        assert s.time_kernel(U, w, reps=2) > 0.0
     L = B.lib()
     ms = C.c_double()
-    for bad in (-1, 10):
-        assert L.dcf_time_kernel(s.ctx, C.c_void_p(U.data_ptr()), bad, 2, C.byref(ms), None) == -1
+    for mode in (0, 1):
+        s = Solver(case, mode=mode)
+        U = s.init_state(P)
+        for w in (0, 1, 2, 3, 4, 6, 7, 8):
+            assert s.time_kernel(U, w, reps=2) > 0.0
+        for bad in (-1, 5, 9, 10):
+            assert L.dcf_time_kernel(s.ctx, C.c_void_p(U.data_ptr()), bad, 2, C.byref(ms),
+                                     None) == -1
     case1, P1 = W.sod(64)
     s1 = Solver(case1)
     U1 = s1.init_state(P1)
@@ -118,8 +121,8 @@ def test_probe_counts_in_loop_launches_and_changes_nothing():
     # event pairs around the stepping calls' launches of one kernel family:
     # one launch per stage, the same state bitwise as an unprobed run
     print("[probe] tgv 12, porous BL 24x16", flush=True)
-    for case, P, K, ids in ((*W.tgv(12), None, (7, 6, 9)),
-                            (*W.porous_bl(nx=24, ny=16, strip=(6, 18)), (1, 5, 6, 8))):
+    for case, P, K, ids in ((*W.tgv(12), None, (7, 6, 8)),
+                            (*W.porous_bl(nx=24, ny=16, strip=(6, 18)), (1, 6, 8))):
         s = Solver(case, K=K)
         U0 = s.init_state(P)
         ref = U0.clone()
@@ -148,7 +151,7 @@ def test_probe_argument_errors():
     s = Solver(case)
     L = B.lib()
     n, ms = C.c_int(), C.c_double()
-    for bad in (-1, 0, 2, 3, 4, 10):
+    for bad in (-1, 0, 2, 3, 4, 5, 9, 10):
         assert L.dcf_probe_begin(s.ctx, bad, 10) == -1
     assert L.dcf_probe_begin(s.ctx, 7, 0) == -1
     assert L.dcf_probe_end(s.ctx, C.byref(n), C.byref(ms)) == -1  # nothing armed

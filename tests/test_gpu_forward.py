@@ -304,9 +304,9 @@ def test_tgv64_1000_step_history_matches_oracle():
 
 @pytest.mark.parametrize("ndim,n", [(3, (13, 9, 7)), (2, (19, 11, 1))], ids=["3d", "2d"])
 def test_all_periodic_viscous_steps_parity(ndim, n):
-    # every face periodic and viscous: the step fills the ghosts and computes
-    # the velocity derivatives in one launch (derivatives from interior cells);
-    # 20 steps at half the CFL step against the oracle on ragged, non-cubic grids
+    # every face periodic and viscous (the tangential derivatives of the
+    # periodic images): 20 steps at half the CFL step against the oracle on
+    # ragged, non-cubic grids
     case = W.Case(name="periodic", ndim=ndim, n=n, lo=(0, 0, 0), hi=(1.0, 0.8, 0.6),
                   stretch=("uniform",) * 3, beta=(0, 0, 0), gamma=1.4, R=1.0, Pr=0.7,
                   visc_law="power", mu_ref=0.01, T_ref=1.0, visc_param=0.7,

@@ -2,8 +2,8 @@
 interpolation limiter, 6th-order central dissipative fluxes) against the
 oracle running the same scheme: one right-hand side on every small case
 (every axis count, boundary kind, grid map, viscosity law, the source term),
-multi-step states, the all-periodic joint ghost + derivative launch, the
-full-size channel, and the calls that do not support the scheme."""
+multi-step states (walled, all-periodic, porous), the full-size channel, and
+the calls that do not support the scheme."""
 import numpy as np
 import pytest
 import torch
@@ -54,8 +54,7 @@ def test_teno_rhs_parity(name, case, P, K):
 def test_teno_steps_parity(which):
     # the fused stepping path (CFL steps chained in one call) against the
     # oracle's steps: 20 steps of a walled channel with the body force, of a
-    # Taylor-Green box (all periodic: the joint ghost + derivative launch) and
-    # of a porous boundary layer
+    # Taylor-Green box (all periodic) and of a porous boundary layer
     if which == "channel":
         case, P = W.channel(nx=20, ny=18, nz=11, scheme="teno6a")
         K = None
