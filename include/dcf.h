@@ -305,8 +305,10 @@ dcf_status dcf_diagnostics(dcf_ctx *ctx, const double *U_dev, double *out_dev, v
  * (dU^{n+1}/dK)^T lam_np1.  stages_dev (nullable dev): the step's stage
  * states U^(1), U^(2) as dcf_rk3_step_keep writes them; NULL recomputes them
  * from U^n (two more right-hand sides).  Branches (HLLC wave-speed cases,
- * min/max) follow the primal.  lam_n may not alias lam_np1.  Workspace mode
- * >= 1; DCF_EUNSUPPORTED with the mass-flux source. */
+ * min/max) follow the primal; with the mass-flux source the body force's
+ * dependence on the state (through every cell's x-momentum right-hand side)
+ * is included.  lam_n may not alias lam_np1.  Workspace mode >= 1;
+ * DCF_EUNSUPPORTED for the TENO6-A scheme. */
 dcf_status dcf_vjp_step(dcf_ctx *ctx, const double *Un_dev, const double *stages_dev,
                         const double *dt_dev, const double *lam_np1_dev, double *lam_n_dev,
                         double *dJdK_dev, void *stream);
@@ -324,8 +326,8 @@ dcf_status dcf_cost_term(dcf_ctx *ctx, const double *U_dev, double w, double *J_
  * segment keeps its states from the forward sweep and is not recomputed
  * (seg_len >= nsteps: no recompute at all).  Any output pointer may be NULL
  * except J_dev.  DCF_EINVAL without a cost face, for another seg_len or for
- * more steps than the workspace holds; DCF_EUNSUPPORTED with the mass-flux
- * source. */
+ * more steps than the workspace holds; DCF_EUNSUPPORTED for the TENO6-A
+ * scheme. */
 dcf_status dcf_gradient(dcf_ctx *ctx, const double *U0_dev, int nsteps, const double *dt_dev,
                         int seg_len, double *J_dev, double *dJdK_dev, double *dJdU0_dev,
                         void *stream);

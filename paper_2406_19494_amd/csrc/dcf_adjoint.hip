@@ -210,13 +210,24 @@ __device__ void hllc_vjp(const double *qL, const double *qR, double gamma, doubl
 
 // Flux adjoint at face f of direction D from the stage-output adjoint Wb:
 // with Rb = b dt Wb (the right-hand-side adjoint, 5-component flux layout),
-// Fb[m] = Rb_m(cell f)/dx_f - Rb_m(cell f-1)/dx_{f-1}.
+// Fb[m] = Rb_m(cell f)/dx_f - Rb_m(cell f-1)/dx_{f-1}.  With the mass-flux
+// body force f = -sum_c V_c R_rhou(c) / W the x-momentum right-hand side of
+// every cell also carries -f-bar V_c / W (the force's dependence on the
+// face fluxes; it telescopes to the boundary faces, as in the forward).
 __device__ __forceinline__ void face_adjoint(const Dev &g, const AdjBuffers &A, int D,
                                              const int *pos, int f, double *Fb) {
   const long nc = g.ncell;
   const int nd = g.ndim;
   const double s = A.bcoef * A.dtp[0];
   const long vo[5] = {0, nc, 2 * nc, 3 * nc, (long)(nd + 1) * nc};
+  const bool force = g.source == SRC_MASSFLUX;
+  const double fw = force ? A.src[1] / A.src[2] : 0.0;  // f-bar / W
+  auto vol = [&](const int *cp) {
+    double V = g.dx[0][cp[0]];
+    if (nd >= 2) V *= g.dx[1][cp[1]];
+    if (nd >= 3) V *= g.dx[2][cp[2]];
+    return V;
+  };
   for (int m = 0; m < 5; ++m) Fb[m] = 0.0;
   int cpos[3] = {pos[0], pos[1], pos[2]};
   if (f < g.n[D]) {
@@ -224,14 +235,22 @@ __device__ __forceinline__ void face_adjoint(const Dev &g, const AdjBuffers &A, 
     long c = ((long)cpos[2] * g.n[1] + cpos[1]) * g.n[0] + cpos[0];
     double id = g.idx[D][f];
     for (int m = 0; m < 5; ++m)
-      if (m < 2 || m == 4 || m <= nd) Fb[m] += (s * A.Wb[vo[m] + c]) * id;
+      if (m < 2 || m == 4 || m <= nd) {
+        double r = s * A.Wb[vo[m] + c];
+        if (force && m == 1) r -= fw * vol(cpos);
+        Fb[m] += r * id;
+      }
   }
   if (f >= 1) {
     cpos[D] = f - 1;
     long c = ((long)cpos[2] * g.n[1] + cpos[1]) * g.n[0] + cpos[0];
     double id = g.idx[D][f - 1];
     for (int m = 0; m < 5; ++m)
-      if (m < 2 || m == 4 || m <= nd) Fb[m] -= (s * A.Wb[vo[m] + c]) * id;
+      if (m < 2 || m == 4 || m <= nd) {
+        double r = s * A.Wb[vo[m] + c];
+        if (force && m == 1) r -= fw * vol(cpos);
+        Fb[m] -= r * id;
+      }
   }
 }
 
@@ -1007,6 +1026,70 @@ __global__ void __launch_bounds__(256) k_disturb_sum(const double *part, long co
 }
 
 // ---------------------------------------------------------------------------
+// Mass-flux body force of a stage, adjoint side: the source adds f to the
+// x-momentum and f u to the energy right-hand side of every cell, so with
+// Rb = b dt Wb, f-bar = sum_c (Rb_rhou(c) + Rb_E(c) u(c)); also the volume
+// W = sum_c V_c.  Two passes, fixed-shape trees (deterministic): src[1] =
+// f-bar, src[2] = W.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_force_adj_partial(Dev g, AdjBuffers A) {
+  __shared__ double sh[2][256];
+  const double s = A.bcoef * A.dtp[0];
+  const long nc = g.ncell;
+  const int nd = g.ndim;
+  const unsigned n0 = g.n[0], n01 = n0 * (unsigned)g.n[1];
+  double v[2] = {0.0, 0.0};
+  for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < nc;
+       c += (long)gridDim.x * blockDim.x) {
+    const unsigned cu = (unsigned)c;
+    const int k = (int)(cu / n01), j = (int)((cu % n01) / n0), i = (int)(cu % n0);
+    const double rb1 = s * A.Wb[nc + c], rbE = s * A.Wb[(long)(nd + 1) * nc + c];
+    v[0] += rb1 + rbE * g.Q[QU][bidx(g, i, j, k)];
+    double V = g.dx[0][i];
+    if (nd >= 2) V *= g.dx[1][j];
+    if (nd >= 3) V *= g.dx[2][k];
+    v[1] += V;
+  }
+  sh[0][threadIdx.x] = v[0];
+  sh[1][threadIdx.x] = v[1];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    A.spart[2 * blockIdx.x] = sh[0][0];
+    A.spart[2 * blockIdx.x + 1] = sh[1][0];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_force_adj_final(AdjBuffers A, int nparts) {
+  __shared__ double sh[2][256];
+  double v[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nparts; b += 256) {
+    v[0] += A.spart[2 * b];
+    v[1] += A.spart[2 * b + 1];
+  }
+  sh[0][threadIdx.x] = v[0];
+  sh[1][threadIdx.x] = v[1];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    A.src[1] = sh[0][0];
+    A.src[2] = sh[1][0];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Interior: Vb = b Wb + (dQ/dU)^T Qb, with Q = (rho, u, v, w, p, T(p, rho)).
 // acc_out = acc_in + a Wb (the Un adjoint accumulator); with fold != 0 the
 // accumulator is added into Vb instead (last stage, V = Un).
@@ -1047,6 +1130,8 @@ __global__ void __launch_bounds__(256) k_interior_vjp(Dev g, AdjBuffers A, const
     for (int phi = 0; phi < NDIM; ++phi) ub[phi] += add[phi];
   }
   if (visc) Tb += dviscosity(g, g.Q[QT][bx], g.Q[QMU][bx]) * mub;
+  if (g.source == SRC_MASSFLUX)  // energy source f u: u-bar += Rb_E f
+    ub[0] += (A.bcoef * A.dtp[0] * Wb[(long)(nd + 1) * nc + c]) * A.src[0];
   double rho = V[c];
   double ir = 1.0 / rho;
   double u[3] = {V[nc + c] * ir, nd >= 2 ? V[2 * nc + c] * ir : 0.0,
@@ -1132,6 +1217,14 @@ static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A0, const double *V,
   A.dtp = dt;
   A.bcoef = b;
   if (!have_box) DCF_TRY(launch_prim_halo(g, V, st));  // the stage's primitive box
+  if (g.source == SRC_MASSFLUX) {
+    // the stage's body force f (as the forward stage computed it) and f-bar
+    DCF_TRY(launch_force_direct(g, A.spart, A.src, st));
+    const unsigned nb = (unsigned)std::min<long>((g.ncell + 255) / 256, RED_BLOCKS);
+    k_force_adj_partial<<<nb, 256, 0, st>>>(g, A);
+    k_force_adj_final<<<1, 256, 0, st>>>(A, (int)nb);
+    DCF_TRY(hipGetLastError());
+  }
   if (g.ndim == 2) {
     const unsigned nx = tile_count<-3, 2>(g, 0), ny = tile_count<-3, 2>(g, 1);
     const unsigned nblk = 8u * ((nx + 7u) / 8u + (ny + 7u) / 8u);
@@ -1164,40 +1257,18 @@ static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A0, const double *V,
   return hipGetLastError();
 }
 
-hipError_t vjp_step(Dev g, const AdjBuffers &A, const double *Un, double *U1, double *U2,
-                    const double *dt, const double *lam1, double *lam0, double *dJdK,
-                    hipStream_t st, bool recompute, const Dev *boxes) {
-  if (boxes) {  // stage boxes cached by the forward recompute (Un, U1, U2)
-    DCF_TRY(stage_vjp(boxes[2], A, U2, lam1, dt, 1.0 / 3.0, 2.0 / 3.0, A.Ub2, nullptr, A.acc, 0,
-                      dJdK, st, true));
-    DCF_TRY(stage_vjp(boxes[1], A, U1, A.Ub2, dt, 0.75, 0.25, A.Ub1, A.acc, A.acc, 0, dJdK, st,
-                      true));
-    DCF_TRY(stage_vjp(boxes[0], A, Un, A.Ub1, dt, 0.0, 1.0, lam0, A.acc, nullptr, 1, dJdK, st,
-                      true));
-    return hipSuccess;
-  }
-  if (recompute) {  // the stage states U1, U2 of Un, as the forward step makes them
-    const bool fused = g.ndim >= 2 && g.source == SRC_NONE;
-    const double *in[2] = {Un, U1};
-    double *out[2] = {U1, U2};
-    const double ca[2] = {0.0, 0.75}, cb[2] = {1.0, 0.25};
-    for (int k = 0; k < 2; ++k) {
-      DCF_TRY(launch_prim_halo(g, in[k], st));
-      if (fused) {
-        DCF_TRY(launch_fluxes_update(g, Un, in[k], out[k], dt, ca[k], cb[k], nullptr, st));
-      } else {
-        DCF_TRY(launch_fluxes(g, st));
-        DCF_TRY(launch_update(g, Un, in[k], out[k], nullptr, dt, ca[k], cb[k], nullptr, st));
-      }
-    }
-  }
+hipError_t vjp_step(Dev g, const AdjBuffers &A, const double *Un, const double *U1,
+                    const double *U2, const double *dt, const double *lam1, double *lam0,
+                    double *dJdK, hipStream_t st, const Dev *boxes) {
+  const bool have = boxes != nullptr;  // stage boxes cached by the forward recompute
+  const Dev &g3 = have ? boxes[2] : g, &g2 = have ? boxes[1] : g, &g1 = have ? boxes[0] : g;
   // stage 3: W = Un/3 + 2/3 (U2 + dt R(U2))
-  DCF_TRY(stage_vjp(g, A, U2, lam1, dt, 1.0 / 3.0, 2.0 / 3.0, A.Ub2, nullptr, A.acc, 0, dJdK, st,
-                    false));
+  DCF_TRY(stage_vjp(g3, A, U2, lam1, dt, 1.0 / 3.0, 2.0 / 3.0, A.Ub2, nullptr, A.acc, 0, dJdK,
+                    st, have));
   // stage 2: W = 3/4 Un + 1/4 (U1 + dt R(U1))
-  DCF_TRY(stage_vjp(g, A, U1, A.Ub2, dt, 0.75, 0.25, A.Ub1, A.acc, A.acc, 0, dJdK, st, false));
+  DCF_TRY(stage_vjp(g2, A, U1, A.Ub2, dt, 0.75, 0.25, A.Ub1, A.acc, A.acc, 0, dJdK, st, have));
   // stage 1: W = Un + dt R(Un)
-  DCF_TRY(stage_vjp(g, A, Un, A.Ub1, dt, 0.0, 1.0, lam0, A.acc, nullptr, 1, dJdK, st, false));
+  DCF_TRY(stage_vjp(g1, A, Un, A.Ub1, dt, 0.0, 1.0, lam0, A.acc, nullptr, 1, dJdK, st, have));
   return hipSuccess;
 }
 

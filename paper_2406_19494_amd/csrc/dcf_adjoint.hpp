@@ -3,6 +3,7 @@
 #pragma once
 
 #include "dcf_common.hpp"
+#include "dcf_kernels.hpp"
 
 namespace dcf {
 
@@ -15,6 +16,8 @@ struct AdjBuffers {
   const double *Wb;  // stage-output adjoint of the stage being reversed
   const double *dtp; // step size (device)
   double bcoef;      // weight b of the stage's V + dt R(V) term
+  double *src;      // body-force adjoint of a stage: f, f-bar = sum Rb_rhou + Rb_E u, volume
+  double *spart;    // reduction partials of the body force and of its adjoint
   double *dpart;    // per-column partial sums of dJ/d(A, kappa), 4 per wall column
   long dcols;       // columns per disturbance-face partial array
   double *zero_begin;  // Qb and Gb are carved back to back: one clear (with the
@@ -45,15 +48,17 @@ template <class Carver> void carve_adjoint(Carver &cv, const Dev &g, AdjBuffers 
   }
   a.dcols = cols;
   a.dpart = cv.template take<double>(4 * cols);
+  a.src = cv.template take<double>(4);
+  a.spart = cv.template take<double>(2 * RED_BLOCKS);
 }
 
 // lam0 = (dU^{n+1}/dU^n)^T lam1 and dJdK += (dU^{n+1}/dK)^T lam1 (if not
-// null).  With recompute, U1 and U2 are scratch arrays that receive the
-// stage states; without, they must already hold the stage states of Un.
-// With `boxes` (three contexts whose Q and G point at the cached primitive
-// boxes of Un, U1, U2) nothing of the forward is recomputed.
-hipError_t vjp_step(Dev g, const AdjBuffers &a, const double *Un, double *U1, double *U2,
-                    const double *dt, const double *lam1, double *lam0, double *dJdK,
-                    hipStream_t st, bool recompute = true, const Dev *boxes = nullptr);
+// null).  U1 and U2 hold the stage states of Un (as the forward step made
+// them).  With `boxes` (three contexts whose Q point at the cached primitive
+// boxes of Un, U1, U2) nothing of the forward is recomputed; without, each
+// stage's primitive box is recomputed into g.Q.
+hipError_t vjp_step(Dev g, const AdjBuffers &a, const double *Un, const double *U1,
+                    const double *U2, const double *dt, const double *lam1, double *lam0,
+                    double *dJdK, hipStream_t st, const Dev *boxes = nullptr);
 
 }  // namespace dcf

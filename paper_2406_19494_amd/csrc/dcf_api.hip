@@ -489,11 +489,14 @@ struct PendingDt {
 // write_next the last update writes the primitives of the new state into
 // box (base + 1) & 1, the first box of a following step with the other base.
 // With pend (box_ready only) the first ghost fill also reduces the previous
-// step's partial maxima into dt, before any stage reads it.
+// step's partial maxima into dt, before any stage reads it.  With nstages = 2
+// only the stage states U1 and U2 are made (U is not written): the step's
+// inner states exactly as the full step makes them.
 static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_t st,
                              double *U1 = nullptr, double *U2 = nullptr,
                              double *dtpart = nullptr, int base = 0, bool box_ready = false,
-                             bool write_next = false, const PendingDt *pend = nullptr) {
+                             bool write_next = false, const PendingDt *pend = nullptr,
+                             int nstages = 3) {
   Dev &g = c->g;
   if (!U1) U1 = c->U1;
   if (!U2) U2 = c->U2;
@@ -512,7 +515,7 @@ static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_
       bo[1].Q[q] = c->qalt.Q[q];
     }
     Probe &pr = c->probe;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < nstages; ++k) {
       const Dev &gk = gs[(base + k) & 1];
       if (k == 0 && !box_ready) {
         DCF_HIP(launch_prim_halo(gk, in[k], st));
@@ -538,6 +541,7 @@ static dcf_status rk3_stages(dcf_ctx *c, double *U, const double *dt, hipStream_
   DCF_HIP(launch_update(g, U, U, U1, nullptr, dt, 0.0, 1.0, c->force, st));
   if ((s = eval_fluxes(c, U1, st))) return s;
   DCF_HIP(launch_update(g, U, U1, U2, nullptr, dt, 0.75, 0.25, c->force, st));
+  if (nstages < 3) return DCF_OK;
   if ((s = eval_fluxes(c, U2, st))) return s;
   DCF_HIP(launch_update(g, U, U2, U, nullptr, dt, 1.0 / 3.0, 2.0 / 3.0, c->force, st, dtpart));
   return DCF_OK;
@@ -783,17 +787,20 @@ dcf_status dcf_vjp_step(dcf_ctx *c, const double *Un, const double *stages, cons
   if (s) return s;
   if (!Un || !dt || !lam1 || !lam0) return fail(DCF_EINVAL, "null array");
   if (lam0 == lam1) return fail(DCF_EINVAL, "lam_n may not alias lam_np1");
-  if (c->g.source != SRC_NONE)
-    return fail(DCF_EUNSUPPORTED, "adjoint of the mass-flux source is not implemented");
   if (c->g.scheme != SCHEME_WENO5)
     return fail(DCF_EUNSUPPORTED, "the adjoint is of the WENO5-JS scheme only");
   const long M = (long)c->g.nv * c->g.ncell;
-  // with the caller's stage states the VJP only reads them (the stage
-  // kernels take non-const pointers for the recompute case)
-  double *S1 = stages ? const_cast<double *>(stages) : c->U1;
-  double *S2 = stages ? const_cast<double *>(stages) + M : c->U2;
-  return vjp_step(c->g, c->adj, Un, S1, S2, dt, lam1, lam0, dJdK, (hipStream_t)stream,
-                  stages == nullptr)
+  hipStream_t st = (hipStream_t)stream;
+  // without the caller's stage states: the two stage states of Un as the
+  // forward step makes them (its first two stages; Un is only read)
+  if (!stages) {
+    dcf_status s2 = rk3_stages(c, const_cast<double *>(Un), dt, st, c->U1, c->U2, nullptr, 0,
+                               false, false, nullptr, 2);
+    if (s2) return s2;
+  }
+  const double *S1 = stages ? stages : c->U1;
+  const double *S2 = stages ? stages + M : c->U2;
+  return vjp_step(c->g, c->adj, Un, S1, S2, dt, lam1, lam0, dJdK, st)
              ? fail(DCF_EDEVICE, "vjp launch failed")
              : DCF_OK;
 }
@@ -807,8 +814,6 @@ dcf_status dcf_gradient_begin(dcf_ctx *c, const double *U0, int nsteps, const do
                 c->ws_nsteps, c->ws_seg, nsteps, seg_len);
   if (!U0 || !dt || !J) return fail(DCF_EINVAL, "null array");
   if (c->cost_face < 0) return fail(DCF_EINVAL, "no cost face set (dcf_set_cost)");
-  if (c->g.source != SRC_NONE)
-    return fail(DCF_EUNSUPPORTED, "adjoint of the mass-flux source is not implemented");
   if (c->g.scheme != SCHEME_WENO5)
     return fail(DCF_EUNSUPPORTED, "the adjoint is of the WENO5-JS scheme only");
   hipStream_t st = (hipStream_t)stream;
@@ -928,7 +933,7 @@ static dcf_status gradient_unit(dcf_ctx *c, hipStream_t st) {
     const bool cached = c->boxc && g.source == SRC_NONE;
     if (cached)
       for (int k = 0; k < 3; ++k) boxes[k] = stage_box(c, n - 1 - n0, k);
-    if (vjp_step(g, c->adj, Uprev, S1, S2, gr.dt, gr.lam, gr.lam_prev, gr.dJdK, st, false,
+    if (vjp_step(g, c->adj, Uprev, S1, S2, gr.dt, gr.lam, gr.lam_prev, gr.dJdK, st,
                  cached ? boxes : nullptr))
       return fail(DCF_EDEVICE, "vjp launch failed");
     double *t = gr.lam;

@@ -748,6 +748,80 @@ __global__ void __launch_bounds__(256) k_force_partial(Dev g, double *part, int 
   }
 }
 
+// x-momentum flux of face f of direction D on the line through p (p[D]
+// ignored), evaluated from the primitive box: face_flux with the cells read
+// from the box instead of a staged tile (the same operands and arithmetic,
+// so the value of the flux kernels bitwise).
+template <int NDIM, int D, bool VISC, int SCH>
+__device__ __forceinline__ double box_face_xmom_flux(const Dev &g, const int *p, int f) {
+  constexpr int NP = Slots<NDIM, VISC>::NP;
+  int pc[3] = {p[0], p[1], p[2]};
+  pc[D] = f;
+  const long b = bidx(g, pc[0], pc[1], pc[2]);
+  const long s = g.sb[D];
+  auto P = [&](int q, int o) { return g.Q[q][b + o * s]; };
+  auto Gv = [&](int kk, int o) {
+    int po[3] = {pc[0], pc[1], pc[2]};
+    po[D] = f + o;
+    return stage_value<NDIM, D, VISC, SCH>(g, NP + kk, b + o * s, po);
+  };
+  double G[5];
+  face_flux<NDIM, D, VISC, SCH>(g, P, Gv, f, G);
+  return G[1];
+}
+
+// Body force, pass 1, from the primitive box alone (the adjoint's stages
+// have no face fluxes): the sums of k_force_partial over every direction,
+// with each boundary flux evaluated by box_face_xmom_flux.  A periodic
+// direction's two boundary faces see the same stencil values, so its terms
+// are exact zeros and the sums equal k_force_partial's bitwise.
+template <int NDIM, bool VISC, int SCH>
+__global__ void __launch_bounds__(256) k_force_direct(Dev g, double *part) {
+  __shared__ double sh[2 * 256];
+  double v[2] = {0.0, 0.0};
+  long nl[3] = {0, 0, 0}, tot = 0;
+  for (int D = 0; D < NDIM; ++D) {
+    nl[D] = (long)g.n[tan1(D)] * g.n[tan2(D)];
+    tot += nl[D];
+  }
+  for (long x = (long)blockIdx.x * blockDim.x + threadIdx.x; x < tot;
+       x += (long)gridDim.x * blockDim.x) {
+    int D = 0;
+    long l = x;
+    while (l >= nl[D]) l -= nl[D++];
+    const int T1 = tan1(D), T2 = tan2(D);
+    const int a = (int)(l % g.n[T1]), b = (int)(l / g.n[T1]);
+    double A = 1.0;
+    if (T1 < NDIM) A *= g.dx[T1][a];
+    if (T2 < NDIM) A *= g.dx[T2][b];
+    int p[3] = {0, 0, 0};
+    p[T1] = a;
+    p[T2] = b;
+    double F0 = 0.0, F1 = 0.0;
+    if (D == 0) {
+      F0 = box_face_xmom_flux<NDIM, 0, VISC, SCH>(g, p, 0);
+      F1 = box_face_xmom_flux<NDIM, 0, VISC, SCH>(g, p, g.n[0]);
+    } else if (NDIM >= 2 && D == 1) {
+      F0 = box_face_xmom_flux<NDIM, NDIM >= 2 ? 1 : 0, VISC, SCH>(g, p, 0);
+      F1 = box_face_xmom_flux<NDIM, NDIM >= 2 ? 1 : 0, VISC, SCH>(g, p, g.n[1]);
+    } else if (NDIM >= 3) {
+      F0 = box_face_xmom_flux<NDIM, NDIM >= 3 ? 2 : 0, VISC, SCH>(g, p, 0);
+      F1 = box_face_xmom_flux<NDIM, NDIM >= 3 ? 2 : 0, VISC, SCH>(g, p, g.n[2]);
+    }
+    v[0] -= A * (F1 - F0);
+    if (D == 0) {  // volume: sum over x-lines of A_x * line length
+      double Lx = 0.0;
+      for (int i = 0; i < g.n[0]; ++i) Lx += g.dx[0][i];
+      v[1] += A * Lx;
+    }
+  }
+  block_sum<2>(v, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = v[0];
+    part[2 * blockIdx.x + 1] = v[1];
+  }
+}
+
 // Body force, pass 2: f = -sum(V R_rhou)/sum(V).
 __global__ void __launch_bounds__(256) k_force_final(const double *part, int nparts, double *f) {
   __shared__ double sh[2 * 256];
@@ -1348,6 +1422,29 @@ hipError_t launch_force(const Dev &g, double *part, double *force, hipStream_t s
   for (int D = 0; D < g.ndim; ++D) lines += (long)g.n[tan1(D)] * g.n[tan2(D)];
   unsigned nb = grid_capped(lines, RED_BLOCKS);
   k_force_partial<<<nb, 256, 0, st>>>(g, part, ndir < 0 ? g.ndim : ndir);
+  k_force_final<<<1, 256, 0, st>>>(part, (int)nb, force);
+  return hipGetLastError();
+}
+template <int NDIM, bool VISC>
+static void launch_force_direct_t(const Dev &g, unsigned nb, double *part, hipStream_t st) {
+  if (g.scheme == SCHEME_TENO6A)
+    k_force_direct<NDIM, VISC, SCHEME_TENO6A><<<nb, 256, 0, st>>>(g, part);
+  else
+    k_force_direct<NDIM, VISC, SCHEME_WENO5><<<nb, 256, 0, st>>>(g, part);
+}
+hipError_t launch_force_direct(const Dev &g, double *part, double *force, hipStream_t st) {
+  long lines = 0;
+  for (int D = 0; D < g.ndim; ++D) lines += (long)g.n[tan1(D)] * g.n[tan2(D)];
+  const unsigned nb = grid_capped(lines, RED_BLOCKS);
+  const bool v = g.visc != VISC_NONE;
+  switch (g.ndim) {
+    case 1: v ? launch_force_direct_t<1, true>(g, nb, part, st)
+              : launch_force_direct_t<1, false>(g, nb, part, st); break;
+    case 2: v ? launch_force_direct_t<2, true>(g, nb, part, st)
+              : launch_force_direct_t<2, false>(g, nb, part, st); break;
+    default: v ? launch_force_direct_t<3, true>(g, nb, part, st)
+               : launch_force_direct_t<3, false>(g, nb, part, st); break;
+  }
   k_force_final<<<1, 256, 0, st>>>(part, (int)nb, force);
   return hipGetLastError();
 }

@@ -43,6 +43,10 @@ hipError_t launch_flux_xy(const Dev &g, hipStream_t st);
 // Body force of the constant-mass-flux source from the boundary face fluxes
 // of directions D < ndir (default: all; the others must be periodic).
 hipError_t launch_force(const Dev &g, double *part, double *force, hipStream_t st, int ndir = -1);
+// The same body force from the primitive box alone (boundary face fluxes
+// evaluated here; bitwise launch_force's value over the flux kernels'
+// fluxes).  part: 2 RED_BLOCKS doubles.
+hipError_t launch_force_direct(const Dev &g, double *part, double *force, hipStream_t st);
 // With dtpart (update_blocks(g) doubles) each block also writes the largest
 // signal rate of its cells' new state (the CFL step of the next step).
 hipError_t launch_update(const Dev &g, const double *Un, const double *Uin, double *Uout,

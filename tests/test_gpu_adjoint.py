@@ -52,7 +52,42 @@ def adjoint_cases():
     c.dirichlet = {0: np.ascontiguousarray(P[:, :, :, 0]) * 1.01,
                    4: np.ascontiguousarray(P[:, 0, :, :]) * 0.99}
     out.append(("dirichlet3d_visc", c, P, None, 1e-3))
+    # the constant-mass-flux body force: a 3D channel (periodic last axis:
+    # the fused step, force from the x and y boundary fluxes) and a 2D one
+    # (walls on the last axis: the unfused step)
+    out.append(("channel_force3d", *_channel3d(), None, 2e-3))
+    out.append(("channel_force2d", *_channel2d(), None, 2e-3))
     return out
+
+
+def _channel3d():
+    """8 x 8 x 6 body-forced channel with a seeded 10 % pressure
+    perturbation.  (The channel's initial state has T = T_w everywhere, so
+    the isothermal wall ghost is the exact mirror image of its source and the
+    HLLC contact speed at the wall faces is zero to rounding: its branch, and
+    with it the linearisation, is then decided by rounding noise, differently
+    in any two implementations.  With T != T_w at the walls it is not.)"""
+    c, P = W.channel(nx=8, ny=8, nz=6)
+    x, y, z = W._mesh(c)
+    P = P.copy()
+    P[4] = P[4] * (1.0 + 0.1 * np.sin(2 * np.pi * x / 6.0) * np.cos(2.0 * y + 0.3) *
+                   np.cos(2 * np.pi * z / 4.0))
+    return c, P
+
+
+def _channel2d():
+    """12 x 10 plane channel with the constant-mass-flux body force (walls
+    along y, periodic along x), a seeded perturbation on the Poiseuille
+    profile."""
+    c = W.Case(name="channel2d", ndim=2, n=(12, 10, 1), lo=(0.0, -1.0, 0.0), hi=(3.0, 1.0, 1.0),
+               stretch=("uniform", "tanh2", "uniform"), beta=(0.0, 1.5, 0.0), gamma=1.4,
+               R=1.0 / 1.4 * 4.0, Pr=0.72, visc_law="power", mu_ref=1.0 / 300.0, T_ref=1.0,
+               visc_param=0.7, bc=("periodic", "periodic", "wall", "wall", "periodic", "periodic"),
+               T_wall=(0.0, 0.0, 1.0, 1.0, 0.0, 0.0), source="massflux")
+    x, y, _ = W._mesh(c)
+    P = W.random_smooth(c, seed=5, amp=0.1, p0=c.R)
+    P[1] = P[1] + 1.5 * (1.0 - y * y)
+    return c, P
 
 
 CASES = adjoint_cases()
@@ -179,21 +214,27 @@ def test_gradient_shorter_than_its_workspace_is_bitwise_the_same():
         assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("which", ["porous", "disturb"])
+@pytest.mark.parametrize("which", ["porous", "disturb", "channel"])
 def test_trajectory_gradient_matches_oracle(which):
-    case, P, K = _tiny_porous() if which == "porous" else _tiny_disturb()
+    if which == "channel":  # wall-pressure cost through the body-forced channel
+        case, P = _channel3d()
+        case.cost_face = 2
+        K = None
+    else:
+        case, P, K = _tiny_porous() if which == "porous" else _tiny_disturb()
     print(f"[trajectory gradient] {which}", flush=True)
     o = Oracle(case, K=K)
     U0 = o.cons(P)
-    dt, nsteps = (1e-3, 5) if which == "porous" else (2e-4, 5)
+    dt, nsteps = {"porous": (1e-3, 5), "disturb": (2e-4, 5), "channel": (2e-3, 5)}[which]
     J_or, gk_or, gu_or = o.gradient(U0, nsteps, dt)
     for seg in (2, 5):
         s = Solver(case, K=K, mode=2, nsteps=nsteps, seg_len=seg)
         J, gk, gu = s.gradient(torch.as_tensor(U0, device="cuda"),
                                torch.full((1,), dt, dtype=torch.float64, device="cuda"))
         assert abs(J.item() - J_or) <= 1e-12 * abs(J_or)
-        gk = gk.cpu().numpy()
-        assert np.abs(gk - gk_or).max() <= VJP_TOL * np.abs(gk_or).max(), (seg, gk, gk_or)
+        if s.nk:
+            gk = gk.cpu().numpy()
+            assert np.abs(gk - gk_or).max() <= VJP_TOL * np.abs(gk_or).max(), (seg, gk, gk_or)
         gu = gu.cpu().numpy()
         err = np.abs(gu - gu_or).max(axis=(1, 2, 3)) / np.abs(gu_or).max(axis=(1, 2, 3))
         assert np.all(err <= VJP_TOL), (seg, err)

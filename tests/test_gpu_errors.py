@@ -60,16 +60,6 @@ def test_unpaired_periodic_face_rejected():
     assert ei.value.code == -1 and "pairs" in str(ei.value)
 
 
-def test_adjoint_of_body_force_unsupported():
-    case, P = W.channel(nx=8, ny=8, nz=8)
-    s = Solver(case, mode=1)
-    U = s.init_state(P)
-    dt = torch.full((1,), 1e-4, dtype=torch.float64, device="cuda")
-    with pytest.raises(B.DcfError) as ei:
-        s.vjp_step(U, dt, torch.zeros_like(U))
-    assert ei.value.code == -6
-
-
 def test_bad_porous_strip_and_params():
     case, P, K = W.porous_bl(nx=32, ny=16, strip=(8, 24), nsteps=1)
     bad = W.Case(**{**case.__dict__, "porous_end": 40})
