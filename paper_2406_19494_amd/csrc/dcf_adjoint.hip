@@ -210,24 +210,14 @@ __device__ void hllc_vjp(const double *qL, const double *qR, double gamma, doubl
 
 // Flux adjoint at face f of direction D from the stage-output adjoint Wb:
 // with Rb = b dt Wb (the right-hand-side adjoint, 5-component flux layout),
-// Fb[m] = Rb_m(cell f)/dx_f - Rb_m(cell f-1)/dx_{f-1}.  With the mass-flux
-// body force f = -sum_c V_c R_rhou(c) / W the x-momentum right-hand side of
-// every cell also carries -f-bar V_c / W (the force's dependence on the
-// face fluxes; it telescopes to the boundary faces, as in the forward).
+// Fb[m] = Rb_m(cell f)/dx_f - Rb_m(cell f-1)/dx_{f-1}.  (With the body
+// force A.Wb is the copy k_force_adj_apply corrected.)
 __device__ __forceinline__ void face_adjoint(const Dev &g, const AdjBuffers &A, int D,
                                              const int *pos, int f, double *Fb) {
   const long nc = g.ncell;
   const int nd = g.ndim;
   const double s = A.bcoef * A.dtp[0];
   const long vo[5] = {0, nc, 2 * nc, 3 * nc, (long)(nd + 1) * nc};
-  const bool force = g.source == SRC_MASSFLUX;
-  const double fw = force ? A.src[1] / A.src[2] : 0.0;  // f-bar / W
-  auto vol = [&](const int *cp) {
-    double V = g.dx[0][cp[0]];
-    if (nd >= 2) V *= g.dx[1][cp[1]];
-    if (nd >= 3) V *= g.dx[2][cp[2]];
-    return V;
-  };
   for (int m = 0; m < 5; ++m) Fb[m] = 0.0;
   int cpos[3] = {pos[0], pos[1], pos[2]};
   if (f < g.n[D]) {
@@ -235,22 +225,14 @@ __device__ __forceinline__ void face_adjoint(const Dev &g, const AdjBuffers &A, 
     long c = ((long)cpos[2] * g.n[1] + cpos[1]) * g.n[0] + cpos[0];
     double id = g.idx[D][f];
     for (int m = 0; m < 5; ++m)
-      if (m < 2 || m == 4 || m <= nd) {
-        double r = s * A.Wb[vo[m] + c];
-        if (force && m == 1) r -= fw * vol(cpos);
-        Fb[m] += r * id;
-      }
+      if (m < 2 || m == 4 || m <= nd) Fb[m] += (s * A.Wb[vo[m] + c]) * id;
   }
   if (f >= 1) {
     cpos[D] = f - 1;
     long c = ((long)cpos[2] * g.n[1] + cpos[1]) * g.n[0] + cpos[0];
     double id = g.idx[D][f - 1];
     for (int m = 0; m < 5; ++m)
-      if (m < 2 || m == 4 || m <= nd) {
-        double r = s * A.Wb[vo[m] + c];
-        if (force && m == 1) r -= fw * vol(cpos);
-        Fb[m] -= r * id;
-      }
+      if (m < 2 || m == 4 || m <= nd) Fb[m] -= (s * A.Wb[vo[m] + c]) * id;
   }
 }
 
@@ -754,7 +736,7 @@ __device__ __forceinline__ void ghost_cell(const Dev &g, long t, int *p) {
 // are the whole value), the tangential gather, and mu'(T) folded into T.
 // Interior cells take the same three steps in k_interior_vjp.
 template <int NDIM>
-__global__ void __launch_bounds__(256) k_tangential_vjp(Dev g, AdjBuffers A) {
+__global__ void __launch_bounds__(64) k_tangential_vjp(Dev g, AdjBuffers A) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.nbox - g.ncell) return;
   int p[3];
@@ -1066,6 +1048,30 @@ __global__ void __launch_bounds__(256) k_force_adj_partial(Dev g, AdjBuffers A) 
   }
 }
 
+// With the mass-flux body force f = -sum_c V_c R_rhou(c) / W every cell's
+// x-momentum right-hand side also carries the force's dependence on the
+// face fluxes: its adjoint gets -f-bar V_c / W (between the cells of a line
+// these terms cancel in the face adjoints, leaving the boundary faces, as in
+// the forward's boundary-flux form).  Written as a copy of the stage-output
+// adjoint whose x-momentum component is Wb_rhou - f-bar V_c / (W b dt); the
+// flux adjoints read the copy (the other kernels the stage's own Wb).
+__global__ void __launch_bounds__(256) k_force_adj_apply(Dev g, AdjBuffers A, double *Wc) {
+  const unsigned cu = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cu >= (unsigned)g.ncell) return;
+  const long nc = g.ncell;
+  const int nd = g.ndim;
+  const unsigned n0 = g.n[0], n01 = n0 * (unsigned)g.n[1];
+  const int k = (int)(cu / n01), j = (int)((cu % n01) / n0), i = (int)(cu % n0);
+  double V = g.dx[0][i];
+  if (nd >= 2) V *= g.dx[1][j];
+  if (nd >= 3) V *= g.dx[2][k];
+  const double s = A.bcoef * A.dtp[0];
+  for (int v = 0; v < nd + 2; ++v) {
+    const double w = A.Wb[(long)v * nc + cu];
+    Wc[(long)v * nc + cu] = v == 1 ? w - (A.src[1] / A.src[2]) * V / s : w;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_force_adj_final(AdjBuffers A, int nparts) {
   __shared__ double sh[2][256];
   double v[2] = {0.0, 0.0};
@@ -1091,14 +1097,15 @@ __global__ void __launch_bounds__(256) k_force_adj_final(AdjBuffers A, int npart
 
 // ---------------------------------------------------------------------------
 // Interior: Vb = b Wb + (dQ/dU)^T Qb, with Q = (rho, u, v, w, p, T(p, rho)).
-// acc_out = acc_in + a Wb (the Un adjoint accumulator); with fold != 0 the
-// accumulator is added into Vb instead (last stage, V = Un).
+// In the first stage (fold != 0, V = Un) Vb also takes the Un terms of the
+// later stages' combinations, a3 W3 + a2 W2 (their output adjoints, still
+// held), so no accumulator crosses the stages.
 // ---------------------------------------------------------------------------
 template <int NDIM>
 __global__ void __launch_bounds__(256) k_interior_vjp(Dev g, AdjBuffers A, const double *V,
                                                       const double *Wb, double a, double b,
-                                                      double *Vb, const double *acc_in,
-                                                      double *acc_out, int fold) {
+                                                      double *Vb, const double *w3, double a3,
+                                                      const double *w2, double a2, int fold) {
   constexpr int nd = NDIM;
   const unsigned cu = blockIdx.x * blockDim.x + threadIdx.x;  // ncell < 2^31
   if (cu >= (unsigned)g.ncell) return;
@@ -1156,12 +1163,11 @@ __global__ void __launch_bounds__(256) k_interior_vjp(Dev g, AdjBuffers A, const
     const long x = (long)v * nc + c;
     double w = Wb[x];
     double vb = b * w + Ub[v];
-    double accv = (acc_in ? acc_in[x] : 0.0) + a * w;
     if (fold) {
+      const double accv = ((0.0 + a3 * w3[x]) + a2 * w2[x]) + a * w;
       Vb[x] = accv + vb;
     } else {
       Vb[x] = vb;
-      acc_out[x] = accv;
     }
   }
 }
@@ -1209,7 +1215,8 @@ static hipError_t disturb_sums(const Dev &g, const AdjBuffers &A, int d, double 
 // (cleared once with the workspace; the kernels keep it so).
 static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A0, const double *V, const double *Wb,
                             const double *dt, double a, double b, double *Vb,
-                            const double *acc_in, double *acc_out, int fold, double *dJdK,
+                            const double *w3, double a3, const double *w2, double a2,
+                            int fold, double *dJdK,
                             hipStream_t st, bool have_box) {
   const bool visc = g.visc != VISC_NONE;
   AdjBuffers A = A0;
@@ -1218,12 +1225,15 @@ static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A0, const double *V,
   A.bcoef = b;
   if (!have_box) DCF_TRY(launch_prim_halo(g, V, st));  // the stage's primitive box
   if (g.source == SRC_MASSFLUX) {
-    // the stage's body force f (as the forward stage computed it) and f-bar
+    // the stage's body force f (as the forward stage computed it), f-bar,
+    // and the x-momentum adjoint corrected for the force's dependence
     DCF_TRY(launch_force_direct(g, A.spart, A.src, st));
     const unsigned nb = (unsigned)std::min<long>((g.ncell + 255) / 256, RED_BLOCKS);
     k_force_adj_partial<<<nb, 256, 0, st>>>(g, A);
     k_force_adj_final<<<1, 256, 0, st>>>(A, (int)nb);
+    k_force_adj_apply<<<blocks(g.ncell), 256, 0, st>>>(g, A, A.fwb);
     DCF_TRY(hipGetLastError());
+    A.Wb = A.fwb;  // for the flux adjoints; k_interior_vjp takes Wb itself
   }
   if (g.ndim == 2) {
     const unsigned nx = tile_count<-3, 2>(g, 0), ny = tile_count<-3, 2>(g, 1);
@@ -1241,7 +1251,7 @@ static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A0, const double *V,
   if ((visc || g.ndim == 2) && g.nbox > g.ncell) {  // 2D: also the y tiles' side arrays
     auto tk = g.ndim == 1 ? k_tangential_vjp<1>
                           : (g.ndim == 2 ? k_tangential_vjp<2> : k_tangential_vjp<3>);
-    tk<<<blocks(g.nbox - g.ncell), 256, 0, st>>>(g, A);
+    tk<<<(unsigned)((g.nbox - g.ncell + 63) / 64), 64, 0, st>>>(g, A);
     DCF_TRY(hipGetLastError());
   }
   // the halo transposes, axes z, y, x
@@ -1253,7 +1263,7 @@ static hipError_t stage_vjp(const Dev &g, const AdjBuffers &A0, const double *V,
     DCF_TRY(disturb_sums(g, A, d, dJdK, st));
   }
   auto ik = g.ndim == 1 ? k_interior_vjp<1> : (g.ndim == 2 ? k_interior_vjp<2> : k_interior_vjp<3>);
-  ik<<<blocks(g.ncell), 256, 0, st>>>(g, A, V, Wb, a, b, Vb, acc_in, acc_out, fold);
+  ik<<<blocks(g.ncell), 256, 0, st>>>(g, A, V, Wb, a, b, Vb, w3, a3, w2, a2, fold);
   return hipGetLastError();
 }
 
@@ -1263,12 +1273,15 @@ hipError_t vjp_step(Dev g, const AdjBuffers &A, const double *Un, const double *
   const bool have = boxes != nullptr;  // stage boxes cached by the forward recompute
   const Dev &g3 = have ? boxes[2] : g, &g2 = have ? boxes[1] : g, &g1 = have ? boxes[0] : g;
   // stage 3: W = Un/3 + 2/3 (U2 + dt R(U2))
-  DCF_TRY(stage_vjp(g3, A, U2, lam1, dt, 1.0 / 3.0, 2.0 / 3.0, A.Ub2, nullptr, A.acc, 0, dJdK,
-                    st, have));
+  DCF_TRY(stage_vjp(g3, A, U2, lam1, dt, 1.0 / 3.0, 2.0 / 3.0, A.Ub2, nullptr, 0.0, nullptr, 0.0,
+                    0, dJdK, st, have));
   // stage 2: W = 3/4 Un + 1/4 (U1 + dt R(U1))
-  DCF_TRY(stage_vjp(g2, A, U1, A.Ub2, dt, 0.75, 0.25, A.Ub1, A.acc, A.acc, 0, dJdK, st, have));
+  DCF_TRY(stage_vjp(g2, A, U1, A.Ub2, dt, 0.75, 0.25, A.Ub1, nullptr, 0.0, nullptr, 0.0, 0, dJdK,
+                    st, have));
   // stage 1: W = Un + dt R(Un)
-  DCF_TRY(stage_vjp(g1, A, Un, A.Ub1, dt, 0.0, 1.0, lam0, A.acc, nullptr, 1, dJdK, st, have));
+  // (Un enters stage 3 with weight 1/3 and stage 2 with 3/4)
+  DCF_TRY(stage_vjp(g1, A, Un, A.Ub1, dt, 0.0, 1.0, lam0, lam1, 1.0 / 3.0, A.Ub2, 0.75, 1, dJdK,
+                    st, have));
   return hipSuccess;
 }
 

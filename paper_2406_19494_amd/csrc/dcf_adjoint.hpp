@@ -12,8 +12,9 @@ struct AdjBuffers {
   double *Gb[9];    // adjoint of cell-centred velocity derivatives d u_phi / d x_t (3 t + phi)
   double *Qby[NQ];  // 2D: the y-direction tiles' Qb contributions (no w), added to Qb's
                     // on ghost and interior cells; every cell read is written each stage
-  double *Ub1, *Ub2, *acc;  // stage adjoints and the running lambda^n accumulator
+  double *Ub1, *Ub2;  // stage adjoints
   const double *Wb;  // stage-output adjoint of the stage being reversed
+  double *fwb;       // (body force) Wb with the corrected x-momentum component
   const double *dtp; // step size (device)
   double bcoef;      // weight b of the stage's V + dt R(V) term
   double *src;      // body-force adjoint of a stage: f, f-bar = sum Rb_rhou + Rb_E u, volume
@@ -39,7 +40,6 @@ template <class Carver> void carve_adjoint(Carver &cv, const Dev &g, AdjBuffers 
     a.Qby[q] = (g.ndim == 2 && q != QW) ? cv.template take<double>(g.nboxp) : nullptr;
   a.Ub1 = cv.template take<double>((long)g.nv * g.ncell);
   a.Ub2 = cv.template take<double>((long)g.nv * g.ncell);
-  a.acc = cv.template take<double>((long)g.nv * g.ncell);
   long cols = 1;
   for (int d = 0; d < g.ndim; ++d) {
     const int t1 = tan1(d), t2 = tan2(d);
@@ -49,6 +49,7 @@ template <class Carver> void carve_adjoint(Carver &cv, const Dev &g, AdjBuffers 
   a.dcols = cols;
   a.dpart = cv.template take<double>(4 * cols);
   a.src = cv.template take<double>(4);
+  a.fwb = cv.template take<double>((long)g.nv * g.ncell);
   a.spart = cv.template take<double>(2 * RED_BLOCKS);
 }
 
