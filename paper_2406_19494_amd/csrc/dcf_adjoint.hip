@@ -212,27 +212,36 @@ __device__ void hllc_vjp(const double *qL, const double *qR, double gamma, doubl
 // with Rb = b dt Wb (the right-hand-side adjoint, 5-component flux layout),
 // Fb[m] = Rb_m(cell f)/dx_f - Rb_m(cell f-1)/dx_{f-1}.  (With the body
 // force A.Wb is the copy k_force_adj_apply corrected.)
+template <int NDIM>
 __device__ __forceinline__ void face_adjoint(const Dev &g, const AdjBuffers &A, int D,
                                              const int *pos, int f, double *Fb) {
   const long nc = g.ncell;
-  const int nd = g.ndim;
   const double s = A.bcoef * A.dtp[0];
-  const long vo[5] = {0, nc, 2 * nc, 3 * nc, (long)(nd + 1) * nc};
-  for (int m = 0; m < 5; ++m) Fb[m] = 0.0;
+  const long vo[5] = {0, nc, 2 * nc, 3 * nc, (long)(NDIM + 1) * nc};
+  // both cells' loads are issued unconditionally (at clamped positions, in
+  // bounds) and together; only the sums depend on the cell existing
+  const bool hr = f < g.n[D], hl = f >= 1;
   int cpos[3] = {pos[0], pos[1], pos[2]};
-  if (f < g.n[D]) {
-    cpos[D] = f;
-    long c = ((long)cpos[2] * g.n[1] + cpos[1]) * g.n[0] + cpos[0];
-    double id = g.idx[D][f];
-    for (int m = 0; m < 5; ++m)
-      if (m < 2 || m == 4 || m <= nd) Fb[m] += (s * A.Wb[vo[m] + c]) * id;
+  cpos[D] = hr ? f : g.n[D] - 1;
+  const long cr = ((long)cpos[2] * g.n[1] + cpos[1]) * g.n[0] + cpos[0];
+  cpos[D] = hl ? f - 1 : 0;
+  const long cl = ((long)cpos[2] * g.n[1] + cpos[1]) * g.n[0] + cpos[0];
+  const double idr = g.idx[D][hr ? f : g.n[D] - 1], idl = g.idx[D][hl ? f - 1 : 0];
+  double wr[5], wl[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const bool on = m < 2 || m == 4 || m <= NDIM;
+    wr[m] = on ? A.Wb[vo[m] + cr] : 0.0;
+    wl[m] = on ? A.Wb[vo[m] + cl] : 0.0;
   }
-  if (f >= 1) {
-    cpos[D] = f - 1;
-    long c = ((long)cpos[2] * g.n[1] + cpos[1]) * g.n[0] + cpos[0];
-    double id = g.idx[D][f - 1];
-    for (int m = 0; m < 5; ++m)
-      if (m < 2 || m == 4 || m <= nd) Fb[m] -= (s * A.Wb[vo[m] + c]) * id;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    Fb[m] = 0.0;
+    if (!(m < 2 || m == 4 || m <= NDIM)) continue;
+    const double r = Fb[m] + (s * wr[m]) * idr;
+    Fb[m] = hr ? r : Fb[m];
+    const double l = Fb[m] - (s * wl[m]) * idl;
+    Fb[m] = hl ? l : Fb[m];
   }
 }
 
@@ -371,7 +380,7 @@ __device__ __forceinline__ void dir_vjp_tile(const Dev &g, const AdjBuffers &A, 
   if (active) {
     int pos[3] = {t.line[0], t.line[1], t.line[2]};
     pos[D] = f;
-    face_adjoint(g, A, D, pos, f, Fb);
+    face_adjoint<NDIM>(g, A, D, pos, f, Fb);
     base = bidx(g, pos[0], pos[1], pos[2]);
     double qL[5], qR[5];
 #pragma unroll
@@ -669,25 +678,47 @@ __device__ __forceinline__ double dviscosity(const Dev &g, double T, double mu) 
 // Gather of the tangential-derivative adjoints at box cell p: y = x + k along
 // t contributes coef(k) mc(y) Gb(y); the metric factors of the (at most
 // four) neighbours along each axis are shared by the NDIM velocity components.
-template <int NDIM>
+// INTERIOR: p is an interior cell (else a box cell of the ghost layers).
+template <int NDIM, bool INTERIOR>
 __device__ __forceinline__ void tangential_gather(const Dev &g, const AdjBuffers &A, const int *p,
                                                   long b, double *add) {
   constexpr int ks[4] = {-1, 1, -2, 2};
   constexpr double cf[4] = {8.0 / 12.0, -8.0 / 12.0, -1.0 / 12.0, 1.0 / 12.0};
-#pragma unroll
-  for (int phi = 0; phi < NDIM; ++phi) add[phi] = 0.0;
+  // Every load is issued first, so all of them are in flight together, then
+  // the terms of the interior neighbours are summed in the order of the
+  // definition (selects, no branches).  A neighbour that is not an interior
+  // cell reads the cell itself and the metric at the cell's (clamped)
+  // position instead, in bounds either way; an interior cell's neighbours
+  // all lie in the box (two of its three ghost layers at most).
+  double mct[NDIM][4], gv[NDIM][4][NDIM];
+  bool in[NDIM][4];
 #pragma unroll
   for (int t = 0; t < NDIM; ++t) {
     const long st = g.sb[t];
+    const int pt = INTERIOR ? p[t] : min(max(p[t], 0), g.n[t] - 1);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int yt = p[t] + ks[r];
-      if (yt < 0 || yt >= g.n[t]) continue;
-      const double w = cf[r] * g.mc[t][yt];
+      in[t][r] = yt >= 0 && yt < g.n[t];
+      mct[t][r] = g.mc[t][in[t][r] ? yt : pt];
+      const long bb = (INTERIOR || in[t][r]) ? b + ks[r] * st : b;
 #pragma unroll
-      for (int phi = 0; phi < NDIM; ++phi) add[phi] += w * A.Gb[3 * t + phi][b + ks[r] * st];
+      for (int phi = 0; phi < NDIM; ++phi) gv[t][r][phi] = A.Gb[3 * t + phi][bb];
     }
   }
+#pragma unroll
+  for (int phi = 0; phi < NDIM; ++phi) add[phi] = 0.0;
+#pragma unroll
+  for (int t = 0; t < NDIM; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double w = cf[r] * mct[t][r];
+#pragma unroll
+      for (int phi = 0; phi < NDIM; ++phi) {
+        const double sum = add[phi] + w * gv[t][r][phi];
+        add[phi] = in[t][r] ? sum : add[phi];
+      }
+    }
 }
 
 // Adjoint components carried through the halo fill: rho, the active
@@ -742,23 +773,44 @@ __global__ void __launch_bounds__(64) k_tangential_vjp(Dev g, AdjBuffers A) {
   int p[3];
   ghost_cell(g, t, p);
   const long b = bidx(g, p[0], p[1], p[2]);
-  if constexpr (NDIM == 2) {
-    if (p[0] >= 0 && p[0] < g.n[0]) {  // a y ghost (x ghosts: x tiles only)
+  const bool visc = g.visc != VISC_NONE;
+  // every load first (Qb, Qby and Gb may overlap as far as the compiler
+  // knows, which would serialise loads behind stores), then the stores
+  // 2D: a y ghost's adjoint is the y tiles' side array (x ghosts: x tiles only)
+  const bool side = NDIM == 2 && p[0] >= 0 && p[0] < g.n[0];
+  const bool gather = NDIM >= 2 && A.Gb[0] != nullptr;
+  // every active component is read (from the side array or from Qb; both
+  // exist for each of them), whichever of them the stores below use
+  double qb[NQ];
 #pragma unroll
-      for (int i = 0; i < HaloQ<2>::nq; ++i) {
-        const int q = HaloQ<2>::qs[i];
-        A.Qb[q][b] = 0.0 + A.Qby[q][b];
-      }
-      if (g.visc != VISC_NONE) A.Qb[QMU][b] = 0.0 + A.Qby[QMU][b];
+  for (int q = 0; q < NQ; ++q) {
+    if (q == QW && NDIM < 3) {
+      qb[q] = 0.0;
+      continue;
+    }
+    const double x = (side ? A.Qby[q] : A.Qb[q])[b];
+    qb[q] = side ? 0.0 + x : x;
+  }
+  double add[NDIM];
+  if (gather) tangential_gather<NDIM, false>(g, A, p, b, add);
+  const double Tq = g.Q[QT][b], muq = g.Q[QMU][b];  // (every box array exists)
+  const double dmu = visc ? dviscosity(g, Tq, muq) : 0.0;
+  if (side) {
+#pragma unroll
+    for (int i = 0; i < HaloQ<NDIM>::nq; ++i) {
+      const int q = HaloQ<NDIM>::qs[i];
+      A.Qb[q][b] = qb[q];
+    }
+    if (visc) A.Qb[QMU][b] = qb[QMU];
+  }
+  if (gather) {
+#pragma unroll
+    for (int phi = 0; phi < NDIM; ++phi) {
+      qb[QU + phi] += add[phi];
+      A.Qb[QU + phi][b] = qb[QU + phi];
     }
   }
-  if (NDIM >= 2 && A.Gb[0] != nullptr) {
-    double add[NDIM];
-    tangential_gather<NDIM>(g, A, p, b, add);
-#pragma unroll
-    for (int phi = 0; phi < NDIM; ++phi) A.Qb[QU + phi][b] += add[phi];
-  }
-  if (g.visc != VISC_NONE) A.Qb[QT][b] += dviscosity(g, g.Q[QT][b], g.Q[QMU][b]) * A.Qb[QMU][b];
+  if (visc) A.Qb[QT][b] = qb[QT] + dmu * qb[QMU];
 }
 
 // Source cell of ghost layer m (0 nearest the face) on side `side` of an axis
@@ -1114,6 +1166,19 @@ __global__ void __launch_bounds__(256) k_interior_vjp(Dev g, AdjBuffers A, const
   const unsigned n0 = g.n[0], n01 = n0 * (unsigned)g.n[1];
   const int k = (int)(cu / n01), j = (int)((cu % n01) / n0), i = (int)(cu % n0);
   const long bx = bidx(g, i, j, k);
+  // the cell's state and stage-output adjoints (and the fold's inputs)
+  // first: every load of the kernel before the first store (Vb may be an
+  // input array as far as the compiler knows), as few round trips as the
+  // branches allow
+  double Vc[nd + 2], wv[nd + 2], f3[nd + 2], f2[nd + 2];
+#pragma unroll
+  for (int v = 0; v < nd + 2; ++v) {
+    const long x = (long)v * nc + c;
+    Vc[v] = V[x];
+    wv[v] = Wb[x];
+    f3[v] = fold ? w3[x] : 0.0;
+    f2[v] = fold ? w2[x] : 0.0;
+  }
   // the primitive adjoint of the cell: the flux adjoints' (x tiles plus, in
   // 2D, the y tiles' side arrays) with the halo transposes' contributions,
   // the tangential gather, and mu'(T) folded into T
@@ -1132,18 +1197,18 @@ __global__ void __launch_bounds__(256) k_interior_vjp(Dev g, AdjBuffers A, const
   if (NDIM >= 2 && A.Gb[0] != nullptr) {
     const int pc[3] = {i, j, k};
     double add[NDIM];
-    tangential_gather<NDIM>(g, A, pc, bx, add);
+    tangential_gather<NDIM, true>(g, A, pc, bx, add);
 #pragma unroll
     for (int phi = 0; phi < NDIM; ++phi) ub[phi] += add[phi];
   }
-  if (visc) Tb += dviscosity(g, g.Q[QT][bx], g.Q[QMU][bx]) * mub;
+  const double Tq = g.Q[QT][bx], muq = g.Q[QMU][bx];  // (every box array exists)
+  if (visc) Tb += dviscosity(g, Tq, muq) * mub;
   if (g.source == SRC_MASSFLUX)  // energy source f u: u-bar += Rb_E f
-    ub[0] += (A.bcoef * A.dtp[0] * Wb[(long)(nd + 1) * nc + c]) * A.src[0];
-  double rho = V[c];
+    ub[0] += (A.bcoef * A.dtp[0] * wv[nd + 1]) * A.src[0];
+  double rho = Vc[0];
   double ir = 1.0 / rho;
-  double u[3] = {V[nc + c] * ir, nd >= 2 ? V[2 * nc + c] * ir : 0.0,
-                 nd >= 3 ? V[3 * nc + c] * ir : 0.0};
-  double E = V[(long)(nd + 1) * nc + c];
+  double u[3] = {Vc[1] * ir, nd >= 2 ? Vc[2] * ir : 0.0, nd >= 3 ? Vc[3] * ir : 0.0};
+  double E = Vc[nd + 1];
   double k2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   double p = (g.gamma - 1.0) * (E - 0.5 * rho * k2);
   double T = p / (rho * g.R);
@@ -1161,10 +1226,10 @@ __global__ void __launch_bounds__(256) k_interior_vjp(Dev g, AdjBuffers A, const
 #pragma unroll
   for (int v = 0; v < nd + 2; ++v) {
     const long x = (long)v * nc + c;
-    double w = Wb[x];
+    const double w = wv[v];
     double vb = b * w + Ub[v];
     if (fold) {
-      const double accv = ((0.0 + a3 * w3[x]) + a2 * w2[x]) + a * w;
+      const double accv = ((0.0 + a3 * f3[v]) + a2 * f2[v]) + a * w;
       Vb[x] = accv + vb;
     } else {
       Vb[x] = vb;

@@ -544,8 +544,15 @@ __device__ __forceinline__ void flux_x_body(const Dev &g, int nwmax, unsigned bi
   for (int m = 0; m < 5; ++m) F[m * fc + t] = G[m];
 }
 
+// Occupancy target of the x / x+y flux launches: 5 waves per SIMD with
+// WENO5-JS (no spill; the tiles are bound by per-wave latency, so the extra
+// wave pays); the TENO6-A instantiations keep the compiler's own allocation
+// (5 waves would spill there).
+constexpr int flux_waves(int sch) { return sch == SCHEME_WENO5 ? 5 : 1; }
+
 template <int NDIM, bool VISC, int SCH = SCHEME_WENO5>
-__global__ void __launch_bounds__(256) k_flux_x(Dev g, int nwmax) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(flux_waves(SCH))))
+k_flux_x(Dev g, int nwmax) {
   extern __shared__ double lds[];
   flux_x_body<NDIM, VISC, SCH>(g, nwmax, blockIdx.x, lds);
 }
@@ -629,8 +636,8 @@ __device__ __forceinline__ void flux_yz_body(const Dev &g, unsigned lin, unsigne
 // first ny_tiles workgroups take y tiles, the rest x chunks; both kinds
 // share one dynamic LDS buffer.
 template <bool VISC, int SCH = SCHEME_WENO5>
-__global__ void __launch_bounds__(256) k_flux_xy(Dev g, int nwmax, unsigned ny_tiles,
-                                                 unsigned nbx, unsigned nby, int remap_x) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(flux_waves(SCH))))
+k_flux_xy(Dev g, int nwmax, unsigned ny_tiles, unsigned nbx, unsigned nby, int remap_x) {
   extern __shared__ double lds[];
   if (blockIdx.x < ny_tiles)
     flux_yz_tile<3, 1, VISC, SCH>(g, *reinterpret_cast<YzTile<3, VISC> *>(lds), blockIdx.x,
@@ -774,7 +781,8 @@ __device__ __forceinline__ double box_face_xmom_flux(const Dev &g, const int *p,
 // have no face fluxes): the sums of k_force_partial over every direction,
 // with each boundary flux evaluated by box_face_xmom_flux.  A periodic
 // direction's two boundary faces see the same stencil values, so its terms
-// are exact zeros and the sums equal k_force_partial's bitwise.
+// are exact zeros (not evaluated) and the sums equal k_force_partial's
+// bitwise.
 template <int NDIM, bool VISC, int SCH>
 __global__ void __launch_bounds__(256) k_force_direct(Dev g, double *part) {
   __shared__ double sh[2 * 256];
@@ -798,7 +806,9 @@ __global__ void __launch_bounds__(256) k_force_direct(Dev g, double *part) {
     p[T1] = a;
     p[T2] = b;
     double F0 = 0.0, F1 = 0.0;
-    if (D == 0) {
+    if (g.bck[2 * D] == BC_PERIODIC && g.bck[2 * D + 1] == BC_PERIODIC) {
+      // equal fluxes: an exact zero either way, not evaluated
+    } else if (D == 0) {
       F0 = box_face_xmom_flux<NDIM, 0, VISC, SCH>(g, p, 0);
       F1 = box_face_xmom_flux<NDIM, 0, VISC, SCH>(g, p, g.n[0]);
     } else if (NDIM >= 2 && D == 1) {
@@ -876,41 +886,77 @@ __device__ __forceinline__ void flux_divergence(const Dev &g, int i, int j, int 
   }
 }
 
-// Source, then Uout = a Un + b (Uin + dt R) for cell c at (i, j, k) (or R
-// itself into Rout); returns the new state's signal rate when want_sigma.
-__device__ __forceinline__ double stage_apply(const Dev &g, const double *Un, const double *Uin,
-                                              double *Uout, double *Rout, const double *dtp,
-                                              double a, double bcoef, const double *force,
-                                              long c, int i, int j, int k, double *R,
-                                              bool want_sigma) {
-  const int nd = g.ndim;
+// The inputs of one cell's stage update: Un, Uin, dt and, with the body
+// force, the force and the cell's velocity.  They are loaded together, before
+// any store: Un or Uin may be Uout itself, so the compiler could not move a
+// later component's loads above an earlier component's store, and each
+// component would wait a full memory round trip.  (Issuing them before the
+// face fluxes of the divergence as well measured no faster.)
+template <int NDIM> struct CellIn {
+  double un[NDIM + 2], ui[NDIM + 2], dt, f, u;
+};
+
+template <int NDIM>
+__device__ __forceinline__ void load_cell(const Dev &g, const double *Un, const double *Uin,
+                                          const double *dtp, const double *force, long c, int i,
+                                          int j, int k, CellIn<NDIM> &in) {
+  const long nc = g.ncell;
+#pragma unroll
+  for (int v = 0; v < NDIM + 2; ++v) {
+    in.un[v] = Un[v * nc + c];
+    in.ui[v] = Uin[v * nc + c];
+  }
+  in.dt = dtp[0];
+  in.f = in.u = 0.0;
   if (g.source == SRC_MASSFLUX) {
-    double f = force[0];
-    long b = bidx(g, i, j, k);
-    R[1] += f;
-    R[4] += f * g.Q[QU][b];
+    in.f = force[0];
+    in.u = g.Q[QU][bidx(g, i, j, k)];
+  }
+}
+
+// Source, then Uout = a Un + b (Uin + dt R) for cell c of an NDIM grid; the
+// new state (rho, the three momenta, E; zeros for the unused ones) is left
+// in st.
+template <int NDIM>
+__device__ __forceinline__ void stage_apply_t(const Dev &g, const CellIn<NDIM> &in, double *Uout,
+                                              double a, double bcoef, long c, double *R,
+                                              double *st) {
+  constexpr int NV = NDIM + 2;
+  if (g.source == SRC_MASSFLUX) {
+    R[1] += in.f;
+    R[4] += in.f * in.u;
   }
   const long nc = g.ncell;
   // conserved component v <- flux entry m
-  double Rv[5];
+  double Rv[NV];
   Rv[0] = R[0];
   Rv[1] = R[1];
-  if (nd >= 2) Rv[2] = R[2];
-  if (nd >= 3) Rv[3] = R[3];
-  Rv[nd + 1] = R[4];
-  if (Rout) {
-    for (int v = 0; v < nd + 2; ++v) Rout[v * nc + c] = Rv[v];
-    return 0.0;
-  }
-  const double dt = dtp[0];
-  double st[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int v = 0; v < nd + 2; ++v) {
-    double un = Un[v * nc + c];
-    double ui = Uin[v * nc + c];
-    double uo = a * un + bcoef * (ui + dt * Rv[v]);
+  if (NDIM >= 2) Rv[2] = R[2];
+  if (NDIM >= 3) Rv[3] = R[3];
+  Rv[NV - 1] = R[4];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) st[v] = 0.0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double uo = a * in.un[v] + bcoef * (in.ui[v] + in.dt * Rv[v]);
     Uout[v * nc + c] = uo;
-    st[v == nd + 1 ? 4 : v] = uo;
+    st[v == NV - 1 ? 4 : v] = uo;
   }
+}
+
+// One cell's divergence + source + stage update of an NDIM grid (no barrier
+// inside); returns the new state's signal rate when want_sigma.
+template <int NDIM>
+__device__ __forceinline__ double update_cell_t(const Dev &g, const double *Un, const double *Uin,
+                                                double *Uout, const double *dtp, double a,
+                                                double bcoef, const double *force, long c,
+                                                int i, int j, int k, bool want_sigma) {
+  double R[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  flux_divergence(g, i, j, k, NDIM, R);
+  CellIn<NDIM> in;
+  load_cell<NDIM>(g, Un, Uin, dtp, force, c, i, j, k, in);
+  double st[5];
+  stage_apply_t<NDIM>(g, in, Uout, a, bcoef, c, R, st);
   if (!want_sigma) return 0.0;
   double q[6];
   prim_of_state(g, st, q);
@@ -918,17 +964,39 @@ __device__ __forceinline__ double stage_apply(const Dev &g, const double *Un, co
   return cell_sigma(g, q, pos);
 }
 
-// One cell's divergence + source + stage update (no barrier inside).
+// One cell's divergence + source + stage update (or R itself into Rout).
 __device__ __forceinline__ double update_cell(const Dev &g, const double *Un, const double *Uin,
                                               double *Uout, double *Rout, const double *dtp,
                                               double a, double bcoef, const double *force,
                                               unsigned cu, bool want_sigma) {
   const unsigned n0 = g.n[0], n01 = n0 * (unsigned)g.n[1];
   const int k = (int)(cu / n01), j = (int)((cu % n01) / n0), i = (int)(cu % n0);
+  const int nd = g.ndim;
+  const long c = (long)cu;
+  if (!Rout) {
+    if (nd == 3) return update_cell_t<3>(g, Un, Uin, Uout, dtp, a, bcoef, force, c, i, j, k,
+                                         want_sigma);
+    if (nd == 2) return update_cell_t<2>(g, Un, Uin, Uout, dtp, a, bcoef, force, c, i, j, k,
+                                         want_sigma);
+    return update_cell_t<1>(g, Un, Uin, Uout, dtp, a, bcoef, force, c, i, j, k, want_sigma);
+  }
   double R[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  flux_divergence(g, i, j, k, g.ndim, R);
-  return stage_apply(g, Un, Uin, Uout, Rout, dtp, a, bcoef, force, (long)cu, i, j, k, R,
-                     want_sigma);
+  flux_divergence(g, i, j, k, nd, R);
+  if (g.source == SRC_MASSFLUX) {
+    double f = force[0];
+    long b = bidx(g, i, j, k);
+    R[1] += f;
+    R[4] += f * g.Q[QU][b];
+  }
+  const long nc = g.ncell;
+  double Rv[5];
+  Rv[0] = R[0];
+  Rv[1] = R[1];
+  if (nd >= 2) Rv[2] = R[2];
+  if (nd >= 3) Rv[3] = R[3];
+  Rv[nd + 1] = R[4];
+  for (int v = 0; v < nd + 2; ++v) Rout[v * nc + c] = Rv[v];
+  return 0.0;
 }
 
 // With dtpart (uniform over the launch) every thread of the block reaches
@@ -994,19 +1062,22 @@ __device__ __forceinline__ void flux_update_body(const Dev &g, unsigned lin, uns
     p[D] = cD;
     p[3 - D] = oc;
     if (NDIM == 2) p[2] = 0;
+    const long c = ((long)p[2] * g.n[1] + p[1]) * g.n[0] + p[0];
     double R[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     flux_divergence(g, p[0], p[1], p[2], D, R);
     const double id = g.idx[D][cD];
 #pragma unroll
     for (int m = 0; m < 5; ++m) R[m] -= (fl[m][ty + 1][tx] - fl[m][ty][tx]) * id;
-    const long c = ((long)p[2] * g.n[1] + p[1]) * g.n[0] + p[0];
-    sig = stage_apply(g, Un, Uin, Uout, nullptr, dtp, a, bcoef, force, c, p[0], p[1], p[2], R,
-                      dtpart != nullptr);
+    CellIn<NDIM> in;
+    load_cell<NDIM>(g, Un, Uin, dtp, force, c, p[0], p[1], p[2], in);
+    double st[5];
+    stage_apply_t<NDIM>(g, in, Uout, a, bcoef, c, R, st);
+    double q[6];
+    if (dtpart || qo.Q[0]) prim_of_state(g, st, q);  // the new state's primitives
+    if (dtpart) sig = cell_sigma(g, q, p);
     if (qo.Q[0]) {
-      // the new state's primitives, converted from the values just stored
-      // exactly as k_prim_interior converts them
-      double q[6];
-      cons_to_prim(g, Uout, c, q);
+      // the new state's primitives (the values just stored, converted as
+      // k_prim_interior converts them) into the next stage's box
       if (!(finite_pos(q[QR]) && finite_pos(q[QP]))) atomicOr(g.flags, 1u);
       const long bx = bidx(g, p[0], p[1], p[2]);
       qo.Q[QR][bx] = q[QR];
@@ -1504,7 +1575,8 @@ __global__ void __launch_bounds__(256) kb_prim_ghost(const BatchEntry *tab) {
 }
 
 template <int NDIM, bool VISC>
-__global__ void __launch_bounds__(256) kb_flux_x(const BatchEntry *tab) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(flux_waves(SCHEME_WENO5))))
+kb_flux_x(const BatchEntry *tab) {
   extern __shared__ double lds[];
   const BatchEntry &e = tab[blockIdx.y];
   if (blockIdx.x >= e.nb_x) return;
@@ -1543,7 +1615,8 @@ __global__ void __launch_bounds__(256) kb_prim_ghost_s(const BatchEntry *tab, in
 }
 
 template <bool VISC>
-__global__ void __launch_bounds__(256) kb_flux_xy(const BatchEntry *tab, int stage) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(flux_waves(SCHEME_WENO5))))
+kb_flux_xy(const BatchEntry *tab, int stage) {
   extern __shared__ double lds[];
   const BatchEntry &e = tab[blockIdx.y];
   const unsigned ny_tiles = e.yz_ntot[1];
@@ -1557,7 +1630,8 @@ __global__ void __launch_bounds__(256) kb_flux_xy(const BatchEntry *tab, int sta
 }
 
 template <bool VISC>
-__global__ void __launch_bounds__(256) kb_flux_x_s(const BatchEntry *tab, int stage) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(flux_waves(SCHEME_WENO5))))
+kb_flux_x_s(const BatchEntry *tab, int stage) {
   extern __shared__ double lds[];
   const BatchEntry &e = tab[blockIdx.y];
   if (blockIdx.x >= e.nb_x) return;
