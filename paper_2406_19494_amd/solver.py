@@ -35,11 +35,14 @@ class Solver:
     forward + single-step VJP, 2 trajectory gradient with
     ``nsteps`` steps and checkpoints every ``seg_len`` steps, 3 as 2 with the
     stage boxes of a segment kept for the reverse sweep (more memory, no
-    recompute in the reverse sweep).
+    recompute in the reverse sweep).  In modes 2 and 3 seg_len = 0 takes the
+    longest spacing whose workspace fits ``seg_budget`` bytes (default 90 %
+    of the device memory free now): the whole trajectory resident whenever
+    it fits, which recomputes nothing (segment_length_for).
     """
 
     def __init__(self, case: Case, K=None, mode: int = 0, nsteps: int = 0, seg_len: int = 0,
-                 device: str = "cuda"):
+                 device: str = "cuda", seg_budget=None):
         if not torch.cuda.is_available():
             raise RuntimeError("the dcf library needs a GPU (no CPU fallback)")
         self.case = case
@@ -87,6 +90,11 @@ class Solver:
             th = K if torch.is_tensor(K) and K.numel() == self.nk else case.theta(
                 None if K is None else (K.cpu().numpy() if torch.is_tensor(K) else K))
             self.set_params(torch.as_tensor(th, dtype=torch.float64, device=self.device))
+        if mode >= 2 and seg_len == 0:
+            if seg_budget is None:
+                free, _ = torch.cuda.mem_get_info(self.device)
+                seg_budget = int(0.9 * free)
+            seg_len = segment_length_for(case, mode, nsteps, int(seg_budget))
         self.mode, self.nsteps, self.seg_len = mode, nsteps, seg_len
         self.workspace = None
         if mode >= 0:  # mode -1: no workspace (for dcf_rk3_step_noalloc)
@@ -291,6 +299,46 @@ def workspace_bytes_for(case: Case, mode: int, nsteps: int = 0, seg_len: int = 0
     B.call("dcf_workspace_size_for", C.byref(g), C.byref(gas), int(mode), int(nsteps),
            int(seg_len), C.byref(size))
     return size.value
+
+
+def segment_length_for(case: Case, mode: int, nsteps: int, budget_bytes: int) -> int:
+    """The checkpoint spacing of an nsteps-step trajectory gradient (mode 2 or
+    3) that recomputes the fewest steps within a workspace budget: the
+    largest seg_len whose workspace fits (every segment but the last is
+    recomputed, so a longer segment recomputes less; seg_len = nsteps keeps
+    the whole trajectory resident and recomputes nothing).  The workspace,
+    about (nsteps / seg_len + 3 seg_len) states in mode 2, grows with seg_len
+    beyond its minimum near sqrt(nsteps / 3), so the search runs on that
+    side.  Raises ValueError when not even the smallest workspace fits."""
+    if mode not in (2, 3) or nsteps < 1:
+        raise ValueError("a trajectory gradient workspace (mode 2 or 3, nsteps >= 1)")
+    def fits(S):
+        return workspace_bytes_for(case, mode, nsteps, S) <= budget_bytes
+    if fits(nsteps):
+        return nsteps
+    # smallest workspace over seg_len (it decreases, then increases)
+    lo = min(range(1, nsteps + 1),
+             key=lambda S: (workspace_bytes_for(case, mode, nsteps, S), -S)) \
+        if nsteps <= 64 else None
+    if lo is None:
+        lo = max(1, int(round((nsteps / 3.0) ** 0.5)))
+        while lo > 1 and workspace_bytes_for(case, mode, nsteps, lo - 1) <= \
+                workspace_bytes_for(case, mode, nsteps, lo):
+            lo -= 1
+        while lo < nsteps and workspace_bytes_for(case, mode, nsteps, lo + 1) < \
+                workspace_bytes_for(case, mode, nsteps, lo):
+            lo += 1
+    if not fits(lo):
+        raise ValueError(f"no checkpoint spacing fits {budget_bytes} bytes "
+                         f"(the smallest workspace is {workspace_bytes_for(case, mode, nsteps, lo)})")
+    hi = nsteps  # does not fit
+    while hi - lo > 1:  # invariant: fits(lo), not fits(hi)
+        mid = (lo + hi) // 2
+        if fits(mid):
+            lo = mid
+        else:
+            hi = mid
+    return lo
 
 
 class BatchPlan:

@@ -7,7 +7,7 @@ import torch
 
 from oracle.pyoracle import Oracle
 from paper_2406_19494_amd import workloads as W
-from paper_2406_19494_amd.solver import Solver
+from paper_2406_19494_amd.solver import Solver, workspace_bytes_for
 from tests.test_oracle_pins import _tiny_disturb, _tiny_porous
 
 pytestmark = pytest.mark.gpu
@@ -212,6 +212,25 @@ def test_gradient_shorter_than_its_workspace_is_bitwise_the_same():
     big.gradient_finish(gU)
     for a, b in zip(exact, (J, gK, gU)):
         assert torch.equal(a, b)
+
+
+def test_budgeted_segment_length_gives_the_same_gradient():
+    # seg_len = 0 picks the spacing from a workspace budget: with room for the
+    # whole trajectory one segment (no recompute), with less a shorter one;
+    # the gradient is the same up to summation order either way
+    case, P, K = _tiny_porous()
+    U0 = torch.as_tensor(Oracle(case, K=K).cons(P), device="cuda")
+    dt = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+    ref = Solver(case, K=K, mode=2, nsteps=12, seg_len=4).gradient(U0, dt)
+    whole = Solver(case, K=K, mode=2, nsteps=12, seg_len=0)
+    assert whole.seg_len == 12
+    tight_budget = workspace_bytes_for(case, 2, 12, 6)
+    tight = Solver(case, K=K, mode=2, nsteps=12, seg_len=0, seg_budget=tight_budget)
+    assert tight.seg_len == 6
+    for s in (whole, tight):
+        out = s.gradient(U0, dt)
+        for a, b in zip(ref, out):
+            assert torch.allclose(a, b, rtol=1e-12, atol=1e-14 * float(b.abs().max()))
 
 
 @pytest.mark.parametrize("which", ["porous", "disturb", "channel"])
