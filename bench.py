@@ -236,10 +236,17 @@ def serving_bench(M=40, rate=20.0, seed=2024, M_low=12, rate_low=2.0, seed_low=2
     for name, kw in (("sequential", None), ("streams", {"batched": False}),
                      ("batched", {"batched": True})):
         progress(f"serving: {name}")
+        retired = [0]
+
+        def on_finish(res, name=name):  # a progress line per 20 retired solves
+            retired[0] += 1
+            if retired[0] % 20 == 0:
+                progress(f"serving: {name}, {retired[0]} of {M} retired")
         if kw is None:
-            res, t, sch = S.serve_sequential(trace)
+            res, t, sch = S.serve_sequential(trace, on_finish=on_finish)
         else:
-            res, t, sch = S.serve(trace, budget_bytes=200e9, max_slots=16, **kw)
+            res, t, sch = S.serve(trace, budget_bytes=200e9, max_slots=16, on_finish=on_finish,
+                                  **kw)
         runs[name] = S.summarize(res, t) | {"peak_active": sch.peak_active}
         if name == "batched":
             runs[name]["graph_captures"] = getattr(sch.b, "recaptures", None)

@@ -129,8 +129,9 @@ class Scheduler:
     batching in epochs.  `backend` provides footprint/start/step/poll/finish."""
 
     def __init__(self, backend, budget_bytes: float, max_slots: int = 16,
-                 clock=time.perf_counter, idle_sleep: float = 2e-4):
+                 clock=time.perf_counter, idle_sleep: float = 2e-4, on_finish=None):
         self.b = backend
+        self.on_finish = on_finish  # called as on_finish(result) as each solve retires
         self.budget = float(budget_bytes)
         self.max_slots = max_slots
         self.clock = clock
@@ -190,6 +191,8 @@ class Scheduler:
                         active.remove(job)
                         self.in_use -= job.footprint
                         progressed = True
+                        if self.on_finish is not None:
+                            self.on_finish(res)
                     else:
                         if not self.b.step(job) and not job.events:
                             raise RuntimeError(f"request {job.spec.rid}: no work in flight "
@@ -570,7 +573,8 @@ class BatchedGpuBackend(GpuBackend):
 
 
 def serve(trace, budget_bytes=200e9, max_slots=16, steps_per_epoch=10, graphs=True,
-          keep_outputs=False, realtime=True, fault=None, batched=False, backend=None):
+          keep_outputs=False, realtime=True, fault=None, batched=False, backend=None,
+          on_finish=None):
     """Serve a trace; returns (results, makespan in s, scheduler).  A backend
     may be passed in to keep its pooled solves between calls."""
     if backend is None:
@@ -582,7 +586,7 @@ def serve(trace, budget_bytes=200e9, max_slots=16, steps_per_epoch=10, graphs=Tr
             backend = GpuBackend(steps_per_epoch=steps_per_epoch, graphs=graphs,
                                  keep_outputs=keep_outputs, fault=fault,
                                  budget_bytes=budget_bytes)
-    sch = Scheduler(backend, budget_bytes, max_slots)
+    sch = Scheduler(backend, budget_bytes, max_slots, on_finish=on_finish)
     t0 = time.perf_counter()
     res = sch.run(trace, realtime=realtime)
     backend.torch.cuda.synchronize()
@@ -590,7 +594,8 @@ def serve(trace, budget_bytes=200e9, max_slots=16, steps_per_epoch=10, graphs=Tr
 
 
 def serve_sequential(trace, steps_per_epoch=10, graphs=True, keep_outputs=False, realtime=True,
-                     backend=None):
+                     backend=None, on_finish=None):
     """Baseline: the same trace FIFO, one solve at a time on the same GPU."""
     return serve(trace, budget_bytes=float("inf"), max_slots=1, steps_per_epoch=steps_per_epoch,
-                 graphs=graphs, keep_outputs=keep_outputs, realtime=realtime, backend=backend)
+                 graphs=graphs, keep_outputs=keep_outputs, realtime=realtime, backend=backend,
+                 on_finish=on_finish)

@@ -83,6 +83,17 @@ def test_budget_never_exceeded_and_all_complete():
     assert sch.peak_in_use <= 100.0
 
 
+def test_completion_callback_sees_each_retired_solve_once():
+    clock = FakeClock()
+    be = FakeBackend(clock)
+    seen = []
+    sch = Scheduler(be, budget_bytes=100.0, max_slots=3, clock=clock, idle_sleep=0,
+                    on_finish=lambda r: seen.append((r.rid, r.status, r.finished is not None)))
+    res = sch.run(_trace([30, 40, 20, 50, 10]))
+    assert sorted(rid for rid, _, _ in seen) == sorted(res)
+    assert all(st == "ok" and done for _, st, done in seen)
+
+
 def test_oversize_request_rejected_others_complete():
     clock = FakeClock()
     be = FakeBackend(clock)
