@@ -208,7 +208,8 @@ dcf_status dcf_create(const dcf_grid *grid, const dcf_gas *gas, dcf_ctx **out) {
   g = g0;
   size_t total = 0;
   for (int d = 0; d < 3; ++d) total += 5 * (size_t)(g.n[d] + 1);
-  hipError_t e = hipMalloc((void **)&c->metric_mem, total * sizeof(double));
+  // (one more double: the x line length, computed once on the device)
+  hipError_t e = hipMalloc((void **)&c->metric_mem, (total + 1) * sizeof(double));
   if (e != hipSuccess) {
     delete c;
     return fail(DCF_EDEVICE, "hipMalloc(metrics): %s", hipGetErrorString(e));
@@ -236,6 +237,16 @@ dcf_status dcf_create(const dcf_grid *grid, const dcf_gas *gas, dcf_ctx **out) {
       return fail(DCF_EDEVICE, "metrics kernel: %s", hipGetErrorString(e));
     }
     p += 5 * m;
+  }
+  // the body force's volume term reads the x line length; summed once here in
+  // the order the reductions used to sum it per line
+  e = launch_line_length(g.dx[0], g.n[0], c->metric_mem + total, 0);
+  if (e == hipSuccess) e = hipMemcpy(&g.Lx, c->metric_mem + total, sizeof(double),
+                                     hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    (void)hipFree(c->metric_mem);
+    delete c;
+    return fail(DCF_EDEVICE, "line length: %s", hipGetErrorString(e));
   }
   *out = c;
   return DCF_OK;

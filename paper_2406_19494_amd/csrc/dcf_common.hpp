@@ -45,6 +45,7 @@ struct Dev {
   // centres (n) and at faces (n+1)
   const double *dx[3], *idx[3], *mc[3], *mf[3];
   const double *xm[3];   // cell-centre coordinates (midpoint of the two faces)
+  double Lx;             // the x cell widths summed in index order (an x line's length)
   // gas
   double gamma, R, Pr, cp, mu_ref, T_ref, vparam;
   double gm1i, cpPr;     // 1/(gamma - 1) and cp/Pr

@@ -51,6 +51,14 @@ __global__ void k_metrics(int kind, double lo, double hi, double beta, int n, do
   }
 }
 
+// The cell widths of an axis summed in index order (one thread: the order of
+// the sum is part of the value).
+__global__ void k_line_length(const double *dx, int n, double *out) {
+  double L = 0.0;
+  for (int i = 0; i < n; ++i) L += dx[i];
+  *out = L;
+}
+
 // ---------------------------------------------------------------------------
 // Primitives from conserved variables (Eq. (2), ideal gas).
 // ---------------------------------------------------------------------------
@@ -743,9 +751,7 @@ __global__ void __launch_bounds__(256) k_force_partial(Dev g, double *part, int 
     const double *F = g.F[D] + 1 * g.fcount[D];
     v[0] -= A * (F[f1] - F[f0]);
     if (D == 0) {  // volume: sum over x-lines of A_x * line length
-      double Lx = 0.0;
-      for (int i = 0; i < g.n[0]; ++i) Lx += g.dx[0][i];
-      v[1] += A * Lx;
+      v[1] += A * g.Lx;
     }
   }
   block_sum<2>(v, sh);
@@ -820,9 +826,7 @@ __global__ void __launch_bounds__(256) k_force_direct(Dev g, double *part) {
     }
     v[0] -= A * (F1 - F0);
     if (D == 0) {  // volume: sum over x-lines of A_x * line length
-      double Lx = 0.0;
-      for (int i = 0; i < g.n[0]; ++i) Lx += g.dx[0][i];
-      v[1] += A * Lx;
+      v[1] += A * g.Lx;
     }
   }
   block_sum<2>(v, sh);
@@ -1332,6 +1336,10 @@ hipError_t launch_axpy(double *y, double a, const double *x, long n, hipStream_t
   return hipGetLastError();
 }
 
+hipError_t launch_line_length(const double *dx, int n, double *out, hipStream_t st) {
+  k_line_length<<<1, 1, 0, st>>>(dx, n, out);
+  return hipGetLastError();
+}
 hipError_t launch_metrics(int kind, double lo, double hi, double beta, int n, double *dx,
                           double *idx, double *mc, double *mf, double *xm, hipStream_t st) {
   k_metrics<<<grid_for(n + 1), 256, 0, st>>>(kind, lo, hi, beta, n, dx, idx, mc, mf, xm);

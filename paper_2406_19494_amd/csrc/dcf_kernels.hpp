@@ -34,6 +34,8 @@ hipError_t launch_batch_step(const BatchEntry *tab_dev, const BatchEntry *tab_ho
 
 hipError_t launch_metrics(int kind, double lo, double hi, double beta, int n, double *dx,
                           double *idx, double *mc, double *mf, double *xm, hipStream_t st);
+// out[0] = dx[0] + dx[1] + ... + dx[n-1], summed in index order.
+hipError_t launch_line_length(const double *dx, int n, double *out, hipStream_t st);
 hipError_t launch_init_state(const Dev &g, const double *P, double *U, hipStream_t st);
 hipError_t launch_prim_halo(const Dev &g, const double *U, hipStream_t st);
 hipError_t launch_fluxes(const Dev &g, hipStream_t st);
