@@ -698,15 +698,16 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *sh /*[NV*BS]*
   for (int q = 0; q < NV; ++q) v[q] = sh[q * BS];
 }
 
+// Maximum over a 256-thread workgroup: within each 64-lane wavefront by lane
+// exchanges, then over the 4 wavefronts through LDS (sh: 4 doubles).  The
+// maximum is exact, so its value does not depend on the order.
 __device__ __forceinline__ double block_max(double v, double *sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  __syncthreads();  // a previous call's readers of sh are done
+  if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = v;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) sh[t] = fmax(sh[t], sh[t + w]);
-    __syncthreads();
-  }
-  return sh[0];
+  return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }
 
 // Body force, pass 1.  The volume-weighted sum of the unforced x-momentum
@@ -1018,7 +1019,7 @@ __device__ __forceinline__ void update_body(const Dev &g, const double *Un, cons
   if (cu < (unsigned)g.ncell)  // ncell < 2^31
     sig = update_cell(g, Un, Uin, Uout, Rout, dtp, a, bcoef, force, cu, dtpart != nullptr);
   if (dtpart) {
-    __shared__ double shx[256];
+    __shared__ double shx[4];
     const double m = block_max(sig, shx);
     if (threadIdx.x == 0) dtpart[blockIdx.x] = m;
   }
@@ -1100,7 +1101,7 @@ __device__ __forceinline__ void flux_update_body(const Dev &g, unsigned lin, uns
     }
   }
   if (dtpart) {
-    __shared__ double shx[256];
+    __shared__ double shx[4];
     const double m = block_max(sig, shx);
     if (threadIdx.x == 0) dtpart[bid] = m;
   }
@@ -1123,7 +1124,7 @@ __global__ void __launch_bounds__(256) k_flux_update(Dev g, const double *Un, co
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void dt_partial_body(const Dev &g, const double *U, double *part,
                                                 unsigned bid, unsigned nblk) {
-  __shared__ double sh[256];
+  __shared__ double sh[4];
   double smax = 0.0;
   for (long c = (long)bid * blockDim.x + threadIdx.x; c < g.ncell;
        c += (long)nblk * blockDim.x) {
@@ -1143,7 +1144,7 @@ __global__ void __launch_bounds__(256) k_dt_partial(Dev g, const double *U, doub
 
 __device__ __forceinline__ void dt_final_body(const double *part, int nparts, double cfl,
                                               double dt_max, double *dt) {
-  __shared__ double sh[256];
+  __shared__ double sh[4];
   double m = 0.0;
   for (int b = threadIdx.x; b < nparts; b += 256) m = fmax(m, part[b]);
   m = block_max(m, sh);
