@@ -307,38 +307,16 @@ def segment_length_for(case: Case, mode: int, nsteps: int, budget_bytes: int) ->
     largest seg_len whose workspace fits (every segment but the last is
     recomputed, so a longer segment recomputes less; seg_len = nsteps keeps
     the whole trajectory resident and recomputes nothing).  The workspace,
-    about (nsteps / seg_len + 3 seg_len) states in mode 2, grows with seg_len
-    beyond its minimum near sqrt(nsteps / 3), so the search runs on that
-    side.  Raises ValueError when not even the smallest workspace fits."""
+    about (ceil(nsteps / seg_len) + 3 seg_len) states in mode 2, is not
+    monotonic in seg_len, so every spacing is tried from the longest down
+    (host arithmetic, one library call each).  Raises ValueError when none
+    fits."""
     if mode not in (2, 3) or nsteps < 1:
         raise ValueError("a trajectory gradient workspace (mode 2 or 3, nsteps >= 1)")
-    def fits(S):
-        return workspace_bytes_for(case, mode, nsteps, S) <= budget_bytes
-    if fits(nsteps):
-        return nsteps
-    # smallest workspace over seg_len (it decreases, then increases)
-    lo = min(range(1, nsteps + 1),
-             key=lambda S: (workspace_bytes_for(case, mode, nsteps, S), -S)) \
-        if nsteps <= 64 else None
-    if lo is None:
-        lo = max(1, int(round((nsteps / 3.0) ** 0.5)))
-        while lo > 1 and workspace_bytes_for(case, mode, nsteps, lo - 1) <= \
-                workspace_bytes_for(case, mode, nsteps, lo):
-            lo -= 1
-        while lo < nsteps and workspace_bytes_for(case, mode, nsteps, lo + 1) < \
-                workspace_bytes_for(case, mode, nsteps, lo):
-            lo += 1
-    if not fits(lo):
-        raise ValueError(f"no checkpoint spacing fits {budget_bytes} bytes "
-                         f"(the smallest workspace is {workspace_bytes_for(case, mode, nsteps, lo)})")
-    hi = nsteps  # does not fit
-    while hi - lo > 1:  # invariant: fits(lo), not fits(hi)
-        mid = (lo + hi) // 2
-        if fits(mid):
-            lo = mid
-        else:
-            hi = mid
-    return lo
+    for S in range(nsteps, 0, -1):
+        if workspace_bytes_for(case, mode, nsteps, S) <= budget_bytes:
+            return S
+    raise ValueError(f"no checkpoint spacing fits {budget_bytes} bytes")
 
 
 class BatchPlan:

@@ -18,7 +18,7 @@ def test_longest_segment_that_fits(mode):
         budget = int(smallest + frac * (full - smallest))
         S = segment_length_for(case, mode, n, budget)
         assert workspace_bytes_for(case, mode, n, S) <= budget
-        # no longer segment fits (the workspace grows with S past its minimum)
+        # no longer segment fits
         assert all(workspace_bytes_for(case, mode, n, T) > budget for T in range(S + 1, n + 1))
         assert S >= prev
         prev = S
