@@ -52,10 +52,19 @@ __global__ void k_metrics(int kind, double lo, double hi, double beta, int n, do
 }
 
 // The cell widths of an axis summed in index order (one thread: the order of
-// the sum is part of the value).
+// the sum is part of the value).  Widths are loaded 16 at a time, all loads
+// of a group issued before its adds, so the sum waits for one memory round
+// trip per group instead of one per cell.
 __global__ void k_line_length(const double *dx, int n, double *out) {
   double L = 0.0;
-  for (int i = 0; i < n; ++i) L += dx[i];
+  for (int i0 = 0; i0 < n; i0 += 16) {
+    double t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) t[u] = i0 + u < n ? dx[i0 + u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (i0 + u < n) L += t[u];
+  }
   *out = L;
 }
 
@@ -1146,7 +1155,17 @@ __device__ __forceinline__ void dt_final_body(const double *part, int nparts, do
                                               double dt_max, double *dt) {
   __shared__ double sh[4];
   double m = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += 256) m = fmax(m, part[b]);
+  int b = threadIdx.x;
+  // 8 partials per thread loaded before they are combined (the same
+  // sequence of maxima per thread as one at a time)
+  for (; b + 7 * 256 < nparts; b += 8 * 256) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = part[b + u * 256];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) m = fmax(m, t[u]);
+  }
+  for (; b < nparts; b += 256) m = fmax(m, part[b]);
   m = block_max(m, sh);
   if (threadIdx.x == 0) dt[0] = fmin(dt_max, cfl / m);
 }
