@@ -267,9 +267,10 @@ def serving_bench(M=40, rate=20.0, seed=2024, M_low=12, rate_low=2.0, seed_low=2
                        "sequential": S.summarize(res_ls, t_ls)}
     out["note"] = ("sequential: FIFO, one solve at a time, each forward epoch a hipGraph replay; "
                    "streams: up to 16 admitted solves on 4 streams, per-solve graph epochs; "
-                   "batched: forward solves of one family share one hipGraph of batched step "
-                   "launches per epoch (captured again when the members change), gradients on "
-                   "the 4 streams; solves pooled per (family, size, kind); offered load = the "
+                   "batched: forward solves of one family of at most 2^17 cells share one "
+                   "hipGraph of batched step launches per epoch (captured again when the members "
+                   "change), larger forward solves and gradients as in streams; solves pooled "
+                   "per (family, size, kind); offered load = the "
                    "trace's cell updates over its arrival span")
     return out
 

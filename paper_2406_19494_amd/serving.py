@@ -470,18 +470,24 @@ class _Family:
 
 
 class BatchedGpuBackend(GpuBackend):
-    """Forward solves of one family (grid dimension, viscous or not, no
-    source) advance together: an epoch is one replay of a hipGraph of k
-    batched steps (one launch per kernel and stage for all members,
-    dcf_batch_rk3_step_table over a device table written outside the
-    capture), on the family's stream.  The graph is captured again only when
-    the members change; a member with fewer than k steps left runs them
-    eagerly.  Gradient solves run as in GpuBackend."""
+    """Small forward solves (at most batch_max_cells cells: too few
+    workgroups per launch to fill the GPU alone) of one family (grid
+    dimension, viscous or not, no source) advance together: an epoch is one
+    replay of a hipGraph of k batched steps (one launch per kernel and stage
+    for all members, dcf_batch_rk3_step_table over a device table written
+    outside the capture), on the family's stream.  The graph is captured
+    again only when the members change; a member with fewer than k steps
+    left runs them eagerly.  Larger forward solves and gradient solves run as
+    in GpuBackend (per-solve graph epochs on the shared streams), so that
+    solves which fill the GPU by themselves still overlap instead of queueing
+    on one family stream."""
 
     def __init__(self, steps_per_epoch: int = 10, keep_outputs: bool = False, inflight: int = 2,
-                 fault: Optional[Dict[int, str]] = None, budget_bytes: float = math.inf):
-        super().__init__(steps_per_epoch=steps_per_epoch, graphs=False, keep_outputs=keep_outputs,
+                 fault: Optional[Dict[int, str]] = None, budget_bytes: float = math.inf,
+                 batch_max_cells: int = 1 << 17):
+        super().__init__(steps_per_epoch=steps_per_epoch, graphs=True, keep_outputs=keep_outputs,
                          inflight=inflight, fault=fault, budget_bytes=budget_bytes)
+        self.batch_max_cells = batch_max_cells
         self.families: Dict[tuple, _Family] = {}
         self.want: Dict[tuple, list] = {}
         self.recaptures = 0
@@ -492,7 +498,7 @@ class BatchedGpuBackend(GpuBackend):
 
     def start(self, spec: RequestSpec):
         case, _, _ = build_case(spec)
-        if spec.kind == "gradient" or case.source != "none":
+        if spec.kind == "gradient" or case.source != "none" or cells_of(spec) > self.batch_max_cells:
             return super().start(spec)
         torch = self.torch
         fk = self._fkey(case)

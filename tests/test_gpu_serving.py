@@ -110,6 +110,28 @@ def test_batched_kernels_backend_matches_unbatched_alone():
             assert np.array_equal(np.asarray(va), np.asarray(m.output[key])), (spec, key)
 
 
+def test_batched_backend_serves_large_solves_per_request():
+    # above the size cut-off a forward solve leaves the family batch and runs
+    # per-solve graph epochs on the shared streams; every result still equals
+    # the solve served alone
+    trace = [
+        S.RequestSpec(0, "sod", 300, "forward", 33, 0.0),
+        S.RequestSpec(1, "sod", 700, "forward", 20, 0.0),
+        S.RequestSpec(2, "tgv", 16, "forward", 25, 0.0),
+        S.RequestSpec(3, "tgv", 24, "forward", 12, 0.0),
+        S.RequestSpec(4, "bl", 1, "forward", 21, 0.0),
+    ]
+    be = S.BatchedGpuBackend(keep_outputs=True, batch_max_cells=1000)
+    mix, _, _ = S.serve(trace, max_slots=5, keep_outputs=True, realtime=False, backend=be)
+    assert {f[0] for f in be.families} == {1}  # only the Sod solves were batched
+    for spec in trace:
+        alone, _, _ = S.serve([spec], max_slots=1, keep_outputs=True, realtime=False)
+        a, m = alone[spec.rid], mix[spec.rid]
+        assert a.status == m.status == "ok", (spec, a.status, m.status, m.message)
+        for key, va in a.output.items():
+            assert np.array_equal(np.asarray(va), np.asarray(m.output[key])), (spec, key)
+
+
 def test_batched_kernels_backend_isolates_nonphysical():
     trace = [S.RequestSpec(0, "sod", 300, "forward", 30, 0.0),
              S.RequestSpec(1, "sod", 400, "forward", 30, 0.0)]
